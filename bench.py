@@ -1,0 +1,194 @@
+"""Throughput of the exponential-Euler step on one MI355X.
+
+Workload: the 128^3 synthetic head (seed 2402; white / gray matter D = 0.13 /
+0.013 mm^2/day, CSF and outside D = 0, no-flux box), rho = 0.025/day,
+tau = 7.3 days, FP32 stencil-Taylor.  A "step" is one full exponential Euler
+step (right-hand side, s*m fused Taylor-term sweeps, update of u).  The
+timed region runs --steps steps from u0 with all inputs resident in HBM; with
+--steps 100 (the default, the two-year run) the result is also compared with
+the stored FP64 oracle result (rel-L2).
+
+Prints one JSON line.  Extra objects:
+  roofline     - the dominant kernel (the fused Taylor-term sweep): algorithmic
+                 bytes per launch over its mean launch time (HIP events on the
+                 library stream), against the 8 TB/s HBM peak;
+  step_rates   - the same bytes model over the whole timed step;
+  cpu_baseline - the FP64 oracle on a bounded sample (a few steps of the same
+                 workload) on the host cores.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxel-updates/s at 128^3 (rel-L2<=1e-5 vs FP64 oracle); % HBM/MFMA roofline"
+HBM_PEAK_GBS = 8000.0
+LABEL_BYTES = 1
+
+
+def term_bytes_per_voxel(w):
+    # read src, read labels, read acc, write y, write acc
+    return 4 * w + LABEL_BYTES
+
+
+def step_bytes_per_voxel(w, s, m):
+    # RHS (read u, labels; write b) + (s*m - 1) term sweeps; the last sweep
+    # reads/writes u instead of writing y/acc (same count).
+    return (2 * w + LABEL_BYTES) + (s * m - 1) * term_bytes_per_voxel(w)
+
+
+def load_traffic(kernel_key):
+    """HBM bytes per launch from the committed rocprof counter summary, if any."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        return data.get(kernel_key)
+    except Exception:
+        return None
+
+
+def cpu_baseline(w, nsteps):
+    import numpy as np
+
+    from oracle import integrator, operator, plan
+
+    op = operator.Operator(w.h, labels=w.labels, class_D=w.class_D)
+    s, m = plan.for_dtype(w.tau * op.norm1(), "f64")
+    t0 = time.perf_counter()
+    u = integrator.advance(op, w.u0, w.rho, w.tau, s, m, nsteps)
+    dt = time.perf_counter() - t0
+    assert np.isfinite(u).all()
+    return {
+        "value": w.nvox * nsteps / dt,
+        "unit": "voxel-updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{nsteps} FP64 oracle steps of the same 128^3 workload (plan {s}x{m}), NumPy on 1 host thread, {dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(
+            "bench.py measures one GPU only: this build runs the step on a single MI355X "
+            "(multi-GPU sharding is a design note, not built); use --gpus 1",
+            file=sys.stderr,
+        )
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2402_02273_amd.expint import ExpInt
+    from workloads import c2_head
+
+    dev = torch.device("cuda:0")
+    dtype = torch.float32 if args.dtype == "f32" else torch.float64
+    w_bytes = 4 if args.dtype == "f32" else 8
+    w = c2_head(n=args.n)
+    ctx = ExpInt(w.shape, w.h, labels=w.labels, class_D=w.class_D, rho=w.rho, tau=w.tau, dtype=dtype, device=dev)
+    plan = ctx.plan
+    u0 = torch.as_tensor(w.u0, dtype=dtype, device=dev).contiguous()
+    u = u0.clone()
+
+    # warm-up on the timed buffer (records the graph), then restore u0
+    if args.warmup > 0:
+        ctx.advance(u, args.warmup)
+    u.copy_(u0)
+    torch.cuda.synchronize()
+
+    stream = ctx.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall0 = time.perf_counter()
+    ev0.record(stream)
+    ctx.advance(u, args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall0
+    ms = ev0.elapsed_time(ev1)
+    ms_per_step = ms / max(args.steps, 1)
+    value = w.nvox * args.steps / (ms / 1e3)
+
+    rel = None
+    if args.n == 128 and args.steps == 100:
+        gpath = os.path.join(ROOT, "tests", "golden", "c2_head_128_u100_f64.npz")
+        if os.path.exists(gpath):
+            g = np.load(gpath)
+            got = u.double().cpu().numpy()
+            rel = float(np.linalg.norm(got - g["u"]) / np.linalg.norm(g["u"]))
+
+    # dominant kernel: mean launch time of the fused Taylor-term sweep
+    ms_term, ms_rhs = ctx.profile(reps=200)
+    tb = term_bytes_per_voxel(w_bytes) * w.nvox
+    achieved = tb / (ms_term * 1e-3) / 1e9
+    traffic = load_traffic(f"term_{args.dtype}_{args.n}")
+    sb = step_bytes_per_voxel(w_bytes, plan.s, plan.m) * w.nvox
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "voxel-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.n}^3 synthetic head seed 2402, D 0.13/0.013/0 mm^2/day, rho 0.025/day, "
+            f"tau 7.3 d, no-flux, stencil-Taylor",
+            "grid": [args.n] * 3,
+            "plan_s_m": [plan.s, plan.m],
+            "norm_A1": plan.norm_A1,
+        },
+        "rel_l2_vs_oracle": rel,
+        "roofline": {
+            "kernel": "k_term (fused stencil + Taylor term + running sum)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "bytes_per_launch": tb,
+            "ms_per_launch": ms_term,
+        },
+        "step_rates": {
+            "algorithmic_bytes_per_step": sb,
+            "achieved_GBs": sb / (ms_per_step * 1e-3) / 1e9,
+            "frac_of_hbm_peak": sb / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "ms_rhs_per_launch": ms_rhs,
+            "launches_per_step": plan.s * plan.m,
+            "wall_s": t_wall,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,223 @@
+/*
+ * expint.h - C ABI of the MI355X exponential-integrator library.
+ *
+ * The library advances the finite-difference Fisher-Kolmogorov glioma model
+ *
+ *     du/dt = div(D(x) grad u) + rho u (1 - u),   zero normal flux   (PDE, section 2)
+ *
+ * by the exponential Euler method in its incremental form (section 2.2)
+ *
+ *     u_{n+1} = u_n + tau phi1(tau A) (A u_n + rho u_n (1 - u_n)),
+ *
+ * where A is the 7-point finite-difference diffusion operator (section 2.1,
+ * taken in conservative flux form with harmonic face means, so that it is
+ * symmetric, negative semidefinite and conserves mass) and the action of
+ * tau phi1(tau A) is computed as exp(tau B) applied to a unit vector of the
+ * augmented matrix B = [[A, b], [0, 0]], exp evaluated as s scaled factors of
+ * a degree-m truncated Taylor series (section 2.2).
+ *
+ * Conventions for every call:
+ *  - Grids are nx * ny * nz voxels of spacing h, stored contiguously in C
+ *    order with z fastest: flat index (i * ny + j) * nz + k.
+ *  - "device" pointers are HIP device allocations on the current device (for
+ *    example the data pointer of a torch tensor); "host" pointers are
+ *    ordinary host memory.  Field pointers carry the context's dtype
+ *    (double for EXPINT_F64, float for EXPINT_F32).
+ *  - Every call returns 0 (EXPINT_OK) or a negative error code; nothing
+ *    throws across the ABI.  expint_last_error() gives a message for the last
+ *    failure on the calling thread.
+ *  - Field computations are asynchronous on the context's stream unless the
+ *    call returns host scalars (then it synchronises that stream).
+ *  - A context is not thread-safe; use one context per stream.  After an
+ *    EXPINT_EHIP failure the context is poisoned and every later call on it
+ *    returns EXPINT_ESTATE (expint_destroy still works).
+ */
+#ifndef EXPINT_H
+#define EXPINT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EXPINT_OK 0
+#define EXPINT_EINVAL (-1)       /* invalid argument */
+#define EXPINT_EUNSUPPORTED (-2) /* valid request this build does not handle */
+#define EXPINT_ENOMEM (-3)       /* device allocation failed or over EXPINT_MAX_BYTES */
+#define EXPINT_EHIP (-4)         /* a HIP runtime call failed; context poisoned */
+#define EXPINT_ENONFINITE (-5)   /* check_finite found a NaN/Inf in the state */
+#define EXPINT_ESTATE (-6)       /* context poisoned by an earlier EXPINT_EHIP */
+
+#define EXPINT_MAX_CLASSES 8
+
+typedef enum { EXPINT_F64 = 0, EXPINT_F32 = 1 } expint_dtype;
+
+/* Box boundary: EXPINT_NOFLUX is the paper's grad u . n = 0 (PDE, section 2),
+ * read as zero flux through the wall faces.  EXPINT_DIRICHLET0 puts a ghost
+ * value u = 0 at distance h outside each wall face (used for closed-form
+ * sine-mode tests). */
+typedef enum { EXPINT_NOFLUX = 0, EXPINT_DIRICHLET0 = 1 } expint_bc;
+
+/* EXPINT_ALGO_STENCIL_TAYLOR: matrix-free stencil inside the scaled Taylor
+ * series (any D).  EXPINT_ALGO_MODAL: uniform D only, A diagonalised by
+ * per-axis cosine (no-flux) or sine (Dirichlet) modes; phi1 applied exactly
+ * in that basis with dense per-axis mode products.  AUTO picks STENCIL_TAYLOR. */
+typedef enum {
+  EXPINT_ALGO_AUTO = 0,
+  EXPINT_ALGO_STENCIL_TAYLOR = 1,
+  EXPINT_ALGO_MODAL = 2
+} expint_algo;
+
+/* Arithmetic of the modal path's mode products (EXPINT_F32 contexts only):
+ * NONE = fp32 vector FMA; BF16_SPLIT / FP16_SPLIT = matrix-core products of
+ * hi + lo split operands with fp32 accumulation. */
+typedef enum {
+  EXPINT_MP_NONE = 0,
+  EXPINT_MP_BF16_SPLIT = 1,
+  EXPINT_MP_FP16_SPLIT = 2
+} expint_mp;
+
+typedef struct {
+  int32_t nx, ny, nz; /* voxels per axis, each >= 1 */
+  double h;           /* grid spacing (> 0), same unit as sqrt(D * time) */
+} expint_grid;
+
+/* Diffusivity D(x) per voxel (section 2: one value per tissue class).
+ * Exactly one of `labels` and `D` is non-NULL.
+ *  - label form: labels (device, nx*ny*nz uint8, each < n_classes) and
+ *    class_D (host, n_classes doubles >= 0), 1 <= n_classes <= 8.
+ *  - dense form: D (device, nx*ny*nz values of the context dtype, >= 0).
+ * The library copies what it needs during expint_create; the caller may free
+ * these buffers afterwards. */
+typedef struct {
+  const uint8_t* labels;
+  int32_t n_classes;
+  const double* class_D;
+  const void* D;
+} expint_dfield;
+
+typedef struct {
+  expint_dtype dtype;   /* arithmetic of the fields */
+  double tau;           /* time step (> 0) */
+  double tol;           /* plan tolerance; 0 = 1e-13 (F64) / 1e-6 (F32) */
+  double theta_max;     /* plan cap on tau*||A||_1/s; 0 = ln 1024 (F64) / ln 16 (F32) */
+  expint_algo algo;
+  expint_mp mp;
+  int32_t s, m;         /* both > 0: use this plan; both 0: choose it */
+  int32_t check_finite; /* nonzero: expint_step / expint_advance scan u for NaN/Inf */
+  void* stream;         /* hipStream_t the context works on; NULL = null stream */
+} expint_opts;
+
+typedef struct expint_ctx expint_ctx;
+
+/* Fill *opts with defaults: F32, tau = 7.3, automatic plan, AUTO, no check,
+ * null stream.  Returns EXPINT_EINVAL for NULL. */
+int expint_opts_default(expint_opts* opts);
+
+/* Create a context for one grid, diffusivity field, rho and boundary.
+ * Validates the arguments, copies the coefficients, computes ||A||_1 on the
+ * device (one stream synchronisation), chooses (s, m) by the plan rule
+ * (section 2.2 asks for a "proper selection"; the rule: minimise s*m subject
+ * to s*theta^(m+1)/(m+1)! <= tol and theta = tau*||A||_1/s <= theta_max,
+ * m <= 60, ties to the smaller s) and allocates the workspace.
+ * Errors: EINVAL (NULL pointer, dims < 1, h <= 0, tau <= 0, rho < 0 or not
+ * finite, n_classes outside 1..8, class_D < 0 or not finite, a label >=
+ * n_classes, D < 0 or not finite, s/m partly set), EUNSUPPORTED (MODAL with a
+ * non-uniform D, or mp without MODAL F32), ENOMEM, EHIP.  *out is NULL on error. */
+int expint_create(const expint_grid* grid, const expint_dfield* dfield, double rho,
+                  expint_bc bc, const expint_opts* opts, expint_ctx** out);
+
+/* Release the context and its workspace.  NULL-safe. */
+void expint_destroy(expint_ctx* ctx);
+
+/* The plan in use: Taylor scaling s, degree m and ||A||_1 (host scalars). */
+int expint_get_plan(const expint_ctx* ctx, int32_t* s, int32_t* m, double* norm_A1);
+
+/* Replace rho and (label form) the class diffusivities.  replan != 0
+ * recomputes ||A||_1 and (s, m) unless the plan was fixed in the options;
+ * replan == 0 keeps the current (s, m) (finite-difference checks need the
+ * computed map to stay smooth).  class_D may be NULL to keep it. */
+int expint_set_params(expint_ctx* ctx, double rho, const double* class_D, int32_t replan);
+
+/* y = A x (device fields).  x and y must not overlap. */
+int expint_apply(expint_ctx* ctx, const void* x, void* y);
+
+/* b = A u + rho u (1 - u): the right-hand side the step applies phi1 to. */
+int expint_rhs(expint_ctx* ctx, const void* u, void* b);
+
+/* x = tau phi1(tau A) b by the scaled Taylor series (section 2.2); with the
+ * MODAL algorithm, exactly in the mode basis.  b and x must not overlap. */
+int expint_phi1(expint_ctx* ctx, const void* b, void* x);
+
+/* One exponential Euler step, in place: u <- u + tau phi1(tau A)(A u + f(u)).
+ * u: device field owned by the caller.  ENONFINITE with check_finite set. */
+int expint_step(expint_ctx* ctx, void* u);
+
+/* nsteps >= 0 steps in place.  The first call for a given u records the step
+ * as a HIP graph on the context stream; later calls replay it. */
+int expint_advance(expint_ctx* ctx, void* u, int32_t nsteps);
+
+/* Deterministic FP64 reductions over a device field of the context dtype:
+ * op 0 = sum x, 1 = sum x*y, 2 = max |x|.  y is used by op 1 only.
+ * Writes the host scalar *out (synchronises the stream).  The tumour volume
+ * diagnostic of the paper's convergence study (section 3.5) is op 0 / n. */
+int expint_reduce(expint_ctx* ctx, int32_t op, const void* x, const void* y, double* out);
+
+/* Gradient of loss = 0.5 ||u_T - u_target||^2, u_T = nsteps steps from u0,
+ * by the discrete adjoint of the computed map with the plan frozen.
+ * u0, u_target: device fields (read only); grad_u0: device field (written);
+ * loss, grad_rho: host scalars; grad_class_D: host array of n_classes
+ * (label form only; dense form gives EINVAL).  u is checkpointed every
+ * ckpt_every steps (>= 1) and recomputed in between. */
+int expint_grad(expint_ctx* ctx, const void* u0, int32_t nsteps, const void* u_target,
+                int32_t ckpt_every, double* loss, void* grad_u0, double* grad_rho,
+                double* grad_class_D);
+
+/* Vector-Jacobian product of the same map for a given cotangent gout = dL/du_T
+ * (device field).  Outputs as in expint_grad. */
+int expint_vjp(expint_ctx* ctx, const void* u0, int32_t nsteps, const void* gout,
+               int32_t ckpt_every, void* grad_u0, double* grad_rho, double* grad_class_D);
+
+/* ---- Batched scenarios: many independent instances advanced together. ---- */
+typedef struct expint_batch expint_batch;
+
+/* count instances, each with its own grid, label field, class table and rho
+ * (arrays of length count; dfield entries must use the label form).  Shared
+ * bc and opts (dtype, tau, tol, theta_max).  Every instance gets its own
+ * plan.  Errors as expint_create. */
+int expint_batch_create(int32_t count, const expint_grid* grids, const expint_dfield* dfields,
+                        const double* rho, expint_bc bc, const expint_opts* opts,
+                        expint_batch** out);
+
+/* Advance every instance by nsteps: u[i] is instance i's device field.  The
+ * first call for a given set of pointers records one HIP graph holding the
+ * whole schedule; later calls replay it. */
+int expint_batch_advance(expint_batch* batch, void* const* u, int32_t nsteps);
+
+int expint_batch_get_plan(const expint_batch* batch, int32_t index, int32_t* s, int32_t* m,
+                          double* norm_A1);
+
+void expint_batch_destroy(expint_batch* batch);
+
+/* ---- Introspection and measurement. ---- */
+
+/* The HIP stream (hipStream_t) the context works on: opts.stream, or a
+ * blocking stream the context created when opts.stream was NULL. */
+int expint_get_stream(const expint_ctx* ctx, void** stream);
+
+/* Times `reps` back-to-back launches of the generic Taylor-term sweep of
+ * this context (A applied to a workspace field, running sum updated in
+ * place) and of the right-hand-side sweep, with HIP events on the context
+ * stream; writes the mean milliseconds per launch (ms_rhs may be NULL).
+ * Uses only the context workspace; synchronises the stream. */
+int expint_profile(expint_ctx* ctx, int32_t reps, double* ms_term, double* ms_rhs);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char* expint_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EXPINT_H */

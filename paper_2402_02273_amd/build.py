@@ -1,0 +1,96 @@
+"""Builds the HIP library ``libexpint.so`` in-tree for gfx950.
+
+Every source under ``csrc/`` is compiled by hipcc (HIP sources and the host
+runtime alike), then linked into a shared library that exports only the
+``expint_*`` symbols of ``include/expint.h``.
+"""
+
+from __future__ import annotations
+
+import concurrent.futures
+import glob
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+BUILD = os.path.join(ROOT, "_build")
+LIB = os.path.join(HERE, "libexpint.so")
+ARCH = os.environ.get("EXPINT_ARCH", "gfx950")
+
+COMMON = [
+    "-std=c++17",
+    "-O3",
+    "-fPIC",
+    "-Wall",
+    "-Wno-unused-function",
+    "-I",
+    INCLUDE,
+    "-I",
+    CSRC,
+    f"--offload-arch={ARCH}",
+    # no packed-FP32 instructions anywhere in the device code
+    "-Xclang",
+    "-target-feature",
+    "-Xclang",
+    "-packed-fp32-ops",
+]
+
+
+def hipcc():
+    path = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(path):
+        raise RuntimeError("hipcc not found")
+    return path
+
+
+def sources():
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
+
+
+def _compile(src):
+    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    cmd = [hipcc(), *COMMON, "-c", src, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    return src, obj, r.returncode, r.stdout + r.stderr
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = sources()
+    jobs = jobs or min(len(srcs), os.cpu_count() or 4, 16)
+    objs = []
+    errors = []
+    with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
+        for src, obj, rc, out in ex.map(_compile, srcs):
+            objs.append(obj)
+            if rc != 0:
+                errors.append(f"--- {os.path.basename(src)} ---\n{out}")
+            elif verbose and out.strip():
+                print(out, file=sys.stderr)
+    if errors:
+        raise RuntimeError("HIP compilation failed:\n" + "\n".join(errors))
+    tmp = LIB + ".tmp"
+    cmd = [
+        hipcc(),
+        "-shared",
+        "-fPIC",
+        f"--offload-arch={ARCH}",
+        "-o",
+        tmp,
+        *objs,
+        f"-Wl,--version-script={os.path.join(CSRC, 'exports.map')}",
+    ]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

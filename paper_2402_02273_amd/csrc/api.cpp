@@ -1,0 +1,536 @@
+// Host runtime of the C ABI declared in include/expint.h: argument
+// validation, coefficient tables, the (s, m) plan, the Taylor-term schedule
+// of one exponential Euler step and its HIP graph.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "context.hpp"
+#include "internal.hpp"
+#include "plan.hpp"
+#include "schedule.hpp"
+
+using namespace expint;
+
+namespace expint {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+const char* last_error() { return g_last_error.c_str(); }
+void clear_error() { g_last_error.clear(); }
+
+size_t dtype_size(expint_dtype dt) { return dt == EXPINT_F64 ? 8 : 4; }
+
+Arena::Arena() {
+  const char* env = std::getenv("EXPINT_MAX_BYTES");
+  if (env && *env) cap_ = static_cast<size_t>(std::strtoull(env, nullptr, 10));
+}
+
+Arena::~Arena() {
+  for (void* p : ptrs_) (void)hipFree(p);
+}
+
+int Arena::alloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 1;
+  if (cap_ && bytes_ + bytes > cap_)
+    return set_error(EXPINT_ENOMEM, "allocation of %zu bytes exceeds EXPINT_MAX_BYTES=%zu (in use %zu)", bytes,
+                     cap_, bytes_);
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return set_error(EXPINT_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  ptrs_.push_back(*p);
+  bytes_ += bytes;
+  return EXPINT_OK;
+}
+
+void destroy_graphs(std::vector<GraphEntry>& gs) {
+  for (auto& e : gs) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+  }
+  gs.clear();
+}
+
+}  // namespace expint
+
+#define HIP_TRY(ctxp, call)                                                                          \
+  do {                                                                                               \
+    const hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) {                                                                          \
+      (ctxp)->poisoned = true;                                                                       \
+      return set_error(EXPINT_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                       __LINE__);                                                                    \
+    }                                                                                                \
+  } while (0)
+
+#define CHECK_CTX(ctxp)                                                              \
+  do {                                                                               \
+    if (!(ctxp)) return set_error(EXPINT_EINVAL, "context is NULL");                 \
+    if ((ctxp)->poisoned) return set_error(EXPINT_ESTATE, "context poisoned by an earlier HIP error"); \
+  } while (0)
+
+namespace {
+
+bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+
+double harmonic(double a, double b) {
+  const double s = a + b;
+  return s > 0.0 ? 2.0 * a * b / s : 0.0;
+}
+
+int ensure_device(expint_ctx* c) {
+  int cur = -1;
+  HIP_TRY(c, hipGetDevice(&cur));
+  if (cur != c->device) HIP_TRY(c, hipSetDevice(c->device));
+  return EXPINT_OK;
+}
+
+// Upload the class-pair tables for the current class_D (label form).
+int upload_tables(expint_ctx* c) {
+  double t64[kTab] = {0}, w64[kMaxClasses] = {0};
+  const double inv_h2 = 1.0 / (c->h * c->h);
+  for (int a = 0; a < c->nclass; ++a) {
+    w64[a] = c->class_D[a] * inv_h2;
+    for (int b = 0; b < c->nclass; ++b) t64[a * kMaxClasses + b] = harmonic(c->class_D[a], c->class_D[b]) * inv_h2;
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->tab64, t64, sizeof(t64), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->wall64, w64, sizeof(w64), hipMemcpyHostToDevice, c->stream));
+  if (c->dtype == EXPINT_F64) {
+    HIP_TRY(c, hipMemcpyAsync(c->tab, t64, sizeof(t64), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->wallc, w64, sizeof(w64), hipMemcpyHostToDevice, c->stream));
+  } else {
+    float t32[kTab], w32[kMaxClasses];
+    for (int i = 0; i < kTab; ++i) t32[i] = static_cast<float>(t64[i]);
+    for (int i = 0; i < kMaxClasses; ++i) w32[i] = static_cast<float>(w64[i]);
+    HIP_TRY(c, hipMemcpyAsync(c->tab, t32, sizeof(t32), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->wallc, w32, sizeof(w32), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));  // the host arrays die at return
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return EXPINT_OK;
+}
+
+// Label scan: ||A||_1 and label validation (one synchronisation).
+int scan_labels(expint_ctx* c, double* bad) {
+  HIP_TRY(c, launch_scan_labels(c->bc, c->g, c->labels, c->nclass, c->tab64, c->wall64, c->partial, c->red,
+                                c->stream));
+  double out[2];
+  HIP_TRY(c, hipMemcpyAsync(out, c->red, sizeof(out), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->norm1 = out[0];
+  *bad = out[1];
+  return EXPINT_OK;
+}
+
+int make_plan(expint_ctx* c) {
+  if (c->fixed_plan) return EXPINT_OK;
+  int s = 0, m = 0;
+  if (!choose_plan(c->tau * c->norm1, c->tol, c->theta_max, &s, &m))
+    return set_error(EXPINT_EINVAL, "no admissible plan for tau*||A||_1 = %g (tol %g, theta_max %g)",
+                     c->tau * c->norm1, c->tol, c->theta_max);
+  c->s = s;
+  c->m = m;
+  return EXPINT_OK;
+}
+
+int run_ops(expint_ctx* c, const std::vector<TermOp>& ops) {
+  const Coef cf = c->coef();
+  for (const TermOp& op : ops) HIP_TRY(c, launch_term(c->dtype, c->bc, c->g, cf, op, c->stream));
+  return EXPINT_OK;
+}
+
+StepBuffers step_buffers(expint_ctx* c) {
+  StepBuffers sb;
+  sb.b = c->b;
+  sb.y[0] = c->y[0];
+  sb.y[1] = c->y[1];
+  sb.acc[0] = c->acc[0];
+  sb.acc[1] = c->acc[1];
+  return sb;
+}
+
+// Launches of one step on c->stream (no synchronisation).
+int enqueue_step(expint_ctx* c, void* u) {
+  HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, c->coef(), u, c->b, c->rho, c->stream));
+  const auto ops = phi1_schedule(step_buffers(c), c->s, c->m, c->tau, c->b, nullptr, u);
+  return run_ops(c, ops);
+}
+
+int check_finite_field(expint_ctx* c, const void* u) {
+  HIP_TRY(c, launch_reduce(c->dtype, 3, u, nullptr, c->g.n, c->partial, c->red, c->stream));
+  double cnt = 0.0;
+  HIP_TRY(c, hipMemcpyAsync(&cnt, c->red, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (cnt != 0.0) return set_error(EXPINT_ENONFINITE, "state holds %.0f non-finite values", cnt);
+  return EXPINT_OK;
+}
+
+int validate_opts(const expint_opts* o) {
+  if (o->dtype != EXPINT_F64 && o->dtype != EXPINT_F32) return set_error(EXPINT_EINVAL, "unknown dtype %d", o->dtype);
+  if (!(o->tau > 0.0) || !std::isfinite(o->tau)) return set_error(EXPINT_EINVAL, "tau must be finite and > 0");
+  if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return set_error(EXPINT_EINVAL, "tol must be finite and >= 0");
+  if (!(o->theta_max >= 0.0) || !std::isfinite(o->theta_max))
+    return set_error(EXPINT_EINVAL, "theta_max must be finite and >= 0");
+  if ((o->s > 0) != (o->m > 0) || o->s < 0 || o->m < 0)
+    return set_error(EXPINT_EINVAL, "give both s and m (> 0) or neither");
+  if (o->m > kPlanMaxDegree) return set_error(EXPINT_EINVAL, "m must be <= %d", kPlanMaxDegree);
+  if (o->algo < EXPINT_ALGO_AUTO || o->algo > EXPINT_ALGO_MODAL) return set_error(EXPINT_EINVAL, "unknown algo");
+  if (o->mp < EXPINT_MP_NONE || o->mp > EXPINT_MP_FP16_SPLIT) return set_error(EXPINT_EINVAL, "unknown mp");
+  return EXPINT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int expint_opts_default(expint_opts* o) {
+  if (!o) return set_error(EXPINT_EINVAL, "opts is NULL");
+  std::memset(o, 0, sizeof(*o));
+  o->dtype = EXPINT_F32;
+  o->tau = 7.3;
+  o->algo = EXPINT_ALGO_AUTO;
+  o->mp = EXPINT_MP_NONE;
+  return EXPINT_OK;
+}
+
+const char* expint_last_error(void) { return expint::last_error(); }
+
+int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, expint_bc bc,
+                  const expint_opts* opts, expint_ctx** out) {
+  if (out) *out = nullptr;
+  if (!grid || !df || !opts || !out) return set_error(EXPINT_EINVAL, "NULL argument");
+  if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1)
+    return set_error(EXPINT_EINVAL, "grid dims must be >= 1 (got %d %d %d)", grid->nx, grid->ny, grid->nz);
+  if (!(grid->h > 0.0) || !std::isfinite(grid->h)) return set_error(EXPINT_EINVAL, "h must be finite and > 0");
+  if (!finite_nonneg(rho)) return set_error(EXPINT_EINVAL, "rho must be finite and >= 0");
+  if (bc != EXPINT_NOFLUX && bc != EXPINT_DIRICHLET0) return set_error(EXPINT_EINVAL, "unknown bc %d", bc);
+  int rc = validate_opts(opts);
+  if (rc) return rc;
+  if ((df->labels == nullptr) == (df->D == nullptr))
+    return set_error(EXPINT_EINVAL, "give exactly one of labels and D");
+  const int64_t n = static_cast<int64_t>(grid->nx) * grid->ny * grid->nz;
+  if (n > (int64_t(1) << 31) - 1) return set_error(EXPINT_EINVAL, "grid too large (%lld voxels)", (long long)n);
+  if (df->labels) {
+    if (df->n_classes < 1 || df->n_classes > EXPINT_MAX_CLASSES)
+      return set_error(EXPINT_EINVAL, "n_classes must be in 1..%d", EXPINT_MAX_CLASSES);
+    if (!df->class_D) return set_error(EXPINT_EINVAL, "class_D is NULL");
+    for (int a = 0; a < df->n_classes; ++a)
+      if (!finite_nonneg(df->class_D[a])) return set_error(EXPINT_EINVAL, "class_D[%d] must be finite and >= 0", a);
+  }
+  const expint_algo algo = opts->algo == EXPINT_ALGO_AUTO ? EXPINT_ALGO_STENCIL_TAYLOR : opts->algo;
+  if (algo == EXPINT_ALGO_MODAL || opts->mp != EXPINT_MP_NONE)
+    return set_error(EXPINT_EUNSUPPORTED, "the modal path is not available in this build");
+
+  expint_ctx* c = new (std::nothrow) expint_ctx();
+  if (!c) return set_error(EXPINT_ENOMEM, "host allocation failed");
+  auto bail = [&](int code) {
+    expint_destroy(c);
+    return code;
+  };
+  c->g.nx = grid->nx;
+  c->g.ny = grid->ny;
+  c->g.nz = grid->nz;
+  c->g.n = n;
+  c->h = grid->h;
+  c->dtype = opts->dtype;
+  c->bc = bc;
+  c->algo = algo;
+  c->mp = opts->mp;
+  c->rho = rho;
+  c->tau = opts->tau;
+  default_tolerances(c->dtype, &c->tol, &c->theta_max);
+  if (opts->tol > 0.0) c->tol = opts->tol;
+  if (opts->theta_max > 0.0) c->theta_max = opts->theta_max;
+  c->fixed_plan = opts->s > 0;
+  if (c->fixed_plan) {
+    c->s = opts->s;
+    c->m = opts->m;
+  }
+  c->check_finite = opts->check_finite;
+  c->labels_form = df->labels != nullptr;
+
+  if (field_block_count(c->g) > (int64_t(1) << 31) - 1) return bail(set_error(EXPINT_EINVAL, "grid too large"));
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(set_error(EXPINT_EHIP, "no HIP device"));
+  }
+  if (opts->stream) {
+    c->stream = static_cast<hipStream_t>(opts->stream);
+  } else {
+    // A blocking stream of our own: ordered with the null stream, and
+    // capturable into a graph (the null stream is not).
+    if (hipStreamCreate(&c->stream) != hipSuccess) {
+      (void)hipGetLastError();
+      return bail(set_error(EXPINT_EHIP, "hipStreamCreate failed"));
+    }
+    c->own_stream = true;
+  }
+
+  const size_t fb = c->field_bytes();
+  // partial sums: the scans write two per voxel-kernel workgroup, the
+  // reductions one per reduction workgroup
+  const int64_t nparts = std::max<int64_t>(field_block_count(c->g), kReduceBlocks);
+  if ((rc = c->arena.alloc(reinterpret_cast<void**>(&c->partial), 2 * nparts * sizeof(double)))) return bail(rc);
+  if ((rc = c->arena.alloc(reinterpret_cast<void**>(&c->red), 2 * sizeof(double)))) return bail(rc);
+
+  double bad = 0.0;
+  if (c->labels_form) {
+    c->nclass = df->n_classes;
+    for (int a = 0; a < c->nclass; ++a) c->class_D[a] = df->class_D[a];
+    if ((rc = c->arena.alloc(reinterpret_cast<void**>(&c->labels), static_cast<size_t>(n)))) return bail(rc);
+    if ((rc = c->arena.alloc(reinterpret_cast<void**>(&c->tab64), kTab * sizeof(double)))) return bail(rc);
+    if ((rc = c->arena.alloc(reinterpret_cast<void**>(&c->wall64), kMaxClasses * sizeof(double)))) return bail(rc);
+    if ((rc = c->arena.alloc(&c->tab, kTab * sizeof(double)))) return bail(rc);
+    if ((rc = c->arena.alloc(&c->wallc, kMaxClasses * sizeof(double)))) return bail(rc);
+    if (hipMemcpyAsync(c->labels, df->labels, static_cast<size_t>(n), hipMemcpyDefault, c->stream) != hipSuccess) {
+      (void)hipGetLastError();
+      return bail(set_error(EXPINT_EINVAL, "labels pointer is not readable"));
+    }
+    if ((rc = upload_tables(c))) return bail(rc);
+    if ((rc = scan_labels(c, &bad))) return bail(rc);
+    if (bad != 0.0) return bail(set_error(EXPINT_EINVAL, "a label is >= n_classes (%d)", c->nclass));
+  } else {
+    if ((rc = c->arena.alloc(&c->fx, fb))) return bail(rc);
+    if ((rc = c->arena.alloc(&c->fy, fb))) return bail(rc);
+    if ((rc = c->arena.alloc(&c->fz, fb))) return bail(rc);
+    if ((rc = c->arena.alloc(&c->wallv, fb))) return bail(rc);
+    const hipError_t e = launch_scan_dense(c->dtype, c->bc, c->g, df->D, 1.0 / (c->h * c->h), c->fx, c->fy, c->fz,
+                                           c->wallv, c->partial, c->red, c->stream);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return bail(set_error(EXPINT_EHIP, "dense scan failed: %s", hipGetErrorString(e)));
+    }
+    double out2[2];
+    if (hipMemcpyAsync(out2, c->red, sizeof(out2), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+      (void)hipGetLastError();
+      return bail(set_error(EXPINT_EHIP, "dense scan readback failed"));
+    }
+    c->norm1 = out2[0];
+    if (out2[1] != 0.0) return bail(set_error(EXPINT_EINVAL, "D holds a negative or non-finite value"));
+  }
+  if ((rc = make_plan(c))) return bail(rc);
+
+  if ((rc = c->arena.alloc(&c->b, fb))) return bail(rc);
+  for (int i = 0; i < 2; ++i) {
+    if ((rc = c->arena.alloc(&c->y[i], fb))) return bail(rc);
+    if ((rc = c->arena.alloc(&c->acc[i], fb))) return bail(rc);
+  }
+  if (std::getenv("EXPINT_LOG"))
+    std::fprintf(stderr, "[expint] grid %dx%dx%d h=%g dtype=%s ||A||_1=%.17g nu=%.6g plan s=%d m=%d workspace %zu B\n",
+                 c->g.nx, c->g.ny, c->g.nz, c->h, c->dtype == EXPINT_F64 ? "f64" : "f32", c->norm1,
+                 c->tau * c->norm1, c->s, c->m, c->arena.bytes());
+  *out = c;
+  expint::clear_error();
+  return EXPINT_OK;
+}
+
+void expint_destroy(expint_ctx* c) {
+  if (!c) return;
+  int cur = -1;
+  if (hipGetDevice(&cur) == hipSuccess && cur != c->device) (void)hipSetDevice(c->device);
+  if (c->stream && !c->poisoned) (void)hipStreamSynchronize(c->stream);
+  destroy_graphs(c->graphs);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  const int dev = c->device;
+  delete c;  // the arena frees the device buffers
+  if (cur >= 0 && cur != dev) (void)hipSetDevice(cur);
+}
+
+int expint_get_plan(const expint_ctx* c, int32_t* s, int32_t* m, double* norm1) {
+  if (!c) return set_error(EXPINT_EINVAL, "context is NULL");
+  if (s) *s = c->s;
+  if (m) *m = c->m;
+  if (norm1) *norm1 = c->norm1;
+  return EXPINT_OK;
+}
+
+int expint_set_params(expint_ctx* c, double rho, const double* class_D, int32_t replan) {
+  CHECK_CTX(c);
+  if (!finite_nonneg(rho)) return set_error(EXPINT_EINVAL, "rho must be finite and >= 0");
+  int rc = ensure_device(c);
+  if (rc) return rc;
+  if (class_D) {
+    if (!c->labels_form) return set_error(EXPINT_EINVAL, "class_D given for a dense-D context");
+    for (int a = 0; a < c->nclass; ++a)
+      if (!finite_nonneg(class_D[a])) return set_error(EXPINT_EINVAL, "class_D[%d] must be finite and >= 0", a);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int a = 0; a < c->nclass; ++a) c->class_D[a] = class_D[a];
+    if ((rc = upload_tables(c))) return rc;
+  }
+  c->rho = rho;
+  if (replan && c->labels_form) {
+    double bad = 0.0;
+    if ((rc = scan_labels(c, &bad))) return rc;
+    if ((rc = make_plan(c))) return rc;
+  }
+  destroy_graphs(c->graphs);  // rho and the schedule are baked into recorded graphs
+  return EXPINT_OK;
+}
+
+int expint_apply(expint_ctx* c, const void* x, void* y) {
+  CHECK_CTX(c);
+  if (!x || !y) return set_error(EXPINT_EINVAL, "NULL field");
+  if (x == y) return set_error(EXPINT_EINVAL, "x and y must not overlap");
+  int rc = ensure_device(c);
+  if (rc) return rc;
+  HIP_TRY(c, launch_apply(c->dtype, c->bc, c->g, c->coef(), x, y, c->stream));
+  return EXPINT_OK;
+}
+
+int expint_rhs(expint_ctx* c, const void* u, void* b) {
+  CHECK_CTX(c);
+  if (!u || !b) return set_error(EXPINT_EINVAL, "NULL field");
+  if (u == b) return set_error(EXPINT_EINVAL, "u and b must not overlap");
+  int rc = ensure_device(c);
+  if (rc) return rc;
+  HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, c->coef(), u, b, c->rho, c->stream));
+  return EXPINT_OK;
+}
+
+int expint_phi1(expint_ctx* c, const void* b, void* x) {
+  CHECK_CTX(c);
+  if (!b || !x) return set_error(EXPINT_EINVAL, "NULL field");
+  if (b == x) return set_error(EXPINT_EINVAL, "b and x must not overlap");
+  int rc = ensure_device(c);
+  if (rc) return rc;
+  const auto ops = phi1_schedule(step_buffers(c), c->s, c->m, c->tau, b, x, nullptr);
+  return run_ops(c, ops);
+}
+
+int expint_step(expint_ctx* c, void* u) {
+  CHECK_CTX(c);
+  if (!u) return set_error(EXPINT_EINVAL, "u is NULL");
+  int rc = ensure_device(c);
+  if (rc) return rc;
+  if ((rc = enqueue_step(c, u))) return rc;
+  if (c->check_finite) return check_finite_field(c, u);
+  return EXPINT_OK;
+}
+
+int expint_advance(expint_ctx* c, void* u, int32_t nsteps) {
+  CHECK_CTX(c);
+  if (!u) return set_error(EXPINT_EINVAL, "u is NULL");
+  if (nsteps < 0) return set_error(EXPINT_EINVAL, "nsteps must be >= 0");
+  int rc = ensure_device(c);
+  if (rc) return rc;
+  if (nsteps == 0) return EXPINT_OK;
+  GraphEntry* ge = nullptr;
+  for (auto& e : c->graphs)
+    if (e.key0 == u) ge = &e;
+  if (!ge) {
+    if (c->graphs.size() >= 4) {
+      std::vector<GraphEntry> old(c->graphs.begin(), c->graphs.begin() + 1);
+      destroy_graphs(old);
+      c->graphs.erase(c->graphs.begin());
+    }
+    GraphEntry e;
+    e.key0 = u;
+    e.nsteps = 1;
+    HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    rc = enqueue_step(c, u);
+    hipGraph_t gr = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c->stream, &gr);
+    if (rc) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return rc;
+    }
+    if (ec != hipSuccess) {
+      c->poisoned = true;
+      return set_error(EXPINT_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(ec));
+    }
+    e.graph = gr;
+    HIP_TRY(c, hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0));
+    c->graphs.push_back(e);
+    ge = &c->graphs.back();
+  }
+  for (int32_t i = 0; i < nsteps; ++i) HIP_TRY(c, hipGraphLaunch(ge->exec, c->stream));
+  if (c->check_finite) return check_finite_field(c, u);
+  return EXPINT_OK;
+}
+
+int expint_reduce(expint_ctx* c, int32_t op, const void* x, const void* y, double* out) {
+  CHECK_CTX(c);
+  if (op < 0 || op > 2) return set_error(EXPINT_EINVAL, "reduce op must be 0, 1 or 2");
+  if (!x || !out || (op == 1 && !y)) return set_error(EXPINT_EINVAL, "NULL argument");
+  int rc = ensure_device(c);
+  if (rc) return rc;
+  HIP_TRY(c, launch_reduce(c->dtype, op, x, y, c->g.n, c->partial, c->red, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(out, c->red, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return EXPINT_OK;
+}
+
+int expint_profile(expint_ctx* c, int32_t reps, double* ms_term, double* ms_rhs) {
+  CHECK_CTX(c);
+  if (reps < 1 || !ms_term) return set_error(EXPINT_EINVAL, "reps must be >= 1 and ms_term non-NULL");
+  int rc = ensure_device(c);
+  if (rc) return rc;
+  // The general Taylor term of the schedule: src = y0, acc in place, y1 out.
+  TermOp op{};
+  op.src = c->y[0];
+  op.acc_in = c->acc[0];
+  op.acc_out = c->acc[0];
+  op.y_out = c->y[1];
+  op.c = c->tau / c->s / 2.0;
+  const Coef cf = c->coef();
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  // defined inputs for the timed sweeps
+  HIP_TRY(c, launch_fill(c->dtype, c->g.n, 0.25, c->y[0], c->stream));
+  HIP_TRY(c, launch_fill(c->dtype, c->g.n, 0.0, c->acc[0], c->stream));
+  HIP_TRY(c, launch_fill(c->dtype, c->g.n, 0.5, c->acc[1], c->stream));
+  HIP_TRY(c, launch_term(c->dtype, c->bc, c->g, cf, op, c->stream));
+  HIP_TRY(c, hipEventRecord(e0, c->stream));
+  for (int r = 0; r < reps; ++r) HIP_TRY(c, launch_term(c->dtype, c->bc, c->g, cf, op, c->stream));
+  HIP_TRY(c, hipEventRecord(e1, c->stream));
+  HIP_TRY(c, hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+  *ms_term = ms / reps;
+  if (ms_rhs) {
+    HIP_TRY(c, hipEventRecord(e0, c->stream));
+    for (int r = 0; r < reps; ++r)
+      HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, cf, c->acc[1], c->b, c->rho, c->stream));
+    HIP_TRY(c, hipEventRecord(e1, c->stream));
+    HIP_TRY(c, hipEventSynchronize(e1));
+    HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+    *ms_rhs = ms / reps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return EXPINT_OK;
+}
+
+int expint_get_stream(const expint_ctx* c, void** stream) {
+  if (!c || !stream) return set_error(EXPINT_EINVAL, "NULL argument");
+  *stream = c->stream;
+  return EXPINT_OK;
+}
+
+}  // extern "C"

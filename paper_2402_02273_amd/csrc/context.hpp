@@ -1,0 +1,100 @@
+// The context object behind expint_ctx* and its helpers (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace expint {
+
+int set_error(int code, const char* fmt, ...);
+
+// Device memory owned by one context or batch, with an optional byte cap
+// (environment variable EXPINT_MAX_BYTES) for out-of-memory tests.
+class Arena {
+ public:
+  Arena();
+  ~Arena();
+  // 0 on success, EXPINT_ENOMEM otherwise (error message set).
+  int alloc(void** p, size_t bytes);
+  size_t bytes() const { return bytes_; }
+
+ private:
+  std::vector<void*> ptrs_;
+  size_t bytes_ = 0;
+  size_t cap_ = 0;
+};
+
+struct GraphEntry {
+  const void* key0 = nullptr;
+  int nsteps = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+void destroy_graphs(std::vector<GraphEntry>& gs);
+
+size_t dtype_size(expint_dtype dt);
+
+}  // namespace expint
+
+struct expint_ctx {
+  expint::Geom g{};
+  double h = 1.0;
+  expint_dtype dtype = EXPINT_F32;
+  expint_bc bc = EXPINT_NOFLUX;
+  expint_algo algo = EXPINT_ALGO_STENCIL_TAYLOR;
+  expint_mp mp = EXPINT_MP_NONE;
+  double rho = 0.0, tau = 0.0, tol = 0.0, theta_max = 0.0;
+  bool fixed_plan = false;
+  int s = 1, m = 1;
+  double norm1 = 0.0;
+  int check_finite = 0;
+
+  bool labels_form = true;
+  int nclass = 0;
+  double class_D[EXPINT_MAX_CLASSES] = {0};
+
+  int device = 0;
+  hipStream_t stream = nullptr;  // the stream every call works on
+  bool own_stream = false;
+
+  expint::Arena arena;
+  uint8_t* labels = nullptr;
+  double* tab64 = nullptr;   // K(D_a, D_b) / h^2, FP64, 8 x 8
+  double* wall64 = nullptr;  // D_a / h^2, FP64
+  void* tab = nullptr;       // same in the context dtype
+  void* wallc = nullptr;
+  void* fx = nullptr;  // dense form face coefficients
+  void* fy = nullptr;
+  void* fz = nullptr;
+  void* wallv = nullptr;
+
+  void* b = nullptr;  // step workspace
+  void* y[2] = {nullptr, nullptr};
+  void* acc[2] = {nullptr, nullptr};
+  double* partial = nullptr;  // 2 * kReduceBlocks
+  double* red = nullptr;      // 2 results
+  double* host_red = nullptr; // pinned host mirror of red
+
+  std::vector<expint::GraphEntry> graphs;
+  bool poisoned = false;
+
+  expint::Coef coef() const {
+    expint::Coef c{};
+    c.labels_form = labels_form;
+    c.labels = labels;
+    c.tab = tab;
+    c.wallc = wallc;
+    c.fx = fx;
+    c.fy = fy;
+    c.fz = fz;
+    c.wallv = wallv;
+    return c;
+  }
+  size_t field_bytes() const { return static_cast<size_t>(g.n) * expint::dtype_size(dtype); }
+};

@@ -1,0 +1,35 @@
+// The sequence of fused Taylor-term sweeps that evaluates
+// x = tau phi1(tau A) b (section 2.2).
+//
+// exp(tau B) applied to the augmented unit vector, B = [[A, b], [0, 0]], is
+// evaluated as s factors of the degree-m Taylor polynomial T_m(h B),
+// h = tau / s.  One factor maps [x; 1] to [x + y_1 + ... + y_m; 1] with
+//   y_1 = h (A x + b),   y_j = (h / j) A y_{j-1},
+// starting from x = 0.  Each y_j costs one application of A, fused with the
+// running sum in a single sweep (TermOp).  Two algebraic shortcuts remove the
+// sweeps that would apply A to the zero vector:
+//   - sub-step 1, term 1: y_1 = h b, so term 2 is (h^2/2) A b with the sum
+//     started at h b;
+//   - if m == 1, sub-step 1 leaves x = h b and sub-step 2 computes
+//     y_1 = h^2 A b + h b with the sum started at h b.
+// The last sweep either adds the sum into u (the step u + x) or stores it.
+#pragma once
+
+#include <vector>
+
+#include "internal.hpp"
+
+namespace expint {
+
+struct StepBuffers {
+  void* b = nullptr;
+  void* y[2] = {nullptr, nullptr};
+  void* acc[2] = {nullptr, nullptr};
+};
+
+// b: the vector phi1 acts on.  Exactly one of x_out (store the result) and
+// u (add the result into u) is non-NULL.
+std::vector<TermOp> phi1_schedule(const StepBuffers& ws, int s, int m, double tau, const void* b, void* x_out,
+                                  void* u);
+
+}  // namespace expint

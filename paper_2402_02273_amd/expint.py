@@ -1,0 +1,271 @@
+"""Python binding of the exponential-integrator library.
+
+``ExpInt`` wraps one ``expint_ctx``: a grid, a diffusivity field, rho, the
+boundary condition, the time step and the (s, m) plan.  Fields are torch
+tensors on the GPU (z fastest, shape (nx, ny, nz)); this module only moves
+pointers and checks shapes and dtypes on the host before each call.  All
+arithmetic happens in the HIP library.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+_DTYPES = {torch.float64: N.F64, torch.float32: N.F32}
+_BCS = {"noflux": N.NOFLUX, "dirichlet0": N.DIRICHLET0}
+_ALGOS = {"auto": N.ALGO_AUTO, "stencil_taylor": N.ALGO_STENCIL_TAYLOR, "modal": N.ALGO_MODAL}
+_MPS = {"none": N.MP_NONE, "bf16_split": N.MP_BF16_SPLIT, "fp16_split": N.MP_FP16_SPLIT}
+
+
+@dataclass
+class Plan:
+    s: int
+    m: int
+    norm_A1: float
+
+    @property
+    def terms(self) -> int:
+        return self.s * self.m
+
+
+def _stream_handle(stream, device):
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(int(stream.cuda_stream) or None)
+
+
+def _as_device(x, device, dtype):
+    t = torch.as_tensor(x)
+    return t.to(device=device, dtype=dtype).contiguous()
+
+
+class ExpInt:
+    """One exponential-Euler integrator context on one GPU."""
+
+    def __init__(
+        self,
+        shape,
+        h: float = 1.0,
+        *,
+        labels=None,
+        class_D=None,
+        D=None,
+        rho: float = 0.025,
+        tau: float = 7.3,
+        dtype=torch.float32,
+        bc: str = "noflux",
+        tol: float = 0.0,
+        theta_max: float = 0.0,
+        s: int = 0,
+        m: int = 0,
+        algo: str = "auto",
+        mp: str = "none",
+        check_finite: bool = False,
+        device=None,
+        stream=None,
+    ):
+        self.lib = N.lib()
+        self.shape = tuple(int(v) for v in shape)
+        if len(self.shape) != 3:
+            raise ValueError("shape must be (nx, ny, nz)")
+        device = torch.device("cuda") if device is None else torch.device(device)
+        if device.type != "cuda":
+            raise ValueError("the library runs on a GPU device")
+        if device.index is None:
+            device = torch.device("cuda", torch.cuda.current_device())
+        self.device = device
+        if dtype not in _DTYPES:
+            raise ValueError("dtype must be torch.float32 or torch.float64")
+        self.dtype = dtype
+        self.n = int(np.prod(self.shape))
+        self.h = float(h)
+        self.tau = float(tau)
+        self._ctx = ctypes.c_void_p()
+
+        grid = N.Grid(self.shape[0], self.shape[1], self.shape[2], self.h)
+        df = N.DField()
+        keep = []
+        if labels is not None:
+            lab = _as_device(labels, self.device, torch.uint8)
+            if lab.numel() != self.n:
+                raise ValueError(f"labels hold {lab.numel()} voxels, grid has {self.n}")
+            cd = (ctypes.c_double * len(class_D))(*[float(v) for v in class_D])
+            keep += [lab, cd]
+            df.labels = lab.data_ptr()
+            df.n_classes = len(class_D)
+            df.class_D = ctypes.cast(cd, ctypes.POINTER(ctypes.c_double))
+            self.n_classes = len(class_D)
+            self.class_D = tuple(float(v) for v in class_D)
+        elif D is not None:
+            Dt = _as_device(D, self.device, dtype)
+            if Dt.numel() != self.n:
+                raise ValueError(f"D holds {Dt.numel()} voxels, grid has {self.n}")
+            keep.append(Dt)
+            df.D = Dt.data_ptr()
+            self.n_classes = 0
+            self.class_D = None
+        opts = N.Opts()
+        N.check(self.lib.expint_opts_default(ctypes.byref(opts)))
+        opts.dtype = _DTYPES[dtype]
+        opts.tau = self.tau
+        opts.tol = float(tol)
+        opts.theta_max = float(theta_max)
+        opts.algo = _ALGOS[algo]
+        opts.mp = _MPS[mp]
+        opts.s = int(s)
+        opts.m = int(m)
+        opts.check_finite = int(bool(check_finite))
+        with torch.cuda.device(self.device):
+            opts.stream = _stream_handle(stream, self.device)
+            N.check(
+                self.lib.expint_create(
+                    ctypes.byref(grid), ctypes.byref(df), float(rho), _BCS[bc], ctypes.byref(opts), ctypes.byref(self._ctx)
+                )
+            )
+        self.rho = float(rho)
+        self.bc = bc
+        del keep
+
+    # ---- lifetime ----
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            self.lib.expint_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---- helpers ----
+    def _field(self, t, name, writable=False):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.device != self.device:
+            raise ValueError(f"{name} is on {t.device}, context on {self.device}")
+        if t.dtype != self.dtype:
+            raise ValueError(f"{name} has dtype {t.dtype}, context uses {self.dtype}")
+        if not t.is_contiguous() or t.numel() != self.n:
+            raise ValueError(f"{name} must be contiguous with {self.n} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def empty(self):
+        return torch.empty(self.shape, device=self.device, dtype=self.dtype)
+
+    @property
+    def stream(self) -> torch.cuda.ExternalStream:
+        p = ctypes.c_void_p()
+        N.check(self.lib.expint_get_stream(self._ctx, ctypes.byref(p)))
+        if not p.value:
+            return torch.cuda.default_stream(self.device)
+        return torch.cuda.ExternalStream(p.value, device=self.device)
+
+    # ---- plan and parameters ----
+    @property
+    def plan(self) -> Plan:
+        s, m, nrm = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        N.check(self.lib.expint_get_plan(self._ctx, ctypes.byref(s), ctypes.byref(m), ctypes.byref(nrm)))
+        return Plan(s.value, m.value, nrm.value)
+
+    def set_params(self, rho=None, class_D=None, replan=True):
+        rho = self.rho if rho is None else float(rho)
+        cd = None
+        if class_D is not None:
+            cd = (ctypes.c_double * len(class_D))(*[float(v) for v in class_D])
+        N.check(self.lib.expint_set_params(self._ctx, rho, cd, int(bool(replan))))
+        self.rho = rho
+        if class_D is not None:
+            self.class_D = tuple(float(v) for v in class_D)
+
+    # ---- operators ----
+    def apply(self, x, out=None):
+        out = self.empty() if out is None else out
+        N.check(self.lib.expint_apply(self._ctx, self._field(x, "x"), self._field(out, "out")))
+        return out
+
+    def rhs(self, u, out=None):
+        out = self.empty() if out is None else out
+        N.check(self.lib.expint_rhs(self._ctx, self._field(u, "u"), self._field(out, "out")))
+        return out
+
+    def phi1(self, b, out=None):
+        out = self.empty() if out is None else out
+        N.check(self.lib.expint_phi1(self._ctx, self._field(b, "b"), self._field(out, "out")))
+        return out
+
+    def step(self, u):
+        N.check(self.lib.expint_step(self._ctx, self._field(u, "u")))
+        return u
+
+    def advance(self, u, nsteps: int):
+        N.check(self.lib.expint_advance(self._ctx, self._field(u, "u"), int(nsteps)))
+        return u
+
+    def reduce(self, op: str, x, y=None) -> float:
+        code = {"sum": 0, "dot": 1, "maxabs": 2}[op]
+        out = ctypes.c_double()
+        yp = self._field(y, "y") if y is not None else None
+        N.check(self.lib.expint_reduce(self._ctx, code, self._field(x, "x"), yp, ctypes.byref(out)))
+        return out.value
+
+    def tumour_volume(self, u) -> float:
+        """Sum of the density over the grid divided by the voxel count."""
+        return self.reduce("sum", u) / self.n
+
+    # ---- gradients ----
+    def grad(self, u0, nsteps, u_target, ckpt_every=10):
+        gu = self.empty()
+        loss, grho = ctypes.c_double(), ctypes.c_double()
+        gD = (ctypes.c_double * max(self.n_classes, 1))()
+        N.check(
+            self.lib.expint_grad(
+                self._ctx,
+                self._field(u0, "u0"),
+                int(nsteps),
+                self._field(u_target, "u_target"),
+                int(ckpt_every),
+                ctypes.byref(loss),
+                self._field(gu, "grad_u0"),
+                ctypes.byref(grho),
+                gD,
+            )
+        )
+        return loss.value, gu, grho.value, list(gD)[: self.n_classes]
+
+    def vjp(self, u0, nsteps, gout, ckpt_every=10):
+        gu = self.empty()
+        grho = ctypes.c_double()
+        gD = (ctypes.c_double * max(self.n_classes, 1))()
+        N.check(
+            self.lib.expint_vjp(
+                self._ctx,
+                self._field(u0, "u0"),
+                int(nsteps),
+                self._field(gout, "gout"),
+                int(ckpt_every),
+                self._field(gu, "grad_u0"),
+                ctypes.byref(grho),
+                gD,
+            )
+        )
+        return gu, grho.value, list(gD)[: self.n_classes]
+
+    # ---- measurement ----
+    def profile(self, reps=50):
+        """Mean ms per launch of the generic Taylor-term sweep and of the RHS sweep."""
+        t, r = ctypes.c_double(), ctypes.c_double()
+        N.check(self.lib.expint_profile(self._ctx, int(reps), ctypes.byref(t), ctypes.byref(r)))
+        return t.value, r.value

@@ -1,0 +1,283 @@
+"""GPU parity of the stencil-Taylor path against the FP64 oracle.
+
+Element-by-element comparisons at sizes the oracle finishes in seconds
+(several workgroup tiles and ragged tails in every axis), plus the full
+128^3 headline workload against the stored oracle result.  Bars: FP64 within
+rounding of the same polynomial (rel-L2 <= 1e-10 for whole runs), FP32 rel-L2
+<= 1e-5 against the FP64 oracle.
+"""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import integrator as oit
+from oracle import operator as oop
+from oracle import plan as oplan
+from oracle import reference as oref
+from workloads import c1_plain, c2_head, make_head
+from workloads.configs import make_ragged, random_field, random_labels
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
+
+
+def make_ctx(native, labels, class_D, dtype, **kw):
+    from paper_2402_02273_amd.expint import ExpInt
+
+    print(f"[case] ctx shape={labels.shape} dtype={dtype} {kw}", flush=True)
+    return ExpInt(labels.shape, labels=labels, class_D=class_D, dtype=dtype, device=DEV, **kw)
+
+
+SHAPES = [(1, 1, 1), (3, 1, 70), (5, 7, 9), (17, 33, 65), (9, 130, 20), (64, 5, 33)]
+CLASS_D = (0.0, 0.13, 0.013)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("bc", ["noflux", "dirichlet0"])
+def test_apply_and_rhs_f64(native, shape, bc):
+    labels = random_labels(shape, 3, seed=sum(shape))
+    x = random_field(shape, seed=3, lo=-1, hi=1)
+    ctx = make_ctx(native, labels, CLASS_D, torch.float64, bc=bc, rho=0.03, h=0.8)
+    D = oop.class_field(labels, CLASS_D)
+    ref = oop.apply_A(x, D, 0.8, bc)
+    got = ctx.apply(dev(x, torch.float64)).cpu().numpy()
+    scale = max(np.abs(ref).max(), 1e-30)
+    assert np.abs(got - ref).max() / scale < 1e-14
+    ref_b = ref + oit.reaction(x, 0.03)
+    got_b = ctx.rhs(dev(x, torch.float64)).cpu().numpy()
+    assert np.abs(got_b - ref_b).max() / max(np.abs(ref_b).max(), 1e-30) < 1e-14
+
+
+@pytest.mark.parametrize("shape", [(5, 7, 9), (17, 33, 65)])
+def test_apply_f32_and_dense_form(native, shape):
+    from paper_2402_02273_amd.expint import ExpInt
+
+    labels = random_labels(shape, 3, seed=5)
+    x = random_field(shape, seed=6, lo=-1, hi=1)
+    D = oop.class_field(labels, CLASS_D)
+    ref = oop.apply_A(x, D, 1.0)
+    ctx = make_ctx(native, labels, CLASS_D, torch.float32)
+    got = ctx.apply(dev(x, torch.float32)).cpu().numpy()
+    assert rel_l2(got, ref) < 1e-6
+    for dt, tol in ((torch.float64, 1e-14), (torch.float32, 1e-6)):
+        for bc in ("noflux", "dirichlet0"):
+            print(f"[case] dense D dtype={dt} bc={bc}", flush=True)
+            cd = ExpInt(shape, D=dev(D, dt), dtype=dt, device=DEV, bc=bc)
+            got = cd.apply(dev(x, dt)).cpu().numpy()
+            assert rel_l2(got, oop.apply_A(x, D, 1.0, bc)) < tol
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_plan_matches_oracle(native, dtype):
+    key = "f64" if dtype == torch.float64 else "f32"
+    for w in (c1_plain(), c2_head()):
+        ctx = make_ctx(native, w.labels, w.class_D, dtype, tau=w.tau, rho=w.rho)
+        op = oop.Operator(w.h, labels=w.labels, class_D=w.class_D)
+        p = ctx.plan
+        assert p.norm_A1 == pytest.approx(op.norm1(), rel=1e-15)
+        assert (p.s, p.m) == oplan.for_dtype(w.tau * op.norm1(), key)
+
+
+@pytest.mark.parametrize("shape", [(5, 7, 9), (17, 33, 65), (24, 24, 24)])
+@pytest.mark.parametrize("sm", [None, (1, 1), (1, 5), (3, 1), (2, 7)])
+def test_phi1_f64_same_polynomial(native, shape, sm):
+    labels = random_labels(shape, 3, seed=11)
+    b = random_field(shape, seed=12, lo=-1, hi=1)
+    kw = {} if sm is None else {"s": sm[0], "m": sm[1]}
+    ctx = make_ctx(native, labels, CLASS_D, torch.float64, tau=7.3, **kw)
+    p = ctx.plan
+    op = oop.Operator(1.0, labels=labels, class_D=CLASS_D)
+    ref = oit.phi1_action(op, b, 7.3, p.s, p.m)
+    got = ctx.phi1(dev(b, torch.float64)).cpu().numpy()
+    assert rel_l2(got, ref) < 1e-13
+
+
+def test_phi1_vs_exact_expm(native):
+    shape = (8, 8, 8)
+    labels = random_labels(shape, 3, seed=2)
+    b = random_field(shape, seed=4, lo=-1, hi=1)
+    ctx = make_ctx(native, labels, CLASS_D, torch.float64, tau=7.3)
+    A = oop.dense_A(oop.class_field(labels, CLASS_D), 1.0)
+    xe, _ = oref.dense_phi1_augmented(A, b, 7.3)
+    got = ctx.phi1(dev(b, torch.float64)).cpu().numpy().ravel()
+    assert rel_l2(got, xe) < 1e-12
+
+
+def _oracle_run(w, nsteps):
+    op = oop.Operator(w.h, labels=w.labels, class_D=w.class_D, bc=w.bc)
+    s, m = oplan.for_dtype(w.tau * op.norm1(), "f64")
+    return oit.advance(op, w.u0, w.rho, w.tau, s, m, nsteps)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-5)])
+def test_c1_plain_run(native, dtype, tol):
+    w = c1_plain()
+    ref = _oracle_run(w, w.nsteps)
+    ctx = make_ctx(native, w.labels, w.class_D, dtype, tau=w.tau, rho=w.rho)
+    u = dev(w.u0, dtype)
+    ctx.advance(u, w.nsteps)
+    got = u.cpu().numpy()
+    assert rel_l2(got, ref) < tol
+    # reflection symmetry of the centred blob on all three axes
+    for ax in range(3):
+        assert np.abs(got - np.flip(got, axis=ax)).max() <= (1e-14 if dtype == torch.float64 else 1e-6)
+
+
+@pytest.mark.parametrize("shape", [(20, 17, 33), (7, 40, 66)])
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-5)])
+def test_ragged_heterogeneous_run(native, shape, dtype, tol):
+    w = make_ragged(shape, seed=21, nsteps=3)
+    ref = _oracle_run(w, w.nsteps)
+    ctx = make_ctx(native, w.labels, w.class_D, dtype, tau=w.tau, rho=w.rho)
+    u = dev(w.u0, dtype)
+    ctx.advance(u, w.nsteps)
+    assert rel_l2(u.cpu().numpy(), ref) < tol
+
+
+def test_step_equals_advance_bitwise(native):
+    w = make_ragged((16, 24, 40), seed=5, nsteps=4)
+    for dtype in (torch.float64, torch.float32):
+        ctx = make_ctx(native, w.labels, w.class_D, dtype)
+        u1 = dev(w.u0, dtype)
+        u2 = u1.clone()
+        for _ in range(4):
+            ctx.step(u1)
+        ctx.advance(u2, 2)  # records the graph
+        ctx.advance(u2, 2)  # replays it
+        torch.cuda.synchronize()
+        assert torch.equal(u1, u2)
+
+
+def test_logistic_and_degenerate_plan(native):
+    # D = 0 everywhere: A = 0, plan (1, 1), the step is forward Euler.
+    shape = (6, 9, 70)
+    labels = np.zeros(shape, dtype=np.uint8)
+    u0 = random_field(shape, seed=8)
+    ctx = make_ctx(native, labels, (0.0,), torch.float64, tau=7.3, rho=0.025)
+    assert (ctx.plan.s, ctx.plan.m) == (1, 1)
+    u = dev(u0, torch.float64)
+    ctx.step(u)
+    np.testing.assert_allclose(u.cpu().numpy(), u0 + 7.3 * 0.025 * u0 * (1 - u0), rtol=1e-15)
+
+
+@pytest.mark.parametrize("bc", ["noflux", "dirichlet0"])
+def test_eigenmode_decay(native, bc):
+    shape = (12, 10, 66)
+    Dc, tau, K = 0.1, 7.3, 5
+    ks = (2, 1, 3)
+    vs = [oref.mode_1d(n, k, bc) for n, k in zip(shape, ks)]
+    v = vs[0][:, None, None] * vs[1][None, :, None] * vs[2][None, None, :]
+    lam = Dc * sum(oref.eigenvalues_1d(n, 1.0, bc)[k] for n, k in zip(shape, ks))
+    labels = np.ones(shape, dtype=np.uint8)
+    for dtype, tol in ((torch.float64, 1e-12), (torch.float32, 2e-6)):
+        ctx = make_ctx(native, labels, (0.0, Dc), dtype, tau=tau, rho=0.0, bc=bc)
+        u = dev(v, dtype)
+        ctx.advance(u, K)
+        expect = np.exp(lam * tau * K) * v
+        assert np.abs(u.cpu().numpy() - expect).max() / np.abs(expect).max() < tol
+
+
+def test_mass_conservation_full_head(native):
+    w = c2_head()
+    for dtype, tol in ((torch.float64, 1e-12), (torch.float32, 2e-6)):
+        ctx = make_ctx(native, w.labels, w.class_D, dtype, tau=w.tau, rho=0.0)
+        u = dev(w.u0, dtype)
+        m0 = ctx.reduce("sum", u)
+        ctx.advance(u, 10)
+        m1 = ctx.reduce("sum", u)
+        assert abs(m1 - m0) / m0 < tol
+        assert m0 == pytest.approx(w.u0.sum(), rel=1e-6 if dtype == torch.float32 else 1e-14)
+
+
+def test_full_head_one_step_elementwise(native):
+    # 128^3 at the bench's launch configuration: one step against the oracle, every voxel.
+    w = c2_head()
+    op = oop.Operator(w.h, labels=w.labels, class_D=w.class_D)
+    s, m = oplan.for_dtype(w.tau * op.norm1(), "f64")
+    ref = oit.step(op, w.u0, w.rho, w.tau, s, m)
+    for dtype, tol in ((torch.float64, 1e-12), (torch.float32, 1e-6)):
+        ctx = make_ctx(native, w.labels, w.class_D, dtype, tau=w.tau, rho=w.rho)
+        u = dev(w.u0, dtype)
+        ctx.advance(u, 1)
+        got = u.cpu().numpy()
+        assert rel_l2(got, ref) < tol
+        assert np.all(got[w.labels == 0] == 0.0)
+
+
+def _golden_c2():
+    path = os.path.join(GOLDEN, "c2_head_128_u100_f64.npz")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle result missing (tests/golden/make_golden.py c2)")
+    return np.load(path)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-5)])
+def test_full_head_100_steps_vs_stored_oracle(native, dtype, tol):
+    g = _golden_c2()
+    w = c2_head()
+    import hashlib
+
+    assert hashlib.sha256(w.labels.tobytes()).hexdigest() == str(g["labels_sha256"])
+    ctx = make_ctx(native, w.labels, w.class_D, dtype, tau=w.tau, rho=w.rho)
+    if dtype == torch.float64:
+        assert (ctx.plan.s, ctx.plan.m) == (int(g["s"]), int(g["m"]))
+    u = dev(w.u0, dtype)
+    ctx.advance(u, 100)
+    got = u.cpu().numpy()
+    err = rel_l2(got, g["u"])
+    print(f"[result] c2 128^3 x100 {dtype}: rel-L2 vs oracle = {err:.3e}", flush=True)
+    assert err < tol
+    assert got.min() >= -1e-6 and got.max() <= 1 + 1e-6
+
+
+def test_check_finite_flags_nan(native):
+    from paper_2402_02273_amd import ExpIntError
+
+    w = make_ragged((8, 8, 8), seed=1)
+    ctx = make_ctx(native, w.labels, w.class_D, torch.float32, check_finite=True)
+    u = dev(w.u0, torch.float32)
+    ctx.step(u)
+    u[3, 3, 3] = float("nan")
+    with pytest.raises(ExpIntError) as e:
+        ctx.step(u)
+    assert "ENONFINITE" in str(e.value)
+
+
+def test_invalid_labels_rejected(native):
+    from paper_2402_02273_amd import ExpIntError
+
+    labels = np.full((4, 5, 6), 2, dtype=np.uint8)
+    labels[1, 2, 3] = 7
+    with pytest.raises(ExpIntError) as e:
+        make_ctx(native, labels, CLASS_D, torch.float32)
+    assert "EINVAL" in str(e.value)
+
+
+def test_set_params_replan(native):
+    w = make_ragged((10, 12, 14), seed=4)
+    ctx = make_ctx(native, w.labels, w.class_D, torch.float64, tau=7.3)
+    p0 = ctx.plan
+    ctx.set_params(rho=0.03, class_D=(0.0, 0.26, 0.026), replan=True)
+    p1 = ctx.plan
+    op = oop.Operator(1.0, labels=w.labels, class_D=(0.0, 0.26, 0.026))
+    assert p1.norm_A1 == pytest.approx(op.norm1(), rel=1e-15)
+    assert p1.norm_A1 == pytest.approx(2 * p0.norm_A1, rel=1e-14)
+    u = dev(w.u0, torch.float64)
+    ctx.step(u)
+    ref = oit.step(op, w.u0, 0.03, 7.3, p1.s, p1.m)
+    assert rel_l2(u.cpu().numpy(), ref) < 1e-12
