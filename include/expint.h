@@ -206,12 +206,13 @@ void expint_batch_destroy(expint_batch* batch);
  * blocking stream the context created when opts.stream was NULL. */
 int expint_get_stream(const expint_ctx* ctx, void** stream);
 
-/* Times `reps` back-to-back launches of the generic Taylor-term sweep of
- * this context (A applied to a workspace field, running sum updated in
- * place) and of the right-hand-side sweep, with HIP events on the context
- * stream; writes the mean milliseconds per launch (ms_rhs may be NULL).
- * Uses only the context workspace; synchronises the stream. */
-int expint_profile(expint_ctx* ctx, int32_t reps, double* ms_term, double* ms_rhs);
+/* Times `reps` back-to-back launches of one sweep of this context's step
+ * schedule with HIP events on the context stream and writes the mean
+ * milliseconds per launch: kernel 0 = Taylor term that adds a pair of terms
+ * to the running sum (reads the source, the sum; writes the term, the sum),
+ * 1 = Taylor term that only writes its term, 2 = right-hand side
+ * A u + rho u (1 - u).  Uses only the context workspace; synchronises. */
+int expint_profile(expint_ctx* ctx, int32_t kernel, int32_t reps, double* ms);
 
 /* Message for the last failed call on this thread ("" if none). */
 const char* expint_last_error(void);

@@ -104,7 +104,7 @@ SIGNATURES = {
     "expint_batch_get_plan": (_I, [_P, _I32, _I32P, _I32P, _DP]),
     "expint_batch_destroy": (None, [_P]),
     "expint_get_stream": (_I, [_P, ctypes.POINTER(_P)]),
-    "expint_profile": (_I, [_P, _I32, _DP, _DP]),
+    "expint_profile": (_I, [_P, _I32, _I32, _DP]),
     "expint_last_error": (ctypes.c_char_p, []),
 }
 

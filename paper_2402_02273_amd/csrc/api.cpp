@@ -16,6 +16,7 @@
 #include "context.hpp"
 #include "internal.hpp"
 #include "plan.hpp"
+#include "autotune.hpp"
 #include "schedule.hpp"
 
 using namespace expint;
@@ -159,7 +160,7 @@ int make_plan(expint_ctx* c) {
 
 int run_ops(expint_ctx* c, const std::vector<TermOp>& ops) {
   const Coef cf = c->coef();
-  for (const TermOp& op : ops) HIP_TRY(c, launch_term(c->dtype, c->bc, c->g, cf, op, c->stream));
+  for (const TermOp& op : ops) HIP_TRY(c, launch_term(c->dtype, c->bc, c->g, c->tiling, cf, op, c->stream));
   return EXPINT_OK;
 }
 
@@ -175,7 +176,7 @@ StepBuffers step_buffers(expint_ctx* c) {
 
 // Launches of one step on c->stream (no synchronisation).
 int enqueue_step(expint_ctx* c, void* u) {
-  HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, c->coef(), u, c->b, c->rho, c->stream));
+  HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, c->tiling, c->coef(), u, c->b, c->rho, c->stream));
   const auto ops = phi1_schedule(step_buffers(c), c->s, c->m, c->tau, c->b, nullptr, u);
   return run_ops(c, ops);
 }
@@ -233,7 +234,9 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
   if ((df->labels == nullptr) == (df->D == nullptr))
     return set_error(EXPINT_EINVAL, "give exactly one of labels and D");
   const int64_t n = static_cast<int64_t>(grid->nx) * grid->ny * grid->nz;
-  if (n > (int64_t(1) << 31) - 1) return set_error(EXPINT_EINVAL, "grid too large (%lld voxels)", (long long)n);
+  // 32-bit voxel indices, with room for the sweeps' one-past-the-chunk offsets
+  if ((static_cast<int64_t>(grid->nx) + 16) * grid->ny * grid->nz > (int64_t(1) << 31) - 1)
+    return set_error(EXPINT_EINVAL, "grid too large (%lld voxels)", (long long)n);
   if (df->labels) {
     if (df->n_classes < 1 || df->n_classes > EXPINT_MAX_CLASSES)
       return set_error(EXPINT_EINVAL, "n_classes must be in 1..%d", EXPINT_MAX_CLASSES);
@@ -340,6 +343,14 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
     if ((rc = c->arena.alloc(&c->y[i], fb))) return bail(rc);
     if ((rc = c->arena.alloc(&c->acc[i], fb))) return bail(rc);
   }
+  {
+    const hipError_t e = autotune_sweep(c->dtype, c->bc, c->g, c->coef(), c->y[0], c->acc[0], c->y[1], c->stream,
+                                        &c->tiling);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return bail(set_error(EXPINT_EHIP, "autotune failed: %s", hipGetErrorString(e)));
+    }
+  }
   if (std::getenv("EXPINT_LOG"))
     std::fprintf(stderr, "[expint] grid %dx%dx%d h=%g dtype=%s ||A||_1=%.17g nu=%.6g plan s=%d m=%d workspace %zu B\n",
                  c->g.nx, c->g.ny, c->g.nz, c->h, c->dtype == EXPINT_F64 ? "f64" : "f32", c->norm1,
@@ -398,7 +409,7 @@ int expint_apply(expint_ctx* c, const void* x, void* y) {
   if (x == y) return set_error(EXPINT_EINVAL, "x and y must not overlap");
   int rc = ensure_device(c);
   if (rc) return rc;
-  HIP_TRY(c, launch_apply(c->dtype, c->bc, c->g, c->coef(), x, y, c->stream));
+  HIP_TRY(c, launch_apply(c->dtype, c->bc, c->g, c->tiling, c->coef(), x, y, c->stream));
   return EXPINT_OK;
 }
 
@@ -408,7 +419,7 @@ int expint_rhs(expint_ctx* c, const void* u, void* b) {
   if (u == b) return set_error(EXPINT_EINVAL, "u and b must not overlap");
   int rc = ensure_device(c);
   if (rc) return rc;
-  HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, c->coef(), u, b, c->rho, c->stream));
+  HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, c->tiling, c->coef(), u, b, c->rho, c->stream));
   return EXPINT_OK;
 }
 
@@ -485,19 +496,31 @@ int expint_reduce(expint_ctx* c, int32_t op, const void* x, const void* y, doubl
   return EXPINT_OK;
 }
 
-int expint_profile(expint_ctx* c, int32_t reps, double* ms_term, double* ms_rhs) {
+int expint_profile(expint_ctx* c, int32_t kernel, int32_t reps, double* ms) {
   CHECK_CTX(c);
-  if (reps < 1 || !ms_term) return set_error(EXPINT_EINVAL, "reps must be >= 1 and ms_term non-NULL");
+  if (reps < 1 || !ms) return set_error(EXPINT_EINVAL, "reps must be >= 1 and ms non-NULL");
+  if (kernel < 0 || kernel > 2) return set_error(EXPINT_EINVAL, "kernel id must be 0, 1 or 2");
   int rc = ensure_device(c);
   if (rc) return rc;
-  // The general Taylor term of the schedule: src = y0, acc in place, y1 out.
-  TermOp op{};
+  // The sweeps of the step schedule, on the context workspace:
+  // 0 = pair-flush term (src y0, running sum updated in place, y1 written),
+  // 1 = skip term (src y0, y1 written), 2 = right-hand side (u = acc1, b).
+  TermOp op;
   op.src = c->y[0];
-  op.acc_in = c->acc[0];
-  op.acc_out = c->acc[0];
-  op.y_out = c->y[1];
   op.c = c->tau / c->s / 2.0;
+  op.y_out = c->y[1];
+  if (kernel == 0) {
+    op.acc_in = c->acc[0];
+    op.ca = 1.0;
+    op.cs = 1.0;
+    op.acc_out = c->acc[0];
+  }
+  classify_term(op);
   const Coef cf = c->coef();
+  auto launch = [&]() -> hipError_t {
+    if (kernel == 2) return launch_rhs(c->dtype, c->bc, c->g, c->tiling, cf, c->acc[1], c->b, c->rho, c->stream);
+    return launch_term(c->dtype, c->bc, c->g, c->tiling, cf, op, c->stream);
+  };
   hipEvent_t e0, e1;
   HIP_TRY(c, hipEventCreate(&e0));
   HIP_TRY(c, hipEventCreate(&e1));
@@ -505,23 +528,14 @@ int expint_profile(expint_ctx* c, int32_t reps, double* ms_term, double* ms_rhs)
   HIP_TRY(c, launch_fill(c->dtype, c->g.n, 0.25, c->y[0], c->stream));
   HIP_TRY(c, launch_fill(c->dtype, c->g.n, 0.0, c->acc[0], c->stream));
   HIP_TRY(c, launch_fill(c->dtype, c->g.n, 0.5, c->acc[1], c->stream));
-  HIP_TRY(c, launch_term(c->dtype, c->bc, c->g, cf, op, c->stream));
+  HIP_TRY(c, launch());
   HIP_TRY(c, hipEventRecord(e0, c->stream));
-  for (int r = 0; r < reps; ++r) HIP_TRY(c, launch_term(c->dtype, c->bc, c->g, cf, op, c->stream));
+  for (int r = 0; r < reps; ++r) HIP_TRY(c, launch());
   HIP_TRY(c, hipEventRecord(e1, c->stream));
   HIP_TRY(c, hipEventSynchronize(e1));
-  float ms = 0.f;
-  HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
-  *ms_term = ms / reps;
-  if (ms_rhs) {
-    HIP_TRY(c, hipEventRecord(e0, c->stream));
-    for (int r = 0; r < reps; ++r)
-      HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, cf, c->acc[1], c->b, c->rho, c->stream));
-    HIP_TRY(c, hipEventRecord(e1, c->stream));
-    HIP_TRY(c, hipEventSynchronize(e1));
-    HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
-    *ms_rhs = ms / reps;
-  }
+  float t = 0.f;
+  HIP_TRY(c, hipEventElapsedTime(&t, e0, e1));
+  *ms = static_cast<double>(t) / reps;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return EXPINT_OK;

@@ -77,9 +77,10 @@ struct expint_ctx {
   void* b = nullptr;  // step workspace
   void* y[2] = {nullptr, nullptr};
   void* acc[2] = {nullptr, nullptr};
-  double* partial = nullptr;  // 2 * kReduceBlocks
-  double* red = nullptr;      // 2 results
-  double* host_red = nullptr; // pinned host mirror of red
+  double* partial = nullptr;  // reduction partials (see expint_create)
+  double* red = nullptr;      // 2 reduction results
+
+  expint::Tiling tiling;  // launch shape of the stencil sweeps (autotuned)
 
   std::vector<expint::GraphEntry> graphs;
   bool poisoned = false;

@@ -27,8 +27,18 @@ struct Shape {
   int gx, gy;  // workgroups along z and y
 };
 Shape choose_shape(const Geom& g);
-// Workgroups of one voxel-kernel launch (gx * gy * nx).
+// Workgroups of one scan launch (gx * gy * nx, one x-plane per workgroup row).
 int64_t field_block_count(const Geom& g);
+
+// Tiling of the stencil sweeps: a workgroup of bx (z) x by (y) threads covers
+// a bx-by-by patch of lp consecutive x-planes; each thread marches through its
+// lp planes (1, 2 or 4) keeping the x-neighbours in registers.
+struct Tiling {
+  int bx = 64, by = 4, lp = 4;
+};
+bool tiling_valid(const Tiling& t);
+int64_t sweep_blocks(const Geom& g, const Tiling& t);
+Tiling default_tiling(const Geom& g);
 
 // Device-side diffusion coefficients of one operator, already divided by h^2.
 //  label form : labels (uint8 per voxel), tab[a * 8 + b] = K(D_a, D_b) / h^2,
@@ -48,27 +58,40 @@ struct Coef {
 
 // One fused Taylor-term sweep (all pointers device, same dtype):
 //   a   = A src
-//   y   = c * a + cb * bsrc            (bsrc may be NULL)
-//   acc = (acc_in ? acc_in : alpha * src) + y
-//   u != NULL : u += acc               (last term of a step; nothing else written)
-//   otherwise : y_out = y (if non-NULL), acc_out = acc
-struct TermOp {
-  const void* src;
-  const void* bsrc;
-  const void* acc_in;
-  void* y_out;
-  void* acc_out;
-  void* u;
-  double c, cb, alpha;
+//   y   = c * a + cb * bsrc                    (bsrc may be NULL)
+//   v   = ca * acc_in + cs * src + y           (acc_in may be NULL)
+//   u != NULL : u += v                         (last sweep of a step)
+//   otherwise : y_out = y and acc_out = v      (each only if non-NULL)
+// `flavor` names the pointer pattern so the kernel can be specialised;
+// classify_term() sets it.
+enum TermFlavor {
+  kGeneric = 0,
+  kSkip = 1,      // y_out only
+  kFlushY = 2,    // acc_out = acc_in + cs*src + y (ca == 1), and y_out
+  kFlushNoY = 3,  // the same without y_out
+  kFirst = 4,     // y = c*a + cb*bsrc; acc_out = cs*src + y; y_out
 };
 
+struct TermOp {
+  const void* src = nullptr;
+  const void* bsrc = nullptr;
+  const void* acc_in = nullptr;
+  void* y_out = nullptr;
+  void* acc_out = nullptr;
+  void* u = nullptr;
+  double c = 0.0, cb = 0.0, ca = 0.0, cs = 0.0;
+  int flavor = kGeneric;
+};
+
+void classify_term(TermOp& op);
+
 // ---- launchers (stencil.hip) ----
-hipError_t launch_term(expint_dtype dt, expint_bc bc, const Geom& g, const Coef& cf, const TermOp& op,
-                       hipStream_t st);
-hipError_t launch_rhs(expint_dtype dt, expint_bc bc, const Geom& g, const Coef& cf, const void* u, void* b,
-                      double rho, hipStream_t st);
-hipError_t launch_apply(expint_dtype dt, expint_bc bc, const Geom& g, const Coef& cf, const void* x, void* y,
-                        hipStream_t st);
+hipError_t launch_term(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,
+                       const TermOp& op, hipStream_t st);
+hipError_t launch_rhs(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf, const void* u,
+                      void* b, double rho, hipStream_t st);
+hipError_t launch_apply(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,
+                        const void* x, void* y, hipStream_t st);
 
 // ||A||_1 and input validation, FP64.  partial: 2 * field_block_count(g)
 // doubles of workspace; out[0] = max column sum of |A|, out[1] = 1 if a label >= nclass or

@@ -2,52 +2,90 @@
 
 namespace expint {
 
+void classify_term(TermOp& op) {
+  op.flavor = kGeneric;
+  if (op.u) return;
+  if (!op.bsrc && !op.acc_in && !op.acc_out && op.y_out) {
+    op.flavor = kSkip;
+  } else if (!op.bsrc && op.acc_in && op.ca == 1.0 && op.acc_out) {
+    op.flavor = op.y_out ? kFlushY : kFlushNoY;
+  } else if (op.bsrc && !op.acc_in && op.acc_out && op.y_out) {
+    op.flavor = kFirst;
+  }
+}
+
 std::vector<TermOp> phi1_schedule(const StepBuffers& ws, int s, int m, double tau, const void* b, void* x_out,
                                   void* u) {
   enum class X { Zero, HB, Buf };
   std::vector<TermOp> ops;
   const double h = tau / s;
-  X xk = X::Zero;
-  int xa = 0;  // acc buffer holding x when xk == Buf
+  X xk = X::Zero;  // what x (the state entering the sub-step) is: 0, h*b, or ws.acc[xa]
+  int xa = 0;
   for (int sig = 1; sig <= s; ++sig) {
-    TermOp op{};
-    int j_next;  // first term index handled by the generic loop below
+    const int out = (xk == X::Buf) ? 1 - xa : 0;
+    void* A = ws.acc[out];  // running sum of this sub-step
+    int ycur = 0;           // buffer with y_{j-1}
+    bool pend = false;      // y_{j-1} not yet in the running sum
+    bool pend_hb = false;   // the sum has not been started: it still lacks h*b
+    int j0;
     if (xk == X::Zero) {
       if (m == 1) {  // x_1 = h b: no sweep
         xk = X::HB;
         continue;
       }
-      op.src = b;  // y_2 = (h/2) A (h b)
-      op.c = h * h / 2.0;
-      op.alpha = h;  // sum starts at y_1 = h b
-      j_next = 3;
-    } else if (xk == X::HB) {
-      op.src = b;  // y_1 = h (A (h b) + b)
-      op.bsrc = b;
-      op.c = h * h;
-      op.cb = h;
-      op.alpha = h;  // sum starts at x = h b
-      j_next = 2;
+      // y_1 = h b is not stored; y_2 = (h/2) A (h b)
+      TermOp t;
+      t.src = b;
+      t.c = h * h / 2.0;
+      if (m == 2) {
+        t.acc_out = A;
+        t.cs = h;  // h b + y_2
+        ops.push_back(t);
+        xk = X::Buf;
+        xa = out;
+        continue;
+      }
+      t.y_out = ws.y[0];
+      ops.push_back(t);
+      pend = true;
+      pend_hb = true;
+      j0 = 3;
     } else {
-      op.src = ws.acc[xa];  // y_1 = h (A x + b)
-      op.bsrc = b;
-      op.c = h;
-      op.cb = h;
-      op.alpha = 1.0;  // sum starts at x
-      j_next = 2;
+      // y_1 = h (A x + b), sum = x + y_1
+      TermOp t;
+      t.src = (xk == X::HB) ? b : ws.acc[xa];
+      t.bsrc = b;
+      t.c = (xk == X::HB) ? h * h : h;  // x = h b: h A (h b)
+      t.cb = h;
+      t.cs = (xk == X::HB) ? h : 1.0;
+      t.acc_out = A;
+      t.y_out = m >= 2 ? ws.y[0] : nullptr;
+      ops.push_back(t);
+      j0 = 2;
     }
-    const int out = (xk == X::Buf) ? 1 - xa : 0;
-    op.acc_out = ws.acc[out];
-    int ycur = 0;
-    op.y_out = j_next <= m ? ws.y[0] : nullptr;
-    ops.push_back(op);
-    for (int j = j_next; j <= m; ++j) {
-      TermOp t{};
+    for (int j = j0; j <= m; ++j) {
+      // y_j = (h/j) A y_{j-1}; add to the sum in pairs (y_{j-1} is the source
+      // already in registers), or alone for the last term
+      TermOp t;
       t.src = ws.y[ycur];
       t.c = h / j;
-      t.acc_in = ws.acc[out];
-      t.acc_out = ws.acc[out];
-      t.y_out = j < m ? ws.y[1 - ycur] : nullptr;
+      const bool last = j == m;
+      if (pend || last) {
+        if (pend_hb) {
+          t.acc_in = b;
+          t.ca = h;
+        } else {
+          t.acc_in = A;
+          t.ca = 1.0;
+        }
+        t.cs = pend ? 1.0 : 0.0;
+        t.acc_out = A;
+        pend = false;
+        pend_hb = false;
+      } else {
+        pend = true;
+      }
+      t.y_out = last ? nullptr : ws.y[1 - ycur];
       ycur = 1 - ycur;
       ops.push_back(t);
     }
@@ -55,10 +93,9 @@ std::vector<TermOp> phi1_schedule(const StepBuffers& ws, int s, int m, double ta
     xa = out;
   }
   if (ops.empty()) {  // s == m == 1: x = tau b
-    TermOp t{};
+    TermOp t;
     t.src = b;
-    t.c = 0.0;
-    t.alpha = h;
+    t.cs = h;
     ops.push_back(t);
   }
   TermOp& last = ops.back();
@@ -69,6 +106,7 @@ std::vector<TermOp> phi1_schedule(const StepBuffers& ws, int s, int m, double ta
   } else {
     last.acc_out = x_out;
   }
+  for (TermOp& t : ops) classify_term(t);
   return ops;
 }
 

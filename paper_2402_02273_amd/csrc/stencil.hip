@@ -24,6 +24,31 @@ Shape choose_shape(const Geom& g) {
   return s;
 }
 
+bool tiling_valid(const Tiling& t) {
+  return (t.bx == 64 || t.bx == 32 || t.bx == 16) && t.by * t.bx == kBlock && (t.lp == 1 || t.lp == 2 || t.lp == 4);
+}
+
+int64_t sweep_blocks(const Geom& g, const Tiling& t) {
+  const int64_t gx = (g.nz + t.bx - 1) / t.bx, gy = (g.ny + t.by - 1) / t.by, gz = (g.nx + t.lp - 1) / t.lp;
+  return gx * gy * gz;
+}
+
+Tiling default_tiling(const Geom& g) {
+  // widest z-row with the least padding; ties to the wider row
+  Tiling t;
+  int best_waste = -1;
+  for (int bx : {64, 32, 16}) {
+    const int waste = ((g.nz + bx - 1) / bx) * bx - g.nz;
+    if (best_waste < 0 || waste < best_waste) {
+      best_waste = waste;
+      t.bx = bx;
+    }
+  }
+  t.by = kBlock / t.bx;
+  t.lp = 4;
+  return t;
+}
+
 int64_t field_block_count(const Geom& g) {
   const Shape s = choose_shape(g);
   return static_cast<int64_t>(s.gx) * s.gy * g.nx;
@@ -76,81 +101,115 @@ __device__ __forceinline__ void load_tables(LdsCoef<T>& s, const Coef& cf) {
   __syncthreads();
 }
 
-// (A x)_p = sum over faces of K_f / h^2 (x_q - x_p); box faces: none (no flux)
-// or -D_p / h^2 x_p (zero ghost at distance h).
-template <typename T, int BC>
-__device__ __forceinline__ T apply_at(const T* __restrict__ x, const Coef& cf, const LdsCoef<T>& s,
-                                      const Geom& g, const Vox& v, T xp) {
-  const int64_t sx = static_cast<int64_t>(g.ny) * g.nz;
-  const int64_t sy = g.nz;
-  T acc = T(0);
+enum SweepKind { kTerm = 0, kRhs = 1, kApply = 2 };
+
+struct SweepArgs {
+  TermOp op;     // kTerm
+  const void* x; // kRhs / kApply input
+  void* out;     // kRhs / kApply output
+  double rho;    // kRhs
+};
+
+// One sweep over a bx x by patch of lp consecutive x-planes.  Each thread
+// owns one (j, k) column and marches along x keeping the x-1 / x / x+1 values
+// (and labels) of the field in registers; the four lateral neighbours are
+// plain loads served by L1/L2.  Neighbour indices outside the box are clamped
+// to the voxel itself, so the difference x_q - x_p of a wall face is exactly 0
+// (zero flux) and every load is unconditional; zero-Dirichlet walls add
+// -D_p/h^2 x_p per wall face instead.
+template <typename T, int BC, int LP, int KIND, int FL>
+__global__ __launch_bounds__(kBlock) void k_sweep(Geom g, int gx, int gy, Coef cf, SweepArgs a) {
+  __shared__ LdsCoef<T> s;
+  load_tables(s, cf);
+  const int L = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+  const int bxi = L % gx;
+  const int t = L / gx;
+  const int byi = t % gy;
+  const int i0 = (t / gy) * LP;
+  const int j = byi * static_cast<int>(blockDim.y) + static_cast<int>(threadIdx.y);
+  const int k = bxi * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x);
+  if (j >= g.ny || k >= g.nz) return;
+  const int sx = g.ny * g.nz;
+  const int dym = j > 0 ? -g.nz : 0, dyp = j < g.ny - 1 ? g.nz : 0;
+  const int dzm = k > 0 ? -1 : 0, dzp = k < g.nz - 1 ? 1 : 0;
+  const int wall_yz = BC ? (j == 0) + (j == g.ny - 1) + (k == 0) + (k == g.nz - 1) : 0;
+  const T* __restrict__ x = static_cast<const T*>(KIND == kTerm ? a.op.src : a.x);
+  const uint8_t* __restrict__ lab = cf.labels;
+  const T* __restrict__ fx = static_cast<const T*>(cf.fx);
+  const T* __restrict__ fy = static_cast<const T*>(cf.fy);
+  const T* __restrict__ fz = static_cast<const T*>(cf.fz);
+  int q = (i0 * g.ny + j) * g.nz + k;
+  const int qm0 = i0 > 0 ? q - sx : q;
+  T xm = x[qm0], xc = x[q];
+  int lm = 0, lc = 0;
+  T km = T(0);  // dense form: coefficient of the -x face
   if (cf.labels_form) {
-    const uint8_t* __restrict__ lab = cf.labels;
-    const int lp = lab[v.p];
-    const T* row = s.tab + lp * kMaxClasses;
-    const T wl = s.wall[lp];
-    if (v.i > 0) acc += row[lab[v.p - sx]] * (x[v.p - sx] - xp); else if (BC) acc -= wl * xp;
-    if (v.i < g.nx - 1) acc += row[lab[v.p + sx]] * (x[v.p + sx] - xp); else if (BC) acc -= wl * xp;
-    if (v.j > 0) acc += row[lab[v.p - sy]] * (x[v.p - sy] - xp); else if (BC) acc -= wl * xp;
-    if (v.j < g.ny - 1) acc += row[lab[v.p + sy]] * (x[v.p + sy] - xp); else if (BC) acc -= wl * xp;
-    if (v.k > 0) acc += row[lab[v.p - 1]] * (x[v.p - 1] - xp); else if (BC) acc -= wl * xp;
-    if (v.k < g.nz - 1) acc += row[lab[v.p + 1]] * (x[v.p + 1] - xp); else if (BC) acc -= wl * xp;
+    lm = lab[qm0];
+    lc = lab[q];
   } else {
-    const T* __restrict__ fx = static_cast<const T*>(cf.fx);
-    const T* __restrict__ fy = static_cast<const T*>(cf.fy);
-    const T* __restrict__ fz = static_cast<const T*>(cf.fz);
-    const T wl = BC ? static_cast<const T*>(cf.wallv)[v.p] : T(0);
-    if (v.i > 0) acc += fx[v.p - sx] * (x[v.p - sx] - xp); else if (BC) acc -= wl * xp;
-    if (v.i < g.nx - 1) acc += fx[v.p] * (x[v.p + sx] - xp); else if (BC) acc -= wl * xp;
-    if (v.j > 0) acc += fy[v.p - sy] * (x[v.p - sy] - xp); else if (BC) acc -= wl * xp;
-    if (v.j < g.ny - 1) acc += fy[v.p] * (x[v.p + sy] - xp); else if (BC) acc -= wl * xp;
-    if (v.k > 0) acc += fz[v.p - 1] * (x[v.p - 1] - xp); else if (BC) acc -= wl * xp;
-    if (v.k < g.nz - 1) acc += fz[v.p] * (x[v.p + 1] - xp); else if (BC) acc -= wl * xp;
+    km = fx[qm0];
   }
-  return acc;
-}
-
-template <typename T, int BC>
-__global__ __launch_bounds__(kBlock) void k_term(Geom g, int gx, int gy, Coef cf, TermOp op) {
-  __shared__ LdsCoef<T> s;
-  load_tables(s, cf);
-  const Vox v = voxel_of(g, gx, gy);
-  if (!v.ok) return;
-  const T* __restrict__ src = static_cast<const T*>(op.src);
-  const T xp = src[v.p];
-  const T a = apply_at<T, BC>(src, cf, s, g, v, xp);
-  T y = static_cast<T>(op.c) * a;
-  if (op.bsrc) y += static_cast<T>(op.cb) * static_cast<const T*>(op.bsrc)[v.p];
-  const T base = op.acc_in ? static_cast<const T*>(op.acc_in)[v.p] : static_cast<T>(op.alpha) * xp;
-  const T acc = base + y;
-  if (op.u) {
-    T* u = static_cast<T*>(op.u);
-    u[v.p] = u[v.p] + acc;
-  } else {
-    if (op.y_out) static_cast<T*>(op.y_out)[v.p] = y;
-    static_cast<T*>(op.acc_out)[v.p] = acc;
+#pragma unroll
+  for (int sp = 0; sp < LP; ++sp) {
+    const int i = i0 + sp;
+    if (i >= g.nx) break;
+    const int qn = i < g.nx - 1 ? q + sx : q;
+    const T xn = x[qn];
+    const T x2 = x[q + dym], x3 = x[q + dyp], x4 = x[q + dzm], x5 = x[q + dzp];
+    T ax;
+    int ln = 0;
+    if (cf.labels_form) {
+      ln = lab[qn];
+      const int l2 = lab[q + dym], l3 = lab[q + dyp], l4 = lab[q + dzm], l5 = lab[q + dzp];
+      const T* row = s.tab + lc * kMaxClasses;
+      ax = row[lm] * (xm - xc) + row[ln] * (xn - xc) + row[l2] * (x2 - xc) + row[l3] * (x3 - xc) +
+           row[l4] * (x4 - xc) + row[l5] * (x5 - xc);
+      if (BC) ax -= s.wall[lc] * xc * T(wall_yz + (i == 0) + (i == g.nx - 1));
+    } else {
+      const T kp = fx[q];
+      ax = km * (xm - xc) + kp * (xn - xc) + fy[q + dym] * (x2 - xc) + fy[q] * (x3 - xc) + fz[q + dzm] * (x4 - xc) +
+           fz[q] * (x5 - xc);
+      if (BC) ax -= static_cast<const T*>(cf.wallv)[q] * xc * T(wall_yz + (i == 0) + (i == g.nx - 1));
+      km = kp;
+    }
+    if (KIND == kTerm) {
+      const TermOp& op = a.op;
+      const T c = static_cast<T>(op.c);
+      if (FL == kSkip) {
+        static_cast<T*>(op.y_out)[q] = c * ax;
+      } else if (FL == kFlushY || FL == kFlushNoY) {
+        const T y = c * ax;
+        T* accp = static_cast<T*>(op.acc_out);
+        accp[q] = static_cast<const T*>(op.acc_in)[q] + static_cast<T>(op.cs) * xc + y;
+        if (FL == kFlushY) static_cast<T*>(op.y_out)[q] = y;
+      } else if (FL == kFirst) {
+        const T y = c * ax + static_cast<T>(op.cb) * static_cast<const T*>(op.bsrc)[q];
+        static_cast<T*>(op.acc_out)[q] = static_cast<T>(op.cs) * xc + y;
+        static_cast<T*>(op.y_out)[q] = y;
+      } else {
+        T y = c * ax;
+        if (op.bsrc) y += static_cast<T>(op.cb) * static_cast<const T*>(op.bsrc)[q];
+        T v = static_cast<T>(op.cs) * xc + y;
+        if (op.acc_in) v += static_cast<T>(op.ca) * static_cast<const T*>(op.acc_in)[q];
+        if (op.u) {
+          T* u = static_cast<T*>(op.u);
+          u[q] = u[q] + v;
+        } else {
+          if (op.y_out) static_cast<T*>(op.y_out)[q] = y;
+          if (op.acc_out) static_cast<T*>(op.acc_out)[q] = v;
+        }
+      }
+    } else if (KIND == kRhs) {
+      static_cast<T*>(a.out)[q] = ax + static_cast<T>(a.rho) * xc * (T(1) - xc);
+    } else {
+      static_cast<T*>(a.out)[q] = ax;
+    }
+    xm = xc;
+    xc = xn;
+    lm = lc;
+    lc = ln;
+    q += sx;
   }
-}
-
-template <typename T, int BC>
-__global__ __launch_bounds__(kBlock) void k_rhs(Geom g, int gx, int gy, Coef cf, const T* __restrict__ u,
-                                                T* __restrict__ b, T rho) {
-  __shared__ LdsCoef<T> s;
-  load_tables(s, cf);
-  const Vox v = voxel_of(g, gx, gy);
-  if (!v.ok) return;
-  const T up = u[v.p];
-  b[v.p] = apply_at<T, BC>(u, cf, s, g, v, up) + rho * up * (T(1) - up);
-}
-
-template <typename T, int BC>
-__global__ __launch_bounds__(kBlock) void k_apply(Geom g, int gx, int gy, Coef cf, const T* __restrict__ x,
-                                                  T* __restrict__ y) {
-  __shared__ LdsCoef<T> s;
-  load_tables(s, cf);
-  const Vox v = voxel_of(g, gx, gy);
-  if (!v.ok) return;
-  y[v.p] = apply_at<T, BC>(x, cf, s, g, v, x[v.p]);
 }
 
 // ---------------------------------------------------------------------------
@@ -342,55 +401,68 @@ int field_blocks(const Geom& g, const Shape& s) { return s.gx * s.gy * g.nx; }
 
 }  // namespace
 
-hipError_t launch_term(expint_dtype dt, expint_bc bc, const Geom& g, const Coef& cf, const TermOp& op,
-                       hipStream_t st) {
-  const Shape s = choose_shape(g);
-  const dim3 grid(field_blocks(g, s)), block(s.bx, s.by);
+template <typename T, int BC, int KIND, int FL>
+static void sweep_lp(const Geom& g, const Tiling& tl, const Coef& cf, const SweepArgs& a, hipStream_t st) {
+  const int gx = (g.nz + tl.bx - 1) / tl.bx, gy = (g.ny + tl.by - 1) / tl.by;
+  const dim3 grid(static_cast<unsigned>(sweep_blocks(g, tl))), block(tl.bx, tl.by);
+  switch (tl.lp) {
+    case 1: k_sweep<T, BC, 1, KIND, FL><<<grid, block, 0, st>>>(g, gx, gy, cf, a); break;
+    case 2: k_sweep<T, BC, 2, KIND, FL><<<grid, block, 0, st>>>(g, gx, gy, cf, a); break;
+    default: k_sweep<T, BC, 4, KIND, FL><<<grid, block, 0, st>>>(g, gx, gy, cf, a); break;
+  }
+}
+
+template <typename T, int BC, int KIND>
+static void sweep_typed(const Geom& g, const Tiling& tl, const Coef& cf, const SweepArgs& a, hipStream_t st) {
+  if (KIND != kTerm) {
+    sweep_lp<T, BC, KIND, kGeneric>(g, tl, cf, a, st);
+    return;
+  }
+  switch (a.op.flavor) {
+    case kSkip: sweep_lp<T, BC, KIND, kSkip>(g, tl, cf, a, st); break;
+    case kFlushY: sweep_lp<T, BC, KIND, kFlushY>(g, tl, cf, a, st); break;
+    case kFlushNoY: sweep_lp<T, BC, KIND, kFlushNoY>(g, tl, cf, a, st); break;
+    case kFirst: sweep_lp<T, BC, KIND, kFirst>(g, tl, cf, a, st); break;
+    default: sweep_lp<T, BC, KIND, kGeneric>(g, tl, cf, a, st); break;
+  }
+}
+
+template <int KIND>
+static hipError_t sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,
+                        const SweepArgs& a, hipStream_t st) {
+  if (!tiling_valid(tl)) return hipErrorInvalidValue;
   if (dt == EXPINT_F64) {
-    if (bc == EXPINT_NOFLUX) k_term<double, 0><<<grid, block, 0, st>>>(g, s.gx, s.gy, cf, op);
-    else k_term<double, 1><<<grid, block, 0, st>>>(g, s.gx, s.gy, cf, op);
+    if (bc == EXPINT_NOFLUX) sweep_typed<double, 0, KIND>(g, tl, cf, a, st);
+    else sweep_typed<double, 1, KIND>(g, tl, cf, a, st);
   } else {
-    if (bc == EXPINT_NOFLUX) k_term<float, 0><<<grid, block, 0, st>>>(g, s.gx, s.gy, cf, op);
-    else k_term<float, 1><<<grid, block, 0, st>>>(g, s.gx, s.gy, cf, op);
+    if (bc == EXPINT_NOFLUX) sweep_typed<float, 0, KIND>(g, tl, cf, a, st);
+    else sweep_typed<float, 1, KIND>(g, tl, cf, a, st);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_rhs(expint_dtype dt, expint_bc bc, const Geom& g, const Coef& cf, const void* u, void* b,
-                      double rho, hipStream_t st) {
-  const Shape s = choose_shape(g);
-  const dim3 grid(field_blocks(g, s)), block(s.bx, s.by);
-  if (dt == EXPINT_F64) {
-    auto* uu = static_cast<const double*>(u);
-    auto* bb = static_cast<double*>(b);
-    if (bc == EXPINT_NOFLUX) k_rhs<double, 0><<<grid, block, 0, st>>>(g, s.gx, s.gy, cf, uu, bb, rho);
-    else k_rhs<double, 1><<<grid, block, 0, st>>>(g, s.gx, s.gy, cf, uu, bb, rho);
-  } else {
-    auto* uu = static_cast<const float*>(u);
-    auto* bb = static_cast<float*>(b);
-    const float r = static_cast<float>(rho);
-    if (bc == EXPINT_NOFLUX) k_rhs<float, 0><<<grid, block, 0, st>>>(g, s.gx, s.gy, cf, uu, bb, r);
-    else k_rhs<float, 1><<<grid, block, 0, st>>>(g, s.gx, s.gy, cf, uu, bb, r);
-  }
-  return hipGetLastError();
+hipError_t launch_term(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,
+                       const TermOp& op, hipStream_t st) {
+  SweepArgs a{};
+  a.op = op;
+  return sweep<kTerm>(dt, bc, g, tl, cf, a, st);
 }
 
-hipError_t launch_apply(expint_dtype dt, expint_bc bc, const Geom& g, const Coef& cf, const void* x, void* y,
-                        hipStream_t st) {
-  const Shape s = choose_shape(g);
-  const dim3 grid(field_blocks(g, s)), block(s.bx, s.by);
-  if (dt == EXPINT_F64) {
-    auto* xx = static_cast<const double*>(x);
-    auto* yy = static_cast<double*>(y);
-    if (bc == EXPINT_NOFLUX) k_apply<double, 0><<<grid, block, 0, st>>>(g, s.gx, s.gy, cf, xx, yy);
-    else k_apply<double, 1><<<grid, block, 0, st>>>(g, s.gx, s.gy, cf, xx, yy);
-  } else {
-    auto* xx = static_cast<const float*>(x);
-    auto* yy = static_cast<float*>(y);
-    if (bc == EXPINT_NOFLUX) k_apply<float, 0><<<grid, block, 0, st>>>(g, s.gx, s.gy, cf, xx, yy);
-    else k_apply<float, 1><<<grid, block, 0, st>>>(g, s.gx, s.gy, cf, xx, yy);
-  }
-  return hipGetLastError();
+hipError_t launch_rhs(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf, const void* u,
+                      void* b, double rho, hipStream_t st) {
+  SweepArgs a{};
+  a.x = u;
+  a.out = b;
+  a.rho = rho;
+  return sweep<kRhs>(dt, bc, g, tl, cf, a, st);
+}
+
+hipError_t launch_apply(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,
+                        const void* x, void* y, hipStream_t st) {
+  SweepArgs a{};
+  a.x = x;
+  a.out = y;
+  return sweep<kApply>(dt, bc, g, tl, cf, a, st);
 }
 
 hipError_t launch_scan_labels(expint_bc bc, const Geom& g, const uint8_t* labels, int nclass, const double* tab64,

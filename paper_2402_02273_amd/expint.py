@@ -264,8 +264,12 @@ class ExpInt:
         return gu, grho.value, list(gD)[: self.n_classes]
 
     # ---- measurement ----
-    def profile(self, reps=50):
-        """Mean ms per launch of the generic Taylor-term sweep and of the RHS sweep."""
-        t, r = ctypes.c_double(), ctypes.c_double()
-        N.check(self.lib.expint_profile(self._ctx, int(reps), ctypes.byref(t), ctypes.byref(r)))
-        return t.value, r.value
+    def profile(self, kernel="flush", reps=50) -> float:
+        """Mean ms per launch of one sweep of the step schedule.
+
+        kernel: "flush" (Taylor term adding a pair of terms to the running sum),
+        "skip" (Taylor term writing only its term) or "rhs"."""
+        ms = ctypes.c_double()
+        kid = {"flush": 0, "skip": 1, "rhs": 2}[kernel]
+        N.check(self.lib.expint_profile(self._ctx, kid, int(reps), ctypes.byref(ms)))
+        return ms.value
