@@ -1,15 +1,242 @@
+// Discrete adjoint of the exponential Euler advance (host orchestration).
+//
+// The forward map with the plan frozen is, per step n,
+//   b_n = A u_n + f(u_n),  x_0 = 0,
+//   sub-step sigma: y_1 = h (A x + b_n), y_j = (h/j) A y_{j-1}, x <- x + sum_j y_j,
+//   u_{n+1} = u_n + x_s,   h = tau / s.
+// For a cotangent lambda_{n+1} = dL/du_{n+1} the reverse sweep runs the Taylor
+// recurrence backwards (A is symmetric):
+//   ybar_m = xbar,  ybar_j = xbar + (h/(j+1)) A ybar_{j+1},
+//   bbar += h ybar_1,  xbar <- xbar + h A ybar_1,
+// starting from xbar = lambda_{n+1}; g = bbar equals P(A) lambda_{n+1} and
+//   lambda_n = lambda_{n+1} + A g + rho (1 - 2 u_n) g,
+//   dL/drho += <g, u_n (1 - u_n)>,
+//   dL/dD_c += <g, A_c u_n> + sum_sigma [h <ybar_1, A_c x_{sigma-1}> + sum_{j>=2} (h/j) <ybar_j, A_c y_{j-1}>],
+// with A_c = dA/dD_c.  u is checkpointed every ckpt_every steps and recomputed
+// inside a segment; each step's Taylor terms are recomputed once and kept.
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
 #include "context.hpp"
+#include "internal.hpp"
 
 using namespace expint;
 
-extern "C" {
+namespace {
 
-int expint_grad(expint_ctx*, const void*, int32_t, const void*, int32_t, double*, void*, double*, double*) {
-  return set_error(EXPINT_EUNSUPPORTED, "adjoint not available in this build");
+int grow(expint_ctx* c, std::vector<void*>& v, size_t count) {
+  const size_t fb = c->field_bytes();
+  while (v.size() < count) {
+    void* p = nullptr;
+    const int rc = c->arena.alloc(&p, fb);
+    if (rc) return rc;
+    v.push_back(p);
+  }
+  return EXPINT_OK;
 }
 
-int expint_vjp(expint_ctx*, const void*, int32_t, const void*, int32_t, void*, double*, double*) {
-  return set_error(EXPINT_EUNSUPPORTED, "adjoint not available in this build");
+int ensure_adj(expint_ctx* c, int nck, int seg) {
+  auto& a = c->adj;
+  const size_t fb = c->field_bytes();
+  int rc;
+  if (!a.lam) {
+    void** singles[] = {&a.lam, &a.gb, &a.work, &a.xb[0], &a.xb[1], &a.yb[0], &a.yb[1]};
+    for (void** p : singles)
+      if ((rc = c->arena.alloc(p, fb))) return rc;
+    if ((rc = c->arena.alloc(reinterpret_cast<void**>(&a.fpart), kReduceBlocks * kMaxClasses * sizeof(double))))
+      return rc;
+    if ((rc = c->arena.alloc(reinterpret_cast<void**>(&a.dev), 16 * sizeof(double)))) return rc;
+    if ((rc = c->arena.alloc(reinterpret_cast<void**>(&a.dtab), kMaxClasses * kTab * sizeof(double)))) return rc;
+    if ((rc = c->arena.alloc(reinterpret_cast<void**>(&a.dwall), kMaxClasses * kMaxClasses * sizeof(double))))
+      return rc;
+  }
+  if ((rc = grow(c, a.ckpt, static_cast<size_t>(nck)))) return rc;
+  if ((rc = grow(c, a.segs, static_cast<size_t>(seg)))) return rc;
+  if ((rc = grow(c, a.xs, static_cast<size_t>(c->s) + 1))) return rc;
+  if ((rc = grow(c, a.tape, static_cast<size_t>(c->s) * c->m))) return rc;
+  return EXPINT_OK;
+}
+
+// Face weights -dK(D_a, D_b)/dD_c / h^2 and wall weights -[a == c] / h^2.
+int upload_weights(expint_ctx* c) {
+  double dt[kMaxClasses * kTab] = {0}, dw[kMaxClasses * kMaxClasses] = {0};
+  const double inv_h2 = 1.0 / (c->h * c->h);
+  for (int cc = 0; cc < c->nclass; ++cc) {
+    dw[cc * kMaxClasses + cc] = -inv_h2;
+    for (int a = 0; a < c->nclass; ++a) {
+      for (int b = 0; b < c->nclass; ++b) {
+        const double da = c->class_D[a], db = c->class_D[b], s = da + db;
+        double d = 0.0;
+        if (a == cc && b == cc) {
+          d = 1.0;  // K(D, D) = D
+        } else if (s > 0.0) {
+          if (a == cc) d += 2.0 * db * db / (s * s);
+          if (b == cc) d += 2.0 * da * da / (s * s);
+        }
+        dt[cc * kTab + a * kMaxClasses + b] = -d * inv_h2;
+      }
+    }
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->adj.dtab, dt, sizeof(dt), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->adj.dwall, dw, sizeof(dw), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return EXPINT_OK;
+}
+
+int faceprod(expint_ctx* c, const void* ybar, const void* y, double w) {
+  HIP_TRY(c, launch_faceprod(c->dtype, c->bc, c->g, c->labels, c->nclass, c->adj.dtab, c->adj.dwall, ybar, y, w,
+                             c->adj.fpart, c->adj.dev, c->stream));
+  return EXPINT_OK;
+}
+
+int term(expint_ctx* c, TermOp op) {
+  classify_term(op);
+  HIP_TRY(c, launch_term(c->dtype, c->bc, c->g, c->tiling, c->coef(), op, c->stream));
+  return EXPINT_OK;
+}
+
+// Reverse sweep of one step; lambda (c->adj.lam) is updated in place.
+int reverse_step(expint_ctx* c, const void* un) {
+  auto& a = c->adj;
+  const int s = c->s, m = c->m;
+  const double h = c->tau / s;
+  const int64_t n = c->g.n;
+  int rc;
+  // b_n and the Taylor tape of every sub-step
+  HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, c->tiling, c->coef(), un, c->b, c->rho, c->stream));
+  for (int sig = 1; sig <= s; ++sig) {
+    void** T = &a.tape[static_cast<size_t>(sig - 1) * m];
+    TermOp t1;
+    t1.src = a.xs[sig - 1];
+    t1.bsrc = c->b;
+    t1.c = h;
+    t1.cb = h;
+    t1.cs = 1.0;
+    t1.acc_out = a.xs[sig];
+    t1.y_out = m >= 2 ? T[0] : nullptr;
+    if ((rc = term(c, t1))) return rc;
+    for (int j = 2; j <= m; ++j) {
+      TermOp t;
+      t.src = T[j - 2];
+      t.c = h / j;
+      t.acc_in = a.xs[sig];
+      t.ca = 1.0;
+      t.acc_out = a.xs[sig];
+      t.y_out = j < m ? T[j - 1] : nullptr;
+      if ((rc = term(c, t))) return rc;
+    }
+  }
+  // reverse through the sub-steps
+  int xi = 0;
+  HIP_TRY(c, launch_copy(c->dtype, n, a.lam, a.xb[0], c->stream));
+  HIP_TRY(c, launch_fill(c->dtype, n, 0.0, a.gb, c->stream));
+  for (int sig = s; sig >= 1; --sig) {
+    void** T = &a.tape[static_cast<size_t>(sig - 1) * m];
+    const void* xprev = a.xs[sig - 1];
+    const void* ynext = a.xb[xi];  // ybar_m = xbar
+    if (m >= 2) {
+      if ((rc = faceprod(c, ynext, T[m - 2], h / m))) return rc;
+    } else {
+      if ((rc = faceprod(c, ynext, xprev, h))) return rc;
+    }
+    int yi = 0;
+    for (int j = m - 1; j >= 1; --j) {
+      TermOp t;  // ybar_j = xbar + (h/(j+1)) A ybar_{j+1}
+      t.src = ynext;
+      t.bsrc = a.xb[xi];
+      t.cb = 1.0;
+      t.c = h / (j + 1);
+      t.y_out = a.yb[yi];
+      if ((rc = term(c, t))) return rc;
+      ynext = a.yb[yi];
+      yi ^= 1;
+      if ((rc = faceprod(c, ynext, j >= 2 ? T[j - 2] : xprev, j >= 2 ? h / j : h))) return rc;
+    }
+    // bbar += h ybar_1;  xbar <- xbar + h A ybar_1
+    HIP_TRY(c, launch_axpby(c->dtype, n, 1.0, a.gb, h, ynext, a.gb, c->stream));
+    TermOp t;
+    t.src = ynext;
+    t.bsrc = a.xb[xi];
+    t.cb = 1.0;
+    t.c = h;
+    t.y_out = a.xb[1 - xi];
+    if ((rc = term(c, t))) return rc;
+    xi ^= 1;
+  }
+  // g = bbar: rho and D contributions of b_n = A u_n + f(u_n), then lambda_n
+  HIP_TRY(c, launch_reduce(c->dtype, 4, a.gb, un, n, c->partial, a.dev + 8, c->stream, true));
+  if ((rc = faceprod(c, a.gb, un, 1.0))) return rc;
+  HIP_TRY(c, launch_adj_rhs(c->dtype, c->bc, c->g, c->tiling, c->coef(), a.gb, un, a.lam, a.lam, c->rho, c->stream));
+  return EXPINT_OK;
+}
+
+int vjp_core(expint_ctx* c, const void* u0, int32_t nsteps, const void* cot, bool cot_is_target, int32_t ckpt_every,
+             double* loss, void* grad_u0, double* grad_rho, double* grad_D) {
+  CHECK_CTX(c);
+  if (!u0 || !cot || !grad_u0) return set_error(EXPINT_EINVAL, "NULL field");
+  if (nsteps < 0) return set_error(EXPINT_EINVAL, "nsteps must be >= 0");
+  if (ckpt_every < 1) return set_error(EXPINT_EINVAL, "ckpt_every must be >= 1");
+  if (!c->labels_form) return set_error(EXPINT_EINVAL, "gradients need the label form of D");
+  int rc = ensure_device(c);
+  if (rc) return rc;
+  const int nck = nsteps > 0 ? (nsteps + ckpt_every - 1) / ckpt_every : 0;
+  const int seg = std::min(ckpt_every, std::max(nsteps, 1));
+  if ((rc = ensure_adj(c, nck, seg))) return rc;
+  if ((rc = upload_weights(c))) return rc;
+  auto& a = c->adj;
+  const int64_t n = c->g.n;
+  HIP_TRY(c, launch_fill(EXPINT_F64, 16, 0.0, a.dev, c->stream));
+  HIP_TRY(c, launch_fill(c->dtype, n, 0.0, a.xs[0], c->stream));
+
+  // forward with checkpoints
+  HIP_TRY(c, launch_copy(c->dtype, n, u0, a.work, c->stream));
+  for (int k = 0; k < nsteps; ++k) {
+    if (k % ckpt_every == 0) HIP_TRY(c, launch_copy(c->dtype, n, a.work, a.ckpt[k / ckpt_every], c->stream));
+    if ((rc = enqueue_step(c, a.work))) return rc;
+  }
+  if (cot_is_target) {
+    HIP_TRY(c, launch_reduce(c->dtype, 5, a.work, cot, n, c->partial, a.dev + 9, c->stream));
+    HIP_TRY(c, launch_axpby(c->dtype, n, 1.0, a.work, -1.0, cot, a.lam, c->stream));
+  } else {
+    HIP_TRY(c, launch_copy(c->dtype, n, cot, a.lam, c->stream));
+  }
+
+  for (int sgi = nck - 1; sgi >= 0; --sgi) {
+    const int start = sgi * ckpt_every;
+    const int stop = std::min(start + ckpt_every, nsteps);
+    HIP_TRY(c, launch_copy(c->dtype, n, a.ckpt[sgi], a.segs[0], c->stream));
+    for (int k = start; k < stop - 1; ++k) {
+      HIP_TRY(c, launch_copy(c->dtype, n, a.segs[k - start], a.segs[k - start + 1], c->stream));
+      if ((rc = enqueue_step(c, a.segs[k - start + 1]))) return rc;
+    }
+    for (int k = stop - 1; k >= start; --k)
+      if ((rc = reverse_step(c, a.segs[k - start]))) return rc;
+  }
+  HIP_TRY(c, launch_copy(c->dtype, n, a.lam, grad_u0, c->stream));
+  double host[16];
+  HIP_TRY(c, hipMemcpyAsync(host, a.dev, sizeof(host), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (loss) *loss = 0.5 * host[9];
+  if (grad_rho) *grad_rho = host[8];
+  if (grad_D)
+    for (int k = 0; k < c->nclass; ++k) grad_D[k] = host[k];
+  return EXPINT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int expint_grad(expint_ctx* c, const void* u0, int32_t nsteps, const void* u_target, int32_t ckpt_every,
+                double* loss, void* grad_u0, double* grad_rho, double* grad_class_D) {
+  return vjp_core(c, u0, nsteps, u_target, true, ckpt_every, loss, grad_u0, grad_rho, grad_class_D);
+}
+
+int expint_vjp(expint_ctx* c, const void* u0, int32_t nsteps, const void* gout, int32_t ckpt_every, void* grad_u0,
+               double* grad_rho, double* grad_class_D) {
+  return vjp_core(c, u0, nsteps, gout, false, ckpt_every, nullptr, grad_u0, grad_rho, grad_class_D);
 }
 
 }  // extern "C"

@@ -48,7 +48,19 @@ Arena::Arena() {
 }
 
 Arena::~Arena() {
-  for (void* p : ptrs_) (void)hipFree(p);
+  for (auto& e : ptrs_) (void)hipFree(e.first);
+}
+
+void Arena::release(void* p) {
+  if (!p) return;
+  for (size_t i = 0; i < ptrs_.size(); ++i) {
+    if (ptrs_[i].first == p) {
+      (void)hipFree(p);
+      bytes_ -= ptrs_[i].second;
+      ptrs_.erase(ptrs_.begin() + static_cast<long>(i));
+      return;
+    }
+  }
 }
 
 int Arena::alloc(void** p, size_t bytes) {
@@ -63,7 +75,7 @@ int Arena::alloc(void** p, size_t bytes) {
     *p = nullptr;
     return set_error(EXPINT_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
   }
-  ptrs_.push_back(*p);
+  ptrs_.emplace_back(*p, bytes);
   bytes_ += bytes;
   return EXPINT_OK;
 }
@@ -78,27 +90,11 @@ void destroy_graphs(std::vector<GraphEntry>& gs) {
 
 }  // namespace expint
 
-#define HIP_TRY(ctxp, call)                                                                          \
-  do {                                                                                               \
-    const hipError_t e_ = (call);                                                                    \
-    if (e_ != hipSuccess) {                                                                          \
-      (ctxp)->poisoned = true;                                                                       \
-      return set_error(EXPINT_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
-                       __LINE__);                                                                    \
-    }                                                                                                \
-  } while (0)
-
-#define CHECK_CTX(ctxp)                                                              \
-  do {                                                                               \
-    if (!(ctxp)) return set_error(EXPINT_EINVAL, "context is NULL");                 \
-    if ((ctxp)->poisoned) return set_error(EXPINT_ESTATE, "context poisoned by an earlier HIP error"); \
-  } while (0)
-
-namespace {
+namespace expint {
 
 bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
 
-double harmonic(double a, double b) {
+double harmonic_mean(double a, double b) {
   const double s = a + b;
   return s > 0.0 ? 2.0 * a * b / s : 0.0;
 }
@@ -116,7 +112,7 @@ int upload_tables(expint_ctx* c) {
   const double inv_h2 = 1.0 / (c->h * c->h);
   for (int a = 0; a < c->nclass; ++a) {
     w64[a] = c->class_D[a] * inv_h2;
-    for (int b = 0; b < c->nclass; ++b) t64[a * kMaxClasses + b] = harmonic(c->class_D[a], c->class_D[b]) * inv_h2;
+    for (int b = 0; b < c->nclass; ++b) t64[a * kMaxClasses + b] = harmonic_mean(c->class_D[a], c->class_D[b]) * inv_h2;
   }
   HIP_TRY(c, hipMemcpyAsync(c->tab64, t64, sizeof(t64), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->wall64, w64, sizeof(w64), hipMemcpyHostToDevice, c->stream));
@@ -189,6 +185,10 @@ int check_finite_field(expint_ctx* c, const void* u) {
   if (cnt != 0.0) return set_error(EXPINT_ENONFINITE, "state holds %.0f non-finite values", cnt);
   return EXPINT_OK;
 }
+
+}  // namespace expint
+
+namespace {
 
 int validate_opts(const expint_opts* o) {
   if (o->dtype != EXPINT_F64 && o->dtype != EXPINT_F32) return set_error(EXPINT_EINVAL, "unknown dtype %d", o->dtype);
@@ -275,6 +275,10 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
   }
   c->check_finite = opts->check_finite;
   c->labels_form = df->labels != nullptr;
+  {
+    const char* ge = std::getenv("EXPINT_GRAPH");
+    c->use_graph = !(ge && ge[0] == '0');
+  }
 
   if (field_block_count(c->g) > (int64_t(1) << 31) - 1) return bail(set_error(EXPINT_EINVAL, "grid too large"));
   if (hipGetDevice(&c->device) != hipSuccess) {
@@ -450,6 +454,12 @@ int expint_advance(expint_ctx* c, void* u, int32_t nsteps) {
   int rc = ensure_device(c);
   if (rc) return rc;
   if (nsteps == 0) return EXPINT_OK;
+  if (!c->use_graph) {
+    for (int32_t i = 0; i < nsteps; ++i)
+      if ((rc = enqueue_step(c, u))) return rc;
+    if (c->check_finite) return check_finite_field(c, u);
+    return EXPINT_OK;
+  }
   GraphEntry* ge = nullptr;
   for (auto& e : c->graphs)
     if (e.key0 == u) ge = &e;

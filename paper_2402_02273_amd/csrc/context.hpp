@@ -21,10 +21,12 @@ class Arena {
   ~Arena();
   // 0 on success, EXPINT_ENOMEM otherwise (error message set).
   int alloc(void** p, size_t bytes);
+  // frees one allocation made by this arena (no-op for NULL)
+  void release(void* p);
   size_t bytes() const { return bytes_; }
 
  private:
-  std::vector<void*> ptrs_;
+  std::vector<std::pair<void*, size_t>> ptrs_;
   size_t bytes_ = 0;
   size_t cap_ = 0;
 };
@@ -41,6 +43,23 @@ void destroy_graphs(std::vector<GraphEntry>& gs);
 size_t dtype_size(expint_dtype dt);
 
 }  // namespace expint
+
+#define HIP_TRY(ctxp, call)                                                                          \
+  do {                                                                                               \
+    const hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) {                                                                          \
+      (ctxp)->poisoned = true;                                                                       \
+      return set_error(EXPINT_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                       __LINE__);                                                                    \
+    }                                                                                                \
+  } while (0)
+
+#define CHECK_CTX(ctxp)                                                              \
+  do {                                                                               \
+    if (!(ctxp)) return set_error(EXPINT_EINVAL, "context is NULL");                 \
+    if ((ctxp)->poisoned) return set_error(EXPINT_ESTATE, "context poisoned by an earlier HIP error"); \
+  } while (0)
+
 
 struct expint_ctx {
   expint::Geom g{};
@@ -82,7 +101,25 @@ struct expint_ctx {
 
   expint::Tiling tiling;  // launch shape of the stencil sweeps (autotuned)
 
+  // adjoint workspace: allocated on the first gradient call, regrown on demand
+  struct Adj {
+    std::vector<void*> ckpt;  // u every ckpt_every steps
+    std::vector<void*> segs;  // states of one checkpoint segment
+    std::vector<void*> xs;    // sub-step states x_0 .. x_s of one step
+    std::vector<void*> tape;  // Taylor terms y_1 .. y_m of every sub-step
+    void* lam = nullptr;      // adjoint state
+    void* gb = nullptr;       // adjoint of b (= P(A) lambda)
+    void* work = nullptr;     // forward state
+    void* xb[2] = {nullptr, nullptr};
+    void* yb[2] = {nullptr, nullptr};
+    double* fpart = nullptr;  // face-product partials, kReduceBlocks * 8
+    double* dev = nullptr;    // [0..7] class sums, [8] d/drho, [9] loss
+    double* dtab = nullptr;   // 8 x 64 face weights
+    double* dwall = nullptr;  // 8 x 8 wall weights
+  } adj;
+
   std::vector<expint::GraphEntry> graphs;
+  bool use_graph = true;  // EXPINT_GRAPH=0: advance launches each step directly
   bool poisoned = false;
 
   expint::Coef coef() const {
@@ -99,3 +136,18 @@ struct expint_ctx {
   }
   size_t field_bytes() const { return static_cast<size_t>(g.n) * expint::dtype_size(dtype); }
 };
+
+namespace expint {
+
+struct StepBuffers;
+
+// Shared host runtime (api.cpp).
+bool finite_nonneg(double v);
+double harmonic_mean(double a, double b);
+int ensure_device(expint_ctx* c);
+int upload_tables(expint_ctx* c);
+int enqueue_step(expint_ctx* c, void* u);
+int run_ops(expint_ctx* c, const std::vector<TermOp>& ops);
+int check_finite_field(expint_ctx* c, const void* u);
+
+}  // namespace expint

@@ -103,13 +103,32 @@ hipError_t launch_scan_dense(expint_dtype dt, expint_bc bc, const Geom& g, const
                              void* fy, void* fz, void* wallv, double* partial, double* out, hipStream_t st);
 
 // Deterministic two-pass FP64 reductions: op 0 sum x, 1 sum x*y, 2 max|x|,
-// 3 count of non-finite x.  partial: kReduceBlocks doubles; out: 1 double.
+// 3 count of non-finite x, 4 sum x*y*(1-y), 5 sum (x-y)^2.  partial:
+// kReduceBlocks doubles; out: 1 double, overwritten or (accumulate) added to.
 hipError_t launch_reduce(expint_dtype dt, int op, const void* x, const void* y, int64_t n, double* partial,
-                         double* out, hipStream_t st);
+                         double* out, hipStream_t st, bool accumulate = false);
+
+// lambda_out = lambda_in + A g + rho (1 - 2 u) g  (adjoint of one step's
+// right-hand side; lambda_out may equal lambda_in).
+hipError_t launch_adj_rhs(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,
+                          const void* gv, const void* u, const void* lam_in, void* lam_out, double rho,
+                          hipStream_t st);
+
+// Class-diffusivity derivatives of <ybar, A y> (label form):
+//   acc[c] += weight * ( sum over interior faces p|q of dtab[c][l_p][l_q] (ybar_p - ybar_q)(y_p - y_q)
+//                        + sum over zero-Dirichlet wall faces of dwall[c][l_p] ybar_p y_p )
+// with dtab[c] = -(dK/dD_c)/h^2 and dwall[c][a] = -[a == c]/h^2, so that acc[c]
+// accumulates <ybar, (dA/dD_c) y>.  dtab: 8 x 64 FP64, dwall: 8 x 8 FP64 (device);
+// partial: kReduceBlocks * 8 doubles; acc: 8 doubles.
+hipError_t launch_faceprod(expint_dtype dt, expint_bc bc, const Geom& g, const uint8_t* labels, int nclass,
+                           const double* dtab, const double* dwall, const void* ybar, const void* y, double weight,
+                           double* partial, double* acc, hipStream_t st);
 
 // Pointwise helpers.
 hipError_t launch_axpy(expint_dtype dt, int64_t n, double a, const void* x, void* y, hipStream_t st);  // y += a x
 hipError_t launch_copy(expint_dtype dt, int64_t n, const void* x, void* y, hipStream_t st);
+hipError_t launch_axpby(expint_dtype dt, int64_t n, double a, const void* x, double b, const void* y, void* out,
+                        hipStream_t st);  // out = a x + b y
 hipError_t launch_fill(expint_dtype dt, int64_t n, double v, void* y, hipStream_t st);
 
 }  // namespace expint

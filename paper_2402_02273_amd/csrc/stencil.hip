@@ -101,13 +101,15 @@ __device__ __forceinline__ void load_tables(LdsCoef<T>& s, const Coef& cf) {
   __syncthreads();
 }
 
-enum SweepKind { kTerm = 0, kRhs = 1, kApply = 2 };
+enum SweepKind { kTerm = 0, kRhs = 1, kApply = 2, kAdjRhs = 3 };
 
 struct SweepArgs {
-  TermOp op;     // kTerm
-  const void* x; // kRhs / kApply input
-  void* out;     // kRhs / kApply output
-  double rho;    // kRhs
+  TermOp op;          // kTerm
+  const void* x;      // kRhs / kApply / kAdjRhs stencil input
+  void* out;          // kRhs / kApply / kAdjRhs output
+  const void* aux0;   // kAdjRhs: lambda in
+  const void* aux1;   // kAdjRhs: u
+  double rho;         // kRhs / kAdjRhs
 };
 
 // One sweep over a bx x by patch of lp consecutive x-planes.  Each thread
@@ -201,6 +203,12 @@ __global__ __launch_bounds__(kBlock) void k_sweep(Geom g, int gx, int gy, Coef c
       }
     } else if (KIND == kRhs) {
       static_cast<T*>(a.out)[q] = ax + static_cast<T>(a.rho) * xc * (T(1) - xc);
+    } else if (KIND == kAdjRhs) {
+      // lambda + A g + rho (1 - 2 u) g: the transpose of the step's Jacobian
+      // applied to g (A is symmetric)
+      const T uq = static_cast<const T*>(a.aux1)[q];
+      static_cast<T*>(a.out)[q] =
+          static_cast<const T*>(a.aux0)[q] + ax + static_cast<T>(a.rho) * (T(1) - T(2) * uq) * xc;
     } else {
       static_cast<T*>(a.out)[q] = ax;
     }
@@ -366,23 +374,39 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const T* __restrict__ x, cons
     if (OP == 1) acc += v * static_cast<double>(y[p]);
     if (OP == 2) acc = fmax(acc, fabs(v));
     if (OP == 3) acc += isfinite(v) ? 0.0 : 1.0;
+    if (OP == 4) {
+      const double w = static_cast<double>(y[p]);
+      acc += v * w * (1.0 - w);
+    }
+    if (OP == 5) {
+      const double d = v - static_cast<double>(y[p]);
+      acc += d * d;
+    }
   }
   acc = block_reduce<OP>(acc);
   if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
 template <int OP>
-__global__ __launch_bounds__(kBlock) void k_reduce_final(const double* __restrict__ partial, int nb, double* out) {
+__global__ __launch_bounds__(kBlock) void k_reduce_final(const double* __restrict__ partial, int nb, double* out,
+                                                         int accumulate) {
   double acc = 0.0;
   for (int i = threadIdx.x; i < nb; i += kBlock) acc = combine<OP>(acc, partial[i]);
   acc = block_reduce<OP>(acc);
-  if (threadIdx.x == 0) out[0] = acc;
+  if (threadIdx.x == 0) out[0] = accumulate ? combine<OP>(out[0], acc) : acc;
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_axpy(int64_t n, T a, const T* __restrict__ x, T* __restrict__ y) {
   const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (p < n) y[p] += a * x[p];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_axpby(int64_t n, T a, const T* __restrict__ x, T b,
+                                                  const T* __restrict__ y, T* __restrict__ out) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (p < n) out[p] = a * x[p] + b * y[p];
 }
 
 template <typename T>
@@ -465,6 +489,18 @@ hipError_t launch_apply(expint_dtype dt, expint_bc bc, const Geom& g, const Tili
   return sweep<kApply>(dt, bc, g, tl, cf, a, st);
 }
 
+hipError_t launch_adj_rhs(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,
+                          const void* gv, const void* u, const void* lam_in, void* lam_out, double rho,
+                          hipStream_t st) {
+  SweepArgs a{};
+  a.x = gv;
+  a.out = lam_out;
+  a.aux0 = lam_in;
+  a.aux1 = u;
+  a.rho = rho;
+  return sweep<kAdjRhs>(dt, bc, g, tl, cf, a, st);
+}
+
 hipError_t launch_scan_labels(expint_bc bc, const Geom& g, const uint8_t* labels, int nclass, const double* tab64,
                               const double* wall64, double* partial, double* out, hipStream_t st) {
   const Shape s = choose_shape(g);
@@ -502,23 +538,33 @@ hipError_t launch_scan_dense(expint_dtype dt, expint_bc bc, const Geom& g, const
   return hipGetLastError();
 }
 
+template <typename T, int OP>
+static void reduce_op(const T* x, const T* y, int64_t n, double* partial, double* out, int acc, hipStream_t st) {
+  k_reduce<T, OP><<<kReduceBlocks, kBlock, 0, st>>>(x, y, n, partial);
+  k_reduce_final<OP><<<1, kBlock, 0, st>>>(partial, kReduceBlocks, out, acc);
+}
+
 template <typename T>
-static void reduce_typed(int op, const T* x, const T* y, int64_t n, double* partial, double* out, hipStream_t st) {
-  const dim3 grid(kReduceBlocks), block(kBlock);
+static void reduce_typed(int op, const T* x, const T* y, int64_t n, double* partial, double* out, int acc,
+                         hipStream_t st) {
   switch (op) {
-    case 0: k_reduce<T, 0><<<grid, block, 0, st>>>(x, y, n, partial); k_reduce_final<0><<<1, kBlock, 0, st>>>(partial, kReduceBlocks, out); break;
-    case 1: k_reduce<T, 1><<<grid, block, 0, st>>>(x, y, n, partial); k_reduce_final<1><<<1, kBlock, 0, st>>>(partial, kReduceBlocks, out); break;
-    case 2: k_reduce<T, 2><<<grid, block, 0, st>>>(x, y, n, partial); k_reduce_final<2><<<1, kBlock, 0, st>>>(partial, kReduceBlocks, out); break;
-    default: k_reduce<T, 3><<<grid, block, 0, st>>>(x, y, n, partial); k_reduce_final<3><<<1, kBlock, 0, st>>>(partial, kReduceBlocks, out); break;
+    case 0: reduce_op<T, 0>(x, y, n, partial, out, acc, st); break;
+    case 1: reduce_op<T, 1>(x, y, n, partial, out, acc, st); break;
+    case 2: reduce_op<T, 2>(x, y, n, partial, out, acc, st); break;
+    case 3: reduce_op<T, 3>(x, y, n, partial, out, acc, st); break;
+    case 4: reduce_op<T, 4>(x, y, n, partial, out, acc, st); break;
+    default: reduce_op<T, 5>(x, y, n, partial, out, acc, st); break;
   }
 }
 
 hipError_t launch_reduce(expint_dtype dt, int op, const void* x, const void* y, int64_t n, double* partial,
-                         double* out, hipStream_t st) {
+                         double* out, hipStream_t st, bool accumulate) {
   if (dt == EXPINT_F64)
-    reduce_typed<double>(op, static_cast<const double*>(x), static_cast<const double*>(y), n, partial, out, st);
+    reduce_typed<double>(op, static_cast<const double*>(x), static_cast<const double*>(y), n, partial, out,
+                         accumulate ? 1 : 0, st);
   else
-    reduce_typed<float>(op, static_cast<const float*>(x), static_cast<const float*>(y), n, partial, out, st);
+    reduce_typed<float>(op, static_cast<const float*>(x), static_cast<const float*>(y), n, partial, out,
+                        accumulate ? 1 : 0, st);
   return hipGetLastError();
 }
 
@@ -529,6 +575,19 @@ hipError_t launch_axpy(expint_dtype dt, int64_t n, double a, const void* x, void
   else
     k_axpy<float><<<grid, block, 0, st>>>(n, static_cast<float>(a), static_cast<const float*>(x),
                                           static_cast<float*>(y));
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(expint_dtype dt, int64_t n, double a, const void* x, double b, const void* y, void* out,
+                        hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>((n + kBlock - 1) / kBlock)), block(kBlock);
+  if (dt == EXPINT_F64)
+    k_axpby<double><<<grid, block, 0, st>>>(n, a, static_cast<const double*>(x), b, static_cast<const double*>(y),
+                                            static_cast<double*>(out));
+  else
+    k_axpby<float><<<grid, block, 0, st>>>(n, static_cast<float>(a), static_cast<const float*>(x),
+                                           static_cast<float>(b), static_cast<const float*>(y),
+                                           static_cast<float*>(out));
   return hipGetLastError();
 }
 

@@ -3,7 +3,8 @@
 Calls only ``oracle/`` (FP64, CPU) on inputs from ``workloads``.  Run from
 the repository root:
 
-    python tests/golden/make_golden.py c2      # 128^3 head, 100 steps (~6 min)
+    python tests/golden/make_golden.py c2      # 128^3 head, 100 steps (~12 min)
+    python tests/golden/make_golden.py c4      # 96^3 gradients, 50 steps (~15 min)
 
 Each file records the plan, the input hashes and the oracle result.
 """
@@ -18,8 +19,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from oracle import integrator, operator, plan  # noqa: E402
-from workloads import c2_head  # noqa: E402
+from oracle import adjoint, integrator, operator, plan  # noqa: E402
+from workloads import c2_head, c4_adjoint  # noqa: E402
+from workloads.configs import c4_synthetic_target  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -56,9 +58,35 @@ def make_c2(n=128, nsteps=100):
     print("wrote", out, "plan", (s, m), "seconds", round(time.time() - t0, 1))
 
 
+def make_c4(n=96, nsteps=50, ckpt=10):
+    """Oracle loss and gradients at the evaluation parameters of the
+    calibration workload, against the synthetic (model-free) target."""
+    w, _ = c4_adjoint(n=n, nsteps=nsteps)
+    target = c4_synthetic_target(n=n)
+    op = operator.Operator(w.h, labels=w.labels, class_D=w.class_D)
+    s, m = plan.for_dtype(w.tau * op.norm1(), "f64")
+    t0 = time.time()
+    loss, gu0, grho, gD = adjoint.loss_and_grad(op, w.u0, w.rho, w.tau, s, m, nsteps, target, ckpt, classes=[0, 1, 2])
+    out = os.path.join(HERE, f"c4_adjoint_{n}_k{nsteps}_f64.npz")
+    np.savez_compressed(
+        out,
+        loss=loss,
+        grad_u0=gu0,
+        grad_rho=grho,
+        grad_D=np.array([gD[0], gD[1], gD[2]]),
+        s=s,
+        m=m,
+        labels_sha256=digest(w.labels),
+        target_sha256=digest(target),
+    )
+    print("wrote", out, "plan", (s, m), "loss", loss, "grad_rho", grho, "grad_D", gD, "seconds", round(time.time() - t0, 1))
+
+
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "c2"
     if which == "c2":
         make_c2()
+    elif which == "c4":
+        make_c4()
     else:
         raise SystemExit(f"unknown golden {which}")

@@ -120,6 +120,16 @@ def c4_adjoint(n: int = 96, nsteps: int = 50, seed: int = 2404, noise_seed: int 
     return w, noise
 
 
+def c4_synthetic_target(n: int = 96, seed: int = 2404, noise_seed: int = 2405):
+    """A target density for gradient parity that does not involve the model:
+    a wider Gaussian blob (amplitude 0.9, sigma = 6 voxels) at the tumour seed,
+    times the tissue mask, plus N(0, 0.01^2) noise on the tissue."""
+    head = make_head(n, seed)
+    blob = gaussian_blob(head.labels.shape, head.seed_voxel, amplitude=0.9, sigma=6.0)
+    noise = np.random.default_rng(noise_seed).normal(0.0, 0.01, size=head.labels.shape)
+    return (blob + noise) * (head.labels != 0)
+
+
 def c5_separable(n: int = 256, nsteps: int = 100) -> Workload:
     c = (n - 1) / 2.0
     labels = uniform_box(n, 1)
