@@ -1,20 +1,372 @@
+// Batched scenarios: many independent grids advanced together (host side).
+//
+// Every instance keeps its own plan (s_i, m_i), coefficient tables, tile
+// shape (autotuned per grid size) and workspace.  One step of the batch is
+// a sequence of launches: launch 0 computes every instance's right-hand side,
+// launch t >= 1 runs Taylor sweep t of every instance that has one (their
+// schedules have different lengths).  The sequence is recorded once as a HIP
+// graph for a given set of state pointers and replayed per step.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <new>
+#include <vector>
+
+#include "autotune.hpp"
+#include "batch.hpp"
 #include "context.hpp"
+#include "plan.hpp"
+#include "schedule.hpp"
 
 using namespace expint;
 
+namespace {
+
+constexpr int kMaxGrid = 4096;  // workgroups of one batched launch (grid stride beyond)
+
+struct Inst {
+  Geom g{};
+  double h = 1.0;
+  int nclass = 0;
+  double class_D[kMaxClasses] = {0};
+  double rho = 0.0;
+  int s = 1, m = 1;
+  double norm1 = 0.0;
+  uint8_t* labels = nullptr;
+  double* tab64 = nullptr;
+  double* wall64 = nullptr;
+  void* tab = nullptr;
+  void* wallc = nullptr;
+  Tiling tiling;
+  StepBuffers ws;
+  Coef coef() const {
+    Coef c{};
+    c.labels_form = true;
+    c.labels = labels;
+    c.tab = tab;
+    c.wallc = wallc;
+    return c;
+  }
+};
+
+struct Launch {
+  int offset, nops, total, grid;
+  bool rhs;
+};
+
+}  // namespace
+
+struct expint_batch {
+  expint_dtype dtype = EXPINT_F32;
+  expint_bc bc = EXPINT_NOFLUX;
+  double tau = 0.0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  Arena arena;
+  std::vector<Inst> inst;
+  BatchInst* d_insts = nullptr;
+  double* partial = nullptr;
+  double* red = nullptr;
+  // schedule recorded for one set of state pointers
+  std::vector<const void*> key;
+  BatchOp* d_ops = nullptr;
+  size_t ops_cap = 0;
+  std::vector<Launch> launches;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool poisoned = false;
+};
+
+namespace {
+
+int fail_hip(expint_batch* b, hipError_t e, const char* what) {
+  (void)hipGetLastError();
+  b->poisoned = true;
+  return set_error(EXPINT_EHIP, "%s failed: %s", what, hipGetErrorString(e));
+}
+
+#define BHIP(call)                                     \
+  do {                                                 \
+    const hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return fail_hip(b, e_, #call); \
+  } while (0)
+
+int setup_instance(expint_batch* b, Inst& in, const uint8_t* labels_src) {
+  const size_t w = dtype_size(b->dtype);
+  const size_t fb = static_cast<size_t>(in.g.n) * w;
+  int rc;
+  if ((rc = b->arena.alloc(reinterpret_cast<void**>(&in.labels), static_cast<size_t>(in.g.n)))) return rc;
+  if ((rc = b->arena.alloc(reinterpret_cast<void**>(&in.tab64), kTab * sizeof(double)))) return rc;
+  if ((rc = b->arena.alloc(reinterpret_cast<void**>(&in.wall64), kMaxClasses * sizeof(double)))) return rc;
+  if ((rc = b->arena.alloc(&in.tab, kTab * sizeof(double)))) return rc;
+  if ((rc = b->arena.alloc(&in.wallc, kMaxClasses * sizeof(double)))) return rc;
+  if ((rc = b->arena.alloc(&in.ws.b, fb))) return rc;
+  for (int i = 0; i < 2; ++i) {
+    if ((rc = b->arena.alloc(&in.ws.y[i], fb))) return rc;
+    if ((rc = b->arena.alloc(&in.ws.acc[i], fb))) return rc;
+  }
+  BHIP(hipMemcpyAsync(in.labels, labels_src, static_cast<size_t>(in.g.n), hipMemcpyDefault, b->stream));
+  double t64[kTab] = {0}, w64[kMaxClasses] = {0};
+  float t32[kTab] = {0}, w32[kMaxClasses] = {0};
+  const double inv_h2 = 1.0 / (in.h * in.h);
+  for (int a = 0; a < in.nclass; ++a) {
+    w64[a] = in.class_D[a] * inv_h2;
+    for (int c = 0; c < in.nclass; ++c) t64[a * kMaxClasses + c] = harmonic_mean(in.class_D[a], in.class_D[c]) * inv_h2;
+  }
+  for (int i = 0; i < kTab; ++i) t32[i] = static_cast<float>(t64[i]);
+  for (int i = 0; i < kMaxClasses; ++i) w32[i] = static_cast<float>(w64[i]);
+  BHIP(hipMemcpyAsync(in.tab64, t64, sizeof(t64), hipMemcpyHostToDevice, b->stream));
+  BHIP(hipMemcpyAsync(in.wall64, w64, sizeof(w64), hipMemcpyHostToDevice, b->stream));
+  if (b->dtype == EXPINT_F64) {
+    BHIP(hipMemcpyAsync(in.tab, t64, sizeof(t64), hipMemcpyHostToDevice, b->stream));
+    BHIP(hipMemcpyAsync(in.wallc, w64, sizeof(w64), hipMemcpyHostToDevice, b->stream));
+  } else {
+    BHIP(hipMemcpyAsync(in.tab, t32, sizeof(t32), hipMemcpyHostToDevice, b->stream));
+    BHIP(hipMemcpyAsync(in.wallc, w32, sizeof(w32), hipMemcpyHostToDevice, b->stream));
+  }
+  BHIP(launch_scan_labels(b->bc, in.g, in.labels, in.nclass, in.tab64, in.wall64, b->partial, b->red, b->stream));
+  double out[2];
+  BHIP(hipMemcpyAsync(out, b->red, sizeof(out), hipMemcpyDeviceToHost, b->stream));
+  BHIP(hipStreamSynchronize(b->stream));  // also retires the host-array copies above
+  if (out[1] != 0.0) return set_error(EXPINT_EINVAL, "a label is >= n_classes (%d)", in.nclass);
+  in.norm1 = out[0];
+  BHIP(autotune_sweep(b->dtype, b->bc, in.g, in.coef(), in.ws.y[0], in.ws.acc[0], in.ws.y[1], b->stream, &in.tiling));
+  return EXPINT_OK;
+}
+
+void destroy_graph(expint_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->key.clear();
+}
+
+int build_schedule(expint_batch* b, void* const* u) {
+  destroy_graph(b);
+  const int count = static_cast<int>(b->inst.size());
+  std::vector<std::vector<TermOp>> per(count);
+  size_t maxlen = 0;
+  for (int i = 0; i < count; ++i) {
+    Inst& in = b->inst[i];
+    per[i] = phi1_schedule(in.ws, in.s, in.m, b->tau, in.ws.b, nullptr, u[i]);
+    maxlen = std::max(maxlen, per[i].size());
+  }
+  // instances ordered by tile count, largest first
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int c) {
+                     return sweep_blocks(b->inst[a].g, b->inst[a].tiling) > sweep_blocks(b->inst[c].g, b->inst[c].tiling);
+                   });
+  std::vector<BatchOp> ops;
+  b->launches.clear();
+  for (size_t t = 0; t <= maxlen; ++t) {
+    Launch L{static_cast<int>(ops.size()), 0, 0, 0, t == 0};
+    for (int i : order) {
+      if (t > 0 && per[i].size() < t) continue;
+      BatchOp bo{};
+      bo.inst = i;
+      bo.block_start = L.total;
+      if (t == 0) {
+        bo.op.src = u[i];
+        bo.op.y_out = b->inst[i].ws.b;
+      } else {
+        bo.op = per[i][t - 1];
+      }
+      ops.push_back(bo);
+      L.total += static_cast<int>(sweep_blocks(b->inst[i].g, b->inst[i].tiling));
+      ++L.nops;
+    }
+    L.grid = std::min(L.total, kMaxGrid);
+    if (L.nops > 0) b->launches.push_back(L);
+  }
+  if (ops.size() > b->ops_cap) {
+    b->arena.release(b->d_ops);
+    b->d_ops = nullptr;
+    int rc = b->arena.alloc(reinterpret_cast<void**>(&b->d_ops), ops.size() * sizeof(BatchOp));
+    if (rc) return rc;
+    b->ops_cap = ops.size();
+  }
+  BHIP(hipMemcpyAsync(b->d_ops, ops.data(), ops.size() * sizeof(BatchOp), hipMemcpyHostToDevice, b->stream));
+  BHIP(hipStreamSynchronize(b->stream));
+  BHIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t err = hipSuccess;
+  for (const Launch& L : b->launches) {
+    err = launch_batch(b->dtype, b->bc, L.rhs, b->d_insts, b->d_ops + L.offset, L.nops, L.total, L.grid, b->stream);
+    if (err != hipSuccess) break;
+  }
+  hipGraph_t gr = nullptr;
+  const hipError_t ec = hipStreamEndCapture(b->stream, &gr);
+  if (err != hipSuccess) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return fail_hip(b, err, "batched launch");
+  }
+  if (ec != hipSuccess) return fail_hip(b, ec, "hipStreamEndCapture");
+  b->graph = gr;
+  BHIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  b->key.assign(u, u + count);
+  return EXPINT_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
-int expint_batch_create(int32_t, const expint_grid*, const expint_dfield*, const double*, expint_bc,
-                        const expint_opts*, expint_batch** out) {
+int expint_batch_create(int32_t count, const expint_grid* grids, const expint_dfield* dfields, const double* rho,
+                        expint_bc bc, const expint_opts* opts, expint_batch** out) {
   if (out) *out = nullptr;
-  return set_error(EXPINT_EUNSUPPORTED, "batch not available in this build");
+  if (count < 1 || !grids || !dfields || !rho || !opts || !out) return set_error(EXPINT_EINVAL, "NULL argument or count < 1");
+  if (bc != EXPINT_NOFLUX && bc != EXPINT_DIRICHLET0) return set_error(EXPINT_EINVAL, "unknown bc %d", bc);
+  if (opts->dtype != EXPINT_F64 && opts->dtype != EXPINT_F32) return set_error(EXPINT_EINVAL, "unknown dtype");
+  if (!(opts->tau > 0.0) || !std::isfinite(opts->tau)) return set_error(EXPINT_EINVAL, "tau must be finite and > 0");
+  if ((opts->s > 0) != (opts->m > 0) || opts->s < 0 || opts->m < 0 || opts->m > kPlanMaxDegree)
+    return set_error(EXPINT_EINVAL, "give both s and m (m <= %d) or neither", kPlanMaxDegree);
+  if (!(opts->tol >= 0.0) || !(opts->theta_max >= 0.0)) return set_error(EXPINT_EINVAL, "bad tolerances");
+  if (opts->algo == EXPINT_ALGO_MODAL || opts->mp != EXPINT_MP_NONE)
+    return set_error(EXPINT_EUNSUPPORTED, "batches run the stencil-Taylor path only");
+  for (int i = 0; i < count; ++i) {
+    const expint_grid& g = grids[i];
+    const expint_dfield& d = dfields[i];
+    if (g.nx < 1 || g.ny < 1 || g.nz < 1 || !(g.h > 0.0) || !std::isfinite(g.h))
+      return set_error(EXPINT_EINVAL, "instance %d: bad grid", i);
+    if ((static_cast<int64_t>(g.nx) + 16) * g.ny * g.nz > (int64_t(1) << 31) - 1)
+      return set_error(EXPINT_EINVAL, "instance %d: grid too large", i);
+    if (!d.labels || d.D) return set_error(EXPINT_EINVAL, "instance %d: batches need the label form", i);
+    if (d.n_classes < 1 || d.n_classes > EXPINT_MAX_CLASSES || !d.class_D)
+      return set_error(EXPINT_EINVAL, "instance %d: n_classes must be in 1..%d", i, EXPINT_MAX_CLASSES);
+    for (int a = 0; a < d.n_classes; ++a)
+      if (!finite_nonneg(d.class_D[a])) return set_error(EXPINT_EINVAL, "instance %d: bad class_D[%d]", i, a);
+    if (!finite_nonneg(rho[i])) return set_error(EXPINT_EINVAL, "instance %d: bad rho", i);
+  }
+  expint_batch* b = new (std::nothrow) expint_batch();
+  if (!b) return set_error(EXPINT_ENOMEM, "host allocation failed");
+  auto bail = [&](int code) {
+    expint_batch_destroy(b);
+    return code;
+  };
+  b->dtype = opts->dtype;
+  b->bc = bc;
+  b->tau = opts->tau;
+  double tol, theta_max;
+  default_tolerances(b->dtype, &tol, &theta_max);
+  if (opts->tol > 0.0) tol = opts->tol;
+  if (opts->theta_max > 0.0) theta_max = opts->theta_max;
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(set_error(EXPINT_EHIP, "no HIP device"));
+  }
+  if (opts->stream) {
+    b->stream = static_cast<hipStream_t>(opts->stream);
+  } else {
+    if (hipStreamCreate(&b->stream) != hipSuccess) {
+      (void)hipGetLastError();
+      return bail(set_error(EXPINT_EHIP, "hipStreamCreate failed"));
+    }
+    b->own_stream = true;
+  }
+  int64_t max_parts = kReduceBlocks;
+  b->inst.resize(count);
+  for (int i = 0; i < count; ++i) {
+    Inst& in = b->inst[i];
+    in.g.nx = grids[i].nx;
+    in.g.ny = grids[i].ny;
+    in.g.nz = grids[i].nz;
+    in.g.n = static_cast<int64_t>(in.g.nx) * in.g.ny * in.g.nz;
+    in.h = grids[i].h;
+    in.nclass = dfields[i].n_classes;
+    for (int a = 0; a < in.nclass; ++a) in.class_D[a] = dfields[i].class_D[a];
+    in.rho = rho[i];
+    max_parts = std::max(max_parts, field_block_count(in.g));
+  }
+  int rc;
+  if ((rc = b->arena.alloc(reinterpret_cast<void**>(&b->partial), 2 * max_parts * sizeof(double)))) return bail(rc);
+  if ((rc = b->arena.alloc(reinterpret_cast<void**>(&b->red), 2 * sizeof(double)))) return bail(rc);
+  std::vector<BatchInst> hi(count);
+  for (int i = 0; i < count; ++i) {
+    Inst& in = b->inst[i];
+    if ((rc = setup_instance(b, in, dfields[i].labels))) return bail(rc);
+    if (opts->s > 0) {
+      in.s = opts->s;
+      in.m = opts->m;
+    } else if (!choose_plan(b->tau * in.norm1, tol, theta_max, &in.s, &in.m)) {
+      return bail(set_error(EXPINT_EINVAL, "instance %d: no admissible plan", i));
+    }
+    BatchInst& d = hi[i];
+    d.g = in.g;
+    d.bx = in.tiling.bx;
+    d.by = in.tiling.by;
+    d.lp = in.tiling.lp;
+    d.gx = (in.g.nz + d.bx - 1) / d.bx;
+    d.gy = (in.g.ny + d.by - 1) / d.by;
+    d.nblocks = static_cast<int>(sweep_blocks(in.g, in.tiling));
+    d.coef = in.coef();
+    d.rho = in.rho;
+  }
+  if ((rc = b->arena.alloc(reinterpret_cast<void**>(&b->d_insts), count * sizeof(BatchInst)))) return bail(rc);
+  if (hipMemcpyAsync(b->d_insts, hi.data(), count * sizeof(BatchInst), hipMemcpyHostToDevice, b->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(b->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(set_error(EXPINT_EHIP, "instance table upload failed"));
+  }
+  if (std::getenv("EXPINT_LOG")) {
+    int64_t vox = 0;
+    long terms = 0;
+    for (auto& in : b->inst) {
+      vox += in.g.n;
+      terms += static_cast<long>(in.s) * in.m;
+    }
+    std::fprintf(stderr, "[expint] batch of %d instances, %lld voxels, %ld Taylor terms per step in total, %zu B\n",
+                 count, static_cast<long long>(vox), terms, b->arena.bytes());
+  }
+  *out = b;
+  return EXPINT_OK;
 }
-int expint_batch_advance(expint_batch*, void* const*, int32_t) {
-  return set_error(EXPINT_EUNSUPPORTED, "batch not available in this build");
+
+int expint_batch_advance(expint_batch* b, void* const* u, int32_t nsteps) {
+  if (!b) return set_error(EXPINT_EINVAL, "batch is NULL");
+  if (b->poisoned) return set_error(EXPINT_ESTATE, "batch poisoned by an earlier HIP error");
+  if (!u) return set_error(EXPINT_EINVAL, "u is NULL");
+  if (nsteps < 0) return set_error(EXPINT_EINVAL, "nsteps must be >= 0");
+  const int count = static_cast<int>(b->inst.size());
+  for (int i = 0; i < count; ++i)
+    if (!u[i]) return set_error(EXPINT_EINVAL, "u[%d] is NULL", i);
+  int cur = -1;
+  BHIP(hipGetDevice(&cur));
+  if (cur != b->device) BHIP(hipSetDevice(b->device));
+  if (nsteps == 0) return EXPINT_OK;
+  bool same = b->exec && static_cast<int>(b->key.size()) == count;
+  for (int i = 0; same && i < count; ++i) same = b->key[i] == u[i];
+  if (!same) {
+    const int rc = build_schedule(b, u);
+    if (rc) return rc;
+  }
+  for (int32_t k = 0; k < nsteps; ++k) BHIP(hipGraphLaunch(b->exec, b->stream));
+  return EXPINT_OK;
 }
-int expint_batch_get_plan(const expint_batch*, int32_t, int32_t*, int32_t*, double*) {
-  return set_error(EXPINT_EUNSUPPORTED, "batch not available in this build");
+
+int expint_batch_get_plan(const expint_batch* b, int32_t index, int32_t* s, int32_t* m, double* norm1) {
+  if (!b || index < 0 || index >= static_cast<int32_t>(b->inst.size()))
+    return set_error(EXPINT_EINVAL, "NULL batch or index out of range");
+  const Inst& in = b->inst[index];
+  if (s) *s = in.s;
+  if (m) *m = in.m;
+  if (norm1) *norm1 = in.norm1;
+  return EXPINT_OK;
 }
-void expint_batch_destroy(expint_batch*) {}
+
+void expint_batch_destroy(expint_batch* b) {
+  if (!b) return;
+  if (b->stream && !b->poisoned) (void)hipStreamSynchronize(b->stream);
+  destroy_graph(b);
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
 
 }  // extern "C"

@@ -12,6 +12,7 @@
 // workgroup reads sit in the same XCD's L2.
 
 #include "internal.hpp"
+#include "sweep_device.hpp"
 
 namespace expint {
 
@@ -84,45 +85,13 @@ __device__ __forceinline__ Vox voxel_of(const Geom& g, int gx, int gy) {
   return v;
 }
 
-template <typename T>
-struct LdsCoef {
-  T tab[kTab];
-  T wall[kMaxClasses];
-};
-
-// Copies the class-pair table into LDS.  Must be reached by every thread.
-template <typename T>
-__device__ __forceinline__ void load_tables(LdsCoef<T>& s, const Coef& cf) {
-  if (cf.labels_form) {
-    const int t = threadIdx.y * blockDim.x + threadIdx.x;
-    if (t < kTab) s.tab[t] = static_cast<const T*>(cf.tab)[t];
-    if (t < kMaxClasses) s.wall[t] = static_cast<const T*>(cf.wallc)[t];
-  }
-  __syncthreads();
-}
-
-enum SweepKind { kTerm = 0, kRhs = 1, kApply = 2, kAdjRhs = 3 };
-
-struct SweepArgs {
-  TermOp op;          // kTerm
-  const void* x;      // kRhs / kApply / kAdjRhs stencil input
-  void* out;          // kRhs / kApply / kAdjRhs output
-  const void* aux0;   // kAdjRhs: lambda in
-  const void* aux1;   // kAdjRhs: u
-  double rho;         // kRhs / kAdjRhs
-};
-
-// One sweep over a bx x by patch of lp consecutive x-planes.  Each thread
-// owns one (j, k) column and marches along x keeping the x-1 / x / x+1 values
-// (and labels) of the field in registers; the four lateral neighbours are
-// plain loads served by L1/L2.  Neighbour indices outside the box are clamped
-// to the voxel itself, so the difference x_q - x_p of a wall face is exactly 0
-// (zero flux) and every load is unconditional; zero-Dirichlet walls add
-// -D_p/h^2 x_p per wall face instead.
+// One sweep over a bx x by patch of lp consecutive x-planes (see
+// sweep_column for the per-thread work).
 template <typename T, int BC, int LP, int KIND, int FL>
 __global__ __launch_bounds__(kBlock) void k_sweep(Geom g, int gx, int gy, Coef cf, SweepArgs a) {
   __shared__ LdsCoef<T> s;
-  load_tables(s, cf);
+  load_tables(s, cf, threadIdx.y * blockDim.x + threadIdx.x, kBlock);
+  __syncthreads();
   const int L = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
   const int bxi = L % gx;
   const int t = L / gx;
@@ -131,93 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(Geom g, int gx, int gy, Coef c
   const int j = byi * static_cast<int>(blockDim.y) + static_cast<int>(threadIdx.y);
   const int k = bxi * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x);
   if (j >= g.ny || k >= g.nz) return;
-  const int sx = g.ny * g.nz;
-  const int dym = j > 0 ? -g.nz : 0, dyp = j < g.ny - 1 ? g.nz : 0;
-  const int dzm = k > 0 ? -1 : 0, dzp = k < g.nz - 1 ? 1 : 0;
-  const int wall_yz = BC ? (j == 0) + (j == g.ny - 1) + (k == 0) + (k == g.nz - 1) : 0;
-  const T* __restrict__ x = static_cast<const T*>(KIND == kTerm ? a.op.src : a.x);
-  const uint8_t* __restrict__ lab = cf.labels;
-  const T* __restrict__ fx = static_cast<const T*>(cf.fx);
-  const T* __restrict__ fy = static_cast<const T*>(cf.fy);
-  const T* __restrict__ fz = static_cast<const T*>(cf.fz);
-  int q = (i0 * g.ny + j) * g.nz + k;
-  const int qm0 = i0 > 0 ? q - sx : q;
-  T xm = x[qm0], xc = x[q];
-  int lm = 0, lc = 0;
-  T km = T(0);  // dense form: coefficient of the -x face
-  if (cf.labels_form) {
-    lm = lab[qm0];
-    lc = lab[q];
-  } else {
-    km = fx[qm0];
-  }
-#pragma unroll
-  for (int sp = 0; sp < LP; ++sp) {
-    const int i = i0 + sp;
-    if (i >= g.nx) break;
-    const int qn = i < g.nx - 1 ? q + sx : q;
-    const T xn = x[qn];
-    const T x2 = x[q + dym], x3 = x[q + dyp], x4 = x[q + dzm], x5 = x[q + dzp];
-    T ax;
-    int ln = 0;
-    if (cf.labels_form) {
-      ln = lab[qn];
-      const int l2 = lab[q + dym], l3 = lab[q + dyp], l4 = lab[q + dzm], l5 = lab[q + dzp];
-      const T* row = s.tab + lc * kMaxClasses;
-      ax = row[lm] * (xm - xc) + row[ln] * (xn - xc) + row[l2] * (x2 - xc) + row[l3] * (x3 - xc) +
-           row[l4] * (x4 - xc) + row[l5] * (x5 - xc);
-      if (BC) ax -= s.wall[lc] * xc * T(wall_yz + (i == 0) + (i == g.nx - 1));
-    } else {
-      const T kp = fx[q];
-      ax = km * (xm - xc) + kp * (xn - xc) + fy[q + dym] * (x2 - xc) + fy[q] * (x3 - xc) + fz[q + dzm] * (x4 - xc) +
-           fz[q] * (x5 - xc);
-      if (BC) ax -= static_cast<const T*>(cf.wallv)[q] * xc * T(wall_yz + (i == 0) + (i == g.nx - 1));
-      km = kp;
-    }
-    if (KIND == kTerm) {
-      const TermOp& op = a.op;
-      const T c = static_cast<T>(op.c);
-      if (FL == kSkip) {
-        static_cast<T*>(op.y_out)[q] = c * ax;
-      } else if (FL == kFlushY || FL == kFlushNoY) {
-        const T y = c * ax;
-        T* accp = static_cast<T*>(op.acc_out);
-        accp[q] = static_cast<const T*>(op.acc_in)[q] + static_cast<T>(op.cs) * xc + y;
-        if (FL == kFlushY) static_cast<T*>(op.y_out)[q] = y;
-      } else if (FL == kFirst) {
-        const T y = c * ax + static_cast<T>(op.cb) * static_cast<const T*>(op.bsrc)[q];
-        static_cast<T*>(op.acc_out)[q] = static_cast<T>(op.cs) * xc + y;
-        static_cast<T*>(op.y_out)[q] = y;
-      } else {
-        T y = c * ax;
-        if (op.bsrc) y += static_cast<T>(op.cb) * static_cast<const T*>(op.bsrc)[q];
-        T v = static_cast<T>(op.cs) * xc + y;
-        if (op.acc_in) v += static_cast<T>(op.ca) * static_cast<const T*>(op.acc_in)[q];
-        if (op.u) {
-          T* u = static_cast<T*>(op.u);
-          u[q] = u[q] + v;
-        } else {
-          if (op.y_out) static_cast<T*>(op.y_out)[q] = y;
-          if (op.acc_out) static_cast<T*>(op.acc_out)[q] = v;
-        }
-      }
-    } else if (KIND == kRhs) {
-      static_cast<T*>(a.out)[q] = ax + static_cast<T>(a.rho) * xc * (T(1) - xc);
-    } else if (KIND == kAdjRhs) {
-      // lambda + A g + rho (1 - 2 u) g: the transpose of the step's Jacobian
-      // applied to g (A is symmetric)
-      const T uq = static_cast<const T*>(a.aux1)[q];
-      static_cast<T*>(a.out)[q] =
-          static_cast<const T*>(a.aux0)[q] + ax + static_cast<T>(a.rho) * (T(1) - T(2) * uq) * xc;
-    } else {
-      static_cast<T*>(a.out)[q] = ax;
-    }
-    xm = xc;
-    xc = xn;
-    lm = lc;
-    lc = ln;
-    q += sx;
-  }
+  sweep_column<T, BC, LP, KIND, FL>(g, cf, s, a, i0, j, k, LP);
 }
 
 // ---------------------------------------------------------------------------

@@ -273,3 +273,107 @@ class ExpInt:
         kid = {"flush": 0, "skip": 1, "rhs": 2}[kernel]
         N.check(self.lib.expint_profile(self._ctx, kid, int(reps), ctypes.byref(ms)))
         return ms.value
+
+
+class ExpIntBatch:
+    """Many independent label-form grids advanced together (one HIP graph per step).
+
+    ``instances``: sequence of dicts with ``labels`` (uint8 (nx, ny, nz)),
+    ``class_D``, ``rho`` and optionally ``h``.  Every instance gets its own
+    (s, m) plan and tile shape; tau, dtype, boundary and tolerances are shared.
+    """
+
+    def __init__(
+        self,
+        instances,
+        *,
+        tau: float = 7.3,
+        dtype=torch.float32,
+        bc: str = "noflux",
+        tol: float = 0.0,
+        theta_max: float = 0.0,
+        s: int = 0,
+        m: int = 0,
+        device=None,
+        stream=None,
+    ):
+        self.lib = N.lib()
+        device = torch.device("cuda") if device is None else torch.device(device)
+        if device.index is None:
+            device = torch.device("cuda", torch.cuda.current_device())
+        self.device = device
+        if dtype not in _DTYPES:
+            raise ValueError("dtype must be torch.float32 or torch.float64")
+        self.dtype = dtype
+        count = len(instances)
+        if count < 1:
+            raise ValueError("empty batch")
+        grids = (N.Grid * count)()
+        dfs = (N.DField * count)()
+        rhos = (ctypes.c_double * count)()
+        keep = []
+        self.shapes = []
+        for i, inst in enumerate(instances):
+            lab = _as_device(inst["labels"], device, torch.uint8)
+            shape = tuple(int(v) for v in np.shape(inst["labels"]))
+            if len(shape) != 3 or lab.numel() != int(np.prod(shape)):
+                raise ValueError(f"instance {i}: labels must be a 3-D array")
+            cd = (ctypes.c_double * len(inst["class_D"]))(*[float(v) for v in inst["class_D"]])
+            keep += [lab, cd]
+            grids[i] = N.Grid(shape[0], shape[1], shape[2], float(inst.get("h", 1.0)))
+            dfs[i].labels = lab.data_ptr()
+            dfs[i].n_classes = len(inst["class_D"])
+            dfs[i].class_D = ctypes.cast(cd, ctypes.POINTER(ctypes.c_double))
+            rhos[i] = float(inst["rho"])
+            self.shapes.append(shape)
+        opts = N.Opts()
+        N.check(self.lib.expint_opts_default(ctypes.byref(opts)))
+        opts.dtype = _DTYPES[dtype]
+        opts.tau = float(tau)
+        opts.tol = float(tol)
+        opts.theta_max = float(theta_max)
+        opts.s = int(s)
+        opts.m = int(m)
+        self._b = ctypes.c_void_p()
+        with torch.cuda.device(device):
+            opts.stream = _stream_handle(stream, device)
+            N.check(
+                self.lib.expint_batch_create(
+                    count, grids, dfs, rhos, _BCS[bc], ctypes.byref(opts), ctypes.byref(self._b)
+                )
+            )
+        self.count = count
+        del keep
+
+    def close(self):
+        if getattr(self, "_b", None) and self._b.value:
+            self.lib.expint_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def plan(self, i) -> Plan:
+        s, m, nrm = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        N.check(self.lib.expint_batch_get_plan(self._b, int(i), ctypes.byref(s), ctypes.byref(m), ctypes.byref(nrm)))
+        return Plan(s.value, m.value, nrm.value)
+
+    @property
+    def plans(self):
+        return [self.plan(i) for i in range(self.count)]
+
+    def advance(self, us, nsteps: int):
+        if len(us) != self.count:
+            raise ValueError(f"{len(us)} fields for {self.count} instances")
+        ptrs = (ctypes.c_void_p * self.count)()
+        for i, (u, shape) in enumerate(zip(us, self.shapes)):
+            if not isinstance(u, torch.Tensor) or u.device != self.device or u.dtype != self.dtype:
+                raise ValueError(f"u[{i}] must be a {self.dtype} tensor on {self.device}")
+            if not u.is_contiguous() or u.numel() != int(np.prod(shape)):
+                raise ValueError(f"u[{i}] must be contiguous with {int(np.prod(shape))} elements")
+            ptrs[i] = u.data_ptr()
+        N.check(self.lib.expint_batch_advance(self._b, ptrs, int(nsteps)))
+        return us

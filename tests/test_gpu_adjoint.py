@@ -193,6 +193,6 @@ def test_autograd_function_matches_oracle(native):
     uT = advance(ctx, u0t, rt, ct, K, ckpt_every=2)
     loss = 0.5 * ((uT - dev(target, torch.float64)) ** 2).sum()
     loss.backward()
-    assert float(loss) == pytest.approx(L, rel=1e-12)
+    assert float(loss.detach()) == pytest.approx(L, rel=1e-12)
     assert rel(u0t.grad.cpu().numpy(), gu) < 1e-10
     check_scalars(float(rt.grad), [float(v) for v in ct.grad], grho, gD, 1e-10)

@@ -1,0 +1,120 @@
+"""GPU parity of the batched path: many grids of different sizes, plans,
+rho and diffusivities advanced in one graph, against the FP64 oracle per
+instance and against single-grid contexts."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import integrator as oit
+from oracle import operator as oop
+from oracle import plan as oplan
+from workloads import c3_batch, make_head
+from workloads.configs import random_field, random_labels
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
+
+
+def small_instances():
+    out = []
+    for i, shape in enumerate([(8, 8, 8), (12, 12, 12), (7, 9, 11), (16, 16, 16), (5, 20, 33)]):
+        labels = random_labels(shape, 3, seed=40 + i)
+        dw = 0.05 + 0.03 * i
+        out.append(
+            {
+                "labels": labels,
+                "class_D": (0.0, dw, dw / 10),
+                "rho": 0.01 + 0.01 * i,
+                "u0": random_field(shape, seed=50 + i) * (labels != 0),
+            }
+        )
+    return out
+
+
+def oracle_run(inst, tau, nsteps, key="f64"):
+    op = oop.Operator(1.0, labels=inst["labels"], class_D=inst["class_D"])
+    s, m = oplan.for_dtype(tau * op.norm1(), key)
+    return oit.advance(op, inst["u0"], inst["rho"], tau, s, m, nsteps), (s, m)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-5)])
+def test_small_batch_vs_oracle(native, dtype, tol):
+    from paper_2402_02273_amd.expint import ExpIntBatch
+
+    insts = small_instances()
+    tau, K = 7.3, 3
+    print(f"[case] small batch {dtype}", flush=True)
+    b = ExpIntBatch(insts, tau=tau, dtype=dtype, device=DEV)
+    us = [dev(i["u0"], dtype) for i in insts]
+    b.advance(us, 2)  # records the graph
+    b.advance(us, 1)  # replays it
+    key = "f64" if dtype == torch.float64 else "f32"
+    for i, inst in enumerate(insts):
+        ref, sm = oracle_run(inst, tau, K)
+        p = b.plan(i)
+        assert (p.s, p.m) == oplan.for_dtype(tau * oop.Operator(1.0, labels=inst["labels"], class_D=inst["class_D"]).norm1(), key)
+        assert rel(us[i].cpu().numpy(), ref) < tol, i
+
+
+def test_batch_matches_single_contexts(native):
+    from paper_2402_02273_amd.expint import ExpInt, ExpIntBatch
+
+    insts = small_instances()
+    for dtype in (torch.float64, torch.float32):
+        b = ExpIntBatch(insts, tau=7.3, dtype=dtype, device=DEV)
+        us = [dev(i["u0"], dtype) for i in insts]
+        b.advance(us, 3)
+        for i, inst in enumerate(insts):
+            c = ExpInt(inst["labels"].shape, labels=inst["labels"], class_D=inst["class_D"], rho=inst["rho"], tau=7.3,
+                       dtype=dtype, device=DEV)
+            u = dev(inst["u0"], dtype)
+            c.advance(u, 3)
+            torch.cuda.synchronize()
+            # same arithmetic per voxel; the two kernels may contract FMAs differently
+            tol = 1e-13 if dtype == torch.float64 else 2e-6
+            assert float((u - us[i]).abs().max()) <= tol * float(u.abs().max()), (dtype, i)
+
+
+def test_c3_full_batch(native):
+    """All 64 scenarios of the batched workload, 50 steps, FP32: plans match the
+    oracle rule, every instance matches a single-grid context, and the three
+    smallest instances match the FP64 oracle over the full 50 steps."""
+    from paper_2402_02273_amd.expint import ExpInt, ExpIntBatch
+
+    insts, nsteps = c3_batch()
+    print(f"[case] c3 batch: {len(insts)} instances, sizes {sorted(set(i.n for i in insts))}", flush=True)
+    dicts = [{"labels": i.labels, "class_D": i.class_D, "rho": i.rho} for i in insts]
+    b = ExpIntBatch(dicts, tau=7.3, dtype=torch.float32, device=DEV)
+    us = [dev(i.u0, torch.float32) for i in insts]
+    b.advance(us, nsteps)
+    torch.cuda.synchronize()
+    for i, inst in enumerate(insts):
+        op = oop.Operator(1.0, labels=inst.labels, class_D=inst.class_D)
+        p = b.plan(i)
+        assert (p.s, p.m) == oplan.for_dtype(7.3 * op.norm1(), "f32"), i
+        got = us[i].cpu().numpy()
+        assert got.min() >= -1e-6 and got.max() <= 1 + 1e-6
+    for i in range(0, 64, 8):
+        inst = insts[i]
+        c = ExpInt(inst.labels.shape, labels=inst.labels, class_D=inst.class_D, rho=inst.rho, tau=7.3,
+                   dtype=torch.float32, device=DEV)
+        u = dev(inst.u0, torch.float32)
+        c.advance(u, nsteps)
+        torch.cuda.synchronize()
+        assert float((u - us[i]).abs().max()) <= 1e-5 * float(u.abs().max()), i
+    small = sorted(range(len(insts)), key=lambda i: insts[i].n)[:3]
+    for i in small:
+        inst = insts[i]
+        ref, _ = oracle_run({"labels": inst.labels, "class_D": inst.class_D, "rho": inst.rho, "u0": inst.u0}, 7.3, nsteps)
+        err = rel(us[i].cpu().numpy(), ref)
+        print(f"[result] c3 instance {i} ({inst.n}^3): rel-L2 vs oracle {err:.2e}", flush=True)
+        assert err < 1e-5
