@@ -206,12 +206,13 @@ void expint_batch_destroy(expint_batch* batch);
  * blocking stream the context created when opts.stream was NULL. */
 int expint_get_stream(const expint_ctx* ctx, void** stream);
 
-/* Times `reps` back-to-back launches of one sweep of this context's step
- * schedule with HIP events on the context stream and writes the mean
- * milliseconds per launch: kernel 0 = Taylor term that adds a pair of terms
- * to the running sum (reads the source, the sum; writes the term, the sum),
- * 1 = Taylor term that only writes its term, 2 = right-hand side
- * A u + rho u (1 - u).  Uses only the context workspace; synchronises. */
+/* Times `reps` back-to-back launches of one kernel of this context's step
+ * with HIP events on the context stream and writes the mean milliseconds per
+ * launch: kernel 0 = Taylor term that adds a pair of terms to the running sum
+ * (reads the source, the sum; writes the term, the sum), 1 = Taylor term that
+ * only writes its term, 2 = right-hand side A u + rho u (1 - u); modal
+ * contexts also 3 = mode product along x (left GEMM shape), 4 = mode product
+ * along z (right GEMM shape).  Uses only the context workspace; synchronises. */
 int expint_profile(expint_ctx* ctx, int32_t kernel, int32_t reps, double* ms);
 
 /* Message for the last failed call on this thread ("" if none). */

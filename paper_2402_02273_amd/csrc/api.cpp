@@ -17,6 +17,7 @@
 #include "internal.hpp"
 #include "plan.hpp"
 #include "autotune.hpp"
+#include "modal.hpp"
 #include "schedule.hpp"
 
 using namespace expint;
@@ -173,6 +174,7 @@ StepBuffers step_buffers(expint_ctx* c) {
 // Launches of one step on c->stream (no synchronisation).
 int enqueue_step(expint_ctx* c, void* u) {
   HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, c->tiling, c->coef(), u, c->b, c->rho, c->stream));
+  if (c->algo == EXPINT_ALGO_MODAL) return modal_phi1(c, c->b, u, true);
   const auto ops = phi1_schedule(step_buffers(c), c->s, c->m, c->tau, c->b, nullptr, u);
   return run_ops(c, ops);
 }
@@ -245,8 +247,15 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
       if (!finite_nonneg(df->class_D[a])) return set_error(EXPINT_EINVAL, "class_D[%d] must be finite and >= 0", a);
   }
   const expint_algo algo = opts->algo == EXPINT_ALGO_AUTO ? EXPINT_ALGO_STENCIL_TAYLOR : opts->algo;
-  if (algo == EXPINT_ALGO_MODAL || opts->mp != EXPINT_MP_NONE)
-    return set_error(EXPINT_EUNSUPPORTED, "the modal path is not available in this build");
+  if (opts->mp != EXPINT_MP_NONE && algo != EXPINT_ALGO_MODAL)
+    return set_error(EXPINT_EUNSUPPORTED, "split matrix-core products belong to the modal algorithm");
+  if (opts->mp != EXPINT_MP_NONE && opts->dtype == EXPINT_F64)
+    return set_error(EXPINT_EUNSUPPORTED, "split matrix-core products are for FP32 contexts");
+  if (algo == EXPINT_ALGO_MODAL) {
+    if (!df->labels) return set_error(EXPINT_EUNSUPPORTED, "the modal path needs the label form of D");
+    if (grid->nx % 32 || grid->ny % 32 || grid->nz % 32)
+      return set_error(EXPINT_EUNSUPPORTED, "the modal path needs every grid dimension to be a multiple of 32");
+  }
 
   expint_ctx* c = new (std::nothrow) expint_ctx();
   if (!c) return set_error(EXPINT_ENOMEM, "host allocation failed");
@@ -355,6 +364,7 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
       return bail(set_error(EXPINT_EHIP, "autotune failed: %s", hipGetErrorString(e)));
     }
   }
+  if (c->algo == EXPINT_ALGO_MODAL && (rc = modal_setup(c))) return bail(rc);
   if (std::getenv("EXPINT_LOG"))
     std::fprintf(stderr, "[expint] grid %dx%dx%d h=%g dtype=%s ||A||_1=%.17g nu=%.6g plan s=%d m=%d workspace %zu B\n",
                  c->g.nx, c->g.ny, c->g.nz, c->h, c->dtype == EXPINT_F64 ? "f64" : "f32", c->norm1,
@@ -433,6 +443,7 @@ int expint_phi1(expint_ctx* c, const void* b, void* x) {
   if (b == x) return set_error(EXPINT_EINVAL, "b and x must not overlap");
   int rc = ensure_device(c);
   if (rc) return rc;
+  if (c->algo == EXPINT_ALGO_MODAL) return modal_phi1(c, b, x, false);
   const auto ops = phi1_schedule(step_buffers(c), c->s, c->m, c->tau, b, x, nullptr);
   return run_ops(c, ops);
 }
@@ -509,7 +520,9 @@ int expint_reduce(expint_ctx* c, int32_t op, const void* x, const void* y, doubl
 int expint_profile(expint_ctx* c, int32_t kernel, int32_t reps, double* ms) {
   CHECK_CTX(c);
   if (reps < 1 || !ms) return set_error(EXPINT_EINVAL, "reps must be >= 1 and ms non-NULL");
-  if (kernel < 0 || kernel > 2) return set_error(EXPINT_EINVAL, "kernel id must be 0, 1 or 2");
+  if (kernel < 0 || kernel > 4) return set_error(EXPINT_EINVAL, "kernel id must be in 0..4");
+  if (kernel >= 3 && c->algo != EXPINT_ALGO_MODAL)
+    return set_error(EXPINT_EINVAL, "kernel ids 3 and 4 time the modal path's mode products");
   int rc = ensure_device(c);
   if (rc) return rc;
   // The sweeps of the step schedule, on the context workspace:
@@ -527,7 +540,23 @@ int expint_profile(expint_ctx* c, int32_t kernel, int32_t reps, double* ms) {
   }
   classify_term(op);
   const Coef cf = c->coef();
+  ModalArgs ma;
+  if (kernel >= 3) {
+    ma.q = c->modal.q[kernel == 3 ? 0 : 2][0];
+    ma.in = c->acc[1];
+    ma.out = c->y[1];
+    if (kernel == 3) {  // x axis: left product over (1, nx, ny*nz)
+      ma.pre = 1;
+      ma.n = c->g.nx;
+      ma.post = static_cast<long>(c->g.ny) * c->g.nz;
+    } else {  // z axis: right product over (nx*ny, nz)
+      ma.pre = c->g.nx * c->g.ny;
+      ma.n = c->g.nz;
+      ma.post = 1;
+    }
+  }
   auto launch = [&]() -> hipError_t {
+    if (kernel >= 3) return launch_mode_product(c->modal.prec, kernel == 3 ? 0 : 1, kEpiStore, ma, c->stream);
     if (kernel == 2) return launch_rhs(c->dtype, c->bc, c->g, c->tiling, cf, c->acc[1], c->b, c->rho, c->stream);
     return launch_term(c->dtype, c->bc, c->g, c->tiling, cf, op, c->stream);
   };

@@ -101,6 +101,15 @@ struct expint_ctx {
 
   expint::Tiling tiling;  // launch shape of the stencil sweeps (autotuned)
 
+  // modal path (uniform D): per-axis operators and eigenvalues, two scratch fields
+  struct Modal {
+    int prec = 0;                       // ModalPrec
+    double Dc = 0.0;                    // the uniform diffusivity
+    void* q[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};  // [axis][fwd, inv]
+    double* lam[3] = {nullptr, nullptr, nullptr};
+    void* t[2] = {nullptr, nullptr};
+  } modal;
+
   // adjoint workspace: allocated on the first gradient call, regrown on demand
   struct Adj {
     std::vector<void*> ckpt;  // u every ckpt_every steps
@@ -149,5 +158,8 @@ int upload_tables(expint_ctx* c);
 int enqueue_step(expint_ctx* c, void* u);
 int run_ops(expint_ctx* c, const std::vector<TermOp>& ops);
 int check_finite_field(expint_ctx* c, const void* u);
+// modal path (modal_host.cpp)
+int modal_setup(expint_ctx* c);
+int modal_phi1(expint_ctx* c, const void* b, void* out, bool add_into_out);
 
 }  // namespace expint

@@ -268,9 +268,10 @@ class ExpInt:
         """Mean ms per launch of one sweep of the step schedule.
 
         kernel: "flush" (Taylor term adding a pair of terms to the running sum),
-        "skip" (Taylor term writing only its term) or "rhs"."""
+        "skip" (Taylor term writing only its term), "rhs", or for modal
+        contexts "mode_x" / "mode_z" (one mode product along x / z)."""
         ms = ctypes.c_double()
-        kid = {"flush": 0, "skip": 1, "rhs": 2}[kernel]
+        kid = {"flush": 0, "skip": 1, "rhs": 2, "mode_x": 3, "mode_z": 4}[kernel]
         N.check(self.lib.expint_profile(self._ctx, kid, int(reps), ctypes.byref(ms)))
         return ms.value
 

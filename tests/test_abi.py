@@ -86,11 +86,14 @@ def test_create_rejects_bad_class_D_and_rho():
     assert _create(None, df)[0] == N.EINVAL
 
 
-def test_modal_request_is_reported():
-    grid = N.Grid(4, 4, 4, 1.0)
+def test_unsupported_modal_requests_rejected_before_hip():
     df, cd = _labels_df()
-    rc, _ = _create(grid, df, algo=N.ALGO_MODAL, mp=N.MP_BF16_SPLIT, dtype=N.F64)
-    assert rc in (N.EUNSUPPORTED, N.EINVAL)
+    rc, _ = _create(N.Grid(32, 32, 32, 1.0), df, algo=N.ALGO_MODAL, mp=N.MP_BF16_SPLIT, dtype=N.F64)
+    assert rc == N.EUNSUPPORTED and "FP32" in N.last_error()
+    rc, _ = _create(N.Grid(32, 32, 40, 1.0), df, algo=N.ALGO_MODAL)
+    assert rc == N.EUNSUPPORTED and "multiple of 32" in N.last_error()
+    rc, _ = _create(N.Grid(32, 32, 32, 1.0), df, mp=N.MP_FP16_SPLIT)
+    assert rc == N.EUNSUPPORTED and "modal" in N.last_error()
 
 
 def test_null_context_calls():
