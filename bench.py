@@ -119,24 +119,7 @@ def cpu_baseline(w, nsteps):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--n", type=int, default=128)
-    ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
-    ap.add_argument("--cpu-steps", type=int, default=8)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(
-            "bench.py measures one GPU only: this build runs the step on a single MI355X "
-            "(multi-GPU sharding is a design note, not built); use --gpus 1",
-            file=sys.stderr,
-        )
-        sys.exit(2)
-
+def run_c2(args):
     import numpy as np
     import torch
 
@@ -239,6 +222,237 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out), flush=True)
+
+
+def _timed(fn, sync):
+    import torch
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1)
+
+
+def run_c3(args):
+    """64 heads of sizes {48, 64, 96, 128}^3 with their own plans, FP32, one graph per step."""
+    import torch
+
+    from paper_2402_02273_amd.expint import ExpIntBatch
+    from workloads import c3_batch
+
+    insts, nsteps = c3_batch()
+    steps = args.steps if args.steps_given else nsteps
+    dicts = [{"labels": i.labels, "class_D": i.class_D, "rho": i.rho} for i in insts]
+    b = ExpIntBatch(dicts, tau=7.3, dtype=torch.float32, device="cuda:0")
+    u0 = [torch.as_tensor(i.u0, dtype=torch.float32, device="cuda:0").contiguous() for i in insts]
+    us = [u.clone() for u in u0]
+    if args.warmup > 0:
+        b.advance(us, args.warmup)
+    for u, v in zip(us, u0):
+        u.copy_(v)
+    ms = _timed(lambda: b.advance(us, steps), None)
+    vox = sum(int(i.labels.size) for i in insts)
+    plans = b.plans
+    step_bytes = sum(step_bytes_per_voxel(4, p.s, p.m)[0] * int(i.labels.size) for p, i in zip(plans, insts))
+    achieved = step_bytes * steps / (ms * 1e-3) / 1e9
+    out = {
+        "metric": "voxel-updates/s, 64 batched scenarios (sum of N^3 x steps / time)",
+        "value": vox * steps / (ms * 1e-3),
+        "unit": "voxel-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "64 synthetic heads, N in {48,64,96,128}, rho~U[0.01,0.05], D_w~U[0.05,0.2], D_g=D_w/10, "
+            "tau 7.3 d, one HIP graph per step",
+            "voxels": vox,
+            "terms_per_step": [min(p.s * p.m for p in plans), max(p.s * p.m for p in plans)],
+            "launches_per_step": 1 + max(step_bytes_per_voxel(4, p.s, p.m)[1] - 1 for p in plans),
+        },
+        "roofline": {
+            "kernel": "k_batch (all batched sweeps of the step)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_step": step_bytes,
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_c4(args):
+    """Gradient of 0.5||u_T - target||^2 on the 96^3 head, 50 steps, checkpoints every 10."""
+    import numpy as np
+    import torch
+
+    from paper_2402_02273_amd.expint import ExpInt
+    from workloads import c4_adjoint
+    from workloads.configs import c4_synthetic_target
+
+    w, _ = c4_adjoint()
+    target = c4_synthetic_target()
+    dt = torch.float32 if args.dtype == "f32" else torch.float64
+    ctx = ExpInt(w.shape, labels=w.labels, class_D=w.class_D, rho=w.rho, tau=w.tau, dtype=dt, device="cuda:0")
+    u0 = torch.as_tensor(w.u0, dtype=dt, device="cuda:0").contiguous()
+    tg = torch.as_tensor(target, dtype=dt, device="cuda:0").contiguous()
+    ctx.grad(u0, w.nsteps, tg, ckpt_every=10)
+    res = {}
+
+    def go():
+        res["g"] = ctx.grad(u0, w.nsteps, tg, ckpt_every=10)
+
+    ms = _timed(go, None)
+    errs = None
+    gpath = os.path.join(ROOT, "tests", "golden", "c4_adjoint_96_k50_f64.npz")
+    if os.path.exists(gpath):
+        g = np.load(gpath)
+        loss, gu, grho, gD = res["g"]
+        errs = {
+            "loss": abs(loss - float(g["loss"])) / float(g["loss"]),
+            "grad_u0_relL2": float(np.linalg.norm(gu.double().cpu().numpy() - g["grad_u0"]) / np.linalg.norm(g["grad_u0"])),
+            "grad_rho": abs(grho - float(g["grad_rho"])) / abs(float(g["grad_rho"])),
+            "grad_D": [abs(gD[c] - float(g["grad_D"][c])) / max(abs(float(v)) for v in g["grad_D"]) for c in range(3)],
+        }
+    out = {
+        "metric": "forward-equivalent voxel-steps/s of a full gradient (96^3, 50 steps)",
+        "value": w.nvox * w.nsteps / (ms * 1e-3),
+        "unit": "voxel-steps/s",
+        "n_gpus": 1,
+        "steps": w.nsteps,
+        "warmup": 1,
+        "ms_per_step": ms / w.nsteps,
+        "ms_per_gradient": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": "96^3 head seed 2404, gradient wrt u0, rho, D per class, ckpt 10", "plan": [ctx.plan.s, ctx.plan.m]},
+        "errors_vs_oracle": errs,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_c5(args):
+    """256^3 uniform D: modal path in FP32 / bf16 split / fp16 split against FP64,
+    and the FP32 stencil-Taylor form, 100 steps each."""
+    import numpy as np
+    import torch
+
+    from paper_2402_02273_amd.expint import ExpInt
+    from workloads import c5_separable
+
+    w = c5_separable()
+    steps = args.steps if args.steps_given else w.nsteps
+    n = w.shape[0]
+    u0d = torch.as_tensor(w.u0, dtype=torch.float64, device="cuda:0").contiguous()
+    rows = {}
+    ref = None
+    for name, dt, algo, mp in (
+        ("modal_f64", torch.float64, "modal", "none"),
+        ("modal_f32", torch.float32, "modal", "none"),
+        ("modal_bf16_split", torch.float32, "modal", "bf16_split"),
+        ("modal_fp16_split", torch.float32, "modal", "fp16_split"),
+        ("stencil_taylor_f32", torch.float32, "stencil_taylor", "none"),
+    ):
+        ctx = ExpInt(w.shape, labels=w.labels, class_D=w.class_D, rho=w.rho, tau=w.tau, dtype=dt, algo=algo, mp=mp,
+                     device="cuda:0")
+        u = u0d.to(dt).clone()
+        ctx.advance(u, 2)
+        u.copy_(u0d.to(dt))
+        ms = _timed(lambda: ctx.advance(u, steps), None)
+        got = u.double().cpu().numpy()
+        if ref is None:
+            ref = got
+        row = {"ms_per_step": ms / steps, "voxel_updates_per_s": w.nvox * steps / (ms * 1e-3),
+               "rel_l2_vs_modal_f64": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
+        if algo == "modal":
+            flop = 2.0 * n * w.nvox  # one mode product, algorithmic
+            ms_x = ctx.profile("mode_x", reps=20)
+            ms_z = ctx.profile("mode_z", reps=20)
+            byts = 2.0 * w.nvox * (8 if dt == torch.float64 else 4)
+            execd = {"none": 1, "bf16_split": 3, "fp16_split": 3}[mp]
+            row["mode_product_x"] = {"ms": ms_x, "alg_TFLOPs": flop / (ms_x * 1e-3) / 1e12,
+                                     "executed_TFLOPs": execd * flop / (ms_x * 1e-3) / 1e12,
+                                     "GBs": byts / (ms_x * 1e-3) / 1e9}
+            row["mode_product_z"] = {"ms": ms_z, "alg_TFLOPs": flop / (ms_z * 1e-3) / 1e12,
+                                     "executed_TFLOPs": execd * flop / (ms_z * 1e-3) / 1e12,
+                                     "GBs": byts / (ms_z * 1e-3) / 1e9}
+        else:
+            row["plan_s_m"] = [ctx.plan.s, ctx.plan.m]
+        rows[name] = row
+        ctx.close()
+    peaks = {"modal_f64": 78.6, "modal_f32": 157.3, "modal_bf16_split": 2500.0, "modal_fp16_split": 2500.0}
+    best = rows["modal_bf16_split"]
+    x = best["mode_product_x"]
+    out = {
+        "metric": "voxel-updates/s at 256^3 uniform D (modal mode products), error per dtype vs FP64",
+        "value": best["voxel_updates_per_s"],
+        "unit": "voxel-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 2,
+        "ms_per_step": best["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16 split (fp32 accumulate)",
+        "data": "synthetic",
+        "config": {"workload": "256^3 uniform D=0.1, no-flux, rho 0.025, tau 7.3 d, Gaussian blob"},
+        "roofline": {
+            "kernel": "k_mode bf16 split, x axis",
+            "bound": "mfma",
+            "achieved": x["executed_TFLOPs"],
+            "peak": peaks["modal_bf16_split"],
+            "unit": "TFLOP/s",
+            "frac": x["executed_TFLOPs"] / peaks["modal_bf16_split"],
+            "traffic": None,
+            "hbm_GBs": x["GBs"],
+            "hbm_frac": x["GBs"] / HBM_PEAK_GBS,
+        },
+        "variants": rows,
+        "speedup_bf16_split_over_f32_modal": rows["modal_f32"]["ms_per_step"] / rows["modal_bf16_split"]["ms_per_step"],
+        "speedup_fp16_split_over_f32_modal": rows["modal_f32"]["ms_per_step"] / rows["modal_fp16_split"]["ms_per_step"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2",
+                    help="c2: 128^3 head (default, the headline); c3: 64 batched heads; c4: gradient; c5: 256^3 modal")
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(
+            "bench.py measures one GPU only: this build runs the step on a single MI355X "
+            "(multi-GPU sharding is a design note, not built); use --gpus 1",
+            file=sys.stderr,
+        )
+        sys.exit(2)
+    args.steps_given = args.steps is not None
+    if args.steps is None:
+        args.steps = 100
+    {"c2": run_c2, "c3": run_c3, "c4": run_c4, "c5": run_c5}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -81,13 +81,29 @@ __global__ __launch_bounds__(kBlock) void k_faceprod(Geom g, const uint8_t* __re
   }
 }
 
-// acc[c] += weight * sum over workgroups of partial[b][c], in workgroup order.
-__global__ void k_faceprod_final(const double* __restrict__ partial, int nb, double weight, double* __restrict__ acc) {
-  const int c = threadIdx.x;
-  if (c >= kMaxClasses) return;
-  double v = 0.0;
-  for (int b = 0; b < nb; ++b) v += partial[b * kMaxClasses + c];
-  acc[c] += weight * v;
+// acc[c] += weight * sum over workgroups of partial[b][c].  Thread t sums the
+// partials b = t, t + 256, ... of every class, then a fixed-order tree over
+// the 256 threads: the combination order never changes (bit-reproducible).
+__global__ __launch_bounds__(kBlock) void k_faceprod_final(const double* __restrict__ partial, int nb, double weight,
+                                                           double* __restrict__ acc) {
+  __shared__ double red[kBlock][kMaxClasses + 1];
+  const int t = threadIdx.x;
+  double v[kMaxClasses];
+#pragma unroll
+  for (int c = 0; c < kMaxClasses; ++c) v[c] = 0.0;
+  for (int b = t; b < nb; b += kBlock)
+#pragma unroll
+    for (int c = 0; c < kMaxClasses; ++c) v[c] += partial[b * kMaxClasses + c];
+#pragma unroll
+  for (int c = 0; c < kMaxClasses; ++c) red[t][c] = v[c];
+  __syncthreads();
+  for (int half = kBlock / 2; half > 0; half >>= 1) {
+    if (t < half)
+#pragma unroll
+      for (int c = 0; c < kMaxClasses; ++c) red[t][c] += red[t + half][c];
+    __syncthreads();
+  }
+  if (t < kMaxClasses) acc[t] += weight * red[0][t];
 }
 
 }  // namespace
@@ -107,7 +123,7 @@ hipError_t launch_faceprod(expint_dtype dt, expint_bc bc, const Geom& g, const u
     if (bc == EXPINT_NOFLUX) k_faceprod<float, 0><<<grid, block, 0, st>>>(g, labels, nclass, dtab, dwall, a, b, partial);
     else k_faceprod<float, 1><<<grid, block, 0, st>>>(g, labels, nclass, dtab, dwall, a, b, partial);
   }
-  k_faceprod_final<<<1, 64, 0, st>>>(partial, kReduceBlocks, weight, acc);
+  k_faceprod_final<<<1, kBlock, 0, st>>>(partial, kReduceBlocks, weight, acc);
   return hipGetLastError();
 }
 

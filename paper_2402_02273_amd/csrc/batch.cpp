@@ -4,7 +4,8 @@
 // shape (autotuned per grid size) and workspace.  One step of the batch is
 // a sequence of launches: launch 0 computes every instance's right-hand side,
 // launch t >= 1 runs Taylor sweep t of every instance that has one (their
-// schedules have different lengths).  The sequence is recorded once as a HIP
+// schedules have different lengths), split into one kernel launch per term
+// flavour and plane count.  The sequence is recorded once as a HIP
 // graph for a given set of state pointers and replayed per step.
 
 #include <hip/hip_runtime.h>
@@ -43,6 +44,7 @@ struct Inst {
   void* wallc = nullptr;
   Tiling tiling;
   StepBuffers ws;
+  std::vector<double> tab_host;  // class table (64) + wall table (8), FP64
   Coef coef() const {
     Coef c{};
     c.labels_form = true;
@@ -54,8 +56,9 @@ struct Inst {
 };
 
 struct Launch {
-  int offset, nops, total, grid;
+  int offset, nitems, total, grid;
   bool rhs;
+  int flavor, lp;
 };
 
 }  // namespace
@@ -69,13 +72,13 @@ struct expint_batch {
   bool own_stream = false;
   Arena arena;
   std::vector<Inst> inst;
-  BatchInst* d_insts = nullptr;
   double* partial = nullptr;
   double* red = nullptr;
   // schedule recorded for one set of state pointers
   std::vector<const void*> key;
-  BatchOp* d_ops = nullptr;
-  size_t ops_cap = 0;
+  BatchItem* d_items = nullptr;
+  void* d_tables = nullptr;
+  size_t items_cap = 0;
   std::vector<Launch> launches;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -118,6 +121,8 @@ int setup_instance(expint_batch* b, Inst& in, const uint8_t* labels_src) {
     w64[a] = in.class_D[a] * inv_h2;
     for (int c = 0; c < in.nclass; ++c) t64[a * kMaxClasses + c] = harmonic_mean(in.class_D[a], in.class_D[c]) * inv_h2;
   }
+  in.tab_host.assign(t64, t64 + kTab);
+  in.tab_host.insert(in.tab_host.end(), w64, w64 + kMaxClasses);
   for (int i = 0; i < kTab; ++i) t32[i] = static_cast<float>(t64[i]);
   for (int i = 0; i < kMaxClasses; ++i) w32[i] = static_cast<float>(w64[i]);
   BHIP(hipMemcpyAsync(in.tab64, t64, sizeof(t64), hipMemcpyHostToDevice, b->stream));
@@ -151,54 +156,112 @@ int build_schedule(expint_batch* b, void* const* u) {
   destroy_graph(b);
   const int count = static_cast<int>(b->inst.size());
   std::vector<std::vector<TermOp>> per(count);
-  size_t maxlen = 0;
   for (int i = 0; i < count; ++i) {
     Inst& in = b->inst[i];
     per[i] = phi1_schedule(in.ws, in.s, in.m, b->tau, in.ws.b, nullptr, u[i]);
-    maxlen = std::max(maxlen, per[i].size());
   }
-  // instances ordered by tile count, largest first
+  // instances ordered by tile count, largest first, then packed greedily into
+  // groups whose working set (u, b, two term buffers, two running sums,
+  // labels) fits the byte budget: a group runs its whole step before the
+  // next, so its fields stay in the Infinity Cache across the step's sweeps.
   std::vector<int> order(count);
   for (int i = 0; i < count; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int c) {
-                     return sweep_blocks(b->inst[a].g, b->inst[a].tiling) > sweep_blocks(b->inst[c].g, b->inst[c].tiling);
-                   });
-  std::vector<BatchOp> ops;
-  b->launches.clear();
-  for (size_t t = 0; t <= maxlen; ++t) {
-    Launch L{static_cast<int>(ops.size()), 0, 0, 0, t == 0};
-    for (int i : order) {
-      if (t > 0 && per[i].size() < t) continue;
-      BatchOp bo{};
-      bo.inst = i;
-      bo.block_start = L.total;
-      if (t == 0) {
-        bo.op.src = u[i];
-        bo.op.y_out = b->inst[i].ws.b;
-      } else {
-        bo.op = per[i][t - 1];
-      }
-      ops.push_back(bo);
-      L.total += static_cast<int>(sweep_blocks(b->inst[i].g, b->inst[i].tiling));
-      ++L.nops;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+    return sweep_blocks(b->inst[a].g, b->inst[a].tiling) > sweep_blocks(b->inst[c].g, b->inst[c].tiling);
+  });
+  const size_t w = dtype_size(b->dtype);
+  size_t budget = static_cast<size_t>(224) << 20;
+  if (const char* env = std::getenv("EXPINT_BATCH_GROUP_BYTES")) budget = std::strtoull(env, nullptr, 10);
+  std::vector<std::vector<int>> groups;
+  size_t used = 0;
+  for (int i : order) {
+    const size_t ws = static_cast<size_t>(b->inst[i].g.n) * (6 * w + 1);
+    if (groups.empty() || (used + ws > budget && !groups.back().empty())) {
+      groups.emplace_back();
+      used = 0;
     }
-    L.grid = std::min(L.total, kMaxGrid);
-    if (L.nops > 0) b->launches.push_back(L);
+    groups.back().push_back(i);
+    used += ws;
   }
-  if (ops.size() > b->ops_cap) {
-    b->arena.release(b->d_ops);
-    b->d_ops = nullptr;
-    int rc = b->arena.alloc(reinterpret_cast<void**>(&b->d_ops), ops.size() * sizeof(BatchOp));
+  std::vector<BatchItem> items;
+  std::vector<double> tabs;  // per item: class table + wall table
+  b->launches.clear();
+  for (const std::vector<int>& grp : groups) {
+  size_t gmax = 0;
+  for (int i : grp) gmax = std::max(gmax, per[i].size());
+  for (size_t t = 0; t <= gmax; ++t) {
+    // the ops of position t, grouped by (flavour, lp), at most kBatchMaxOps
+    // per launch
+    for (int fl = kGeneric; fl <= kFirst; ++fl) {
+      for (int lp : {1, 2, 4}) {
+        Launch L{static_cast<int>(items.size()), 0, 0, 0, t == 0, fl, lp};
+        auto close = [&]() {
+          L.grid = std::min(L.total, kMaxGrid);
+          if (L.nitems > 0) b->launches.push_back(L);
+          L = Launch{static_cast<int>(items.size()), 0, 0, 0, t == 0, fl, lp};
+        };
+        for (int i : grp) {
+          const Inst& in = b->inst[i];
+          if (in.tiling.lp != lp) continue;
+          if (t == 0) {
+            if (fl != kGeneric) continue;
+          } else {
+            if (per[i].size() < t || per[i][t - 1].flavor != fl) continue;
+          }
+          if (L.nitems == kBatchMaxOps) close();
+          BatchItem it{};
+          it.block_start = L.total;
+          it.nx = in.g.nx;
+          it.ny = in.g.ny;
+          it.nz = in.g.nz;
+          it.bx = in.tiling.bx;
+          it.by = in.tiling.by;
+          it.bx_log2 = it.bx == 64 ? 6 : (it.bx == 32 ? 5 : 4);
+          it.gx = (in.g.nz + it.bx - 1) / it.bx;
+          it.gy = (in.g.ny + it.by - 1) / it.by;
+          it.labels = in.labels;
+          it.rho = in.rho;
+          if (t == 0) {
+            it.op.src = u[i];
+            it.op.y_out = in.ws.b;
+          } else {
+            it.op = per[i][t - 1];
+          }
+          items.push_back(it);
+          tabs.insert(tabs.end(), in.tab_host.begin(), in.tab_host.end());
+          L.total += static_cast<int>(sweep_blocks(in.g, in.tiling));
+          ++L.nitems;
+        }
+        close();
+      }
+    }
+  }
+  }
+  if (items.size() > b->items_cap) {
+    b->arena.release(b->d_items);
+    b->arena.release(b->d_tables);
+    b->d_items = nullptr;
+    b->d_tables = nullptr;
+    int rc = b->arena.alloc(reinterpret_cast<void**>(&b->d_items), items.size() * sizeof(BatchItem));
+    if (!rc) rc = b->arena.alloc(&b->d_tables, items.size() * (kTab + kMaxClasses) * w);
     if (rc) return rc;
-    b->ops_cap = ops.size();
+    b->items_cap = items.size();
   }
-  BHIP(hipMemcpyAsync(b->d_ops, ops.data(), ops.size() * sizeof(BatchOp), hipMemcpyHostToDevice, b->stream));
+  std::vector<float> tabs32;
+  const void* tsrc = tabs.data();
+  if (b->dtype == EXPINT_F32) {
+    tabs32.assign(tabs.begin(), tabs.end());
+    tsrc = tabs32.data();
+  }
+  BHIP(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice, b->stream));
+  BHIP(hipMemcpyAsync(b->d_tables, tsrc, tabs.size() * w, hipMemcpyHostToDevice, b->stream));
   BHIP(hipStreamSynchronize(b->stream));
   BHIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   hipError_t err = hipSuccess;
   for (const Launch& L : b->launches) {
-    err = launch_batch(b->dtype, b->bc, L.rhs, b->d_insts, b->d_ops + L.offset, L.nops, L.total, L.grid, b->stream);
+    const void* tb = static_cast<const char*>(b->d_tables) + static_cast<size_t>(L.offset) * (kTab + kMaxClasses) * w;
+    err = launch_batch(b->dtype, b->bc, L.rhs, L.flavor, L.lp, b->d_items + L.offset, tb, L.nitems, L.total, L.grid,
+                       b->stream);
     if (err != hipSuccess) break;
   }
   hipGraph_t gr = nullptr;
@@ -287,7 +350,6 @@ int expint_batch_create(int32_t count, const expint_grid* grids, const expint_df
   int rc;
   if ((rc = b->arena.alloc(reinterpret_cast<void**>(&b->partial), 2 * max_parts * sizeof(double)))) return bail(rc);
   if ((rc = b->arena.alloc(reinterpret_cast<void**>(&b->red), 2 * sizeof(double)))) return bail(rc);
-  std::vector<BatchInst> hi(count);
   for (int i = 0; i < count; ++i) {
     Inst& in = b->inst[i];
     if ((rc = setup_instance(b, in, dfields[i].labels))) return bail(rc);
@@ -297,23 +359,6 @@ int expint_batch_create(int32_t count, const expint_grid* grids, const expint_df
     } else if (!choose_plan(b->tau * in.norm1, tol, theta_max, &in.s, &in.m)) {
       return bail(set_error(EXPINT_EINVAL, "instance %d: no admissible plan", i));
     }
-    BatchInst& d = hi[i];
-    d.g = in.g;
-    d.bx = in.tiling.bx;
-    d.by = in.tiling.by;
-    d.lp = in.tiling.lp;
-    d.gx = (in.g.nz + d.bx - 1) / d.bx;
-    d.gy = (in.g.ny + d.by - 1) / d.by;
-    d.nblocks = static_cast<int>(sweep_blocks(in.g, in.tiling));
-    d.coef = in.coef();
-    d.rho = in.rho;
-  }
-  if ((rc = b->arena.alloc(reinterpret_cast<void**>(&b->d_insts), count * sizeof(BatchInst)))) return bail(rc);
-  if (hipMemcpyAsync(b->d_insts, hi.data(), count * sizeof(BatchInst), hipMemcpyHostToDevice, b->stream) !=
-          hipSuccess ||
-      hipStreamSynchronize(b->stream) != hipSuccess) {
-    (void)hipGetLastError();
-    return bail(set_error(EXPINT_EHIP, "instance table upload failed"));
   }
   if (std::getenv("EXPINT_LOG")) {
     int64_t vox = 0;

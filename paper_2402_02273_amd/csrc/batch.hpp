@@ -5,25 +5,26 @@
 
 namespace expint {
 
-// One instance of a batch, as the batched kernel sees it.
-struct BatchInst {
-  Geom g;
-  int bx, by, lp;  // tile: bx (z) x by (y) threads, lp x-planes per thread
-  int gx, gy;      // tiles along z and y
-  int nblocks;     // tiles of one sweep
-  Coef coef;       // label form
-  double rho;
-};
+constexpr int kBatchMaxOps = 64;  // ops per batched launch (the host splits larger ones)
 
-// One sweep of one instance inside a launch.  For a right-hand-side launch,
-// op.src is u and op.y_out is b.
-struct BatchOp {
-  int inst;
-  int block_start;  // offset of this instance's tiles in the launch's work list
+// One sweep of one instance inside a launch, with everything the kernel
+// needs about that instance.  For a right-hand-side launch, op.src is u and
+// op.y_out is b.
+struct BatchItem {
+  int block_start;      // offset of this instance's tiles in the launch's work list
+  int nx, ny, nz;
+  int gx, gy, by;       // tiles along z and y; threads along y
+  int bx, bx_log2;      // threads along z (16, 32 or 64)
+  const uint8_t* labels;
+  double rho;
   TermOp op;
 };
 
-hipError_t launch_batch(expint_dtype dt, expint_bc bc, bool rhs, const BatchInst* insts, const BatchOp* ops, int nops,
-                        int total_blocks, int grid, hipStream_t st);
+// One launch over items[0 .. nitems) (nitems <= kBatchMaxOps): all of them
+// right-hand sides (rhs) or all Taylor terms of the given flavour; every
+// instance involved uses lp planes per thread.  tables: per item the class
+// table (64 values) followed by the wall table (8 values), in the dtype.
+hipError_t launch_batch(expint_dtype dt, expint_bc bc, bool rhs, int flavor, int lp, const BatchItem* items,
+                        const void* tables, int nitems, int total_blocks, int grid, hipStream_t st);
 
 }  // namespace expint
