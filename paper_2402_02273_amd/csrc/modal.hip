@@ -25,6 +25,8 @@
 
 #include "modal.hpp"
 
+#include <cstdlib>
+
 namespace expint {
 
 namespace {
@@ -259,8 +261,245 @@ __global__ __launch_bounds__(256) void k_mode(ModalArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-core strip kernels (split precisions).  One wavefront owns a whole
+// output strip and streams its operands straight from memory into MFMA
+// fragments; no LDS, no workgroup barriers.
+//   left  (x, y axes): strip = all n output modes x 32 columns q of one p;
+//                      the field column block B_p[:, q0 .. q0+32) is read once.
+//   right (z axis):    strip = 32 rows p x all n output modes; the field rows
+//                      are read once.
+// The per-axis operator (n x n hi + lo, <= 256 KB at n = 256) is re-read from
+// L2 by every wavefront.  MT output tiles of 32 are held at once (2, 4 or 8;
+// fp16 needs a second accumulator for its scaled cross terms); larger n loops
+// over blocks of MT tiles, re-reading the field block.
+// Fragment layouts of v_mfma_f32_32x32x16_{bf16,f16} (checked on the device):
+// A row = lane % 32, B column = lane % 32, k = 8 * (lane / 32) + element;
+// D[row][col] with col = lane % 32, row = 8 (r / 4) + 4 (lane / 32) + r % 4.
+// ---------------------------------------------------------------------------
+
+template <int PREC>
+struct Frag;
+template <>
+struct Frag<kPrecBF16> {
+  using V = bf16x8;
+  static __device__ __forceinline__ f32x16 mma(V a, V b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Frag<kPrecF16> {
+  using V = f16x8;
+  static __device__ __forceinline__ f32x16 mma(V a, V b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <int PREC>
+__device__ __forceinline__ void split8(const float (&v)[8], typename Frag<PREC>::V& hi, typename Frag<PREC>::V& lo) {
+  using E = typename Elem<PREC>::E;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    E h, l;
+    split<PREC>(v[e], h, l);
+    hi[e] = h;
+    lo[e] = l;
+  }
+}
+
+template <int PREC, int EPI, int MT>
+__global__ __launch_bounds__(256) void k_mode_left_mfma(ModalArgs a) {
+  using E = typename Elem<PREC>::E;
+  using V = typename Frag<PREC>::V;
+  constexpr bool two_acc = PREC == kPrecF16;
+  const float* __restrict__ in = static_cast<const float*>(a.in);
+  float* __restrict__ out = static_cast<float*>(a.out);
+  const E* __restrict__ qhi = static_cast<const E*>(a.q);
+  const int n = a.n;
+  const long post = a.post;
+  const long nn = static_cast<long>(n) * n;
+  const E* __restrict__ qlo = qhi + nn;
+  const int lane = threadIdx.x & 63;
+  const long strips_per_p = (post + 31) / 32;
+  const long strip = static_cast<long>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (strip >= strips_per_p * a.pre) return;  // whole wavefront
+  const int p = static_cast<int>(strip / strips_per_p);
+  const long q0 = (strip % strips_per_p) * 32;
+  const long col = q0 + (lane & 31);
+  const bool col_ok = col < post;
+  const float* __restrict__ inp = in + static_cast<long>(p) * n * post;
+  const int kh = (lane >> 5) * 8;
+  for (int mb = 0; mb < n; mb += MT * 32) {
+    f32x16 acc[MT], accx[two_acc ? MT : 1];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      acc[t] = f32x16{};
+      if (two_acc) accx[two_acc ? t : 0] = f32x16{};
+    }
+    // the field fragment of the next K step is loaded before the current
+    // step's matrix-core work (one step of register double buffering)
+    float bnext[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) bnext[e] = col_ok ? inp[static_cast<long>(kh + e) * post + col] : 0.f;
+    for (int k0 = 0; k0 < n; k0 += 16) {
+      float bv[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) bv[e] = bnext[e];
+      if (k0 + 16 < n) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bnext[e] = col_ok ? inp[static_cast<long>(k0 + 16 + kh + e) * post + col] : 0.f;
+      }
+      V bh, bl;
+      split8<PREC>(bv, bh, bl);
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        const int m = mb + t * 32 + (lane & 31);
+        if (mb + t * 32 < n) {
+          const long off = static_cast<long>(m) * n + k0 + kh;
+          const V ah = *reinterpret_cast<const V*>(qhi + off);
+          const V al = *reinterpret_cast<const V*>(qlo + off);
+          acc[t] = Frag<PREC>::mma(ah, bh, acc[t]);
+          if (two_acc) {
+            accx[two_acc ? t : 0] = Frag<PREC>::mma(ah, bl, accx[two_acc ? t : 0]);
+            accx[two_acc ? t : 0] = Frag<PREC>::mma(al, bh, accx[two_acc ? t : 0]);
+          } else {
+            acc[t] = Frag<PREC>::mma(ah, bl, acc[t]);
+            acc[t] = Frag<PREC>::mma(al, bh, acc[t]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      if (mb + t * 32 >= n || !col_ok) continue;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = mb + t * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        float v = acc[t][r];
+        if (two_acc) v += accx[two_acc ? t : 0][r] * (1.0f / kF16LoScale);
+        if (EPI == kEpiMul) {
+          const int jj = static_cast<int>(col / a.nz), kk = static_cast<int>(col % a.nz);
+          const float z = static_cast<float>(a.tauD * (a.lam_x[m] + a.lam_y[jj] + a.lam_z[kk]));
+          v *= phi1_times_tau(z, static_cast<float>(a.tau));
+        }
+        out[static_cast<long>(p) * n * post + static_cast<long>(m) * post + col] = v;
+      }
+    }
+  }
+}
+
+template <int PREC, int EPI, int NT>
+__global__ __launch_bounds__(256) void k_mode_right_mfma(ModalArgs a) {
+  using E = typename Elem<PREC>::E;
+  using V = typename Frag<PREC>::V;
+  constexpr bool two_acc = PREC == kPrecF16;
+  const float* __restrict__ in = static_cast<const float*>(a.in);
+  float* __restrict__ out = static_cast<float*>(a.out);
+  const E* __restrict__ qhi = static_cast<const E*>(a.q);
+  const int n = a.n, pre = a.pre;
+  const E* __restrict__ qlo = qhi + static_cast<long>(n) * n;
+  const int lane = threadIdx.x & 63;
+  const long strip = static_cast<long>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const long strips = (pre + 31) / 32;
+  if (strip >= strips) return;  // whole wavefront
+  const long p0 = strip * 32;
+  const long prow = p0 + (lane & 31);
+  const bool row_ok = prow < pre;
+  const float* __restrict__ inrow = in + (row_ok ? prow : p0) * n;
+  const int kh = (lane >> 5) * 8;
+  for (int nb = 0; nb < n; nb += NT * 32) {
+    f32x16 acc[NT], accx[two_acc ? NT : 1];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      acc[t] = f32x16{};
+      if (two_acc) accx[two_acc ? t : 0] = f32x16{};
+    }
+    float4 n0 = *reinterpret_cast<const float4*>(inrow + kh);
+    float4 n1 = *reinterpret_cast<const float4*>(inrow + kh + 4);
+    for (int k0 = 0; k0 < n; k0 += 16) {
+      float av[8];
+      const float4 v0 = n0, v1 = n1;
+      if (k0 + 16 < n) {  // next K step's field fragment, ahead of the matrix-core work
+        n0 = *reinterpret_cast<const float4*>(inrow + k0 + 16 + kh);
+        n1 = *reinterpret_cast<const float4*>(inrow + k0 + 16 + kh + 4);
+      }
+      av[0] = v0.x; av[1] = v0.y; av[2] = v0.z; av[3] = v0.w;
+      av[4] = v1.x; av[5] = v1.y; av[6] = v1.z; av[7] = v1.w;
+      if (!row_ok)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) av[e] = 0.f;
+      V ah, al;
+      split8<PREC>(av, ah, al);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        if (nb + t * 32 < n) {
+          const long off = static_cast<long>(nb + t * 32 + (lane & 31)) * n + k0 + kh;
+          const V bh = *reinterpret_cast<const V*>(qhi + off);
+          const V bl = *reinterpret_cast<const V*>(qlo + off);
+          acc[t] = Frag<PREC>::mma(ah, bh, acc[t]);
+          if (two_acc) {
+            accx[two_acc ? t : 0] = Frag<PREC>::mma(ah, bl, accx[two_acc ? t : 0]);
+            accx[two_acc ? t : 0] = Frag<PREC>::mma(al, bh, accx[two_acc ? t : 0]);
+          } else {
+            acc[t] = Frag<PREC>::mma(ah, bl, acc[t]);
+            acc[t] = Frag<PREC>::mma(al, bh, acc[t]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (nb + t * 32 >= n) continue;
+      const int colk = nb + t * 32 + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const long row = p0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (row >= pre) continue;
+        float v = acc[t][r];
+        if (two_acc) v += accx[two_acc ? t : 0][r] * (1.0f / kF16LoScale);
+        const long idx = row * n + colk;
+        if (EPI == kEpiAddU) out[idx] = out[idx] + v;
+        else out[idx] = v;
+      }
+    }
+  }
+}
+
+// Output tiles held per wavefront: fewer tiles, fewer accumulator registers,
+// more wavefronts in flight (the field block is then re-read from L2).
+int modal_tiles() {
+  static const int t = [] {
+    const char* e = std::getenv("EXPINT_MODAL_TILES");
+    const int v = e ? std::atoi(e) : 4;
+    return (v == 2 || v == 4 || v == 8) ? v : 4;
+  }();
+  return t;
+}
+
+template <int PREC, int SIDE, int EPI, int T>
+void launch_mode_mfma_t(const ModalArgs& a, hipStream_t st) {
+  long strips;
+  if (SIDE == 0) strips = static_cast<long>(a.pre) * ((a.post + 31) / 32);
+  else strips = (static_cast<long>(a.pre) + 31) / 32;
+  const dim3 grid(static_cast<unsigned>((strips + 3) / 4)), block(256);
+  if (SIDE == 0) k_mode_left_mfma<PREC, EPI, T><<<grid, block, 0, st>>>(a);
+  else k_mode_right_mfma<PREC, EPI, T><<<grid, block, 0, st>>>(a);
+}
+
+template <int PREC, int SIDE, int EPI>
+void launch_mode_mfma(const ModalArgs& a, hipStream_t st) {
+  const int t = modal_tiles();
+  if (t == 2) launch_mode_mfma_t<PREC, SIDE, EPI, 2>(a, st);
+  else if (t == 8 && PREC == kPrecBF16) launch_mode_mfma_t<PREC, SIDE, EPI, 8>(a, st);
+  else launch_mode_mfma_t<PREC, SIDE, EPI, 4>(a, st);
+}
+
 template <int PREC, int SIDE, int EPI>
 void launch_mode_t(const ModalArgs& a, hipStream_t st) {
+  if constexpr (is_split<PREC>()) {
+    launch_mode_mfma<PREC, SIDE, EPI>(a, st);
+    return;
+  }
   long tiles;
   if (SIDE == 0) tiles = static_cast<long>(a.pre) * ((a.n + TM - 1) / TM) * ((a.post + TN - 1) / TN);
   else tiles = static_cast<long>((a.pre + TM - 1) / TM) * ((a.n + TN - 1) / TN);
