@@ -3,15 +3,18 @@
 Workload: the 128^3 synthetic head (seed 2402; white / gray matter D = 0.13 /
 0.013 mm^2/day, CSF and outside D = 0, no-flux box), rho = 0.025/day,
 tau = 7.3 days, FP32 stencil-Taylor.  A "step" is one full exponential Euler
-step (right-hand side, s*m fused Taylor-term sweeps, update of u).  The
+step (right-hand side, the s*m Taylor terms in sweeps of one or two terms
+each, update of u).  The
 timed region runs --steps steps from u0 with all inputs resident in HBM; with
 --steps 100 (the default, the two-year run) the result is also compared with
 the stored FP64 oracle result (rel-L2).
 
 Prints one JSON line.  Extra objects:
-  roofline     - the dominant kernel (the fused Taylor-term sweep): algorithmic
-                 bytes per launch over its mean launch time (HIP events on the
-                 library stream), against the 8 TB/s HBM peak;
+  roofline     - the dominant kernel (the pair sweep, or with single-term
+                 sweeps the term sweep that adds two terms to the running
+                 sum): algorithmic bytes per launch over its mean launch time
+                 (HIP events on the library stream), against the 8 TB/s HBM
+                 peak;
   step_rates   - the same bytes model over the whole timed step;
   cpu_baseline - the FP64 oracle on a bounded sample (a few steps of the same
                  workload) on the host cores.
@@ -42,6 +45,8 @@ def sweep_bytes(w, reads=(), writes=()):
 FLUSH_BYTES = lambda w: sweep_bytes(w, reads=("acc",), writes=("y", "acc"))  # noqa: E731
 SKIP_BYTES = lambda w: sweep_bytes(w, writes=("y",))  # noqa: E731
 RHS_BYTES = lambda w: sweep_bytes(w, writes=("b",))  # noqa: E731
+# pair sweep inside a sub-step: source, labels, running sum in; second term and sum out
+PAIR_BYTES = lambda w: sweep_bytes(w, reads=("acc",), writes=("y", "acc"))  # noqa: E731
 
 
 def step_bytes_per_voxel(w, s, m):
@@ -84,6 +89,28 @@ def step_bytes_per_voxel(w, s, m):
     for r, wr in ops:
         total += sweep_bytes(w, r, wr)
     return total, len(ops) + 1
+
+
+def step_bytes_per_voxel_pairs(w, s, m):
+    """The same for the pair schedule (m >= 2): per sub-step the Taylor terms
+    two at a time, (1, 2), (3, 4), ... ((2, 3), (4, 5), ... in sub-step 1,
+    whose term 1 is h b), the first of each pair kept on chip; a term left
+    over at the end is a single-term sweep.  Each sweep reads its source and
+    the labels; the first sweep of sub-steps 2.. also reads b, later ones the
+    running sum; every sweep writes the sum and, unless it ends the sub-step,
+    its second term; the last sweep of the step reads and writes u instead of
+    storing the sum."""
+    ops = []
+    for sig in range(s):
+        j, first = (2 if sig == 0 else 1), True
+        while j <= m:
+            reads = ("b",) if (first and sig > 0) else (() if first else ("acc",))
+            nxt = j + (2 if j < m else 1)
+            ops.append((reads, ("acc",) + (("y",) if nxt <= m else ())))
+            first, j = False, nxt
+    r, _ = ops[-1]
+    ops[-1] = (r + ("u",), ("u",))
+    return RHS_BYTES(w) + sum(sweep_bytes(w, r, wr) for r, wr in ops), len(ops) + 1
 
 
 def load_traffic(kernel_key):
@@ -130,8 +157,12 @@ def run_c2(args):
     dtype = torch.float32 if args.dtype == "f32" else torch.float64
     w_bytes = 4 if args.dtype == "f32" else 8
     w = c2_head(n=args.n)
-    ctx = ExpInt(w.shape, w.h, labels=w.labels, class_D=w.class_D, rho=w.rho, tau=w.tau, dtype=dtype, device=dev)
+    ctx = ExpInt(w.shape, w.h, labels=w.labels, class_D=w.class_D, rho=w.rho, tau=w.tau, dtype=dtype, device=dev,
+                 sweeps=args.sweeps)
     plan = ctx.plan
+    sweeps, ptiling = ctx.sweeps()
+    launch = ctx.launch_info()
+    pairs = sweeps == "pairs" and plan.m >= 2
     u0 = torch.as_tensor(w.u0, dtype=dtype, device=dev).contiguous()
     u = u0.clone()
 
@@ -163,15 +194,27 @@ def run_c2(args):
             got = u.double().cpu().numpy()
             rel = float(np.linalg.norm(got - g["u"]) / np.linalg.norm(g["u"]))
 
-    # dominant kernel: the Taylor-term sweep that adds a pair of terms to the
-    # running sum; mean launch time from HIP events on the library stream
+    # dominant kernel: the pair sweep inside a sub-step (two Taylor terms,
+    # both added to the running sum), or with single-term sweeps the term that
+    # adds a pair of terms to the running sum; mean launch time from HIP
+    # events on the library stream
     ms_flush = ctx.profile("flush", reps=200)
     ms_skip = ctx.profile("skip", reps=200)
     ms_rhs = ctx.profile("rhs", reps=200)
-    tb = FLUSH_BYTES(w_bytes) * w.nvox
-    achieved = tb / (ms_flush * 1e-3) / 1e9
-    traffic = load_traffic(f"flush_{args.dtype}_{args.n}")
-    sbv, nlaunch = step_bytes_per_voxel(w_bytes, plan.s, plan.m)
+    ms_pair = ctx.profile("pair", reps=200) if pairs else None
+    if pairs:
+        kname = f"k_pair (two Taylor terms per sweep, stencil twice + running sum), ty={ptiling[0]} lp={ptiling[1]}"
+        tb = PAIR_BYTES(w_bytes) * w.nvox
+        ms_dom = ms_pair
+        traffic = load_traffic(f"pair_{args.dtype}_{args.n}")
+        sbv, nlaunch = step_bytes_per_voxel_pairs(w_bytes, plan.s, plan.m)
+    else:
+        kname = "k_sweep term, pair-flush flavour (stencil + Taylor term + running sum)"
+        tb = FLUSH_BYTES(w_bytes) * w.nvox
+        ms_dom = ms_flush
+        traffic = load_traffic(f"flush_{args.dtype}_{args.n}")
+        sbv, nlaunch = step_bytes_per_voxel(w_bytes, plan.s, plan.m)
+    achieved = tb / (ms_dom * 1e-3) / 1e9
     sb = sbv * w.nvox
     sweep_model = 4 * w_bytes + LABEL_BYTES  # one read/write of y and the sum per term
     out = {
@@ -196,7 +239,7 @@ def run_c2(args):
         },
         "rel_l2_vs_oracle": rel,
         "roofline": {
-            "kernel": "k_sweep term, pair-flush flavour (stencil + Taylor term + running sum)",
+            "kernel": kname,
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
@@ -204,7 +247,7 @@ def run_c2(args):
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "bytes_per_launch": tb,
-            "ms_per_launch": ms_flush,
+            "ms_per_launch": ms_dom,
         },
         "step_rates": {
             "algorithmic_bytes_per_step": sb,
@@ -213,6 +256,9 @@ def run_c2(args):
             "sweep_model_bytes_per_step": (RHS_BYTES(w_bytes) + (plan.s * plan.m - 1) * sweep_model) * w.nvox,
             "sweep_model_frac_of_hbm_peak": (RHS_BYTES(w_bytes) + (plan.s * plan.m - 1) * sweep_model)
             * w.nvox / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "sweeps": sweeps,
+            "launch": launch,
+            "ms_flush_per_launch": ms_flush,
             "ms_skip_per_launch": ms_skip,
             "ms_rhs_per_launch": ms_rhs,
             "launches_per_step": nlaunch,
@@ -440,6 +486,8 @@ def main():
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
     ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--sweeps", choices=["auto", "single", "pairs"], default="auto",
+                    help="Taylor terms per stencil sweep (auto: timed at context creation)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -78,6 +78,19 @@ typedef enum {
   EXPINT_MP_FP16_SPLIT = 2
 } expint_mp;
 
+/* How the stencil-Taylor path groups the Taylor terms of a sub-step into
+ * sweeps over the grid.  SINGLE: one sweep per term.  PAIRS: two consecutive
+ * terms per sweep, the first kept on chip (label form only, else
+ * EXPINT_EUNSUPPORTED; grids whose x-planes hold 4 GiB or more of field data
+ * fall back to SINGLE).  AUTO: times both at creation and keeps the faster
+ * (PAIRS only where PAIRS applies).  Same polynomial either way; results
+ * agree to rounding.  expint_get_launch reports the choice. */
+typedef enum {
+  EXPINT_SWEEPS_AUTO = 0,
+  EXPINT_SWEEPS_SINGLE = 1,
+  EXPINT_SWEEPS_PAIRS = 2
+} expint_sweeps;
+
 typedef struct {
   int32_t nx, ny, nz; /* voxels per axis, each >= 1 */
   double h;           /* grid spacing (> 0), same unit as sqrt(D * time) */
@@ -106,13 +119,14 @@ typedef struct {
   expint_mp mp;
   int32_t s, m;         /* both > 0: use this plan; both 0: choose it */
   int32_t check_finite; /* nonzero: expint_step / expint_advance scan u for NaN/Inf */
+  expint_sweeps sweeps; /* term grouping of the stencil-Taylor sweeps */
   void* stream;         /* hipStream_t the context works on; NULL = null stream */
 } expint_opts;
 
 typedef struct expint_ctx expint_ctx;
 
-/* Fill *opts with defaults: F32, tau = 7.3, automatic plan, AUTO, no check,
- * null stream.  Returns EXPINT_EINVAL for NULL. */
+/* Fill *opts with defaults: F32, tau = 7.3, automatic plan, AUTO algorithm,
+ * AUTO sweeps, no check, null stream.  Returns EXPINT_EINVAL for NULL. */
 int expint_opts_default(expint_opts* opts);
 
 /* Create a context for one grid, diffusivity field, rho and boundary.
@@ -133,6 +147,20 @@ void expint_destroy(expint_ctx* ctx);
 
 /* The plan in use: Taylor scaling s, degree m and ||A||_1 (host scalars). */
 int expint_get_plan(const expint_ctx* ctx, int32_t* s, int32_t* m, double* norm_A1);
+
+/* Launch configuration the context resolved at creation (autotuned). */
+typedef struct {
+  expint_sweeps sweeps; /* EXPINT_SWEEPS_SINGLE or EXPINT_SWEEPS_PAIRS (modal: SINGLE) */
+  int32_t pair_ty;      /* pair sweeps: output rows along y per workgroup (0 if SINGLE) */
+  int32_t pair_lp;      /* pair sweeps: x-planes per workgroup (0 if SINGLE) */
+  int32_t vec;          /* single-term sweeps: 1 = z-vectorised (4 voxels per lane) */
+  int32_t bx, by;       /* scalar sweep: threads along z and y (0 if vec) */
+  int32_t rw;           /* vectorised sweep: lanes per z-segment (0 if scalar) */
+  int32_t lp;           /* single-term sweeps: x-planes per thread */
+} expint_launch_info;
+
+/* The context's launch configuration.  EXPINT_EINVAL for NULL arguments. */
+int expint_get_launch(const expint_ctx* ctx, expint_launch_info* info);
 
 /* Replace rho and (label form) the class diffusivities.  replan != 0
  * recomputes ||A||_1 and (s, m) unless the plan was fixed in the options;
@@ -212,7 +240,10 @@ int expint_get_stream(const expint_ctx* ctx, void** stream);
  * (reads the source, the sum; writes the term, the sum), 1 = Taylor term that
  * only writes its term, 2 = right-hand side A u + rho u (1 - u); modal
  * contexts also 3 = mode product along x (left GEMM shape), 4 = mode product
- * along z (right GEMM shape).  Uses only the context workspace; synchronises. */
+ * along z (right GEMM shape); contexts that take their Taylor terms two at a
+ * time (pair sweeps, label form) also 5 = pair sweep inside a sub-step (reads
+ * the source, the sum; writes the second term, the sum), else
+ * EXPINT_EUNSUPPORTED.  Uses only the context workspace; synchronises. */
 int expint_profile(expint_ctx* ctx, int32_t kernel, int32_t reps, double* ms);
 
 /* Message for the last failed call on this thread ("" if none). */

@@ -35,6 +35,7 @@ F64, F32 = 0, 1
 NOFLUX, DIRICHLET0 = 0, 1
 ALGO_AUTO, ALGO_STENCIL_TAYLOR, ALGO_MODAL = 0, 1, 2
 MP_NONE, MP_BF16_SPLIT, MP_FP16_SPLIT = 0, 1, 2
+SWEEPS_AUTO, SWEEPS_SINGLE, SWEEPS_PAIRS = 0, 1, 2
 MAX_CLASSES = 8
 
 
@@ -57,6 +58,19 @@ class DField(ctypes.Structure):
     ]
 
 
+class LaunchInfo(ctypes.Structure):
+    _fields_ = [
+        ("sweeps", ctypes.c_int),
+        ("pair_ty", ctypes.c_int32),
+        ("pair_lp", ctypes.c_int32),
+        ("vec", ctypes.c_int32),
+        ("bx", ctypes.c_int32),
+        ("by", ctypes.c_int32),
+        ("rw", ctypes.c_int32),
+        ("lp", ctypes.c_int32),
+    ]
+
+
 class Opts(ctypes.Structure):
     _fields_ = [
         ("dtype", ctypes.c_int),
@@ -68,6 +82,7 @@ class Opts(ctypes.Structure):
         ("s", ctypes.c_int32),
         ("m", ctypes.c_int32),
         ("check_finite", ctypes.c_int32),
+        ("sweeps", ctypes.c_int),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -87,6 +102,7 @@ SIGNATURES = {
     ),
     "expint_destroy": (None, [_P]),
     "expint_get_plan": (_I, [_P, _I32P, _I32P, _DP]),
+    "expint_get_launch": (_I, [_P, ctypes.POINTER(LaunchInfo)]),
     "expint_set_params": (_I, [_P, _D, _DP, _I32]),
     "expint_apply": (_I, [_P, _P, _P]),
     "expint_rhs": (_I, [_P, _P, _P]),

@@ -157,7 +157,10 @@ int make_plan(expint_ctx* c) {
 
 int run_ops(expint_ctx* c, const std::vector<TermOp>& ops) {
   const Coef cf = c->coef();
-  for (const TermOp& op : ops) HIP_TRY(c, launch_term(c->dtype, c->bc, c->g, c->tiling, cf, op, c->stream));
+  for (const TermOp& op : ops) {
+    if (op.pair) HIP_TRY(c, launch_pair(c->dtype, c->bc, c->g, c->ptiling, cf, op, c->stream));
+    else HIP_TRY(c, launch_term(c->dtype, c->bc, c->g, c->tiling, cf, op, c->stream));
+  }
   return EXPINT_OK;
 }
 
@@ -171,12 +174,17 @@ StepBuffers step_buffers(expint_ctx* c) {
   return sb;
 }
 
+std::vector<TermOp> step_schedule(expint_ctx* c, const void* b, void* x_out, void* u) {
+  if (c->ptiling.ty != 0 && c->labels_form && c->m >= 2)
+    return phi1_schedule_pairs(step_buffers(c), c->s, c->m, c->tau, b, x_out, u);
+  return phi1_schedule(step_buffers(c), c->s, c->m, c->tau, b, x_out, u);
+}
+
 // Launches of one step on c->stream (no synchronisation).
 int enqueue_step(expint_ctx* c, void* u) {
   HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, c->tiling, c->coef(), u, c->b, c->rho, c->stream));
   if (c->algo == EXPINT_ALGO_MODAL) return modal_phi1(c, c->b, u, true);
-  const auto ops = phi1_schedule(step_buffers(c), c->s, c->m, c->tau, c->b, nullptr, u);
-  return run_ops(c, ops);
+  return run_ops(c, step_schedule(c, c->b, nullptr, u));
 }
 
 int check_finite_field(expint_ctx* c, const void* u) {
@@ -203,6 +211,8 @@ int validate_opts(const expint_opts* o) {
   if (o->m > kPlanMaxDegree) return set_error(EXPINT_EINVAL, "m must be <= %d", kPlanMaxDegree);
   if (o->algo < EXPINT_ALGO_AUTO || o->algo > EXPINT_ALGO_MODAL) return set_error(EXPINT_EINVAL, "unknown algo");
   if (o->mp < EXPINT_MP_NONE || o->mp > EXPINT_MP_FP16_SPLIT) return set_error(EXPINT_EINVAL, "unknown mp");
+  if (o->sweeps < EXPINT_SWEEPS_AUTO || o->sweeps > EXPINT_SWEEPS_PAIRS)
+    return set_error(EXPINT_EINVAL, "unknown sweeps");
   return EXPINT_OK;
 }
 
@@ -251,6 +261,8 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
     return set_error(EXPINT_EUNSUPPORTED, "split matrix-core products belong to the modal algorithm");
   if (opts->mp != EXPINT_MP_NONE && opts->dtype == EXPINT_F64)
     return set_error(EXPINT_EUNSUPPORTED, "split matrix-core products are for FP32 contexts");
+  if (opts->sweeps == EXPINT_SWEEPS_PAIRS && !df->labels)
+    return set_error(EXPINT_EUNSUPPORTED, "pair sweeps need the label form of D");
   if (algo == EXPINT_ALGO_MODAL) {
     if (!df->labels) return set_error(EXPINT_EUNSUPPORTED, "the modal path needs the label form of D");
     if (grid->nx % 32 || grid->ny % 32 || grid->nz % 32)
@@ -358,10 +370,18 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
   }
   {
     const hipError_t e = autotune_sweep(c->dtype, c->bc, c->g, c->coef(), c->y[0], c->acc[0], c->y[1], c->stream,
-                                        &c->tiling);
+                                        true, &c->tiling);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return bail(set_error(EXPINT_EHIP, "autotune failed: %s", hipGetErrorString(e)));
+    }
+  }
+  if (c->algo != EXPINT_ALGO_MODAL) {
+    const hipError_t e = autotune_pairs(c->dtype, c->bc, c->g, c->coef(), c->y[0], c->acc[0], c->y[1], c->stream,
+                                        c->tiling, opts->sweeps, &c->ptiling);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return bail(set_error(EXPINT_EHIP, "pair-sweep autotune failed: %s", hipGetErrorString(e)));
     }
   }
   if (c->algo == EXPINT_ALGO_MODAL && (rc = modal_setup(c))) return bail(rc);
@@ -391,6 +411,20 @@ int expint_get_plan(const expint_ctx* c, int32_t* s, int32_t* m, double* norm1) 
   if (s) *s = c->s;
   if (m) *m = c->m;
   if (norm1) *norm1 = c->norm1;
+  return EXPINT_OK;
+}
+
+int expint_get_launch(const expint_ctx* c, expint_launch_info* info) {
+  if (!c || !info) return set_error(EXPINT_EINVAL, "NULL argument");
+  const bool pairs = c->ptiling.ty != 0;
+  info->sweeps = pairs ? EXPINT_SWEEPS_PAIRS : EXPINT_SWEEPS_SINGLE;
+  info->pair_ty = pairs ? c->ptiling.ty : 0;
+  info->pair_lp = pairs ? c->ptiling.lp : 0;
+  info->vec = c->tiling.vec ? 1 : 0;
+  info->bx = c->tiling.vec ? 0 : c->tiling.bx;
+  info->by = c->tiling.vec ? 0 : c->tiling.by;
+  info->rw = c->tiling.vec ? c->tiling.rw : 0;
+  info->lp = c->tiling.lp;
   return EXPINT_OK;
 }
 
@@ -444,8 +478,7 @@ int expint_phi1(expint_ctx* c, const void* b, void* x) {
   int rc = ensure_device(c);
   if (rc) return rc;
   if (c->algo == EXPINT_ALGO_MODAL) return modal_phi1(c, b, x, false);
-  const auto ops = phi1_schedule(step_buffers(c), c->s, c->m, c->tau, b, x, nullptr);
-  return run_ops(c, ops);
+  return run_ops(c, step_schedule(c, b, x, nullptr));
 }
 
 int expint_step(expint_ctx* c, void* u) {
@@ -520,28 +553,38 @@ int expint_reduce(expint_ctx* c, int32_t op, const void* x, const void* y, doubl
 int expint_profile(expint_ctx* c, int32_t kernel, int32_t reps, double* ms) {
   CHECK_CTX(c);
   if (reps < 1 || !ms) return set_error(EXPINT_EINVAL, "reps must be >= 1 and ms non-NULL");
-  if (kernel < 0 || kernel > 4) return set_error(EXPINT_EINVAL, "kernel id must be in 0..4");
-  if (kernel >= 3 && c->algo != EXPINT_ALGO_MODAL)
+  if (kernel < 0 || kernel > 5) return set_error(EXPINT_EINVAL, "kernel id must be in 0..5");
+  if ((kernel == 3 || kernel == 4) && c->algo != EXPINT_ALGO_MODAL)
     return set_error(EXPINT_EINVAL, "kernel ids 3 and 4 time the modal path's mode products");
+  if (kernel == 5 && c->ptiling.ty == 0)
+    return set_error(EXPINT_EUNSUPPORTED, "this context does not use pair sweeps");
   int rc = ensure_device(c);
   if (rc) return rc;
   // The sweeps of the step schedule, on the context workspace:
   // 0 = pair-flush term (src y0, running sum updated in place, y1 written),
-  // 1 = skip term (src y0, y1 written), 2 = right-hand side (u = acc1, b).
+  // 1 = skip term (src y0, y1 written), 2 = right-hand side (u = acc1, b),
+  // 5 = pair sweep inside a sub-step (src y0, two terms added to the running
+  // sum in place, the second term written to y1).
   TermOp op;
   op.src = c->y[0];
   op.c = c->tau / c->s / 2.0;
   op.y_out = c->y[1];
-  if (kernel == 0) {
+  if (kernel == 0 || kernel == 5) {
     op.acc_in = c->acc[0];
     op.ca = 1.0;
-    op.cs = 1.0;
+    op.cs = kernel == 0 ? 1.0 : 0.0;
     op.acc_out = c->acc[0];
   }
-  classify_term(op);
+  if (kernel == 5) {
+    op.pair = 1;
+    op.c2 = c->tau / c->s / 3.0;
+  } else {
+    classify_term(op);
+  }
   const Coef cf = c->coef();
   ModalArgs ma;
-  if (kernel >= 3) {
+  const bool mode = kernel == 3 || kernel == 4;
+  if (mode) {
     ma.q = c->modal.q[kernel == 3 ? 0 : 2][0];
     ma.in = c->acc[1];
     ma.out = c->y[1];
@@ -556,8 +599,9 @@ int expint_profile(expint_ctx* c, int32_t kernel, int32_t reps, double* ms) {
     }
   }
   auto launch = [&]() -> hipError_t {
-    if (kernel >= 3) return launch_mode_product(c->modal.prec, kernel == 3 ? 0 : 1, kEpiStore, ma, c->stream);
+    if (mode) return launch_mode_product(c->modal.prec, kernel == 3 ? 0 : 1, kEpiStore, ma, c->stream);
     if (kernel == 2) return launch_rhs(c->dtype, c->bc, c->g, c->tiling, cf, c->acc[1], c->b, c->rho, c->stream);
+    if (kernel == 5) return launch_pair(c->dtype, c->bc, c->g, c->ptiling, cf, op, c->stream);
     return launch_term(c->dtype, c->bc, c->g, c->tiling, cf, op, c->stream);
   };
   hipEvent_t e0, e1;

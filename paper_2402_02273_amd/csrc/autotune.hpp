@@ -7,12 +7,26 @@
 
 namespace expint {
 
-// Times every valid (bx, lp) tiling of the Taylor-term sweep for this grid,
-// dtype, boundary and coefficient form on `st`, using the three scratch fields
-// (each g.n values of dtype; their contents are overwritten), and returns the
-// fastest.  Results are cached per (grid, dtype, bc, form) for the process.
-// EXPINT_AUTOTUNE=0 in the environment skips the search (default_tiling).
+// Times every valid tiling of the Taylor-term sweep for this grid, dtype,
+// boundary and coefficient form on `st` -- (bx, lp) of the scalar sweep and,
+// if allow_vec and the grid qualifies, (rw, lp) of the z-vectorised sweep --
+// using the three scratch fields (each g.n values of dtype; their contents are
+// overwritten), and returns the fastest.  Results are cached per (grid, dtype,
+// bc, form, candidate set) for the process.  EXPINT_AUTOTUNE=0 in the
+// environment skips the search (default_tiling); EXPINT_TILE=scalar or vec
+// restricts the candidates to one sweep shape.
 hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Coef& cf, void* f0, void* f1, void* f2,
-                          hipStream_t st, Tiling* out);
+                          hipStream_t st, bool allow_vec, Tiling* out);
+
+// Decides whether the step takes its Taylor terms two at a time (pair
+// sweeps, label form only) and with which tiling.  mode SINGLE: never (ty = 0
+// in *out).  PAIRS: always, in the fastest pair tiling.  AUTO: times every
+// pair tiling against a single-term skip sweep plus a flush sweep in the
+// tiling `single` and keeps the pair sweeps if the fastest is quicker than
+// those two.  Dense-form coefficients always get ty = 0.  Cached per (grid,
+// dtype, bc, mode) for the process.  EXPINT_AUTOTUNE=0 in the environment
+// skips the timing: pairs (ty = 8, lp = 8) unless mode is SINGLE.
+hipError_t autotune_pairs(expint_dtype dt, expint_bc bc, const Geom& g, const Coef& cf, void* f0, void* f1, void* f2,
+                          hipStream_t st, const Tiling& single, expint_sweeps mode, PairTiling* out);
 
 }  // namespace expint

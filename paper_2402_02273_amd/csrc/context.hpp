@@ -100,6 +100,7 @@ struct expint_ctx {
   double* red = nullptr;      // 2 reduction results
 
   expint::Tiling tiling;  // launch shape of the stencil sweeps (autotuned)
+  expint::PairTiling ptiling;  // pair sweeps (two terms per sweep) if ptiling.ty != 0
 
   // modal path (uniform D): per-axis operators and eigenvalues, two scratch fields
   struct Modal {
@@ -157,6 +158,9 @@ int ensure_device(expint_ctx* c);
 int upload_tables(expint_ctx* c);
 int enqueue_step(expint_ctx* c, void* u);
 int run_ops(expint_ctx* c, const std::vector<TermOp>& ops);
+// The Taylor sweeps of tau phi1(tau A) b for this context's plan: pair sweeps
+// when the context uses them, else one sweep per term (see phi1_schedule).
+std::vector<TermOp> step_schedule(expint_ctx* c, const void* b, void* x_out, void* u);
 int check_finite_field(expint_ctx* c, const void* u);
 // modal path (modal_host.cpp)
 int modal_setup(expint_ctx* c);

@@ -15,6 +15,8 @@ constexpr int kTab = kMaxClasses * kMaxClasses;
 constexpr int kBlock = 256;        // threads per workgroup of the field kernels
 constexpr int kReduceBlocks = 1024;  // fixed partial count -> deterministic reductions
 
+inline constexpr int dtype_bytes(expint_dtype dt) { return dt == EXPINT_F64 ? 8 : 4; }
+
 struct Geom {
   int nx, ny, nz;
   int64_t n;
@@ -32,10 +34,16 @@ int64_t field_block_count(const Geom& g);
 
 // Tiling of the stencil sweeps: a workgroup of bx (z) x by (y) threads covers
 // a bx-by-by patch of lp consecutive x-planes; each thread marches through its
-// lp planes (1, 2 or 4) keeping the x-neighbours in registers.
+// lp planes (1, 2 or 4) keeping the x-neighbours in registers.  vec != 0
+// selects the z-vectorised sweep instead (label form, nz % 4 == 0): a lane
+// owns four consecutive z voxels, a 256-thread workgroup covers 256 / rw rows
+// of one z-segment of rw lanes (rw in 16, 32, 64) and lp x-planes.
 struct Tiling {
   int bx = 64, by = 4, lp = 4;
+  int vec = 0, rw = 64;
 };
+// Whether the z-vectorised sweep handles this grid and coefficient form.
+bool vec_sweep_ok(const Geom& g, bool labels_form);
 bool tiling_valid(const Tiling& t);
 int64_t sweep_blocks(const Geom& g, const Tiling& t);
 Tiling default_tiling(const Geom& g);
@@ -72,6 +80,15 @@ enum TermFlavor {
   kFirst = 4,     // y = c*a + cb*bsrc; acc_out = cs*src + y; y_out
 };
 
+//
+// A pair sweep (pair != 0, label form only) evaluates two consecutive terms:
+//   y   = c * A src + cb * bsrc                (term j, kept on chip)
+//   w   = c2 * A y                             (term j + 1)
+//   v   = ca * acc_in + cs * src + y + w
+//   u != NULL : u += v
+//   otherwise : y_out = w and acc_out = v      (each only if non-NULL)
+// A pair sweep reads src and bsrc around its tile, so neither may alias an
+// output of the same sweep.
 struct TermOp {
   const void* src = nullptr;
   const void* bsrc = nullptr;
@@ -80,12 +97,27 @@ struct TermOp {
   void* acc_out = nullptr;
   void* u = nullptr;
   double c = 0.0, cb = 0.0, ca = 0.0, cs = 0.0;
+  double c2 = 0.0;
   int flavor = kGeneric;
+  int pair = 0;
 };
 
 void classify_term(TermOp& op);
 
-// ---- launchers (stencil.hip) ----
+// Tiling of the pair sweeps: a workgroup of 256 threads covers 64 (z) x ty
+// (y) output columns of lp consecutive x-planes; ty == 0 means the pair
+// sweeps are not used (every term is its own sweep).
+struct PairTiling {
+  int ty = 0, lp = 8;
+};
+bool pair_tiling_valid(const PairTiling& t);
+// Whether pair sweeps handle this grid (an x-plane of fields below 4 GiB).
+bool pair_grid_ok(const Geom& g, expint_dtype dt);
+int64_t pair_blocks(const Geom& g, const PairTiling& t);
+
+// ---- launchers (stencil.hip, pair.hip) ----
+hipError_t launch_pair(expint_dtype dt, expint_bc bc, const Geom& g, const PairTiling& tl, const Coef& cf,
+                       const TermOp& op, hipStream_t st);
 hipError_t launch_term(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,
                        const TermOp& op, hipStream_t st);
 hipError_t launch_rhs(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf, const void* u,

@@ -509,6 +509,9 @@ void launch_mode_t(const ModalArgs& a, hipStream_t st) {
 }  // namespace
 
 hipError_t launch_mode_product(int prec, int side, int epi, const ModalArgs& a, hipStream_t st) {
+  if (!a.in || !a.out || !a.q || a.pre < 1 || a.n < 1 || a.post < 1) return hipErrorInvalidValue;
+  if (side == 1 && a.post != 1) return hipErrorInvalidValue;
+  if (epi == kEpiMul && (side != 0 || !a.lam_x || !a.lam_y || !a.lam_z)) return hipErrorInvalidValue;
 #define EXPINT_MODE_CASE(P)                                                         \
   case P:                                                                           \
     if (side == 0) {                                                                \

@@ -110,4 +110,65 @@ std::vector<TermOp> phi1_schedule(const StepBuffers& ws, int s, int m, double ta
   return ops;
 }
 
+std::vector<TermOp> phi1_schedule_pairs(const StepBuffers& ws, int s, int m, double tau, const void* b,
+                                        void* x_out, void* u) {
+  std::vector<TermOp> ops;
+  if (m < 2) return ops;
+  const double h = tau / s;
+  int xa = -1;  // the sub-step's start state x: -1 for x = 0, else ws.acc[xa]
+  for (int sig = 1; sig <= s; ++sig) {
+    const int out = xa < 0 ? 0 : 1 - xa;
+    void* A = ws.acc[out];  // running sum of this sub-step
+    int ycur = -1;          // ws.y[ycur] holds the term the next sweep starts from
+    bool first = true;
+    for (int j = xa < 0 ? 2 : 1; j <= m;) {
+      TermOp t;
+      if (first && xa < 0) {
+        // y_1 = h b is never stored: term 2 is (h^2/2) A b, the sum starts at h b
+        t.src = b;
+        t.c = h * h / 2.0;
+        t.cs = h;
+      } else if (first) {
+        // y_1 = h (A x + b), the sum starts at x
+        t.src = ws.acc[xa];
+        t.bsrc = b;
+        t.c = h;
+        t.cb = h;
+        t.cs = 1.0;
+      } else {
+        t.src = ws.y[ycur];
+        t.c = h / j;
+        t.acc_in = A;
+        t.ca = 1.0;
+      }
+      const bool two = j < m;
+      if (two) {
+        t.pair = 1;
+        t.c2 = h / (j + 1);
+      }
+      t.acc_out = A;
+      const int next = j + (two ? 2 : 1);
+      if (next <= m) {
+        ycur = ycur == 0 ? 1 : 0;
+        t.y_out = ws.y[ycur];
+      }
+      ops.push_back(t);
+      first = false;
+      j = next;
+    }
+    xa = out;
+  }
+  TermOp& last = ops.back();
+  last.y_out = nullptr;
+  if (u) {
+    last.u = u;
+    last.acc_out = nullptr;
+  } else {
+    last.acc_out = x_out;
+  }
+  for (TermOp& t : ops)
+    if (!t.pair) classify_term(t);
+  return ops;
+}
+
 }  // namespace expint

@@ -32,4 +32,12 @@ struct StepBuffers {
 std::vector<TermOp> phi1_schedule(const StepBuffers& ws, int s, int m, double tau, const void* b, void* x_out,
                                   void* u);
 
+// The same polynomial with the terms of every sub-step taken two at a time
+// by pair sweeps (TermOp::pair; label form, m >= 2): sub-step terms
+// (1, 2), (3, 4), ... (terms (2, 3), (4, 5), ... in sub-step 1, whose term 1
+// is h b), and a single-term sweep for a term left over at the end.  The
+// running sum gains two terms per sweep.
+std::vector<TermOp> phi1_schedule_pairs(const StepBuffers& ws, int s, int m, double tau, const void* b,
+                                        void* x_out, void* u);
+
 }  // namespace expint

@@ -26,10 +26,18 @@ Shape choose_shape(const Geom& g) {
 }
 
 bool tiling_valid(const Tiling& t) {
-  return (t.bx == 64 || t.bx == 32 || t.bx == 16) && t.by * t.bx == kBlock && (t.lp == 1 || t.lp == 2 || t.lp == 4);
+  const bool lp_ok = t.lp == 1 || t.lp == 2 || t.lp == 4;
+  if (t.vec) return (t.rw == 16 || t.rw == 32 || t.rw == 64) && lp_ok;
+  return (t.bx == 64 || t.bx == 32 || t.bx == 16) && t.by * t.bx == kBlock && lp_ok;
 }
 
+bool vec_sweep_ok(const Geom& g, bool labels_form) { return labels_form && g.nz % 4 == 0; }
+
 int64_t sweep_blocks(const Geom& g, const Tiling& t) {
+  if (t.vec) {
+    const int64_t nz4 = g.nz / 4, rows = kBlock / t.rw;
+    return ((nz4 + t.rw - 1) / t.rw) * ((g.ny + rows - 1) / rows) * ((g.nx + t.lp - 1) / t.lp);
+  }
   const int64_t gx = (g.nz + t.bx - 1) / t.bx, gy = (g.ny + t.by - 1) / t.by, gz = (g.nx + t.lp - 1) / t.lp;
   return gx * gy * gz;
 }
@@ -63,14 +71,6 @@ struct Vox {
   bool ok;
 };
 
-__device__ __forceinline__ int xcd_remap(int L, int nb) {
-  if ((nb & 7) == 0) {
-    const int per = nb >> 3;
-    return (L & 7) * per + (L >> 3);
-  }
-  return L;
-}
-
 __device__ __forceinline__ Vox voxel_of(const Geom& g, int gx, int gy) {
   const int L = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
   const int bxi = L % gx;
@@ -101,6 +101,26 @@ __global__ __launch_bounds__(kBlock) void k_sweep(Geom g, int gx, int gy, Coef c
   const int k = bxi * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x);
   if (j >= g.ny || k >= g.nz) return;
   sweep_column<T, BC, LP, KIND, FL>(g, cf, s, a, i0, j, k, LP);
+}
+
+// The z-vectorised sweep (sweep_column4): workgroup = 256 / rw rows of one
+// z-segment of rw lanes, lp planes.
+template <typename T, int BC, int LP, int KIND, int FL>
+__global__ __launch_bounds__(kBlock) void k_sweep4(Geom g, int gzs, int gy, int rw, Coef cf, SweepArgs a) {
+  __shared__ LdsCoef<T> s;
+  load_tables(s, cf, static_cast<int>(threadIdx.x), kBlock);
+  __syncthreads();
+  const int L = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+  const int zs = L % gzs;
+  const int t = L / gzs;
+  const int yb = t % gy;
+  const int i0 = (t / gy) * LP;
+  const int tid = static_cast<int>(threadIdx.x);
+  const int kq = tid & (rw - 1);
+  const int j = yb * (kBlock / rw) + tid / rw;
+  const int k4 = zs * rw + kq;
+  if (j >= g.ny || k4 >= (g.nz >> 2)) return;
+  sweep_column4<T, BC, LP, KIND, FL>(g, cf.labels, s, a, i0, j, k4, kq, rw);
 }
 
 // ---------------------------------------------------------------------------
@@ -310,6 +330,17 @@ int field_blocks(const Geom& g, const Shape& s) { return s.gx * s.gy * g.nx; }
 
 template <typename T, int BC, int KIND, int FL>
 static void sweep_lp(const Geom& g, const Tiling& tl, const Coef& cf, const SweepArgs& a, hipStream_t st) {
+  if (tl.vec) {
+    const int rows = kBlock / tl.rw;
+    const int gzs = ((g.nz >> 2) + tl.rw - 1) / tl.rw, gy = (g.ny + rows - 1) / rows;
+    const dim3 grid(static_cast<unsigned>(sweep_blocks(g, tl))), block(kBlock);
+    switch (tl.lp) {
+      case 1: k_sweep4<T, BC, 1, KIND, FL><<<grid, block, 0, st>>>(g, gzs, gy, tl.rw, cf, a); break;
+      case 2: k_sweep4<T, BC, 2, KIND, FL><<<grid, block, 0, st>>>(g, gzs, gy, tl.rw, cf, a); break;
+      default: k_sweep4<T, BC, 4, KIND, FL><<<grid, block, 0, st>>>(g, gzs, gy, tl.rw, cf, a); break;
+    }
+    return;
+  }
   const int gx = (g.nz + tl.bx - 1) / tl.bx, gy = (g.ny + tl.by - 1) / tl.by;
   const dim3 grid(static_cast<unsigned>(sweep_blocks(g, tl))), block(tl.bx, tl.by);
   switch (tl.lp) {
@@ -334,10 +365,23 @@ static void sweep_typed(const Geom& g, const Tiling& tl, const Coef& cf, const S
   }
 }
 
+// Whether every field the sweep touches starts on a 4-value boundary (the
+// z-vectorised sweep moves 4-value vectors; caller buffers may be views).
+static bool vec_aligned(int kind, const SweepArgs& a, const Coef& cf, expint_dtype dt) {
+  const uintptr_t m = 4 * dtype_bytes(dt) - 1;
+  auto ok = [m](const void* p) { return (reinterpret_cast<uintptr_t>(p) & m) == 0; };
+  if ((reinterpret_cast<uintptr_t>(cf.labels) & 3) != 0) return false;
+  if (kind == kTerm)
+    return ok(a.op.src) && ok(a.op.bsrc) && ok(a.op.acc_in) && ok(a.op.y_out) && ok(a.op.acc_out) && ok(a.op.u);
+  return ok(a.x) && ok(a.out) && ok(a.aux0) && ok(a.aux1);
+}
+
 template <int KIND>
-static hipError_t sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,
+static hipError_t sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl_in, const Coef& cf,
                         const SweepArgs& a, hipStream_t st) {
-  if (!tiling_valid(tl)) return hipErrorInvalidValue;
+  if (!tiling_valid(tl_in) || (tl_in.vec && !vec_sweep_ok(g, cf.labels_form))) return hipErrorInvalidValue;
+  // a misaligned field takes the scalar sweep for this launch
+  const Tiling tl = tl_in.vec && !vec_aligned(KIND, a, cf, dt) ? default_tiling(g) : tl_in;
   if (dt == EXPINT_F64) {
     if (bc == EXPINT_NOFLUX) sweep_typed<double, 0, KIND>(g, tl, cf, a, st);
     else sweep_typed<double, 1, KIND>(g, tl, cf, a, st);

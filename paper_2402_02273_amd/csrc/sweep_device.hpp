@@ -32,6 +32,17 @@ __device__ __forceinline__ void load_tables(LdsCoef<T>& s, const Coef& cf, int t
   }
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin; map workgroup L of nb to a
+// tile so that each XCD takes a contiguous run of tiles (neighbouring planes
+// then share that XCD's L2).
+__device__ __forceinline__ int xcd_remap(int L, int nb) {
+  if ((nb & 7) == 0) {
+    const int per = nb >> 3;
+    return (L & 7) * per + (L >> 3);
+  }
+  return L;
+}
+
 enum SweepKind { kTerm = 0, kRhs = 1, kApply = 2, kAdjRhs = 3 };
 constexpr int kRuntimeFlavor = -1;
 
@@ -153,6 +164,187 @@ __device__ __forceinline__ void sweep_column(const Geom& g, const Coef& cf, cons
     lm = lc;
     lc = ln;
     q += sx;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// z-vectorised sweep: a lane owns four consecutive z voxels (one 4-value
+// vector of each field and one 32-bit word of labels), so every load and
+// store of a wavefront is a run of 16-byte (FP32) or 32-byte (FP64) vectors.
+// Lanes are grouped in z-segments of rw lanes (4 rw voxels); the z
+// neighbours of a lane's first and last voxel come from the adjacent lanes of
+// the segment by shuffles, at a segment edge inside the row by one scalar
+// load, at a wall from the voxel itself (zero flux).  Needs nz % 4 == 0 and
+// the label form.  Same arithmetic per voxel as sweep_column.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct alignas(4 * sizeof(T)) Vec4 {
+  T v[4];
+};
+
+template <typename T>
+__device__ __forceinline__ Vec4<T> ld4(const void* p, int q4) {
+  return static_cast<const Vec4<T>*>(p)[q4];
+}
+template <typename T>
+__device__ __forceinline__ void st4(void* p, int q4, const Vec4<T>& v) {
+  static_cast<Vec4<T>*>(p)[q4] = v;
+}
+
+__device__ __forceinline__ int label_byte(uint32_t w, int e) { return static_cast<int>((w >> (8 * e)) & 255u); }
+
+// Outputs of one Taylor-term sweep on the four voxels of vector q4 (see TermOp).
+template <typename T, int FL>
+__device__ __forceinline__ void term_store4(const TermOp& op, int q4, const T (&ax)[4], const Vec4<T>& xc) {
+  const T c = static_cast<T>(op.c), cs = static_cast<T>(op.cs);
+  Vec4<T> y;
+  if (FL == kSkip) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) y.v[e] = c * ax[e];
+    st4<T>(op.y_out, q4, y);
+  } else if (FL == kFlushY || FL == kFlushNoY) {
+    const Vec4<T> ai = ld4<T>(op.acc_in, q4);
+    Vec4<T> v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      y.v[e] = c * ax[e];
+      v.v[e] = ai.v[e] + cs * xc.v[e] + y.v[e];
+    }
+    st4<T>(op.acc_out, q4, v);
+    if (FL == kFlushY) st4<T>(op.y_out, q4, y);
+  } else if (FL == kFirst) {
+    const Vec4<T> b = ld4<T>(op.bsrc, q4);
+    const T cb = static_cast<T>(op.cb);
+    Vec4<T> v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      y.v[e] = c * ax[e] + cb * b.v[e];
+      v.v[e] = cs * xc.v[e] + y.v[e];
+    }
+    st4<T>(op.acc_out, q4, v);
+    st4<T>(op.y_out, q4, y);
+  } else {
+    Vec4<T> v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) y.v[e] = c * ax[e];
+    if (op.bsrc) {
+      const Vec4<T> b = ld4<T>(op.bsrc, q4);
+      const T cb = static_cast<T>(op.cb);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) y.v[e] += cb * b.v[e];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v.v[e] = cs * xc.v[e] + y.v[e];
+    if (op.acc_in) {
+      const Vec4<T> ai = ld4<T>(op.acc_in, q4);
+      const T ca = static_cast<T>(op.ca);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v.v[e] += ca * ai.v[e];
+    }
+    if (op.u) {
+      Vec4<T> uu = ld4<T>(op.u, q4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) uu.v[e] = uu.v[e] + v.v[e];
+      st4<T>(op.u, q4, uu);
+    } else {
+      if (op.y_out) st4<T>(op.y_out, q4, y);
+      if (op.acc_out) st4<T>(op.acc_out, q4, v);
+    }
+  }
+}
+
+// The sweep of one lane: vector k4 (voxels 4 k4 .. 4 k4 + 3) of row j,
+// planes i0 .. i0 + LP - 1 (clipped to the grid); kq is the lane's index in
+// its z-segment of rw lanes.  Lanes outside the grid need not call this: a
+// lane only uses a neighbour's shuffled values when that neighbour is in the
+// same row and inside the grid (else the wall or segment-edge value).
+template <typename T, int BC, int LP, int KIND, int FL>
+__device__ __forceinline__ void sweep_column4(const Geom& g, const uint8_t* lab, const LdsCoef<T>& s,
+                                              const SweepArgs& a, int i0, int j, int k4, int kq, int rw) {
+  const int nz4 = g.nz >> 2;
+  const int sx4 = g.ny * nz4;
+  const int dym = j > 0 ? -nz4 : 0, dyp = j < g.ny - 1 ? nz4 : 0;
+  const bool wall_lo = k4 == 0, wall_hi = k4 == nz4 - 1;          // z walls
+  const bool edge_lo = !wall_lo && kq == 0, edge_hi = !wall_hi && kq == rw - 1;  // segment edges in the row
+  const int wall_y = BC ? (j == 0) + (j == g.ny - 1) : 0;
+  const T* __restrict__ x = static_cast<const T*>(KIND == kTerm ? a.op.src : a.x);
+  const uint32_t* __restrict__ l4 = reinterpret_cast<const uint32_t*>(lab);
+  int q = (i0 * g.ny + j) * nz4 + k4;
+  const int qm0 = i0 > 0 ? q - sx4 : q;
+  Vec4<T> xm = ld4<T>(x, qm0), xc = ld4<T>(x, q);
+  uint32_t lm = l4[qm0], lc = l4[q];
+#pragma unroll
+  for (int sp = 0; sp < LP; ++sp) {
+    const int i = i0 + sp;
+    if (i >= g.nx) break;
+    const int qn = i < g.nx - 1 ? q + sx4 : q;
+    const Vec4<T> xn = ld4<T>(x, qn);
+    const uint32_t ln = l4[qn];
+    const Vec4<T> ya = ld4<T>(x, q + dym), yb = ld4<T>(x, q + dyp);
+    const uint32_t la = l4[q + dym], lb = l4[q + dyp];
+    // z neighbours of voxels 0 and 3
+    T zl = __shfl_up(xc.v[3], 1, rw), zr = __shfl_down(xc.v[0], 1, rw);
+    int lzl = label_byte(__shfl_up(lc, 1, rw), 3), lzr = label_byte(__shfl_down(lc, 1, rw), 0);
+    if (wall_lo) {
+      zl = xc.v[0];
+      lzl = label_byte(lc, 0);
+    } else if (edge_lo) {
+      zl = x[4 * q - 1];
+      lzl = lab[4 * q - 1];
+    }
+    if (wall_hi) {
+      zr = xc.v[3];
+      lzr = label_byte(lc, 3);
+    } else if (edge_hi) {
+      zr = x[4 * q + 4];
+      lzr = lab[4 * q + 4];
+    }
+    const int wall_x = BC ? wall_y + (i == 0) + (i == g.nx - 1) : 0;
+    T ax[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const T v = xc.v[e];
+      const int le = label_byte(lc, e);
+      const T* row = s.tab + le * kMaxClasses;
+      const T vzm = e > 0 ? xc.v[e - 1] : zl;
+      const int lzm = e > 0 ? label_byte(lc, e - 1) : lzl;
+      const T vzp = e < 3 ? xc.v[e + 1] : zr;
+      const int lzp = e < 3 ? label_byte(lc, e + 1) : lzr;
+      ax[e] = row[label_byte(lm, e)] * (xm.v[e] - v) + row[label_byte(ln, e)] * (xn.v[e] - v) +
+              row[label_byte(la, e)] * (ya.v[e] - v) + row[label_byte(lb, e)] * (yb.v[e] - v) +
+              row[lzm] * (vzm - v) + row[lzp] * (vzp - v);
+      if (BC) {
+        const int nw = wall_x + (e == 0 && wall_lo) + (e == 3 && wall_hi);
+        ax[e] -= s.wall[le] * v * T(nw);
+      }
+    }
+    if (KIND == kTerm) {
+      term_store4<T, FL>(a.op, q, ax, xc);
+    } else if (KIND == kRhs) {
+      Vec4<T> o;
+      const T rho = static_cast<T>(a.rho);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) o.v[e] = ax[e] + rho * xc.v[e] * (T(1) - xc.v[e]);
+      st4<T>(a.out, q, o);
+    } else if (KIND == kAdjRhs) {
+      const Vec4<T> lam = ld4<T>(a.aux0, q), uq = ld4<T>(a.aux1, q);
+      const T rho = static_cast<T>(a.rho);
+      Vec4<T> o;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) o.v[e] = lam.v[e] + ax[e] + rho * (T(1) - T(2) * uq.v[e]) * xc.v[e];
+      st4<T>(a.out, q, o);
+    } else {
+      Vec4<T> o;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) o.v[e] = ax[e];
+      st4<T>(a.out, q, o);
+    }
+    xm = xc;
+    xc = xn;
+    lm = lc;
+    lc = ln;
+    q += sx4;
   }
 }
 

@@ -21,6 +21,7 @@ _DTYPES = {torch.float64: N.F64, torch.float32: N.F32}
 _BCS = {"noflux": N.NOFLUX, "dirichlet0": N.DIRICHLET0}
 _ALGOS = {"auto": N.ALGO_AUTO, "stencil_taylor": N.ALGO_STENCIL_TAYLOR, "modal": N.ALGO_MODAL}
 _MPS = {"none": N.MP_NONE, "bf16_split": N.MP_BF16_SPLIT, "fp16_split": N.MP_FP16_SPLIT}
+_SWEEPS = {"auto": N.SWEEPS_AUTO, "single": N.SWEEPS_SINGLE, "pairs": N.SWEEPS_PAIRS}
 
 
 @dataclass
@@ -67,6 +68,7 @@ class ExpInt:
         algo: str = "auto",
         mp: str = "none",
         check_finite: bool = False,
+        sweeps: str = "auto",
         device=None,
         stream=None,
     ):
@@ -121,6 +123,7 @@ class ExpInt:
         opts.s = int(s)
         opts.m = int(m)
         opts.check_finite = int(bool(check_finite))
+        opts.sweeps = _SWEEPS[sweeps]
         with torch.cuda.device(self.device):
             opts.stream = _stream_handle(stream, self.device)
             N.check(
@@ -174,6 +177,19 @@ class ExpInt:
         return torch.cuda.ExternalStream(p.value, device=self.device)
 
     # ---- plan and parameters ----
+    def launch_info(self) -> dict:
+        """The launch configuration resolved at creation (see expint_launch_info)."""
+        li = N.LaunchInfo()
+        N.check(self.lib.expint_get_launch(self._ctx, ctypes.byref(li)))
+        return {f: getattr(li, f) for f, _ in N.LaunchInfo._fields_}
+
+    def sweeps(self):
+        """("single" or "pairs", pair tiling (ty, lp) or None) as resolved at creation."""
+        li = self.launch_info()
+        if li["sweeps"] == N.SWEEPS_PAIRS:
+            return "pairs", (li["pair_ty"], li["pair_lp"])
+        return "single", None
+
     @property
     def plan(self) -> Plan:
         s, m, nrm = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
@@ -268,10 +284,11 @@ class ExpInt:
         """Mean ms per launch of one sweep of the step schedule.
 
         kernel: "flush" (Taylor term adding a pair of terms to the running sum),
-        "skip" (Taylor term writing only its term), "rhs", or for modal
-        contexts "mode_x" / "mode_z" (one mode product along x / z)."""
+        "skip" (Taylor term writing only its term), "rhs", for modal
+        contexts "mode_x" / "mode_z" (one mode product along x / z), for
+        contexts with pair sweeps "pair" (two terms in one sweep)."""
         ms = ctypes.c_double()
-        kid = {"flush": 0, "skip": 1, "rhs": 2, "mode_x": 3, "mode_z": 4}[kernel]
+        kid = {"flush": 0, "skip": 1, "rhs": 2, "mode_x": 3, "mode_z": 4, "pair": 5}[kernel]
         N.check(self.lib.expint_profile(self._ctx, kid, int(reps), ctypes.byref(ms)))
         return ms.value
 

@@ -61,6 +61,7 @@ def _labels_df():
         (lambda g, d, o: d.__setattr__("n_classes", 0), "n_classes"),
         (lambda g, d, o: d.__setattr__("D", 99), "exactly one"),
         (lambda g, d, o: o.__setitem__("dtype", 7), "dtype"),
+        (lambda g, d, o: o.__setitem__("sweeps", 3), "sweeps"),
     ],
 )
 def test_create_rejects_invalid_arguments(change, needle):
@@ -96,10 +97,18 @@ def test_unsupported_modal_requests_rejected_before_hip():
     assert rc == N.EUNSUPPORTED and "modal" in N.last_error()
 
 
+def test_pair_sweeps_need_label_form():
+    df = N.DField()
+    df.D = 1234  # never dereferenced: rejected first
+    rc, _ = _create(N.Grid(8, 8, 8, 1.0), df, sweeps=N.SWEEPS_PAIRS)
+    assert rc == N.EUNSUPPORTED and "label form" in N.last_error()
+
+
 def test_null_context_calls():
     L = N.lib()
     assert L.expint_step(None, None) == N.EINVAL
     assert L.expint_advance(None, None, 1) == N.EINVAL
     assert L.expint_get_plan(None, None, None, None) == N.EINVAL
+    assert L.expint_get_launch(None, None) == N.EINVAL
     L.expint_destroy(None)  # NULL-safe
     L.expint_batch_destroy(None)

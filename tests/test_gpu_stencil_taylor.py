@@ -45,6 +45,8 @@ def make_ctx(native, labels, class_D, dtype, **kw):
 
 SHAPES = [(1, 1, 1), (3, 1, 70), (5, 7, 9), (17, 33, 65), (9, 130, 20), (64, 5, 33)]
 CLASS_D = (0.0, 0.13, 0.013)
+# one Taylor term per sweep, or two (the first kept in LDS)
+SWEEPS = ["single", "pairs"]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -93,13 +95,15 @@ def test_plan_matches_oracle(native, dtype):
         assert (p.s, p.m) == oplan.for_dtype(w.tau * op.norm1(), key)
 
 
-@pytest.mark.parametrize("shape", [(5, 7, 9), (17, 33, 65), (24, 24, 24)])
-@pytest.mark.parametrize("sm", [None, (1, 1), (1, 5), (3, 1), (2, 7)])
-def test_phi1_f64_same_polynomial(native, shape, sm):
+@pytest.mark.parametrize("sweeps", SWEEPS)
+@pytest.mark.parametrize("shape", [(5, 7, 9), (17, 33, 65), (24, 24, 24), (1, 1, 1), (19, 9, 130)])
+@pytest.mark.parametrize("sm", [None, (1, 1), (1, 5), (3, 1), (2, 7), (1, 2), (2, 2), (3, 4)])
+def test_phi1_f64_same_polynomial(native, shape, sm, sweeps):
     labels = random_labels(shape, 3, seed=11)
     b = random_field(shape, seed=12, lo=-1, hi=1)
     kw = {} if sm is None else {"s": sm[0], "m": sm[1]}
-    ctx = make_ctx(native, labels, CLASS_D, torch.float64, tau=7.3, **kw)
+    ctx = make_ctx(native, labels, CLASS_D, torch.float64, tau=7.3, sweeps=sweeps, **kw)
+    assert ctx.sweeps()[0] == sweeps
     p = ctx.plan
     op = oop.Operator(1.0, labels=labels, class_D=CLASS_D)
     ref = oit.phi1_action(op, b, 7.3, p.s, p.m)
@@ -124,11 +128,12 @@ def _oracle_run(w, nsteps):
     return oit.advance(op, w.u0, w.rho, w.tau, s, m, nsteps)
 
 
+@pytest.mark.parametrize("sweeps", SWEEPS)
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-5)])
-def test_c1_plain_run(native, dtype, tol):
+def test_c1_plain_run(native, dtype, tol, sweeps):
     w = c1_plain()
     ref = _oracle_run(w, w.nsteps)
-    ctx = make_ctx(native, w.labels, w.class_D, dtype, tau=w.tau, rho=w.rho)
+    ctx = make_ctx(native, w.labels, w.class_D, dtype, tau=w.tau, rho=w.rho, sweeps=sweeps)
     u = dev(w.u0, dtype)
     ctx.advance(u, w.nsteps)
     got = u.cpu().numpy()
@@ -138,21 +143,23 @@ def test_c1_plain_run(native, dtype, tol):
         assert np.abs(got - np.flip(got, axis=ax)).max() <= (1e-14 if dtype == torch.float64 else 1e-6)
 
 
-@pytest.mark.parametrize("shape", [(20, 17, 33), (7, 40, 66)])
+@pytest.mark.parametrize("sweeps", SWEEPS)
+@pytest.mark.parametrize("shape", [(20, 17, 33), (7, 40, 66), (35, 19, 129)])
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-5)])
-def test_ragged_heterogeneous_run(native, shape, dtype, tol):
+def test_ragged_heterogeneous_run(native, shape, dtype, tol, sweeps):
     w = make_ragged(shape, seed=21, nsteps=3)
     ref = _oracle_run(w, w.nsteps)
-    ctx = make_ctx(native, w.labels, w.class_D, dtype, tau=w.tau, rho=w.rho)
+    ctx = make_ctx(native, w.labels, w.class_D, dtype, tau=w.tau, rho=w.rho, sweeps=sweeps)
     u = dev(w.u0, dtype)
     ctx.advance(u, w.nsteps)
     assert rel_l2(u.cpu().numpy(), ref) < tol
 
 
-def test_step_equals_advance_bitwise(native):
+@pytest.mark.parametrize("sweeps", SWEEPS)
+def test_step_equals_advance_bitwise(native, sweeps):
     w = make_ragged((16, 24, 40), seed=5, nsteps=4)
     for dtype in (torch.float64, torch.float32):
-        ctx = make_ctx(native, w.labels, w.class_D, dtype)
+        ctx = make_ctx(native, w.labels, w.class_D, dtype, sweeps=sweeps)
         u1 = dev(w.u0, dtype)
         u2 = u1.clone()
         for _ in range(4):
@@ -175,8 +182,9 @@ def test_logistic_and_degenerate_plan(native):
     np.testing.assert_allclose(u.cpu().numpy(), u0 + 7.3 * 0.025 * u0 * (1 - u0), rtol=1e-15)
 
 
+@pytest.mark.parametrize("sweeps", SWEEPS)
 @pytest.mark.parametrize("bc", ["noflux", "dirichlet0"])
-def test_eigenmode_decay(native, bc):
+def test_eigenmode_decay(native, bc, sweeps):
     shape = (12, 10, 66)
     Dc, tau, K = 0.1, 7.3, 5
     ks = (2, 1, 3)
@@ -185,7 +193,7 @@ def test_eigenmode_decay(native, bc):
     lam = Dc * sum(oref.eigenvalues_1d(n, 1.0, bc)[k] for n, k in zip(shape, ks))
     labels = np.ones(shape, dtype=np.uint8)
     for dtype, tol in ((torch.float64, 1e-12), (torch.float32, 2e-6)):
-        ctx = make_ctx(native, labels, (0.0, Dc), dtype, tau=tau, rho=0.0, bc=bc)
+        ctx = make_ctx(native, labels, (0.0, Dc), dtype, tau=tau, rho=0.0, bc=bc, sweeps=sweeps)
         u = dev(v, dtype)
         ctx.advance(u, K)
         expect = np.exp(lam * tau * K) * v
@@ -204,14 +212,16 @@ def test_mass_conservation_full_head(native):
         assert m0 == pytest.approx(w.u0.sum(), rel=1e-6 if dtype == torch.float32 else 1e-14)
 
 
-def test_full_head_one_step_elementwise(native):
-    # 128^3 at the bench's launch configuration: one step against the oracle, every voxel.
+@pytest.mark.parametrize("sweeps", ["auto"] + SWEEPS)
+def test_full_head_one_step_elementwise(native, sweeps):
+    # 128^3 at the bench's launch configuration (auto): one step against the oracle, every voxel.
     w = c2_head()
     op = oop.Operator(w.h, labels=w.labels, class_D=w.class_D)
     s, m = oplan.for_dtype(w.tau * op.norm1(), "f64")
     ref = oit.step(op, w.u0, w.rho, w.tau, s, m)
     for dtype, tol in ((torch.float64, 1e-12), (torch.float32, 1e-6)):
-        ctx = make_ctx(native, w.labels, w.class_D, dtype, tau=w.tau, rho=w.rho)
+        ctx = make_ctx(native, w.labels, w.class_D, dtype, tau=w.tau, rho=w.rho, sweeps=sweeps)
+        print(f"[case] resolved sweeps {ctx.sweeps()}", flush=True)
         u = dev(w.u0, dtype)
         ctx.advance(u, 1)
         got = u.cpu().numpy()
@@ -226,21 +236,22 @@ def _golden_c2():
     return np.load(path)
 
 
+@pytest.mark.parametrize("sweeps", SWEEPS)
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-5)])
-def test_full_head_100_steps_vs_stored_oracle(native, dtype, tol):
+def test_full_head_100_steps_vs_stored_oracle(native, dtype, tol, sweeps):
     g = _golden_c2()
     w = c2_head()
     import hashlib
 
     assert hashlib.sha256(w.labels.tobytes()).hexdigest() == str(g["labels_sha256"])
-    ctx = make_ctx(native, w.labels, w.class_D, dtype, tau=w.tau, rho=w.rho)
+    ctx = make_ctx(native, w.labels, w.class_D, dtype, tau=w.tau, rho=w.rho, sweeps=sweeps)
     if dtype == torch.float64:
         assert (ctx.plan.s, ctx.plan.m) == (int(g["s"]), int(g["m"]))
     u = dev(w.u0, dtype)
     ctx.advance(u, 100)
     got = u.cpu().numpy()
     err = rel_l2(got, g["u"])
-    print(f"[result] c2 128^3 x100 {dtype}: rel-L2 vs oracle = {err:.3e}", flush=True)
+    print(f"[result] c2 128^3 x100 {dtype} {sweeps}: rel-L2 vs oracle = {err:.3e}", flush=True)
     assert err < tol
     assert got.min() >= -1e-6 and got.max() <= 1 + 1e-6
 
@@ -281,3 +292,47 @@ def test_set_params_replan(native):
     ctx.step(u)
     ref = oit.step(op, w.u0, 0.03, 7.3, p1.s, p1.m)
     assert rel_l2(u.cpu().numpy(), ref) < 1e-12
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-13), (torch.float32, 2e-6)])
+def test_pairs_agree_with_single_terms(native, dtype, tol):
+    # same polynomial, different rounding order; several tiles in every axis
+    # with ragged tails (64-wide z tiles, 4/8-row y tiles, 4..16-plane x chunks)
+    w = make_ragged((37, 27, 150), seed=9, nsteps=2)
+    out = {}
+    for sw in SWEEPS:
+        ctx = make_ctx(native, w.labels, w.class_D, dtype, tau=w.tau, rho=w.rho, sweeps=sw)
+        assert ctx.sweeps()[0] == sw
+        u = dev(w.u0, dtype)
+        ctx.advance(u, w.nsteps)
+        out[sw] = u.cpu().numpy()
+    assert rel_l2(out["pairs"], out["single"]) < tol
+
+
+def test_dense_form_uses_single_terms(native):
+    from paper_2402_02273_amd.expint import ExpInt
+
+    shape = (9, 10, 11)
+    D = oop.class_field(random_labels(shape, 3, seed=3), CLASS_D)
+    ctx = ExpInt(shape, D=dev(D, torch.float64), dtype=torch.float64, device=DEV)
+    assert ctx.sweeps() == ("single", None)
+
+
+def test_profile_kernel_ids(native):
+    # every sweep id times its own kernel: 5 (pair sweep) only on contexts
+    # that use pair sweeps, 3 / 4 (mode products) only on modal contexts
+    from paper_2402_02273_amd import ExpIntError
+
+    w = make_ragged((24, 20, 70), seed=2)
+    for sw in SWEEPS:
+        ctx = make_ctx(native, w.labels, w.class_D, torch.float32, sweeps=sw)
+        for k in ("flush", "skip", "rhs"):
+            assert ctx.profile(k, reps=3) > 0.0
+        if sw == "pairs":
+            assert ctx.profile("pair", reps=3) > 0.0
+        else:
+            with pytest.raises(ExpIntError, match="EUNSUPPORTED"):
+                ctx.profile("pair", reps=3)
+        for k in ("mode_x", "mode_z"):
+            with pytest.raises(ExpIntError, match="EINVAL"):
+                ctx.profile(k, reps=3)

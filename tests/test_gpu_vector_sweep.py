@@ -1,0 +1,146 @@
+"""GPU parity of the z-vectorised stencil sweep (four z voxels per lane)
+against the FP64 oracle and against the scalar sweep.
+
+The sweep shape is forced per context: EXPINT_TILE=vec restricts the
+autotuner to the vectorised sweep, and with EXPINT_AUTOTUNE=0 it takes the
+narrowest z-segment that spans the row (so nz > 256 has two segments per row
+and exercises the segment-edge loads).  Shapes have nz % 4 == 0 and ragged
+tails in x and y.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint as oadj
+from oracle import integrator as oit
+from oracle import operator as oop
+from workloads.configs import make_ragged, random_field, random_labels
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+CLASS_D = (0.0, 0.13, 0.013)
+SHAPES = [(1, 1, 4), (5, 7, 12), (17, 33, 68), (9, 130, 20), (3, 5, 264), (6, 3, 520)]
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
+
+
+@pytest.fixture(params=["tuned", "default"])
+def vec_env(request, monkeypatch):
+    monkeypatch.setenv("EXPINT_TILE", "vec")
+    if request.param == "default":
+        monkeypatch.setenv("EXPINT_AUTOTUNE", "0")
+    return request.param
+
+
+def make_ctx(labels, class_D, dtype, **kw):
+    from paper_2402_02273_amd.expint import ExpInt
+
+    ctx = ExpInt(labels.shape, labels=labels, class_D=class_D, dtype=dtype, device=DEV, sweeps="single", **kw)
+    info = ctx.launch_info()
+    print(f"[case] shape={labels.shape} dtype={dtype} {kw} launch={info}", flush=True)
+    assert info["vec"] == 1
+    return ctx
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("bc", ["noflux", "dirichlet0"])
+def test_apply_and_rhs_vec(native, vec_env, shape, bc):
+    labels = random_labels(shape, 3, seed=sum(shape) + 1)
+    x = random_field(shape, seed=7, lo=-1, hi=1)
+    D = oop.class_field(labels, CLASS_D)
+    ref = oop.apply_A(x, D, 0.8, bc)
+    ref_b = ref + oit.reaction(x, 0.03)
+    for dtype, tol in ((torch.float64, 1e-14), (torch.float32, 2e-6)):
+        ctx = make_ctx(labels, CLASS_D, dtype, bc=bc, rho=0.03, h=0.8)
+        got = ctx.apply(dev(x, dtype)).cpu().numpy()
+        assert np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-30) < tol
+        got_b = ctx.rhs(dev(x, dtype)).cpu().numpy()
+        assert np.abs(got_b - ref_b).max() / max(np.abs(ref_b).max(), 1e-30) < tol
+
+
+@pytest.mark.parametrize("shape", [(5, 7, 12), (17, 33, 68), (3, 5, 264)])
+@pytest.mark.parametrize("sm", [None, (1, 1), (1, 5), (2, 7), (3, 4)])
+def test_phi1_vec_same_polynomial(native, vec_env, shape, sm):
+    labels = random_labels(shape, 3, seed=11)
+    b = random_field(shape, seed=12, lo=-1, hi=1)
+    kw = {} if sm is None else {"s": sm[0], "m": sm[1]}
+    ctx = make_ctx(labels, CLASS_D, torch.float64, tau=7.3, **kw)
+    p = ctx.plan
+    op = oop.Operator(1.0, labels=labels, class_D=CLASS_D)
+    ref = oit.phi1_action(op, b, 7.3, p.s, p.m)
+    got = ctx.phi1(dev(b, torch.float64)).cpu().numpy()
+    assert rel_l2(got, ref) < 1e-13
+
+
+@pytest.mark.parametrize("shape", [(20, 17, 36), (7, 40, 264)])
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-5)])
+def test_ragged_run_vec(native, vec_env, shape, dtype, tol):
+    w = make_ragged(shape, seed=21, nsteps=3)
+    op = oop.Operator(w.h, labels=w.labels, class_D=w.class_D, bc=w.bc)
+    ctx = make_ctx(w.labels, w.class_D, dtype, tau=w.tau, rho=w.rho)
+    p = ctx.plan
+    ref = oit.advance(op, w.u0, w.rho, w.tau, p.s, p.m, w.nsteps)
+    u = dev(w.u0, dtype)
+    ctx.advance(u, w.nsteps)
+    assert rel_l2(u.cpu().numpy(), ref) < tol
+
+
+def test_vec_matches_scalar_sweep(native, monkeypatch):
+    # same arithmetic per voxel in both sweep shapes
+    w = make_ragged((19, 22, 132), seed=3, nsteps=3)
+    out = {}
+    for shape_env in ("scalar", "vec"):
+        monkeypatch.setenv("EXPINT_TILE", shape_env)
+        from paper_2402_02273_amd.expint import ExpInt
+
+        ctx = ExpInt(w.shape, labels=w.labels, class_D=w.class_D, tau=w.tau, rho=w.rho, dtype=torch.float32,
+                     device=DEV, sweeps="single")
+        assert ctx.launch_info()["vec"] == (1 if shape_env == "vec" else 0)
+        u = dev(w.u0, torch.float32)
+        ctx.advance(u, w.nsteps)
+        out[shape_env] = u.cpu().numpy()
+    assert rel_l2(out["vec"], out["scalar"]) < 1e-6
+
+
+def test_misaligned_fields_take_scalar_sweep(native, vec_env):
+    # views that start one value into a buffer are not 16-byte aligned: the
+    # library falls back to the scalar sweep for those launches
+    shape = (6, 9, 40)
+    labels = random_labels(shape, 3, seed=4)
+    x = random_field(shape, seed=5, lo=-1, hi=1)
+    ref = oop.apply_A(x, oop.class_field(labels, CLASS_D), 1.0)
+    ctx = make_ctx(labels, CLASS_D, torch.float32)
+    n = int(np.prod(shape))
+    buf_x = torch.zeros(n + 1, dtype=torch.float32, device=DEV)
+    buf_y = torch.zeros(n + 1, dtype=torch.float32, device=DEV)
+    xv = buf_x[1:].view(shape)
+    xv.copy_(dev(x, torch.float32))
+    yv = buf_y[1:].view(shape)
+    ctx.apply(xv, out=yv)
+    assert rel_l2(yv.cpu().numpy(), ref) < 2e-6
+
+
+def test_adjoint_vec(native, vec_env):
+    w = make_ragged((10, 12, 24), seed=6, nsteps=4)
+    target = random_field(w.shape, seed=8)
+    ctx = make_ctx(w.labels, w.class_D, torch.float64, tau=w.tau, rho=w.rho)
+    p = ctx.plan
+    op = oop.Operator(w.h, labels=w.labels, class_D=w.class_D)
+    loss, gu, grho, gD = oadj.loss_and_grad(op, w.u0, w.rho, w.tau, p.s, p.m, w.nsteps, target, ckpt_every=2,
+                                            classes=list(range(len(w.class_D))))
+    got = ctx.grad(dev(w.u0, torch.float64), w.nsteps, dev(target, torch.float64), ckpt_every=2)
+    assert got[0] == pytest.approx(loss, rel=1e-12)
+    assert rel_l2(got[1].cpu().numpy(), gu) < 1e-12
+    assert got[2] == pytest.approx(grho, rel=1e-10)
+    ref_D = [gD[c] for c in range(len(w.class_D))]
+    np.testing.assert_allclose(got[3], ref_D, rtol=1e-10, atol=1e-12 * max(abs(v) for v in ref_D))
