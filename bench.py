@@ -113,17 +113,20 @@ def step_bytes_per_voxel_pairs(w, s, m):
     return RHS_BYTES(w) + sum(sweep_bytes(w, r, wr) for r, wr in ops), len(ops) + 1
 
 
-def load_traffic(kernel_key):
-    """HBM bytes per launch from the committed rocprof counter summary, if any."""
+def load_traffic(kernel_key, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprof counter
+    summary, or None if there is none for this kernel and workload."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         with open(path) as f:
-            data = json.load(f)
-        return data.get(kernel_key)
-    except Exception:
+            entry = json.load(f).get(kernel_key)
+    except (OSError, ValueError):
         return None
+    if not entry or entry.get("kernel") != kernel:
+        return None
+    return entry.get("bytes_per_launch")
 
 
 def cpu_baseline(w, nsteps):
@@ -206,13 +209,13 @@ def run_c2(args):
         kname = f"k_pair (two Taylor terms per sweep, stencil twice + running sum), ty={ptiling[0]} lp={ptiling[1]}"
         tb = PAIR_BYTES(w_bytes) * w.nvox
         ms_dom = ms_pair
-        traffic = load_traffic(f"pair_{args.dtype}_{args.n}")
+        traffic = load_traffic(f"pair_{args.dtype}_{args.n}", "k_pair")
         sbv, nlaunch = step_bytes_per_voxel_pairs(w_bytes, plan.s, plan.m)
     else:
         kname = "k_sweep term, pair-flush flavour (stencil + Taylor term + running sum)"
         tb = FLUSH_BYTES(w_bytes) * w.nvox
         ms_dom = ms_flush
-        traffic = load_traffic(f"flush_{args.dtype}_{args.n}")
+        traffic = load_traffic(f"flush_{args.dtype}_{args.n}", "k_sweep4" if launch["vec"] else "k_sweep")
         sbv, nlaunch = step_bytes_per_voxel(w_bytes, plan.s, plan.m)
     achieved = tb / (ms_dom * 1e-3) / 1e9
     sb = sbv * w.nvox

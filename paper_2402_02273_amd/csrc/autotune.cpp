@@ -4,6 +4,7 @@
 #include <cstdlib>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -14,8 +15,72 @@ namespace {
 using Key = std::tuple<int, int, int, int, int, int>;
 std::mutex g_mu;
 std::map<Key, Tiling> g_cache;
-
 std::map<Key, PairTiling> g_pair_cache;
+
+// Optional persistent cache: EXPINT_TUNE_FILE names a text file of earlier
+// choices, read when first named and appended to after every new search, so
+// that later processes (a profiled rerun, a deployment) launch exactly the
+// same shapes without timing anything.  Lines:
+//   sweep nx ny nz dtype bc flags  bx by lp vec rw
+//   pair  nx ny nz dtype bc forced ty lp
+std::string g_loaded_file;  // the tuning file last read into the caches
+
+const char* tune_file() {
+  const char* f = std::getenv("EXPINT_TUNE_FILE");
+  return (f && f[0]) ? f : nullptr;
+}
+
+// Caller holds g_mu.  Reads the file named by EXPINT_TUNE_FILE if it is not
+// the one read last; its entries replace cached ones.
+void load_tune_file() {
+  const char* path = tune_file();
+  if (!path || g_loaded_file == path) return;
+  g_loaded_file = path;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char kind[16];
+  int a[6], v[5];
+  while (std::fscanf(f, "%15s", kind) == 1) {
+    if (std::string(kind) == "sweep" &&
+        std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d", &a[0], &a[1], &a[2], &a[3], &a[4], &a[5], &v[0], &v[1],
+                    &v[2], &v[3], &v[4]) == 11) {
+      Tiling t;
+      t.bx = v[0];
+      t.by = v[1];
+      t.lp = v[2];
+      t.vec = v[3];
+      t.rw = v[4];
+      if (tiling_valid(t)) g_cache[Key{a[0], a[1], a[2], a[3], a[4], a[5]}] = t;
+    } else if (std::string(kind) == "pair" &&
+               std::fscanf(f, "%d %d %d %d %d %d %d %d", &a[0], &a[1], &a[2], &a[3], &a[4], &a[5], &v[0], &v[1]) ==
+                   8) {
+      PairTiling t;
+      t.ty = v[0];
+      t.lp = v[1];
+      if (t.ty == 0 || pair_tiling_valid(t)) g_pair_cache[Key{a[0], a[1], a[2], a[3], a[4], a[5]}] = t;
+    } else {
+      break;  // malformed: keep what was read
+    }
+  }
+  std::fclose(f);
+}
+
+// Caller holds g_mu.
+void append_tune_file(const char* line) {
+  const char* path = tune_file();
+  if (!path) return;
+  if (FILE* f = std::fopen(path, "a")) {
+    std::fputs(line, f);
+    std::fclose(f);
+  }
+}
+
+std::string key_text(const Key& k) {
+  char b[96];
+  std::snprintf(b, sizeof(b), "%d %d %d %d %d %d", std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
+                std::get<4>(k), std::get<5>(k));
+  return b;
+}
 
 // Average time of `reps` launches after one warm-up launch, in ms.
 template <typename F>
@@ -56,6 +121,7 @@ hipError_t autotune_pairs(expint_dtype dt, expint_bc bc, const Geom& g, const Co
   const Key key{g.nx, g.ny, g.nz, static_cast<int>(dt), static_cast<int>(bc), forced ? 1 : 0};
   {
     std::lock_guard<std::mutex> lk(g_mu);
+    load_tune_file();
     auto it = g_pair_cache.find(key);
     if (it != g_pair_cache.end()) {
       *out = it->second;
@@ -123,6 +189,8 @@ hipError_t autotune_pairs(expint_dtype dt, expint_bc bc, const Geom& g, const Co
                  t_skip * 1000.f, t_flush * 1000.f, out->ty ? "pairs" : "single terms");
   std::lock_guard<std::mutex> lk(g_mu);
   g_pair_cache[key] = *out;
+  append_tune_file(("pair " + key_text(key) + " " + std::to_string(out->ty) + " " + std::to_string(out->lp) + "\n")
+                       .c_str());
   return hipSuccess;
 }
 
@@ -148,6 +216,7 @@ hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Co
                 (cf.labels_form ? 1 : 0) | (vec_ok ? 2 : 0) | (scalar_ok ? 4 : 0)};
   {
     std::lock_guard<std::mutex> lk(g_mu);
+    load_tune_file();
     auto it = g_cache.find(key);
     if (it != g_cache.end()) {
       *out = it->second;
@@ -216,6 +285,10 @@ hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Co
   }
   std::lock_guard<std::mutex> lk(g_mu);
   g_cache[key] = best_t;
+  char line[160];
+  std::snprintf(line, sizeof(line), "sweep %s %d %d %d %d %d\n", key_text(key).c_str(), best_t.bx, best_t.by, best_t.lp,
+                best_t.vec, best_t.rw);
+  append_tune_file(line);
   return hipSuccess;
 }
 

@@ -14,7 +14,8 @@ namespace expint {
 // overwritten), and returns the fastest.  Results are cached per (grid, dtype,
 // bc, form, candidate set) for the process.  EXPINT_AUTOTUNE=0 in the
 // environment skips the search (default_tiling); EXPINT_TILE=scalar or vec
-// restricts the candidates to one sweep shape.
+// restricts the candidates to one sweep shape; EXPINT_TUNE_FILE=path keeps
+// the choices in a text file that later processes read instead of timing.
 hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Coef& cf, void* f0, void* f1, void* f2,
                           hipStream_t st, bool allow_vec, Tiling* out);
 

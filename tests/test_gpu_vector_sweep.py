@@ -144,3 +144,31 @@ def test_adjoint_vec(native, vec_env):
     assert got[2] == pytest.approx(grho, rel=1e-10)
     ref_D = [gD[c] for c in range(len(w.class_D))]
     np.testing.assert_allclose(got[3], ref_D, rtol=1e-10, atol=1e-12 * max(abs(v) for v in ref_D))
+
+
+def test_tune_file_pins_launch_shapes(native, monkeypatch, tmp_path):
+    # a tuning file from an earlier process fixes the shapes without timing;
+    # new grids are tuned and appended
+    from paper_2402_02273_amd.expint import ExpInt
+
+    path = tmp_path / "tune.txt"
+    # key: nx ny nz dtype(F32 = 1) bc(no-flux = 0) flags(label form 1 | vector ok 2 | scalar ok 4)
+    path.write_text("sweep 20 24 36 1 0 7 32 8 2 0 64\npair 20 24 36 1 0 0 0 8\n")
+    monkeypatch.setenv("EXPINT_TUNE_FILE", str(path))
+    w = make_ragged((20, 24, 36), seed=2)
+    ctx = ExpInt(w.shape, labels=w.labels, class_D=w.class_D, dtype=torch.float32, device=DEV)
+    info = ctx.launch_info()
+    assert (info["vec"], info["bx"], info["by"], info["lp"], info["sweeps"]) == (0, 32, 8, 2, 1)
+    w2 = make_ragged((12, 10, 44), seed=3)
+    ctx2 = ExpInt(w2.shape, labels=w2.labels, class_D=w2.class_D, dtype=torch.float32, device=DEV)
+    lines = path.read_text().splitlines()
+    assert any(ln.startswith("sweep 12 10 44 1 0 ") for ln in lines)
+    assert any(ln.startswith("pair 12 10 44 1 0 0 ") for ln in lines)
+    # the result does not depend on the shapes
+    op = oop.Operator(w.h, labels=w.labels, class_D=w.class_D)
+    p = ctx.plan
+    ref = oit.advance(op, w.u0, w.rho, w.tau, p.s, p.m, 2)
+    u = dev(w.u0, torch.float32)
+    ctx.advance(u, 2)
+    assert rel_l2(u.cpu().numpy(), ref) < 1e-5
+    del ctx2
