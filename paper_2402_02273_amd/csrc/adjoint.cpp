@@ -45,7 +45,8 @@ int ensure_adj(expint_ctx* c, int nck, int seg) {
     void** singles[] = {&a.lam, &a.gb, &a.work, &a.xb[0], &a.xb[1], &a.yb[0], &a.yb[1]};
     for (void** p : singles)
       if ((rc = c->arena.alloc(p, fb))) return rc;
-    if ((rc = c->arena.alloc(reinterpret_cast<void**>(&a.fpart), kReduceBlocks * kMaxClasses * sizeof(double))))
+    if ((rc = c->arena.alloc(reinterpret_cast<void**>(&a.fpart),
+                             static_cast<size_t>(faceprod_slots(c->g, c->tiling)) * kMaxClasses * sizeof(double))))
       return rc;
     if ((rc = c->arena.alloc(reinterpret_cast<void**>(&a.dev), 16 * sizeof(double)))) return rc;
     if ((rc = c->arena.alloc(reinterpret_cast<void**>(&a.dtab), kMaxClasses * kTab * sizeof(double)))) return rc;
@@ -85,9 +86,10 @@ int upload_weights(expint_ctx* c) {
   return EXPINT_OK;
 }
 
+// Adds w <ybar, (dA/dD_c) y> for every class into the face-product slots.
 int faceprod(expint_ctx* c, const void* ybar, const void* y, double w) {
-  HIP_TRY(c, launch_faceprod(c->dtype, c->bc, c->g, c->labels, c->nclass, c->adj.dtab, c->adj.dwall, ybar, y, w,
-                             c->adj.fpart, c->adj.dev, c->stream));
+  HIP_TRY(c, launch_faceprod(c->dtype, c->bc, c->g, c->tiling, c->labels, c->nclass, c->adj.dtab, c->adj.dwall, ybar,
+                             y, w, c->adj.fpart, c->stream));
   return EXPINT_OK;
 }
 
@@ -187,7 +189,9 @@ int vjp_core(expint_ctx* c, const void* u0, int32_t nsteps, const void* cot, boo
   if ((rc = upload_weights(c))) return rc;
   auto& a = c->adj;
   const int64_t n = c->g.n;
+  const int64_t slots = faceprod_slots(c->g, c->tiling);
   HIP_TRY(c, launch_fill(EXPINT_F64, 16, 0.0, a.dev, c->stream));
+  HIP_TRY(c, launch_fill(EXPINT_F64, slots * kMaxClasses, 0.0, a.fpart, c->stream));
   HIP_TRY(c, launch_fill(c->dtype, n, 0.0, a.xs[0], c->stream));
 
   // forward with checkpoints
@@ -215,6 +219,7 @@ int vjp_core(expint_ctx* c, const void* u0, int32_t nsteps, const void* cot, boo
       if ((rc = reverse_step(c, a.segs[k - start]))) return rc;
   }
   HIP_TRY(c, launch_copy(c->dtype, n, a.lam, grad_u0, c->stream));
+  HIP_TRY(c, launch_faceprod_final(a.fpart, slots, a.dev, c->stream));
   double host[16];
   HIP_TRY(c, hipMemcpyAsync(host, a.dev, sizeof(host), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));

@@ -7,67 +7,35 @@
 // so its derivative with respect to the diffusivity D_c of tissue class c is
 // a weighted sum of face products: the weights -dK(D_a, D_b)/dD_c / h^2 (and
 // -[a == c] / h^2 at walls) come precomputed per class pair in FP64.  Every
-// face is visited once (the +x, +y, +z faces of each voxel); partial sums are
-// per workgroup in FP64 and combined in a fixed order, so results are
-// bit-reproducible.
+// face is visited once (the +x, +y, +z faces of each voxel).
+//
+// A gradient evaluates thousands of such forms (one per Taylor term of the
+// reverse pass), so they are not reduced one by one: workgroup b adds
+// weight * (its FP64 partial sums) into slot b of a partial buffer that stays
+// on the device, and one fixed-order reduction at the end turns the slots into
+// the class gradients.  Each slot is updated by one workgroup per launch and
+// launches are stream-ordered, so results are bit-reproducible.
+
+#include <algorithm>
 
 #include "internal.hpp"
+#include "sweep_device.hpp"
 
 namespace expint {
 
 namespace {
+
+constexpr int kFaceLP = 4;  // x-planes per lane of the vectorised face products
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
-template <typename T, int BC>
-__global__ __launch_bounds__(kBlock) void k_faceprod(Geom g, const uint8_t* __restrict__ lab, int nclass,
-                                                     const double* __restrict__ dtab, const double* __restrict__ dwall,
-                                                     const T* __restrict__ yb, const T* __restrict__ y,
-                                                     double* __restrict__ partial) {
-  __shared__ double st[kMaxClasses * kTab];
-  __shared__ double sw[kMaxClasses * kMaxClasses];
+// Sums acc over the workgroup (fixed order) and adds weight * sum into
+// partial[blockIdx.x * 8 + c].  Every thread of the workgroup must call it.
+__device__ __forceinline__ void block_accumulate(double (&acc)[kMaxClasses], double weight, double* partial) {
   __shared__ double red[kBlock / 64][kMaxClasses];
-  for (int t = threadIdx.x; t < kMaxClasses * kTab; t += kBlock) st[t] = dtab[t];
-  if (threadIdx.x < kMaxClasses * kMaxClasses) sw[threadIdx.x] = dwall[threadIdx.x];
-  __syncthreads();
-
-  double acc[kMaxClasses];
-#pragma unroll
-  for (int c = 0; c < kMaxClasses; ++c) acc[c] = 0.0;
-
-  const int sx = g.ny * g.nz, sy = g.nz;
-  const int n = static_cast<int>(g.n);
-  for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) {
-    const int k = p % g.nz;
-    const int t = p / g.nz;
-    const int j = t % g.ny;
-    const int i = t / g.ny;
-    const int lp = lab[p];
-    const double ybp = static_cast<double>(yb[p]), yp = static_cast<double>(y[p]);
-    const double* row = st + lp * kMaxClasses;  // + c * kTab + l_q
-    auto face = [&](int q) {
-      const double prod = (ybp - static_cast<double>(yb[q])) * (yp - static_cast<double>(y[q]));
-      const double* w = row + lab[q];
-#pragma unroll
-      for (int c = 0; c < kMaxClasses; ++c)
-        if (c < nclass) acc[c] += w[c * kTab] * prod;
-    };
-    if (i < g.nx - 1) face(p + sx);
-    if (j < g.ny - 1) face(p + sy);
-    if (k < g.nz - 1) face(p + 1);
-    if (BC) {
-      const int nw = (i == 0) + (i == g.nx - 1) + (j == 0) + (j == g.ny - 1) + (k == 0) + (k == g.nz - 1);
-      if (nw) {
-        const double v = ybp * yp * nw;
-#pragma unroll
-        for (int c = 0; c < kMaxClasses; ++c)
-          if (c < nclass) acc[c] += sw[c * kMaxClasses + lp] * v;
-      }
-    }
-  }
 #pragma unroll
   for (int c = 0; c < kMaxClasses; ++c) {
     const double v = wave_sum(acc[c]);
@@ -77,14 +45,159 @@ __global__ __launch_bounds__(kBlock) void k_faceprod(Geom g, const uint8_t* __re
   if (threadIdx.x < kMaxClasses) {
     double v = 0.0;
     for (int w = 0; w < kBlock / 64; ++w) v += red[w][threadIdx.x];
-    partial[blockIdx.x * kMaxClasses + threadIdx.x] = v;
+    double* slot = partial + static_cast<size_t>(blockIdx.x) * kMaxClasses + threadIdx.x;
+    *slot = *slot + weight * v;
   }
 }
 
-// acc[c] += weight * sum over workgroups of partial[b][c].  Thread t sums the
-// partials b = t, t + 256, ... of every class, then a fixed-order tree over
-// the 256 threads: the combination order never changes (bit-reproducible).
-__global__ __launch_bounds__(kBlock) void k_faceprod_final(const double* __restrict__ partial, int nb, double weight,
+struct FaceTables {
+  double tab[kMaxClasses * kTab];          // [c][a][b]
+  double wall[kMaxClasses * kMaxClasses];  // [c][a]
+};
+
+__device__ __forceinline__ void load_face_tables(FaceTables& ft, const double* dtab, const double* dwall) {
+  for (int t = threadIdx.x; t < kMaxClasses * kTab; t += kBlock) ft.tab[t] = dtab[t];
+  if (threadIdx.x < kMaxClasses * kMaxClasses) ft.wall[threadIdx.x] = dwall[threadIdx.x];
+}
+
+template <int NC>
+__device__ __forceinline__ void add_face(double (&acc)[kMaxClasses], const FaceTables& ft, int la, int lb,
+                                         double prod) {
+  const double* w = ft.tab + la * kMaxClasses + lb;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] += w[c * kTab] * prod;
+}
+
+// Scalar form: any grid; grid-stride over voxels.  NC = number of classes.
+template <typename T, int BC, int NC>
+__global__ __launch_bounds__(kBlock) void k_faceprod(Geom g, const uint8_t* __restrict__ lab,
+                                                     const double* __restrict__ dtab, const double* __restrict__ dwall,
+                                                     const T* __restrict__ yb, const T* __restrict__ y, double weight,
+                                                     double* __restrict__ partial) {
+  __shared__ FaceTables ft;
+  load_face_tables(ft, dtab, dwall);
+  __syncthreads();
+  double acc[kMaxClasses];
+#pragma unroll
+  for (int c = 0; c < kMaxClasses; ++c) acc[c] = 0.0;
+  const int sx = g.ny * g.nz, sy = g.nz;
+  const int n = static_cast<int>(g.n);
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) {
+    const int k = p % g.nz;
+    const int t = p / g.nz;
+    const int j = t % g.ny;
+    const int i = t / g.ny;
+    const int lp = lab[p];
+    const double ybp = static_cast<double>(yb[p]), yp = static_cast<double>(y[p]);
+    auto face = [&](int q) {
+      add_face<NC>(acc, ft, lp, lab[q], (ybp - static_cast<double>(yb[q])) * (yp - static_cast<double>(y[q])));
+    };
+    if (i < g.nx - 1) face(p + sx);
+    if (j < g.ny - 1) face(p + sy);
+    if (k < g.nz - 1) face(p + 1);
+    if (BC) {
+      const int nw = (i == 0) + (i == g.nx - 1) + (j == 0) + (j == g.ny - 1) + (k == 0) + (k == g.nz - 1);
+      if (nw) {
+        const double v = ybp * yp * nw;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] += ft.wall[c * kMaxClasses + lp] * v;
+      }
+    }
+  }
+  block_accumulate(acc, weight, partial);
+}
+
+// z-vectorised form (nz % 4 == 0, 4-value aligned fields): the z-segments of
+// the vectorised sweeps; a lane owns four z voxels of one row and marches over
+// kFaceLP planes; the +z face of its last voxel pairs with the next lane's first
+// (shuffle), the next segment's first (load) or nothing at the wall.
+template <typename T, int BC, int NC>
+__global__ __launch_bounds__(kBlock) void k_faceprod4(Geom g, int gzs, int gy, int rw, const uint8_t* __restrict__ lab,
+                                                      const double* __restrict__ dtab,
+                                                      const double* __restrict__ dwall, const T* __restrict__ yb,
+                                                      const T* __restrict__ y, double weight,
+                                                      double* __restrict__ partial) {
+  __shared__ FaceTables ft;
+  load_face_tables(ft, dtab, dwall);
+  __syncthreads();
+  double acc[kMaxClasses];
+#pragma unroll
+  for (int c = 0; c < kMaxClasses; ++c) acc[c] = 0.0;
+  const int L = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+  const int zs = L % gzs;
+  const int t = L / gzs;
+  const int ybk = t % gy;
+  const int i0 = (t / gy) * kFaceLP;
+  const int tid = static_cast<int>(threadIdx.x);
+  const int kq = tid & (rw - 1);
+  const int j = ybk * (kBlock / rw) + tid / rw;
+  const int nz4 = g.nz >> 2;
+  const int k4 = zs * rw + kq;
+  const bool live = j < g.ny && k4 < nz4;
+  if (live) {
+    const int sx4 = g.ny * nz4;
+    const uint32_t* l4 = reinterpret_cast<const uint32_t*>(lab);
+    const int dyp = j < g.ny - 1 ? nz4 : 0;
+    const bool wall_hi = k4 == nz4 - 1, edge_hi = !wall_hi && kq == rw - 1;
+    int q = (i0 * g.ny + j) * nz4 + k4;
+    Vec4<T> bc = ld4<T>(yb, q), vc = ld4<T>(y, q);
+    uint32_t lc = l4[q];
+#pragma unroll 2
+    for (int sp = 0; sp < kFaceLP; ++sp) {
+      const int i = i0 + sp;
+      if (i >= g.nx) break;
+      const int qn = i < g.nx - 1 ? q + sx4 : q;
+      const Vec4<T> bn = ld4<T>(yb, qn), vn = ld4<T>(y, qn);
+      const uint32_t ln = l4[qn];
+      const Vec4<T> by = ld4<T>(yb, q + dyp), vy = ld4<T>(y, q + dyp);
+      const uint32_t ly = l4[q + dyp];
+      T bz = __shfl_down(bc.v[0], 1, rw), vz = __shfl_down(vc.v[0], 1, rw);
+      int lz = label_byte(__shfl_down(lc, 1, rw), 0);
+      if (wall_hi) {
+        bz = bc.v[3];
+        vz = vc.v[3];
+        lz = label_byte(lc, 3);
+      } else if (edge_hi) {
+        bz = yb[4 * q + 4];
+        vz = y[4 * q + 4];
+        lz = lab[4 * q + 4];
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int le = label_byte(lc, e);
+        const double bp = static_cast<double>(bc.v[e]), vp = static_cast<double>(vc.v[e]);
+        // +x and +y faces (the voxel itself at the far walls: product 0)
+        add_face<NC>(acc, ft, le, label_byte(ln, e),
+                     (bp - static_cast<double>(bn.v[e])) * (vp - static_cast<double>(vn.v[e])));
+        add_face<NC>(acc, ft, le, label_byte(ly, e),
+                     (bp - static_cast<double>(by.v[e])) * (vp - static_cast<double>(vy.v[e])));
+        // +z face
+        const double bq = static_cast<double>(e < 3 ? bc.v[e + 1] : bz);
+        const double vq = static_cast<double>(e < 3 ? vc.v[e + 1] : vz);
+        add_face<NC>(acc, ft, le, e < 3 ? label_byte(lc, e + 1) : lz, (bp - bq) * (vp - vq));
+        if (BC) {
+          const int nw = (i == 0) + (i == g.nx - 1) + (j == 0) + (j == g.ny - 1) + (e == 0 && k4 == 0) +
+                         (e == 3 && wall_hi);
+          if (nw) {
+            const double v = bp * vp * nw;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[c] += ft.wall[c * kMaxClasses + le] * v;
+          }
+        }
+      }
+      bc = bn;
+      vc = vn;
+      lc = ln;
+      q += sx4;
+    }
+  }
+  block_accumulate(acc, weight, partial);
+}
+
+// acc[c] += sum over slots b of partial[b][c]: thread t sums the slots
+// b = t, t + 256, ... of every class, then a fixed-order tree over the 256
+// threads (bit-reproducible).
+__global__ __launch_bounds__(kBlock) void k_faceprod_final(const double* __restrict__ partial, int nb,
                                                            double* __restrict__ acc) {
   __shared__ double red[kBlock][kMaxClasses + 1];
   const int t = threadIdx.x;
@@ -103,27 +216,75 @@ __global__ __launch_bounds__(kBlock) void k_faceprod_final(const double* __restr
       for (int c = 0; c < kMaxClasses; ++c) red[t][c] += red[t + half][c];
     __syncthreads();
   }
-  if (t < kMaxClasses) acc[t] += weight * red[0][t];
+  if (t < kMaxClasses) acc[t] += red[0][t];
+}
+
+// Tiling of the vectorised face products: the z-segments of the sweeps'
+// tiling, kFaceLP planes per lane.
+Tiling face_tiling(const Tiling& tl) {
+  Tiling f = tl;
+  f.lp = kFaceLP;
+  return f;
+}
+
+template <typename T, int BC, int NC>
+void faceprod_nc(const Geom& g, const Tiling& tl, bool vec, const uint8_t* labels, const double* dtab,
+                 const double* dwall, const T* yb, const T* y, double weight, double* partial, hipStream_t st) {
+  const dim3 block(kBlock);
+  if (vec) {
+    const Tiling ft = face_tiling(tl);
+    const int rows = kBlock / ft.rw;
+    const int gzs = ((g.nz >> 2) + ft.rw - 1) / ft.rw, gy = (g.ny + rows - 1) / rows;
+    const dim3 grid(static_cast<unsigned>(sweep_blocks(g, ft)));
+    k_faceprod4<T, BC, NC><<<grid, block, 0, st>>>(g, gzs, gy, ft.rw, labels, dtab, dwall, yb, y, weight, partial);
+  } else {
+    k_faceprod<T, BC, NC><<<dim3(kReduceBlocks), block, 0, st>>>(g, labels, dtab, dwall, yb, y, weight, partial);
+  }
+}
+
+template <typename T, int BC>
+void faceprod_bc(const Geom& g, const Tiling& tl, bool vec, const uint8_t* labels, int nclass, const double* dtab,
+                 const double* dwall, const T* yb, const T* y, double weight, double* partial, hipStream_t st) {
+  switch (nclass) {
+    case 1: faceprod_nc<T, BC, 1>(g, tl, vec, labels, dtab, dwall, yb, y, weight, partial, st); break;
+    case 2: faceprod_nc<T, BC, 2>(g, tl, vec, labels, dtab, dwall, yb, y, weight, partial, st); break;
+    case 3: faceprod_nc<T, BC, 3>(g, tl, vec, labels, dtab, dwall, yb, y, weight, partial, st); break;
+    case 4: faceprod_nc<T, BC, 4>(g, tl, vec, labels, dtab, dwall, yb, y, weight, partial, st); break;
+    default: faceprod_nc<T, BC, 8>(g, tl, vec, labels, dtab, dwall, yb, y, weight, partial, st); break;
+  }
+}
+
+template <typename T>
+hipError_t faceprod_typed(expint_bc bc, const Geom& g, const Tiling& tl, const uint8_t* labels, int nclass,
+                          const double* dtab, const double* dwall, const void* ybar, const void* y, double weight,
+                          double* partial, hipStream_t st) {
+  auto* a = static_cast<const T*>(ybar);
+  auto* b = static_cast<const T*>(y);
+  const uintptr_t m = 4 * sizeof(T) - 1;
+  const bool vec = tl.vec && vec_sweep_ok(g, true) && (reinterpret_cast<uintptr_t>(a) & m) == 0 &&
+                   (reinterpret_cast<uintptr_t>(b) & m) == 0 && (reinterpret_cast<uintptr_t>(labels) & 3) == 0;
+  if (bc == EXPINT_NOFLUX) faceprod_bc<T, 0>(g, tl, vec, labels, nclass, dtab, dwall, a, b, weight, partial, st);
+  else faceprod_bc<T, 1>(g, tl, vec, labels, nclass, dtab, dwall, a, b, weight, partial, st);
+  return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_faceprod(expint_dtype dt, expint_bc bc, const Geom& g, const uint8_t* labels, int nclass,
-                           const double* dtab, const double* dwall, const void* ybar, const void* y, double weight,
-                           double* partial, double* acc, hipStream_t st) {
-  const dim3 grid(kReduceBlocks), block(kBlock);
-  if (dt == EXPINT_F64) {
-    auto* a = static_cast<const double*>(ybar);
-    auto* b = static_cast<const double*>(y);
-    if (bc == EXPINT_NOFLUX) k_faceprod<double, 0><<<grid, block, 0, st>>>(g, labels, nclass, dtab, dwall, a, b, partial);
-    else k_faceprod<double, 1><<<grid, block, 0, st>>>(g, labels, nclass, dtab, dwall, a, b, partial);
-  } else {
-    auto* a = static_cast<const float*>(ybar);
-    auto* b = static_cast<const float*>(y);
-    if (bc == EXPINT_NOFLUX) k_faceprod<float, 0><<<grid, block, 0, st>>>(g, labels, nclass, dtab, dwall, a, b, partial);
-    else k_faceprod<float, 1><<<grid, block, 0, st>>>(g, labels, nclass, dtab, dwall, a, b, partial);
-  }
-  k_faceprod_final<<<1, kBlock, 0, st>>>(partial, kReduceBlocks, weight, acc);
+int64_t faceprod_slots(const Geom& g, const Tiling& tl) {
+  int64_t n = kReduceBlocks;
+  if (tl.vec && vec_sweep_ok(g, true)) n = std::max<int64_t>(n, sweep_blocks(g, face_tiling(tl)));
+  return n;
+}
+
+hipError_t launch_faceprod(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const uint8_t* labels,
+                           int nclass, const double* dtab, const double* dwall, const void* ybar, const void* y,
+                           double weight, double* partial, hipStream_t st) {
+  if (dt == EXPINT_F64) return faceprod_typed<double>(bc, g, tl, labels, nclass, dtab, dwall, ybar, y, weight, partial, st);
+  return faceprod_typed<float>(bc, g, tl, labels, nclass, dtab, dwall, ybar, y, weight, partial, st);
+}
+
+hipError_t launch_faceprod_final(const double* partial, int64_t slots, double* acc, hipStream_t st) {
+  k_faceprod_final<<<1, kBlock, 0, st>>>(partial, static_cast<int>(slots), acc);
   return hipGetLastError();
 }
 

@@ -182,7 +182,8 @@ hipError_t autotune_pairs(expint_dtype dt, expint_bc bc, const Geom& g, const Co
       }
     }
   }
-  if (forced || best < t_skip + t_flush) *out = best_t;
+  // pairs only when clearly faster: timing noise must not flip the choice
+  if (forced || best < 0.9f * (t_skip + t_flush)) *out = best_t;
   if (std::getenv("EXPINT_LOG"))
     std::fprintf(stderr, "[expint] pair sweeps %dx%dx%d %s: best ty=%d lp=%d %.2f us vs skip+flush %.2f+%.2f us -> %s\n",
                  g.nx, g.ny, g.nz, dt == EXPINT_F64 ? "f64" : "f32", best_t.ty, best_t.lp, best * 1000.f,

@@ -146,15 +146,22 @@ hipError_t launch_adj_rhs(expint_dtype dt, expint_bc bc, const Geom& g, const Ti
                           const void* gv, const void* u, const void* lam_in, void* lam_out, double rho,
                           hipStream_t st);
 
-// Class-diffusivity derivatives of <ybar, A y> (label form):
-//   acc[c] += weight * ( sum over interior faces p|q of dtab[c][l_p][l_q] (ybar_p - ybar_q)(y_p - y_q)
-//                        + sum over zero-Dirichlet wall faces of dwall[c][l_p] ybar_p y_p )
-// with dtab[c] = -(dK/dD_c)/h^2 and dwall[c][a] = -[a == c]/h^2, so that acc[c]
-// accumulates <ybar, (dA/dD_c) y>.  dtab: 8 x 64 FP64, dwall: 8 x 8 FP64 (device);
-// partial: kReduceBlocks * 8 doubles; acc: 8 doubles.
-hipError_t launch_faceprod(expint_dtype dt, expint_bc bc, const Geom& g, const uint8_t* labels, int nclass,
-                           const double* dtab, const double* dwall, const void* ybar, const void* y, double weight,
-                           double* partial, double* acc, hipStream_t st);
+// Class-diffusivity derivatives of <ybar, A y> (label form), accumulated on
+// the device: workgroup b of the launch adds
+//   weight * ( sum over its interior faces p|q of dtab[c][l_p][l_q] (ybar_p - ybar_q)(y_p - y_q)
+//            + sum over its zero-Dirichlet wall faces of dwall[c][l_p] ybar_p y_p )
+// into partial[b * 8 + c], with dtab[c] = -(dK/dD_c)/h^2 and dwall[c][a] =
+// -[a == c]/h^2, so the slots accumulate <ybar, (dA/dD_c) y>.  The launch
+// uses the z-vectorised form in tiling tl when tl.vec is set and the fields are
+// 4-value aligned, else a scalar grid-stride form; partial needs
+// faceprod_slots(g, tl) * 8 doubles, zeroed before the first launch.
+// launch_faceprod_final adds the slot sums (fixed order) into acc[0..7].
+// dtab: 8 x 64 FP64, dwall: 8 x 8 FP64 (device).
+int64_t faceprod_slots(const Geom& g, const Tiling& tl);
+hipError_t launch_faceprod(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const uint8_t* labels,
+                           int nclass, const double* dtab, const double* dwall, const void* ybar, const void* y,
+                           double weight, double* partial, hipStream_t st);
+hipError_t launch_faceprod_final(const double* partial, int64_t slots, double* acc, hipStream_t st);
 
 // Pointwise helpers.
 hipError_t launch_axpy(expint_dtype dt, int64_t n, double a, const void* x, void* y, hipStream_t st);  // y += a x
