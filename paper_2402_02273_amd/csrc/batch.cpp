@@ -140,7 +140,7 @@ int setup_instance(expint_batch* b, Inst& in, const uint8_t* labels_src) {
   BHIP(hipStreamSynchronize(b->stream));  // also retires the host-array copies above
   if (out[1] != 0.0) return set_error(EXPINT_EINVAL, "a label is >= n_classes (%d)", in.nclass);
   in.norm1 = out[0];
-  BHIP(autotune_sweep(b->dtype, b->bc, in.g, in.coef(), in.ws.y[0], in.ws.acc[0], in.ws.y[1], b->stream, false,
+  BHIP(autotune_sweep(b->dtype, b->bc, in.g, in.coef(), in.ws.y[0], in.ws.acc[0], in.ws.y[1], b->stream, true,
                       &in.tiling));
   return EXPINT_OK;
 }
@@ -157,9 +157,15 @@ int build_schedule(expint_batch* b, void* const* u) {
   destroy_graph(b);
   const int count = static_cast<int>(b->inst.size());
   std::vector<std::vector<TermOp>> per(count);
+  // launch shape per instance: its autotuned tiling, or the scalar default
+  // when the caller's u is not aligned for 4-value vectors
+  std::vector<Tiling> tl(count);
+  const uintptr_t vmask = 4 * dtype_size(b->dtype) - 1;
   for (int i = 0; i < count; ++i) {
     Inst& in = b->inst[i];
     per[i] = phi1_schedule(in.ws, in.s, in.m, b->tau, in.ws.b, nullptr, u[i]);
+    tl[i] = in.tiling;
+    if (tl[i].vec && (reinterpret_cast<uintptr_t>(u[i]) & vmask) != 0) tl[i] = default_tiling(in.g);
   }
   // instances ordered by tile count, largest first, then packed greedily into
   // groups whose working set (u, b, two term buffers, two running sums,
@@ -168,7 +174,7 @@ int build_schedule(expint_batch* b, void* const* u) {
   std::vector<int> order(count);
   for (int i = 0; i < count; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
-    return sweep_blocks(b->inst[a].g, b->inst[a].tiling) > sweep_blocks(b->inst[c].g, b->inst[c].tiling);
+    return sweep_blocks(b->inst[a].g, tl[a]) > sweep_blocks(b->inst[c].g, tl[c]);
   });
   const size_t w = dtype_size(b->dtype);
   size_t budget = static_cast<size_t>(224) << 20;
@@ -203,7 +209,8 @@ int build_schedule(expint_batch* b, void* const* u) {
         };
         for (int i : grp) {
           const Inst& in = b->inst[i];
-          if (in.tiling.lp != lp) continue;
+          const Tiling& ti = tl[i];
+          if (ti.lp != lp) continue;
           if (t == 0) {
             if (fl != kGeneric) continue;
           } else {
@@ -215,10 +222,17 @@ int build_schedule(expint_batch* b, void* const* u) {
           it.nx = in.g.nx;
           it.ny = in.g.ny;
           it.nz = in.g.nz;
-          it.bx = in.tiling.bx;
-          it.by = in.tiling.by;
+          if (ti.vec) {
+            it.vec = 1;
+            it.bx = ti.rw;
+            it.by = kBlock / ti.rw;
+            it.gx = ((in.g.nz >> 2) + ti.rw - 1) / ti.rw;
+          } else {
+            it.bx = ti.bx;
+            it.by = ti.by;
+            it.gx = (in.g.nz + it.bx - 1) / it.bx;
+          }
           it.bx_log2 = it.bx == 64 ? 6 : (it.bx == 32 ? 5 : 4);
-          it.gx = (in.g.nz + it.bx - 1) / it.bx;
           it.gy = (in.g.ny + it.by - 1) / it.by;
           it.labels = in.labels;
           it.rho = in.rho;
@@ -230,7 +244,7 @@ int build_schedule(expint_batch* b, void* const* u) {
           }
           items.push_back(it);
           tabs.insert(tabs.end(), in.tab_host.begin(), in.tab_host.end());
-          L.total += static_cast<int>(sweep_blocks(in.g, in.tiling));
+          L.total += static_cast<int>(sweep_blocks(in.g, ti));
           ++L.nitems;
         }
         close();

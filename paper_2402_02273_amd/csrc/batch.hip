@@ -6,8 +6,9 @@
 // with a stride; a workgroup finds the instance owning tile w by binary search over the per-op
 // block offsets, loads that instance's class table into LDS and runs the same
 // column sweep as the single-grid kernels (sweep_device.hpp) with the
-// instance's own tile shape (bx x by threads of a 1-D workgroup).  The ops of
-// one launch share the term flavour and the plane count lp, which are
+// instance's own tile shape (bx x by threads of a 1-D workgroup, scalar or
+// z-vectorised as the instance's autotuned tiling says).  The ops of one
+// launch share the term flavour and the plane count lp, which are
 // compile-time parameters as in the single-grid kernels.
 // Every workgroup exits after its last work item: no inter-workgroup waits.
 
@@ -62,8 +63,9 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchItem* __restrict__ 
     const int byi = t % it.gy;
     const int i0 = (t / it.gy) * LP;
     const int j = byi * it.by + (static_cast<int>(threadIdx.x) >> it.bx_log2);
-    const int k = bxi * it.bx + (static_cast<int>(threadIdx.x) & (it.bx - 1));
-    if (j < it.ny && k < it.nz) {
+    const int kq = static_cast<int>(threadIdx.x) & (it.bx - 1);
+    const int k = bxi * it.bx + kq;  // vec: the lane's 4-voxel vector index
+    if (j < it.ny && k < (it.vec ? (it.nz >> 2) : it.nz)) {
       Geom g;
       g.nx = it.nx;
       g.ny = it.ny;
@@ -80,7 +82,8 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchItem* __restrict__ 
         a.out = it.op.y_out;
         a.rho = it.rho;
       }
-      sweep_column<T, BC, LP, KIND, FL>(g, cf, st[lo], a, i0, j, k, LP);
+      if (it.vec) sweep_column4<T, BC, LP, KIND, FL>(g, it.labels, st[lo], a, i0, j, k, kq, it.bx);
+      else sweep_column<T, BC, LP, KIND, FL>(g, cf, st[lo], a, i0, j, k, LP);
     }
   }
 }

@@ -118,3 +118,32 @@ def test_c3_full_batch(native):
         err = rel(us[i].cpu().numpy(), ref)
         print(f"[result] c3 instance {i} ({inst.n}^3): rel-L2 vs oracle {err:.2e}", flush=True)
         assert err < 1e-5
+
+
+@pytest.mark.parametrize("tile", ["vec", "scalar"])
+def test_batch_sweep_shapes_vs_oracle(native, monkeypatch, tile):
+    # every instance in one sweep shape; nz % 4 == 0 so the vectorised shape
+    # applies (one instance's u is a misaligned view: it takes the scalar
+    # shape inside the same launches)
+    from paper_2402_02273_amd.expint import ExpIntBatch
+
+    monkeypatch.setenv("EXPINT_TILE", tile)
+    shapes = [(9, 10, 12), (6, 33, 68), (17, 5, 264), (12, 12, 20)]
+    insts = []
+    for i, shape in enumerate(shapes):
+        labels = random_labels(shape, 3, seed=70 + i)
+        insts.append({"labels": labels, "class_D": (0.0, 0.1 + 0.02 * i, 0.01), "rho": 0.02,
+                      "u0": random_field(shape, seed=80 + i) * (labels != 0)})
+    tau, K = 7.3, 3
+    for dtype, tol in ((torch.float64, 1e-10), (torch.float32, 1e-5)):
+        print(f"[case] batch shapes tile={tile} {dtype}", flush=True)
+        b = ExpIntBatch(insts, tau=tau, dtype=dtype, device=DEV)
+        us = [dev(i["u0"], dtype) for i in insts]
+        n3 = int(np.prod(shapes[3]))
+        buf = torch.zeros(n3 + 1, dtype=dtype, device=DEV)
+        us[3] = buf[1:].view(shapes[3])
+        us[3].copy_(dev(insts[3]["u0"], dtype))
+        b.advance(us, K)
+        for i, inst in enumerate(insts):
+            ref, _ = oracle_run(inst, tau, K)
+            assert rel(us[i].cpu().numpy(), ref) < tol, (dtype, i)
