@@ -108,8 +108,6 @@ __global__ __launch_bounds__(kBlock) void k_sweep(Geom g, int gx, int gy, Coef c
 template <typename T, int BC, int LP, int KIND, int FL>
 __global__ __launch_bounds__(kBlock) void k_sweep4(Geom g, int gzs, int gy, int rw, Coef cf, SweepArgs a) {
   __shared__ LdsCoef<T> s;
-  load_tables(s, cf, static_cast<int>(threadIdx.x), kBlock);
-  __syncthreads();
   const int L = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
   const int zs = L % gzs;
   const int t = L / gzs;
@@ -119,8 +117,16 @@ __global__ __launch_bounds__(kBlock) void k_sweep4(Geom g, int gzs, int gy, int 
   const int kq = tid & (rw - 1);
   const int j = yb * (kBlock / rw) + tid / rw;
   const int k4 = zs * rw + kq;
-  if (j >= g.ny || k4 >= (g.nz >> 2)) return;
-  sweep_column4<T, BC, LP, KIND, FL>(g, cf.labels, s, a, i0, j, k4, kq, rw);
+  // the class table is staged after the first field loads are in flight
+  auto ready = [&]() {
+    load_tables(s, cf, tid, kBlock);
+    __syncthreads();
+  };
+  if (j >= g.ny || k4 >= (g.nz >> 2)) {
+    ready();
+    return;
+  }
+  sweep_column4<T, BC, LP, KIND, FL>(g, cf.labels, s, a, i0, j, k4, kq, rw, ready);
 }
 
 // ---------------------------------------------------------------------------

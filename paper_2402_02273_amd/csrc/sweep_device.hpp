@@ -254,14 +254,22 @@ __device__ __forceinline__ void term_store4(const TermOp& op, int q4, const T (&
   }
 }
 
+// No-op for callers whose class tables are already in LDS.
+struct TablesReady {
+  __device__ __forceinline__ void operator()() const {}
+};
+
 // The sweep of one lane: vector k4 (voxels 4 k4 .. 4 k4 + 3) of row j,
 // planes i0 .. i0 + LP - 1 (clipped to the grid); kq is the lane's index in
 // its z-segment of rw lanes.  Lanes outside the grid need not call this: a
 // lane only uses a neighbour's shuffled values when that neighbour is in the
 // same row and inside the grid (else the wall or segment-edge value).
-template <typename T, int BC, int LP, int KIND, int FL>
+// ready() runs after the first plane's loads are issued and before the class
+// table is read: a caller that stages the table there overlaps the two.
+template <typename T, int BC, int LP, int KIND, int FL, typename Ready = TablesReady>
 __device__ __forceinline__ void sweep_column4(const Geom& g, const uint8_t* lab, const LdsCoef<T>& s,
-                                              const SweepArgs& a, int i0, int j, int k4, int kq, int rw) {
+                                              const SweepArgs& a, int i0, int j, int k4, int kq, int rw,
+                                              Ready&& ready = Ready{}) {
   const int nz4 = g.nz >> 2;
   const int sx4 = g.ny * nz4;
   const int dym = j > 0 ? -nz4 : 0, dyp = j < g.ny - 1 ? nz4 : 0;
@@ -274,15 +282,27 @@ __device__ __forceinline__ void sweep_column4(const Geom& g, const uint8_t* lab,
   const int qm0 = i0 > 0 ? q - sx4 : q;
   Vec4<T> xm = ld4<T>(x, qm0), xc = ld4<T>(x, q);
   uint32_t lm = l4[qm0], lc = l4[q];
+  // loads of the plane computed next: +x neighbour, lateral neighbours
+  Vec4<T> fxn, fya, fyb;
+  uint32_t fln, fla, flb;
+  auto fetch = [&](int i, int qq) {
+    const int qn = i < g.nx - 1 ? qq + sx4 : qq;
+    fxn = ld4<T>(x, qn);
+    fln = l4[qn];
+    fya = ld4<T>(x, qq + dym);
+    fyb = ld4<T>(x, qq + dyp);
+    fla = l4[qq + dym];
+    flb = l4[qq + dyp];
+  };
+  fetch(i0, q);
+  ready();
 #pragma unroll
   for (int sp = 0; sp < LP; ++sp) {
     const int i = i0 + sp;
     if (i >= g.nx) break;
-    const int qn = i < g.nx - 1 ? q + sx4 : q;
-    const Vec4<T> xn = ld4<T>(x, qn);
-    const uint32_t ln = l4[qn];
-    const Vec4<T> ya = ld4<T>(x, q + dym), yb = ld4<T>(x, q + dyp);
-    const uint32_t la = l4[q + dym], lb = l4[q + dyp];
+    const Vec4<T> xn = fxn, ya = fya, yb = fyb;
+    const uint32_t ln = fln, la = fla, lb = flb;
+    if (sp + 1 < LP && i + 1 < g.nx) fetch(i + 1, q + sx4);
     // z neighbours of voxels 0 and 3
     T zl = __shfl_up(xc.v[3], 1, rw), zr = __shfl_down(xc.v[0], 1, rw);
     int lzl = label_byte(__shfl_up(lc, 1, rw), 3), lzr = label_byte(__shfl_down(lc, 1, rw), 0);
