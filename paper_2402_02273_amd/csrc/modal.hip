@@ -26,6 +26,8 @@
 #include "modal.hpp"
 
 #include <cstdlib>
+#include <initializer_list>
+#include <type_traits>
 
 namespace expint {
 
@@ -269,10 +271,11 @@ __global__ __launch_bounds__(256) void k_mode(ModalArgs a) {
 //                      the field column block B_p[:, q0 .. q0+32) is read once.
 //   right (z axis):    strip = 32 rows p x all n output modes; the field rows
 //                      are read once.
-// The per-axis operator (n x n hi + lo, <= 256 KB at n = 256) is re-read from
-// L2 by every wavefront.  MT output tiles of 32 are held at once (2, 4 or 8;
-// fp16 needs a second accumulator for its scaled cross terms); larger n loops
-// over blocks of MT tiles, re-reading the field block.
+// The per-axis operator (n x n hi + lo, <= 256 KB at n = 256) is read from
+// L2 by every wavefront; each of its fragments feeds NB (1 or 2) blocks of 32
+// in the other GEMM dimension.  MT output tiles of 32 are held at once (2, 4
+// or 8; fp16 needs a second accumulator for its scaled cross terms); larger n
+// loops over blocks of MT tiles, re-reading the field block.
 // Fragment layouts of v_mfma_f32_32x32x16_{bf16,f16} (checked on the device):
 // A row = lane % 32, B column = lane % 32, k = 8 * (lane / 32) + element;
 // D[row][col] with col = lane % 32, row = 8 (r / 4) + 4 (lane / 32) + r % 4.
@@ -307,7 +310,7 @@ __device__ __forceinline__ void split8(const float (&v)[8], typename Frag<PREC>:
   }
 }
 
-template <int PREC, int EPI, int MT>
+template <int PREC, int EPI, int MT, int NB>
 __global__ __launch_bounds__(256) void k_mode_left_mfma(ModalArgs a) {
   using E = typename Elem<PREC>::E;
   using V = typename Frag<PREC>::V;
@@ -320,75 +323,99 @@ __global__ __launch_bounds__(256) void k_mode_left_mfma(ModalArgs a) {
   const long nn = static_cast<long>(n) * n;
   const E* __restrict__ qlo = qhi + nn;
   const int lane = threadIdx.x & 63;
-  const long strips_per_p = (post + 31) / 32;
+  const long strips_per_p = (post + 32 * NB - 1) / (32 * NB);
   const long strip = static_cast<long>(blockIdx.x) * 4 + (threadIdx.x >> 6);
   if (strip >= strips_per_p * a.pre) return;  // whole wavefront
   const int p = static_cast<int>(strip / strips_per_p);
-  const long q0 = (strip % strips_per_p) * 32;
-  const long col = q0 + (lane & 31);
-  const bool col_ok = col < post;
+  const long q0 = (strip % strips_per_p) * 32 * NB;
+  long col[NB];
+  bool col_ok[NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    col[u] = q0 + 32 * u + (lane & 31);
+    col_ok[u] = col[u] < post;
+  }
   const float* __restrict__ inp = in + static_cast<long>(p) * n * post;
   const int kh = (lane >> 5) * 8;
   for (int mb = 0; mb < n; mb += MT * 32) {
-    f32x16 acc[MT], accx[two_acc ? MT : 1];
+    f32x16 acc[MT][NB], accx[two_acc ? MT : 1][two_acc ? NB : 1];
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      acc[t] = f32x16{};
-      if (two_acc) accx[two_acc ? t : 0] = f32x16{};
-    }
-    // the field fragment of the next K step is loaded before the current
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        acc[t][u] = f32x16{};
+        if (two_acc) accx[two_acc ? t : 0][two_acc ? u : 0] = f32x16{};
+      }
+    // the field fragments of the next K step are loaded before the current
     // step's matrix-core work (one step of register double buffering)
-    float bnext[8];
+    float bnext[NB][8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) bnext[e] = col_ok ? inp[static_cast<long>(kh + e) * post + col] : 0.f;
+    for (int u = 0; u < NB; ++u)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) bnext[u][e] = col_ok[u] ? inp[static_cast<long>(kh + e) * post + col[u]] : 0.f;
     for (int k0 = 0; k0 < n; k0 += 16) {
-      float bv[8];
+      V bh[NB], bl[NB];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) bv[e] = bnext[e];
+      for (int u = 0; u < NB; ++u) {
+        float bv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bv[e] = bnext[u][e];
+        split8<PREC>(bv, bh[u], bl[u]);
+      }
       if (k0 + 16 < n) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) bnext[e] = col_ok ? inp[static_cast<long>(k0 + 16 + kh + e) * post + col] : 0.f;
+        for (int u = 0; u < NB; ++u)
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            bnext[u][e] = col_ok[u] ? inp[static_cast<long>(k0 + 16 + kh + e) * post + col[u]] : 0.f;
       }
-      V bh, bl;
-      split8<PREC>(bv, bh, bl);
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
         const int m = mb + t * 32 + (lane & 31);
         if (mb + t * 32 < n) {
+          // one operator fragment feeds the NB column blocks
           const long off = static_cast<long>(m) * n + k0 + kh;
           const V ah = *reinterpret_cast<const V*>(qhi + off);
           const V al = *reinterpret_cast<const V*>(qlo + off);
-          acc[t] = Frag<PREC>::mma(ah, bh, acc[t]);
-          if (two_acc) {
-            accx[two_acc ? t : 0] = Frag<PREC>::mma(ah, bl, accx[two_acc ? t : 0]);
-            accx[two_acc ? t : 0] = Frag<PREC>::mma(al, bh, accx[two_acc ? t : 0]);
-          } else {
-            acc[t] = Frag<PREC>::mma(ah, bl, acc[t]);
-            acc[t] = Frag<PREC>::mma(al, bh, acc[t]);
+#pragma unroll
+          for (int u = 0; u < NB; ++u) {
+            acc[t][u] = Frag<PREC>::mma(ah, bh[u], acc[t][u]);
+            if (two_acc) {
+              auto& x = accx[two_acc ? t : 0][two_acc ? u : 0];
+              x = Frag<PREC>::mma(ah, bl[u], x);
+              x = Frag<PREC>::mma(al, bh[u], x);
+            } else {
+              acc[t][u] = Frag<PREC>::mma(ah, bl[u], acc[t][u]);
+              acc[t][u] = Frag<PREC>::mma(al, bh[u], acc[t][u]);
+            }
           }
         }
       }
     }
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
-      if (mb + t * 32 >= n || !col_ok) continue;
+      if (mb + t * 32 >= n) continue;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = mb + t * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        float v = acc[t][r];
-        if (two_acc) v += accx[two_acc ? t : 0][r] * (1.0f / kF16LoScale);
-        if (EPI == kEpiMul) {
-          const int jj = static_cast<int>(col / a.nz), kk = static_cast<int>(col % a.nz);
-          const float z = static_cast<float>(a.tauD * (a.lam_x[m] + a.lam_y[jj] + a.lam_z[kk]));
-          v *= phi1_times_tau(z, static_cast<float>(a.tau));
+      for (int u = 0; u < NB; ++u) {
+        if (!col_ok[u]) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int m = mb + t * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          float v = acc[t][u][r];
+          if (two_acc) v += accx[two_acc ? t : 0][two_acc ? u : 0][r] * (1.0f / kF16LoScale);
+          if (EPI == kEpiMul) {
+            const int jj = static_cast<int>(col[u] / a.nz), kk = static_cast<int>(col[u] % a.nz);
+            const float z = static_cast<float>(a.tauD * (a.lam_x[m] + a.lam_y[jj] + a.lam_z[kk]));
+            v *= phi1_times_tau(z, static_cast<float>(a.tau));
+          }
+          out[static_cast<long>(p) * n * post + static_cast<long>(m) * post + col[u]] = v;
         }
-        out[static_cast<long>(p) * n * post + static_cast<long>(m) * post + col] = v;
       }
     }
   }
 }
 
-template <int PREC, int EPI, int NT>
+template <int PREC, int EPI, int NT, int NB>
 __global__ __launch_bounds__(256) void k_mode_right_mfma(ModalArgs a) {
   using E = typename Elem<PREC>::E;
   using V = typename Frag<PREC>::V;
@@ -400,49 +427,68 @@ __global__ __launch_bounds__(256) void k_mode_right_mfma(ModalArgs a) {
   const E* __restrict__ qlo = qhi + static_cast<long>(n) * n;
   const int lane = threadIdx.x & 63;
   const long strip = static_cast<long>(blockIdx.x) * 4 + (threadIdx.x >> 6);
-  const long strips = (pre + 31) / 32;
+  const long strips = (pre + 32 * NB - 1) / (32 * NB);
   if (strip >= strips) return;  // whole wavefront
-  const long p0 = strip * 32;
-  const long prow = p0 + (lane & 31);
-  const bool row_ok = prow < pre;
-  const float* __restrict__ inrow = in + (row_ok ? prow : p0) * n;
+  const long p0 = strip * 32 * NB;
+  bool row_ok[NB];
+  const float* __restrict__ inrow[NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const long prow = p0 + 32 * u + (lane & 31);
+    row_ok[u] = prow < pre;
+    inrow[u] = in + (row_ok[u] ? prow : p0) * n;
+  }
   const int kh = (lane >> 5) * 8;
   for (int nb = 0; nb < n; nb += NT * 32) {
-    f32x16 acc[NT], accx[two_acc ? NT : 1];
+    f32x16 acc[NT][NB], accx[two_acc ? NT : 1][two_acc ? NB : 1];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      acc[t] = f32x16{};
-      if (two_acc) accx[two_acc ? t : 0] = f32x16{};
-    }
-    float4 n0 = *reinterpret_cast<const float4*>(inrow + kh);
-    float4 n1 = *reinterpret_cast<const float4*>(inrow + kh + 4);
-    for (int k0 = 0; k0 < n; k0 += 16) {
-      float av[8];
-      const float4 v0 = n0, v1 = n1;
-      if (k0 + 16 < n) {  // next K step's field fragment, ahead of the matrix-core work
-        n0 = *reinterpret_cast<const float4*>(inrow + k0 + 16 + kh);
-        n1 = *reinterpret_cast<const float4*>(inrow + k0 + 16 + kh + 4);
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        acc[t][u] = f32x16{};
+        if (two_acc) accx[two_acc ? t : 0][two_acc ? u : 0] = f32x16{};
       }
-      av[0] = v0.x; av[1] = v0.y; av[2] = v0.z; av[3] = v0.w;
-      av[4] = v1.x; av[5] = v1.y; av[6] = v1.z; av[7] = v1.w;
-      if (!row_ok)
+    float4 n0[NB], n1[NB];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) av[e] = 0.f;
-      V ah, al;
-      split8<PREC>(av, ah, al);
+    for (int u = 0; u < NB; ++u) {
+      n0[u] = *reinterpret_cast<const float4*>(inrow[u] + kh);
+      n1[u] = *reinterpret_cast<const float4*>(inrow[u] + kh + 4);
+    }
+    for (int k0 = 0; k0 < n; k0 += 16) {
+      V ah[NB], al[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        float av[8] = {n0[u].x, n0[u].y, n0[u].z, n0[u].w, n1[u].x, n1[u].y, n1[u].z, n1[u].w};
+        if (!row_ok[u])
+#pragma unroll
+          for (int e = 0; e < 8; ++e) av[e] = 0.f;
+        split8<PREC>(av, ah[u], al[u]);
+      }
+      if (k0 + 16 < n) {  // next K step's field fragments, ahead of the matrix-core work
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+          n0[u] = *reinterpret_cast<const float4*>(inrow[u] + k0 + 16 + kh);
+          n1[u] = *reinterpret_cast<const float4*>(inrow[u] + k0 + 16 + kh + 4);
+        }
+      }
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         if (nb + t * 32 < n) {
+          // one operator fragment feeds the NB row blocks
           const long off = static_cast<long>(nb + t * 32 + (lane & 31)) * n + k0 + kh;
           const V bh = *reinterpret_cast<const V*>(qhi + off);
           const V bl = *reinterpret_cast<const V*>(qlo + off);
-          acc[t] = Frag<PREC>::mma(ah, bh, acc[t]);
-          if (two_acc) {
-            accx[two_acc ? t : 0] = Frag<PREC>::mma(ah, bl, accx[two_acc ? t : 0]);
-            accx[two_acc ? t : 0] = Frag<PREC>::mma(al, bh, accx[two_acc ? t : 0]);
-          } else {
-            acc[t] = Frag<PREC>::mma(ah, bl, acc[t]);
-            acc[t] = Frag<PREC>::mma(al, bh, acc[t]);
+#pragma unroll
+          for (int u = 0; u < NB; ++u) {
+            acc[t][u] = Frag<PREC>::mma(ah[u], bh, acc[t][u]);
+            if (two_acc) {
+              auto& x = accx[two_acc ? t : 0][two_acc ? u : 0];
+              x = Frag<PREC>::mma(ah[u], bl, x);
+              x = Frag<PREC>::mma(al[u], bh, x);
+            } else {
+              acc[t][u] = Frag<PREC>::mma(ah[u], bl, acc[t][u]);
+              acc[t][u] = Frag<PREC>::mma(al[u], bh, acc[t][u]);
+            }
           }
         }
       }
@@ -452,46 +498,346 @@ __global__ __launch_bounds__(256) void k_mode_right_mfma(ModalArgs a) {
       if (nb + t * 32 >= n) continue;
       const int colk = nb + t * 32 + (lane & 31);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const long row = p0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (row >= pre) continue;
-        float v = acc[t][r];
-        if (two_acc) v += accx[two_acc ? t : 0][r] * (1.0f / kF16LoScale);
-        const long idx = row * n + colk;
-        if (EPI == kEpiAddU) out[idx] = out[idx] + v;
-        else out[idx] = v;
+      for (int u = 0; u < NB; ++u) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const long row = p0 + 32 * u + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          if (row >= pre) continue;
+          float v = acc[t][u][r];
+          if (two_acc) v += accx[two_acc ? t : 0][two_acc ? u : 0][r] * (1.0f / kF16LoScale);
+          const long idx = row * n + colk;
+          if (EPI == kEpiAddU) out[idx] = out[idx] + v;
+          else out[idx] = v;
+        }
       }
     }
   }
 }
 
-// Output tiles held per wavefront: fewer tiles, fewer accumulator registers,
-// more wavefronts in flight (the field block is then re-read from L2).
-int modal_tiles() {
-  static const int t = [] {
-    const char* e = std::getenv("EXPINT_MODAL_TILES");
-    const int v = e ? std::atoi(e) : 4;
-    return (v == 2 || v == 4 || v == 8) ? v : 4;
-  }();
-  return t;
+// ---------------------------------------------------------------------------
+// LDS-staged matrix-core GEMM for the split precisions.  A workgroup of
+// TMW x TNW waves computes a (64 TMW) x (64 TNW) output tile
+// C[m][c] = sum_k A[m][k] B[k][c]; each wave owns a 64 x 64 block = 2 x 2
+// MFMA tiles of 32.  K advances in chunks of 32 staged in LDS (two buffers;
+// the global loads of the next two chunks are held in registers while the
+// current chunk's matrix-core work runs).  Both LDS arrays keep k contiguous
+// per row (A by m, B by c), so a fragment (8 consecutive k of one row or
+// column) is one 16-byte LDS read; the 80-byte row pitch keeps those reads
+// free of bank conflicts.
+//   left  (SIDE 0): A = Qop (n x n, pre-split hi / lo), B[k][c] = in[p][k][q0 + c]
+//                   (fp32, split while staging); C -> out[p][m][q]
+//   right (SIDE 1): A[m][k] = in[p0 + m][k] (fp32, split while staging),
+//                   B[k][c] = Qop[c][k]; C -> out[p0 + m][c]
+// With n = 256 the launch spans all modes in one tile (left 256 x 128, right
+// 128 x 256), so every field element is read from memory once.  Rows and
+// columns beyond the problem are staged as zeros and not stored.
+// ---------------------------------------------------------------------------
+constexpr int GK = 32;       // K chunk
+constexpr int GKP = GK + 8;  // padded LDS row (80 bytes for 16-bit elements)
+
+template <int PREC, int TMW, int TNW>
+struct GemmLds {
+  using E = typename Elem<PREC>::E;
+  alignas(16) E a_hi[2][64 * TMW][GKP];
+  alignas(16) E a_lo[2][64 * TMW][GKP];
+  alignas(16) E b_hi[2][64 * TNW][GKP];
+  alignas(16) E b_lo[2][64 * TNW][GKP];
+};
+
+// NE consecutive 16-bit elements as NE / 8 16-byte vectors.
+template <int NE>
+struct EV {
+  uint4 v[NE / 8];
+};
+
+// v if ok, else zeros; per component (a select of whole uint4 aggregates is
+// lowered to a select of their addresses, which forces them into scratch).
+__device__ __forceinline__ uint4 keep_if(bool ok, const uint4& v) {
+  return make_uint4(ok ? v.x : 0u, ok ? v.y : 0u, ok ? v.z : 0u, ok ? v.w : 0u);
 }
 
-template <int PREC, int SIDE, int EPI, int T>
+template <int PREC, int NE>
+__device__ __forceinline__ void split_n(const float (&v)[NE], EV<NE>& hi, EV<NE>& lo) {
+  using E = typename Elem<PREC>::E;
+  E h[NE], l[NE];
+#pragma unroll
+  for (int e = 0; e < NE; ++e) split<PREC>(v[e], h[e], l[e]);
+  __builtin_memcpy(&hi, h, sizeof(h));
+  __builtin_memcpy(&lo, l, sizeof(l));
+}
+
+template <int PREC, int SIDE, int EPI, int TMW, int TNW>
+__global__ __launch_bounds__(64 * TMW * TNW) void k_mode_gemm(ModalArgs a) {
+  using E = typename Elem<PREC>::E;
+  using V = typename Frag<PREC>::V;
+  constexpr bool two_acc = PREC == kPrecF16;
+  constexpr int NT = 64 * TMW * TNW;  // threads
+  constexpr int GM = 64 * TMW, GN = 64 * TNW;
+  constexpr int EA = GM * GK / NT, EB = GN * GK / NT;  // staged elements per thread of A and B
+  // the operator is A on the left, B on the right; the field the other one
+  constexpr int EO = SIDE == 0 ? EA : EB, EF = SIDE == 0 ? EB : EA;
+  static_assert(EO % 8 == 0 && EF % 4 == 0, "16-byte staging pieces");
+  __shared__ GemmLds<PREC, TMW, TNW> s;
+  const float* __restrict__ in = static_cast<const float*>(a.in);
+  float* __restrict__ out = static_cast<float*>(a.out);
+  const E* __restrict__ qhi = static_cast<const E*>(a.q);
+  const int n = a.n;
+  const E* __restrict__ qlo = qhi + static_cast<long>(n) * n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave / TNW) * 64, wn = (wave % TNW) * 64;  // the wave's block
+
+  // tile coordinates: left: (p, m-tile, column tile); right: (row tile, mode tile)
+  long m0, c0;
+  int p = 0;
+  long mrows, ncols;  // valid rows / columns of the whole problem
+  if (SIDE == 0) {
+    const long ct = (a.post + GN - 1) / GN, mt = (n + GM - 1) / GM;
+    long b = blockIdx.x;
+    const long cti = b % ct;
+    b /= ct;
+    m0 = (b % mt) * GM;
+    p = static_cast<int>(b / mt);
+    c0 = cti * GN;
+    mrows = n;
+    ncols = a.post;
+  } else {
+    const long ct = (n + GN - 1) / GN;
+    m0 = (blockIdx.x / ct) * GM;
+    c0 = (blockIdx.x % ct) * GN;
+    mrows = a.pre;
+    ncols = n;
+  }
+  const float* __restrict__ inp = in + (SIDE == 0 ? static_cast<long>(p) * n * a.post : 0);
+
+  // Staging pieces.  Operator rows (and right-side field rows): thread t ->
+  // row t / (32 / E), k offset (t % (32 / E)) * E.  Left-side field (columns
+  // q, k strided by post): thread t -> column t % GN, k offset (t / GN) * EF.
+  const int orow_l = tid / (GK / EO), ok_ = (tid % (GK / EO)) * EO;
+  const int frow_l = SIDE == 0 ? tid % GN : tid / (GK / EF);
+  const int fk_ = SIDE == 0 ? (tid / GN) * EF : (tid % (GK / EF)) * EF;
+  const long orow = (SIDE == 0 ? m0 : c0) + orow_l;
+  const bool op_ok = orow < (SIDE == 0 ? mrows : ncols);
+  const long orow_c = op_ok ? orow : 0;
+  const long fidx = (SIDE == 0 ? c0 : m0) + frow_l;  // field column (left) / row (right)
+  const bool fld_ok = fidx < (SIDE == 0 ? ncols : mrows);
+  const long fidx_c = fld_ok ? fidx : 0;
+
+  // Two chunks in flight between global load and LDS write.  The operator
+  // part is already split; the field part stays fp32 until the LDS write
+  // (splitting at load time would wait for the load at once).  Loads are
+  // unconditional, at clamped rows / columns, so the number in flight is known
+  // to the compiler; out-of-range rows / columns are zeroed at the LDS write.
+  struct Pending {
+    EV<EO> op_hi, op_lo;
+    float fld[EF];
+  } pend0, pend1;  // named, not an array: a runtime index would put them in scratch
+  auto load_chunk = [&](int k0, Pending& pd) __attribute__((always_inline)) {
+    const long off = orow_c * n + k0 + ok_;
+#pragma unroll
+    for (int i = 0; i < EO / 8; ++i) {
+      pd.op_hi.v[i] = *reinterpret_cast<const uint4*>(qhi + off + 8 * i);
+      pd.op_lo.v[i] = *reinterpret_cast<const uint4*>(qlo + off + 8 * i);
+    }
+    if (SIDE == 0) {
+#pragma unroll
+      for (int e = 0; e < EF; ++e) pd.fld[e] = inp[static_cast<long>(k0 + fk_ + e) * a.post + fidx_c];
+    } else {
+      const float4* src = reinterpret_cast<const float4*>(in + fidx_c * n + k0 + fk_);
+#pragma unroll
+      for (int i = 0; i < EF / 4; ++i) {
+        const float4 f = src[i];
+        pd.fld[4 * i] = f.x;
+        pd.fld[4 * i + 1] = f.y;
+        pd.fld[4 * i + 2] = f.z;
+        pd.fld[4 * i + 3] = f.w;
+      }
+    }
+  };
+  auto store_chunk = [&](const Pending& pd, int buf) __attribute__((always_inline)) {
+    float fv[EF];
+#pragma unroll
+    for (int e = 0; e < EF; ++e) fv[e] = fld_ok ? pd.fld[e] : 0.f;
+    EV<EF> f_hi, f_lo;
+    split_n<PREC, EF>(fv, f_hi, f_lo);
+    E(*ohi)[GKP] = SIDE == 0 ? s.a_hi[buf] : s.b_hi[buf];
+    E(*olo)[GKP] = SIDE == 0 ? s.a_lo[buf] : s.b_lo[buf];
+#pragma unroll
+    for (int i = 0; i < EO / 8; ++i) {
+      *reinterpret_cast<uint4*>(&ohi[orow_l][ok_ + 8 * i]) = keep_if(op_ok, pd.op_hi.v[i]);
+      *reinterpret_cast<uint4*>(&olo[orow_l][ok_ + 8 * i]) = keep_if(op_ok, pd.op_lo.v[i]);
+    }
+    E(*fhi)[GKP] = SIDE == 0 ? s.b_hi[buf] : s.a_hi[buf];
+    E(*flo)[GKP] = SIDE == 0 ? s.b_lo[buf] : s.a_lo[buf];
+#pragma unroll
+    for (int i = 0; i < EF / 8; ++i) {
+      *reinterpret_cast<uint4*>(&fhi[frow_l][fk_ + 8 * i]) = f_hi.v[i];
+      *reinterpret_cast<uint4*>(&flo[frow_l][fk_ + 8 * i]) = f_lo.v[i];
+    }
+  };
+
+  f32x16 acc[2][2], accx[two_acc ? 2 : 1][two_acc ? 2 : 1];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      acc[t][u] = f32x16{};
+      if (two_acc) accx[two_acc ? t : 0][two_acc ? u : 0] = f32x16{};
+    }
+  const int fr = lane & 31, fk = (lane >> 5) * 8;  // fragment row / column and k offset
+  const int nchunks = n / GK;
+  // one chunk: loads of chunk c + 2 into the register set that held chunk c
+  // (already in LDS), the matrix-core work on chunk c, chunk c + 1 from the
+  // other set into the other LDS buffer, barrier
+  auto iteration = [&](int c, auto which) __attribute__((always_inline)) {
+    Pending& ld = decltype(which)::value == 0 ? pend0 : pend1;
+    const Pending& nx = decltype(which)::value == 0 ? pend1 : pend0;
+    const int buf = c & 1;
+    load_chunk(min(c + 2, nchunks - 1) * GK, ld);  // past the end: a harmless reload
+#pragma unroll
+    for (int ks = 0; ks < GK; ks += 16) {
+      V ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        ah[t] = *reinterpret_cast<const V*>(&s.a_hi[buf][wm + 32 * t + fr][ks + fk]);
+        al[t] = *reinterpret_cast<const V*>(&s.a_lo[buf][wm + 32 * t + fr][ks + fk]);
+        bh[t] = *reinterpret_cast<const V*>(&s.b_hi[buf][wn + 32 * t + fr][ks + fk]);
+        bl[t] = *reinterpret_cast<const V*>(&s.b_lo[buf][wn + 32 * t + fr][ks + fk]);
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          acc[t][u] = Frag<PREC>::mma(ah[t], bh[u], acc[t][u]);
+          if (two_acc) {
+            auto& x = accx[two_acc ? t : 0][two_acc ? u : 0];
+            x = Frag<PREC>::mma(ah[t], bl[u], x);
+            x = Frag<PREC>::mma(al[t], bh[u], x);
+          } else {
+            acc[t][u] = Frag<PREC>::mma(ah[t], bl[u], acc[t][u]);
+            acc[t][u] = Frag<PREC>::mma(al[t], bh[u], acc[t][u]);
+          }
+        }
+    }
+    if (c + 1 < nchunks) store_chunk(nx, buf ^ 1);
+    __syncthreads();
+  };
+  load_chunk(0, pend0);
+  load_chunk(min(1, nchunks - 1) * GK, pend1);
+  store_chunk(pend0, 0);
+  __syncthreads();
+  for (int c = 0; c < nchunks; c += 2) {
+    iteration(c, std::integral_constant<int, 0>{});
+    if (c + 1 < nchunks) iteration(c + 1, std::integral_constant<int, 1>{});
+  }
+
+  // epilogue: D[row][col], col = lane % 32, row = 8 (r / 4) + 4 (lane / 32) + r % 4
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const long col = c0 + wn + 32 * u + fr;
+      if (col >= ncols) continue;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const long row = m0 + wm + 32 * t + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (row >= mrows) continue;
+        float v = acc[t][u][r];
+        if (two_acc) v += accx[two_acc ? t : 0][two_acc ? u : 0][r] * (1.0f / kF16LoScale);
+        if (SIDE == 0) {
+          if (EPI == kEpiMul) {
+            const int jj = static_cast<int>(col / a.nz), kk = static_cast<int>(col % a.nz);
+            const float z = static_cast<float>(a.tauD * (a.lam_x[row] + a.lam_y[jj] + a.lam_z[kk]));
+            v *= phi1_times_tau(z, static_cast<float>(a.tau));
+          }
+          out[static_cast<long>(p) * n * a.post + row * a.post + col] = v;
+        } else {
+          const long idx = row * n + col;
+          if (EPI == kEpiAddU) out[idx] = out[idx] + v;
+          else out[idx] = v;
+        }
+      }
+    }
+}
+
+template <int PREC, int SIDE, int EPI, int TMW, int TNW>
+void launch_mode_gemm_t(const ModalArgs& a, hipStream_t st) {
+  constexpr int GM = 64 * TMW, GN = 64 * TNW;
+  long blocks;
+  if (SIDE == 0) blocks = static_cast<long>(a.pre) * ((a.n + GM - 1) / GM) * ((a.post + GN - 1) / GN);
+  else blocks = ((static_cast<long>(a.pre) + GM - 1) / GM) * ((a.n + GN - 1) / GN);
+  k_mode_gemm<PREC, SIDE, EPI, TMW, TNW><<<dim3(static_cast<unsigned>(blocks)), dim3(64 * TMW * TNW), 0, st>>>(a);
+}
+
+// Tile shape: all 256 modes in one tile when n >= 256 (the field is then read
+// once), else 128 x 128.
+template <int PREC, int SIDE, int EPI>
+void launch_mode_gemm(const ModalArgs& a, hipStream_t st) {
+  const char* e = std::getenv("EXPINT_MODAL_GEMM_TILE");
+  const bool big = e ? e[0] == 'b' : a.n >= 256;
+  if (!big) launch_mode_gemm_t<PREC, SIDE, EPI, 2, 2>(a, st);
+  else if (SIDE == 0) launch_mode_gemm_t<PREC, SIDE, EPI, 4, 2>(a, st);
+  else launch_mode_gemm_t<PREC, SIDE, EPI, 2, 4>(a, st);
+}
+
+// Which matrix-core kernel runs the split products: the LDS-staged GEMM
+// (default) or the strip kernels (EXPINT_MODAL_KERNEL=strip).
+bool modal_use_gemm() {
+  const char* e = std::getenv("EXPINT_MODAL_KERNEL");
+  return !(e && e[0] == 's');
+}
+
+// Output tiles held per wavefront (MT): fewer tiles, fewer accumulator
+// registers, more wavefronts in flight (the field block is then re-read from
+// L2).  Blocks of 32 held in the other GEMM dimension (NB, columns for the
+// left product, rows for the right): each operator fragment then feeds NB
+// blocks, which divides the operator's L2 traffic by NB.  Measured defaults
+// at 256^3: bf16 split MT 4, NB 1; fp16 split (two accumulators) MT 2, NB 2.
+// EXPINT_MODAL_TILES / EXPINT_MODAL_NB override them.
+int modal_env(const char* name, int fallback, std::initializer_list<int> allowed) {
+  const char* e = std::getenv(name);
+  if (!e) return fallback;
+  const int v = std::atoi(e);
+  for (int a : allowed)
+    if (v == a) return v;
+  return fallback;
+}
+
+template <int PREC>
+int modal_tiles() {
+  return modal_env("EXPINT_MODAL_TILES", PREC == kPrecF16 ? 2 : 4, {2, 4, 8});
+}
+
+template <int PREC>
+int modal_blocks() {
+  return modal_env("EXPINT_MODAL_NB", PREC == kPrecF16 ? 2 : 1, {1, 2});
+}
+
+template <int PREC, int SIDE, int EPI, int T, int NB>
 void launch_mode_mfma_t(const ModalArgs& a, hipStream_t st) {
   long strips;
-  if (SIDE == 0) strips = static_cast<long>(a.pre) * ((a.post + 31) / 32);
-  else strips = (static_cast<long>(a.pre) + 31) / 32;
+  if (SIDE == 0) strips = static_cast<long>(a.pre) * ((a.post + 32 * NB - 1) / (32 * NB));
+  else strips = (static_cast<long>(a.pre) + 32 * NB - 1) / (32 * NB);
   const dim3 grid(static_cast<unsigned>((strips + 3) / 4)), block(256);
-  if (SIDE == 0) k_mode_left_mfma<PREC, EPI, T><<<grid, block, 0, st>>>(a);
-  else k_mode_right_mfma<PREC, EPI, T><<<grid, block, 0, st>>>(a);
+  if (SIDE == 0) k_mode_left_mfma<PREC, EPI, T, NB><<<grid, block, 0, st>>>(a);
+  else k_mode_right_mfma<PREC, EPI, T, NB><<<grid, block, 0, st>>>(a);
+}
+
+template <int PREC, int SIDE, int EPI, int NB>
+void launch_mode_mfma_nb(const ModalArgs& a, hipStream_t st) {
+  const int t = modal_tiles<PREC>();
+  if (t == 2) launch_mode_mfma_t<PREC, SIDE, EPI, 2, NB>(a, st);
+  else if (t == 8 && PREC == kPrecBF16 && NB == 1) launch_mode_mfma_t<PREC, SIDE, EPI, 8, 1>(a, st);
+  else launch_mode_mfma_t<PREC, SIDE, EPI, 4, NB>(a, st);
 }
 
 template <int PREC, int SIDE, int EPI>
 void launch_mode_mfma(const ModalArgs& a, hipStream_t st) {
-  const int t = modal_tiles();
-  if (t == 2) launch_mode_mfma_t<PREC, SIDE, EPI, 2>(a, st);
-  else if (t == 8 && PREC == kPrecBF16) launch_mode_mfma_t<PREC, SIDE, EPI, 8>(a, st);
-  else launch_mode_mfma_t<PREC, SIDE, EPI, 4>(a, st);
+  if (modal_use_gemm()) {
+    launch_mode_gemm<PREC, SIDE, EPI>(a, st);
+    return;
+  }
+  if (modal_blocks<PREC>() == 2) launch_mode_mfma_nb<PREC, SIDE, EPI, 2>(a, st);
+  else launch_mode_mfma_nb<PREC, SIDE, EPI, 1>(a, st);
 }
 
 template <int PREC, int SIDE, int EPI>
