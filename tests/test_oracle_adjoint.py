@@ -74,3 +74,12 @@ def test_adjoint_of_b_is_forward_action():
     lam0, _, _ = adj.vjp(A_op, u0, 0.0, tau, s, m, 1, e, classes=[])
     expect = e + A_op(it.phi1_action(A_op, e, tau, s, m))
     np.testing.assert_allclose(lam0, expect, atol=1e-14)
+
+
+def test_forward_matches_integrator():
+    # the adjoint's own forward pass is the integrator's step (itself pinned
+    # against expm): a mistake there would be consistent with its reverse pass
+    A_op, factory, u0, target, cd, tau, s, m, _ = _setup(n=8)
+    for rho in (0.0, 0.02):
+        np.testing.assert_allclose(adj._step(A_op, u0, rho, tau, s, m), it.step(A_op, u0, rho, tau, s, m),
+                                   rtol=0, atol=1e-14)
