@@ -246,6 +246,27 @@ int expint_get_stream(const expint_ctx* ctx, void** stream);
  * EXPINT_EUNSUPPORTED.  Uses only the context workspace; synchronises. */
 int expint_profile(expint_ctx* ctx, int32_t kernel, int32_t reps, double* ms);
 
+/* ---- Peak probes (measurement of the device; not part of the method). ---- */
+
+/* Times `reps` copies of `bytes` bytes (a positive multiple of 16, at most
+ * 256 * (2^31 - 1) 16-byte vectors) from src to dst (device buffers, 16-byte
+ * aligned, not overlapping), one 16-byte vector per lane, on `stream`
+ * (hipStream_t, NULL = null stream); writes the mean milliseconds per copy to
+ * *ms (bytes moved per copy = 2 * bytes).  nontemporal != 0 uses
+ * non-temporal loads and stores (the fastest form for HBM streams); 0 uses
+ * ordinary ones (for buffers that stay in the Infinity Cache).  Buffers well
+ * above 256 MB measure HBM; smaller ones the Infinity Cache.  Synchronises.
+ * EXPINT_EINVAL for bad arguments. */
+int expint_probe_copy(const void* src, void* dst, int64_t bytes, int32_t reps, int32_t nontemporal, void* stream,
+                      double* ms);
+
+/* Runs `blocks` workgroups of 4 wavefronts; each wavefront issues `iters` x 8
+ * independent v_mfma_f32_32x32x16 instructions (f16 != 0: fp16 inputs, else
+ * bf16) on register operands.  Writes the executed TFLOP/s (2*32*32*16 flops
+ * per instruction) to *tflops.  sink: device buffer of blocks * 256 floats
+ * that receives the accumulator sums (overwritten).  Synchronises. */
+int expint_probe_mfma(int32_t f16, int32_t iters, int32_t blocks, void* sink, void* stream, double* tflops);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char* expint_last_error(void);
 

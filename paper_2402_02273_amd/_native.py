@@ -121,6 +121,8 @@ SIGNATURES = {
     "expint_batch_destroy": (None, [_P]),
     "expint_get_stream": (_I, [_P, ctypes.POINTER(_P)]),
     "expint_profile": (_I, [_P, _I32, _I32, _DP]),
+    "expint_probe_copy": (_I, [_P, _P, ctypes.c_int64, _I32, _I32, _P, _DP]),
+    "expint_probe_mfma": (_I, [_I32, _I32, _I32, _P, _P, _DP]),
     "expint_last_error": (ctypes.c_char_p, []),
 }
 

@@ -395,3 +395,31 @@ class ExpIntBatch:
             ptrs[i] = u.data_ptr()
         N.check(self.lib.expint_batch_advance(self._b, ptrs, int(nsteps)))
         return us
+
+
+def probe_peaks(device=None, hbm_bytes=1 << 30, cache_bytes=32 << 20, mfma_blocks=2048, mfma_iters=2048):
+    """Attainable peaks of the device, measured by the library's probe kernels:
+    copy bandwidth of an HBM-sized and of an Infinity-Cache-sized buffer
+    (GB/s, bytes read + written) and the executed bf16 / fp16 matrix-core rate
+    (TFLOP/s).  Allocates two buffers of hbm_bytes."""
+    lib = N.lib()
+    device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    out = {}
+    with torch.cuda.device(device):
+        st = torch.cuda.current_stream(device).cuda_stream
+        a = torch.empty(hbm_bytes // 4, dtype=torch.float32, device=device).fill_(1.0)
+        b = torch.empty_like(a)
+        ms = ctypes.c_double()
+        for name, nbytes, reps, nt in (("copy_hbm_GBs", hbm_bytes, 10, 1), ("copy_cache_GBs", cache_bytes, 200, 0)):
+            N.check(lib.expint_probe_copy(a.data_ptr(), b.data_ptr(), int(nbytes), reps, nt, st, ctypes.byref(ms)))
+            out[name] = 2.0 * nbytes / (ms.value * 1e-3) / 1e9
+        del a, b
+        sink = torch.empty(mfma_blocks * 256, dtype=torch.float32, device=device)
+        tf = ctypes.c_double()
+        for name, f16 in (("mfma_bf16_TFLOPs", 0), ("mfma_fp16_TFLOPs", 1)):
+            N.check(lib.expint_probe_mfma(f16, mfma_iters, mfma_blocks, sink.data_ptr(), st, ctypes.byref(tf)))
+            out[name] = tf.value
+    out["note"] = (f"copy of {hbm_bytes >> 20} MiB (non-temporal) and {cache_bytes >> 20} MiB buffers "
+                   f"(one 16-byte vector per lane); "
+                   f"{mfma_blocks} x 4 waves x {mfma_iters} x 8 independent v_mfma_f32_32x32x16")
+    return out

@@ -112,3 +112,14 @@ def test_null_context_calls():
     assert L.expint_get_launch(None, None) == N.EINVAL
     L.expint_destroy(None)  # NULL-safe
     L.expint_batch_destroy(None)
+
+
+def test_probes_reject_bad_arguments():
+    L = N.lib()
+    ms = ctypes.c_double()
+    assert L.expint_probe_copy(None, None, 1024, 1, 0, None, ctypes.byref(ms)) == N.EINVAL
+    assert L.expint_probe_copy(16, 4096, 1000, 1, 0, None, ctypes.byref(ms)) == N.EINVAL  # not a multiple of 16
+    assert L.expint_probe_copy(17, 4096, 1024, 1, 1, None, ctypes.byref(ms)) == N.EINVAL  # misaligned
+    assert L.expint_probe_copy(16, 512, 1024, 1, 0, None, ctypes.byref(ms)) == N.EINVAL  # overlapping
+    assert L.expint_probe_copy(16, 1 << 40, 1 << 45, 1, 1, None, ctypes.byref(ms)) == N.EINVAL  # beyond one launch
+    assert L.expint_probe_mfma(0, 0, 1, 16, None, ctypes.byref(ms)) == N.EINVAL

@@ -336,3 +336,16 @@ def test_profile_kernel_ids(native):
         for k in ("mode_x", "mode_z"):
             with pytest.raises(ExpIntError, match="EINVAL"):
                 ctx.profile(k, reps=3)
+
+
+def test_peak_probes_plausible(native):
+    # the probes measure the device; sanity bounds only (datasheet: 8 TB/s HBM,
+    # 2.5 PFLOP/s dense bf16 / fp16)
+    from paper_2402_02273_amd.expint import probe_peaks
+
+    p = probe_peaks(DEV, hbm_bytes=256 << 20, cache_bytes=16 << 20, mfma_blocks=512, mfma_iters=256)
+    print(f"[result] probes {p}", flush=True)
+    assert 500 < p["copy_hbm_GBs"] < 20000
+    assert 500 < p["copy_cache_GBs"] < 60000
+    assert 50 < p["mfma_bf16_TFLOPs"] < 3000
+    assert 50 < p["mfma_fp16_TFLOPs"] < 3000
