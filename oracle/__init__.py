@@ -21,9 +21,13 @@ Plain, slow, obviously-correct NumPy/SciPy in float64:
 * ``reference``  exact semi-discrete references: dense expm of the augmented
                  matrix, eigen-decomposition, and the separable DCT/DST modal
                  solution for uniform D;
+* ``rosenbrock`` the paper's linearised step: the linear part of the reaction
+                 moved into the matrix, J_n = A + rho diag(1 - 2 u_n), source
+                 rho u_n^2 (section 2.1), stepped by the same phi1 scheme
+                 (exponential Rosenbrock-Euler);
 * ``adjoint``    discrete adjoint (gradients of 0.5||u_T - u_target||^2 with
                  respect to u0, rho and the class diffusivities) and central
                  finite differences.
 """
 
-from . import operator, plan, integrator, reference, adjoint  # noqa: F401
+from . import operator, plan, integrator, reference, adjoint, rosenbrock  # noqa: F401

@@ -15,10 +15,12 @@ import test_oracle_adjoint as T_adj
 import test_oracle_integrator as T_int
 import test_oracle_operator as T_op
 import test_oracle_plan as T_plan
+import test_oracle_rosenbrock as T_rb
 from oracle import adjoint as oadj
 from oracle import integrator as oit
 from oracle import operator as oop
 from oracle import plan as oplan
+from oracle import rosenbrock as orb
 
 
 def caught(*checks):
@@ -212,3 +214,56 @@ def test_adjoint_forward_mutant_caught(monkeypatch):
         return ys
     monkeypatch.setattr(oadj, "taylor_terms", taylor_terms)
     assert caught(T_adj.test_forward_matches_integrator)
+
+
+# ---- mutants of the linearised step (section 2.1's splitting, section 2.2) ----
+
+def rosenbrock_pins():
+    return (
+        lambda: T_rb.test_pure_reaction_closed_form(7.3),
+        lambda: T_rb.test_step_vs_dense_expm("noflux"),
+        T_rb.test_phi1_action_vs_dense,
+        T_rb.test_logistic_second_order_convergence,
+        T_rb.test_rhs_equals_plain_rhs,
+        T_rb.test_uniform_state_takes_scalar_map,
+    )
+
+
+_DIAGONAL_MUTANTS = {
+    "sign": lambda u, rho: rho * (2.0 * np.asarray(u, dtype=np.float64) - 1.0),
+    "factor": lambda u, rho: rho * (1.0 - np.asarray(u, dtype=np.float64)),
+    "none": lambda u, rho: np.zeros_like(np.asarray(u, dtype=np.float64)),
+}
+
+
+@pytest.mark.parametrize("mistake", sorted(_DIAGONAL_MUTANTS))
+def test_rosenbrock_diagonal_mutants_caught(monkeypatch, mistake):
+    monkeypatch.setattr(orb, "jacobian_diagonal", _DIAGONAL_MUTANTS[mistake])
+    assert caught(*rosenbrock_pins()), mistake
+
+
+def test_rosenbrock_source_dropped_caught(monkeypatch):
+    monkeypatch.setattr(orb, "source", lambda u, rho: np.zeros_like(np.asarray(u, dtype=np.float64)))
+    assert caught(*rosenbrock_pins())
+
+
+def test_rosenbrock_whole_reaction_as_source_caught(monkeypatch):
+    # the full reaction kept as the source on top of the linear part moved
+    # into the matrix: the linear part is counted twice
+    monkeypatch.setattr(orb, "source", lambda u, rho: rho * np.asarray(u) * (1.0 - np.asarray(u)))
+    assert caught(*rosenbrock_pins())
+
+
+def test_rosenbrock_phi1_of_A_caught(monkeypatch):
+    # phi1 of A instead of J_n: the plain step, first order
+    monkeypatch.setattr(orb, "phi1_action",
+                        lambda apply_A, u, b, rho, tau, s, m: oit.phi1_action(apply_A, b, tau, s, m))
+    assert caught(*rosenbrock_pins())
+
+
+def test_rosenbrock_jacobian_at_wrong_field_caught(monkeypatch):
+    # J taken at the vector phi1 acts on instead of at the state u_n
+    monkeypatch.setattr(orb, "phi1_action",
+                        lambda apply_A, u, b, rho, tau, s, m: oit.phi1_action(orb.linearised(apply_A, b, rho), b,
+                                                                             tau, s, m))
+    assert caught(*rosenbrock_pins())
