@@ -25,9 +25,13 @@ Plain, slow, obviously-correct NumPy/SciPy in float64:
                  moved into the matrix, J_n = A + rho diag(1 - 2 u_n), source
                  rho u_n^2 (section 2.1), stepped by the same phi1 scheme
                  (exponential Rosenbrock-Euler);
+* ``exprk2``     tau phi1(tau A) b + tau phi2(tau A) d from the augmented matrix
+                 with both columns of its omega block (section 2.2), and the
+                 second-order exponential Runge-Kutta step built on it (the
+                 higher-order extension section 1 mentions);
 * ``adjoint``    discrete adjoint (gradients of 0.5||u_T - u_target||^2 with
                  respect to u0, rho and the class diffusivities) and central
                  finite differences.
 """
 
-from . import operator, plan, integrator, reference, adjoint, rosenbrock  # noqa: F401
+from . import operator, plan, integrator, reference, adjoint, rosenbrock, exprk2  # noqa: F401

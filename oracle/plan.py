@@ -24,6 +24,11 @@ relative accuracy to rounding.
 
 Defaults: FP64 tol = 1e-13, theta_max = ln 1024; FP32 tol = 1e-6,
 theta_max = ln 16.
+
+A lower limit m_min on the degree: the augmented matrix that also carries
+phi2 (both columns of the omega block of section 2.2, with the nilpotent J
+block) reaches its phi2 vector only through the term (hB)^2 / 2, so a scheme
+that needs phi2 takes m >= 2 (at A = 0 the degree-2 truncation is then exact).
 """
 
 from __future__ import annotations
@@ -45,12 +50,14 @@ def remainder_bound(s: int, m: int, theta: float) -> float:
     return t
 
 
-def choose(nu: float, tol: float, theta_max: float, m_max: int = M_MAX):
-    """Return (s, m) for the given nu = tau * ||A||_1."""
+def choose(nu: float, tol: float, theta_max: float, m_max: int = M_MAX, m_min: int = 1):
+    """Return (s, m) for the given nu = tau * ||A||_1, with m >= m_min."""
     if not (nu >= 0.0) or math.isinf(nu):
         raise ValueError("nu must be finite and >= 0")
+    if not 1 <= m_min <= m_max:
+        raise ValueError("need 1 <= m_min <= m_max")
     if nu == 0.0:
-        return 1, 1
+        return 1, m_min
     s = max(1, math.ceil(nu / theta_max))
     # ceil can land one short when nu/theta_max is an integer up to rounding
     while nu / s > theta_max:
@@ -59,7 +66,7 @@ def choose(nu: float, tol: float, theta_max: float, m_max: int = M_MAX):
     while True:
         theta = nu / s
         m_found = None
-        for m in range(1, m_max + 1):
+        for m in range(m_min, m_max + 1):
             if remainder_bound(s, m, theta) <= tol:
                 m_found = m
                 break
@@ -76,6 +83,7 @@ def choose(nu: float, tol: float, theta_max: float, m_max: int = M_MAX):
     return best[1], best[2]
 
 
-def for_dtype(nu: float, dtype: str = "f64", tol: float | None = None, theta_max: float | None = None):
+def for_dtype(nu: float, dtype: str = "f64", tol: float | None = None, theta_max: float | None = None,
+              m_min: int = 1):
     t0, th0 = DEFAULTS[dtype]
-    return choose(nu, t0 if tol is None else tol, th0 if theta_max is None else theta_max)
+    return choose(nu, t0 if tol is None else tol, th0 if theta_max is None else theta_max, m_min=m_min)

@@ -12,11 +12,13 @@ import numpy as np
 import pytest
 
 import test_oracle_adjoint as T_adj
+import test_oracle_exprk2 as T_ek
 import test_oracle_integrator as T_int
 import test_oracle_operator as T_op
 import test_oracle_plan as T_plan
 import test_oracle_rosenbrock as T_rb
 from oracle import adjoint as oadj
+from oracle import exprk2 as oek
 from oracle import integrator as oit
 from oracle import operator as oop
 from oracle import plan as oplan
@@ -190,7 +192,8 @@ def test_remainder_bound_far_too_loose_caught_by_expm(monkeypatch):
 
 def test_theta_cap_ignored_caught(monkeypatch):
     orig = oplan.choose
-    monkeypatch.setattr(oplan, "choose", lambda nu, tol, theta_max, m_max=oplan.M_MAX: orig(nu, tol, 1e9, m_max))
+    monkeypatch.setattr(oplan, "choose",
+                        lambda nu, tol, theta_max, m_max=oplan.M_MAX, m_min=1: orig(nu, tol, 1e9, m_max, m_min))
     assert caught(lambda: T_plan.test_plan_is_exhaustive_optimum(11.39, "f32"))
 
 
@@ -267,3 +270,69 @@ def test_rosenbrock_jacobian_at_wrong_field_caught(monkeypatch):
                         lambda apply_A, u, b, rho, tau, s, m: oit.phi1_action(orb.linearised(apply_A, b, rho), b,
                                                                              tau, s, m))
     assert caught(*rosenbrock_pins())
+
+
+# ---- mutants of the phi1 + phi2 action and the second-order step ----
+
+def exprk2_pins():
+    return (
+        lambda: T_ek.test_phi12_vs_dense_expm_and_eigh("noflux", 7.3),
+        T_ek.test_each_vector_alone,
+        lambda: T_ek.test_low_degree_truncations_are_the_taylor_polynomial((3, 3)),
+        T_ek.test_pure_reaction_is_heun,
+        T_ek.test_logistic_second_order_convergence,
+    )
+
+
+def _phi12_variant(mistake):
+    def phi12_action(apply_A, b, d, tau, s, m):
+        ref = b if b is not None else d
+        zero = np.zeros(np.shape(ref))
+        w2 = zero if b is None else np.asarray(b, dtype=np.float64)
+        w1 = zero if d is None else np.asarray(d, dtype=np.float64) / (1.0 if mistake == "no_scale" else tau)
+        if mistake == "swap":
+            w1, w2 = w2 / tau, w1 * tau
+        h = tau / s
+        x = np.zeros(np.shape(ref))
+        eta = np.array([0.0, 1.0])
+        J = np.array([[0.0, 1.0], [0.0, 0.0]])
+        for _ in range(s):
+            acc, acc_eta = x.copy(), eta.copy()
+            y, ye = x, eta
+            for j in range(1, m + 1):
+                by = apply_A(y) + ye[0] * w1 + ye[1] * w2
+                be = J @ ye
+                y, ye = (h / j) * by, (h / j) * be
+                acc, acc_eta = acc + y, acc_eta + ye
+            x = acc
+            if mistake != "frozen_eta":
+                eta = acc_eta
+        return x
+    return phi12_action
+
+
+@pytest.mark.parametrize("mistake", ["no_scale", "swap", "frozen_eta"])
+def test_phi12_mutants_caught(monkeypatch, mistake):
+    monkeypatch.setattr(oek, "phi12_action", _phi12_variant(mistake))
+    assert caught(*exprk2_pins()), mistake
+
+
+def test_exprk2_correction_sign_caught(monkeypatch):
+    def step(apply_A, u, rho, tau, s, m):
+        u = np.asarray(u, dtype=np.float64)
+        U = u + oek.phi12_action(apply_A, oit.rhs(apply_A, u, rho), None, tau, s, m)
+        d = oit.reaction(u, rho) - oit.reaction(U, rho)
+        return U + oek.phi12_action(apply_A, None, d, tau, s, m)
+    monkeypatch.setattr(oek, "step", step)
+    assert caught(*exprk2_pins())
+
+
+def test_exprk2_correction_through_phi1_caught(monkeypatch):
+    # the correction weighted by phi1 instead of phi2
+    def step(apply_A, u, rho, tau, s, m):
+        u = np.asarray(u, dtype=np.float64)
+        U = u + oek.phi12_action(apply_A, oit.rhs(apply_A, u, rho), None, tau, s, m)
+        d = oit.reaction(U, rho) - oit.reaction(u, rho)
+        return U + oek.phi12_action(apply_A, d, None, tau, s, m)
+    monkeypatch.setattr(oek, "step", step)
+    assert caught(*exprk2_pins())

@@ -37,8 +37,29 @@ def test_plan_is_exhaustive_optimum(nu, dtype):
     assert (s, m) == (best[1], best[2])
 
 
+@pytest.mark.parametrize("nu,dtype", [(0.3, "f64"), (0.05, "f32"), (4.38, "f32"), (11.39, "f64")])
+def test_plan_with_degree_floor_is_exhaustive_optimum(nu, dtype):
+    # the rule restricted to m >= 2 (schemes that need phi2)
+    tol, thmax = plan.DEFAULTS[dtype]
+    s, m = plan.for_dtype(nu, dtype, m_min=2)
+    best = None
+    for ss in range(1, 400):
+        th = nu / ss
+        if th > thmax:
+            continue
+        for mm in range(2, plan.M_MAX + 1):
+            if _bound(ss, mm, th) <= tol:
+                if best is None or ss * mm < best[0] or (ss * mm == best[0] and ss < best[1]):
+                    best = (ss * mm, ss, mm)
+                break
+    assert (s, m) == (best[1], best[2]) and m >= 2
+
+
 def test_plan_zero_operator():
     assert plan.choose(0.0, 1e-13, 1.0) == (1, 1)
+    assert plan.choose(0.0, 1e-13, 1.0, m_min=2) == (1, 2)
+    with pytest.raises(ValueError):
+        plan.choose(1.0, 1e-13, 1.0, m_min=0)
 
 
 def test_plan_rejects_bad_nu():
