@@ -43,19 +43,23 @@ def sweep_bytes(w, reads=(), writes=()):
 
 
 FLUSH_BYTES = lambda w: sweep_bytes(w, reads=("acc",), writes=("y", "acc"))  # noqa: E731
+# the same sweep of the linearised operator also reads u_n
+FLUSH_BYTES_LIN = lambda w: sweep_bytes(w, reads=("acc", "u"), writes=("y", "acc"))  # noqa: E731
 SKIP_BYTES = lambda w: sweep_bytes(w, writes=("y",))  # noqa: E731
 RHS_BYTES = lambda w: sweep_bytes(w, writes=("b",))  # noqa: E731
 # pair sweep inside a sub-step: source, labels, running sum in; second term and sum out
 PAIR_BYTES = lambda w: sweep_bytes(w, reads=("acc",), writes=("y", "acc"))  # noqa: E731
 
 
-def step_bytes_per_voxel(w, s, m):
+def step_bytes_per_voxel(w, s, m, linearised=False):
     """Algorithmic bytes per voxel of one step, sweep by sweep, following the
     library's term schedule: the right-hand side, then per sub-step the Taylor
     terms, which add their terms to the running sum in pairs (a term that
     skips the sum writes only its term; the next one reads the running sum and
     adds both); the first term of a sub-step also reads b; the last sweep of
-    the step reads and writes u instead of storing the sum."""
+    the step reads and writes u instead of storing the sum.  With the
+    linearised operator every term sweep also reads u_n (the last one reads u
+    anyway)."""
     total = RHS_BYTES(w)
     ops = []  # (reads, writes)
     x_zero, x_hb = True, False
@@ -84,8 +88,10 @@ def step_bytes_per_voxel(w, s, m):
                 pend = True
     if not ops:
         ops.append(((), ("acc",)))
+    if linearised:
+        ops = [(r + ("u",), wr) for r, wr in ops]
     r, wr = ops[-1]
-    ops[-1] = (tuple(x for x in r) + ("u",), ("u",))  # u += sum replaces the stored sum
+    ops[-1] = (tuple(x for x in r if x != "u") + ("u",), ("u",))  # u += sum replaces the stored sum
     for r, wr in ops:
         total += sweep_bytes(w, r, wr)
     return total, len(ops) + 1
@@ -129,15 +135,19 @@ def load_traffic(kernel_key, kernel):
     return entry.get("bytes_per_launch")
 
 
-def cpu_baseline(w, nsteps):
+def cpu_baseline(w, nsteps, scheme="exp_euler"):
     import numpy as np
 
-    from oracle import integrator, operator, plan
+    from oracle import integrator, operator, plan, rosenbrock
 
     op = operator.Operator(w.h, labels=w.labels, class_D=w.class_D)
-    s, m = plan.for_dtype(w.tau * op.norm1(), "f64")
     t0 = time.perf_counter()
-    u = integrator.advance(op, w.u0, w.rho, w.tau, s, m, nsteps)
+    if scheme == "linearised":
+        s, m = plan.for_dtype(w.tau * rosenbrock.norm1_bound(op.norm1(), w.rho), "f64")
+        u = rosenbrock.advance(op, w.u0, w.rho, w.tau, s, m, nsteps)
+    else:
+        s, m = plan.for_dtype(w.tau * op.norm1(), "f64")
+        u = integrator.advance(op, w.u0, w.rho, w.tau, s, m, nsteps)
     dt = time.perf_counter() - t0
     assert np.isfinite(u).all()
     return {
@@ -145,7 +155,8 @@ def cpu_baseline(w, nsteps):
         "unit": "voxel-updates/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"{nsteps} FP64 oracle steps of the same 128^3 workload (plan {s}x{m}), NumPy on 1 host thread, {dt:.1f} s",
+        "sample": f"{nsteps} FP64 oracle steps ({scheme}) of the same 128^3 workload (plan {s}x{m}), NumPy on 1 host "
+        f"thread, {dt:.1f} s",
     }
 
 
@@ -160,8 +171,9 @@ def run_c2(args):
     dtype = torch.float32 if args.dtype == "f32" else torch.float64
     w_bytes = 4 if args.dtype == "f32" else 8
     w = c2_head(n=args.n)
+    lin = args.scheme == "linearised"
     ctx = ExpInt(w.shape, w.h, labels=w.labels, class_D=w.class_D, rho=w.rho, tau=w.tau, dtype=dtype, device=dev,
-                 sweeps=args.sweeps)
+                 sweeps="single" if lin else args.sweeps, scheme=args.scheme)
     plan = ctx.plan
     sweeps, ptiling = ctx.sweeps()
     launch = ctx.launch_info()
@@ -191,7 +203,8 @@ def run_c2(args):
 
     rel = None
     if args.n == 128 and args.steps == 100:
-        gpath = os.path.join(ROOT, "tests", "golden", "c2_head_128_u100_f64.npz")
+        gname = "c2l_head_128_u100_f64.npz" if lin else "c2_head_128_u100_f64.npz"
+        gpath = os.path.join(ROOT, "tests", "golden", gname)
         if os.path.exists(gpath):
             g = np.load(gpath)
             got = u.double().cpu().numpy()
@@ -211,6 +224,12 @@ def run_c2(args):
         ms_dom = ms_pair
         traffic = load_traffic(f"pair_{args.dtype}_{args.n}", "k_pair")
         sbv, nlaunch = step_bytes_per_voxel_pairs(w_bytes, plan.s, plan.m)
+    elif lin:
+        kname = "k_sweep term of the linearised operator, pair-flush flavour (stencil + diagonal + Taylor term + sum)"
+        tb = FLUSH_BYTES_LIN(w_bytes) * w.nvox
+        ms_dom = ms_flush
+        traffic = load_traffic(f"flush_lin_{args.dtype}_{args.n}", "k_sweep4" if launch["vec"] else "k_sweep")
+        sbv, nlaunch = step_bytes_per_voxel(w_bytes, plan.s, plan.m, linearised=True)
     else:
         kname = "k_sweep term, pair-flush flavour (stencil + Taylor term + running sum)"
         tb = FLUSH_BYTES(w_bytes) * w.nvox
@@ -238,7 +257,9 @@ def run_c2(args):
         "data": "synthetic",
         "config": {
             "workload": f"{args.n}^3 synthetic head seed 2402, D 0.13/0.013/0 mm^2/day, rho 0.025/day, "
-            f"tau 7.3 d, no-flux, stencil-Taylor",
+            f"tau 7.3 d, no-flux, stencil-Taylor"
+            + (", linearised step (J_n = A + rho diag(1 - 2 u_n))" if lin else ""),
+            "scheme": args.scheme,
             "grid": [args.n] * 3,
             "plan_s_m": [plan.s, plan.m],
             "norm_A1": plan.norm_A1,
@@ -275,7 +296,7 @@ def run_c2(args):
         },
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, args.scheme)
     print(json.dumps(out), flush=True)
 
 
@@ -510,6 +531,8 @@ def main():
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
     ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--scheme", choices=["exp_euler", "linearised"], default="exp_euler",
+                    help="c2: the plain exponential Euler step, or the paper's linearised step")
     ap.add_argument("--sweeps", choices=["auto", "single", "pairs"], default="auto",
                     help="Taylor terms per stencil sweep (auto: timed at context creation)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

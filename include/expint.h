@@ -91,6 +91,25 @@ typedef enum {
   EXPINT_SWEEPS_PAIRS = 2
 } expint_sweeps;
 
+/* The step a context takes.
+ * EXP_EULER: u <- u + tau phi1(tau A)(A u + f(u)), f(u) = rho u (1 - u): the
+ *   reaction frozen at u_n over the step (section 2.2).
+ * LINEARISED: the paper's splitting of the reaction (section 2.1, the
+ *   rewritten F and the new F after it).  The part linear in the new state
+ *   moves into the matrix, J_n = A + rho diag(1 - 2 u_n), leaving the source
+ *   rho u_n^2, and the section 2.2 step is taken with J_n:
+ *   u <- u + tau phi1(tau J_n)(J_n u_n + rho u_n^2), which equals
+ *   u + tau phi1(tau J_n)(A u_n + f(u_n)).  J_n is the Jacobian at u_n, so
+ *   this is exponential Rosenbrock-Euler, second order in tau.  The plan is
+ *   chosen for tau (||A||_1 + rho), which bounds tau ||J_n||_1 for every
+ *   state with 0 <= u <= 1 (the tolerance is not guaranteed outside that
+ *   range).  Stencil-Taylor algorithm with single-term sweeps only; batches
+ *   and gradients give EXPINT_EUNSUPPORTED. */
+typedef enum {
+  EXPINT_SCHEME_EXP_EULER = 0,
+  EXPINT_SCHEME_LINEARISED = 1
+} expint_scheme;
+
 typedef struct {
   int32_t nx, ny, nz; /* voxels per axis, each >= 1 */
   double h;           /* grid spacing (> 0), same unit as sqrt(D * time) */
@@ -120,13 +139,15 @@ typedef struct {
   int32_t s, m;         /* both > 0: use this plan; both 0: choose it */
   int32_t check_finite; /* nonzero: expint_step / expint_advance scan u for NaN/Inf */
   expint_sweeps sweeps; /* term grouping of the stencil-Taylor sweeps */
+  expint_scheme scheme; /* the step: EXP_EULER (default) or LINEARISED */
   void* stream;         /* hipStream_t the context works on; NULL = null stream */
 } expint_opts;
 
 typedef struct expint_ctx expint_ctx;
 
 /* Fill *opts with defaults: F32, tau = 7.3, automatic plan, AUTO algorithm,
- * AUTO sweeps, no check, null stream.  Returns EXPINT_EINVAL for NULL. */
+ * AUTO sweeps, EXP_EULER scheme, no check, null stream.  Returns
+ * EXPINT_EINVAL for NULL. */
 int expint_opts_default(expint_opts* opts);
 
 /* Create a context for one grid, diffusivity field, rho and boundary.
@@ -138,14 +159,17 @@ int expint_opts_default(expint_opts* opts);
  * Errors: EINVAL (NULL pointer, dims < 1, h <= 0, tau <= 0, rho < 0 or not
  * finite, n_classes outside 1..8, class_D < 0 or not finite, a label >=
  * n_classes, D < 0 or not finite, s/m partly set), EUNSUPPORTED (MODAL with a
- * non-uniform D, or mp without MODAL F32), ENOMEM, EHIP.  *out is NULL on error. */
+ * non-uniform D, mp without MODAL F32, LINEARISED with MODAL or PAIRS), ENOMEM,
+ * EHIP.  A LINEARISED context plans for tau*(||A||_1 + rho) in place of
+ * tau*||A||_1.  *out is NULL on error. */
 int expint_create(const expint_grid* grid, const expint_dfield* dfield, double rho,
                   expint_bc bc, const expint_opts* opts, expint_ctx** out);
 
 /* Release the context and its workspace.  NULL-safe. */
 void expint_destroy(expint_ctx* ctx);
 
-/* The plan in use: Taylor scaling s, degree m and ||A||_1 (host scalars). */
+/* The plan in use: Taylor scaling s, degree m and ||A||_1 (host scalars;
+ * ||A||_1 of the diffusion operator alone, also for LINEARISED contexts). */
 int expint_get_plan(const expint_ctx* ctx, int32_t* s, int32_t* m, double* norm_A1);
 
 /* Launch configuration the context resolved at creation (autotuned). */
@@ -178,8 +202,17 @@ int expint_rhs(expint_ctx* ctx, const void* u, void* b);
  * MODAL algorithm, exactly in the mode basis.  b and x must not overlap. */
 int expint_phi1(expint_ctx* ctx, const void* b, void* x);
 
-/* One exponential Euler step, in place: u <- u + tau phi1(tau A)(A u + f(u)).
- * u: device field owned by the caller.  ENONFINITE with check_finite set. */
+/* x = tau phi1(tau J) b with J = A + rho diag(1 - 2 u), the linearised
+ * operator of section 2.1 at the state u, by the scaled Taylor series of
+ * section 2.2 with the context's plan.  LINEARISED contexts only (else
+ * EXPINT_EUNSUPPORTED).  u, b: device fields, read only (they may be the same
+ * field); x: device field, written, overlapping neither u nor b. */
+int expint_phi1_lin(expint_ctx* ctx, const void* u, const void* b, void* x);
+
+/* One step in place, of the context's scheme: EXP_EULER
+ * u <- u + tau phi1(tau A)(A u + f(u)); LINEARISED
+ * u <- u + tau phi1(tau J_n)(A u + f(u)).  u: device field owned by the
+ * caller.  ENONFINITE with check_finite set. */
 int expint_step(expint_ctx* ctx, void* u);
 
 /* nsteps >= 0 steps in place.  The first call for a given u records the step
@@ -197,7 +230,8 @@ int expint_reduce(expint_ctx* ctx, int32_t op, const void* x, const void* y, dou
  * u0, u_target: device fields (read only); grad_u0: device field (written);
  * loss, grad_rho: host scalars; grad_class_D: host array of n_classes
  * (label form only; dense form gives EINVAL).  u is checkpointed every
- * ckpt_every steps (>= 1) and recomputed in between. */
+ * ckpt_every steps (>= 1) and recomputed in between.  EXP_EULER contexts
+ * only (LINEARISED: EXPINT_EUNSUPPORTED). */
 int expint_grad(expint_ctx* ctx, const void* u0, int32_t nsteps, const void* u_target,
                 int32_t ckpt_every, double* loss, void* grad_u0, double* grad_rho,
                 double* grad_class_D);
@@ -213,7 +247,8 @@ typedef struct expint_batch expint_batch;
 /* count instances, each with its own grid, label field, class table and rho
  * (arrays of length count; dfield entries must use the label form).  Shared
  * bc and opts (dtype, tau, tol, theta_max).  Every instance gets its own
- * plan.  Errors as expint_create. */
+ * plan.  Errors as expint_create; the LINEARISED scheme gives
+ * EXPINT_EUNSUPPORTED. */
 int expint_batch_create(int32_t count, const expint_grid* grids, const expint_dfield* dfields,
                         const double* rho, expint_bc bc, const expint_opts* opts,
                         expint_batch** out);

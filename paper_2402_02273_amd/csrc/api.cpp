@@ -144,12 +144,17 @@ int scan_labels(expint_ctx* c, double* bad) {
   return EXPINT_OK;
 }
 
+double plan_norm(const expint_ctx* c) {
+  return c->scheme == EXPINT_SCHEME_LINEARISED ? c->norm1 + c->rho : c->norm1;
+}
+
 int make_plan(expint_ctx* c) {
   if (c->fixed_plan) return EXPINT_OK;
   int s = 0, m = 0;
-  if (!choose_plan(c->tau * c->norm1, c->tol, c->theta_max, &s, &m))
-    return set_error(EXPINT_EINVAL, "no admissible plan for tau*||A||_1 = %g (tol %g, theta_max %g)",
-                     c->tau * c->norm1, c->tol, c->theta_max);
+  const double nu = c->tau * plan_norm(c);
+  if (!choose_plan(nu, c->tol, c->theta_max, &s, &m))
+    return set_error(EXPINT_EINVAL, "no admissible plan for nu = %g (tol %g, theta_max %g)", nu, c->tol,
+                     c->theta_max);
   c->s = s;
   c->m = m;
   return EXPINT_OK;
@@ -180,11 +185,16 @@ std::vector<TermOp> step_schedule(expint_ctx* c, const void* b, void* x_out, voi
   return phi1_schedule(step_buffers(c), c->s, c->m, c->tau, b, x_out, u);
 }
 
-// Launches of one step on c->stream (no synchronisation).
+// Launches of one step on c->stream (no synchronisation).  The right-hand
+// side is A u + f(u) for both schemes (for LINEARISED it is J_n u_n + rho u_n^2,
+// the same field); LINEARISED applies phi1 to J_n, taken at u before the last
+// sweep adds the result into it.
 int enqueue_step(expint_ctx* c, void* u) {
   HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, c->tiling, c->coef(), u, c->b, c->rho, c->stream));
   if (c->algo == EXPINT_ALGO_MODAL) return modal_phi1(c, c->b, u, true);
-  return run_ops(c, step_schedule(c, c->b, nullptr, u));
+  std::vector<TermOp> ops = step_schedule(c, c->b, nullptr, u);
+  if (c->scheme == EXPINT_SCHEME_LINEARISED) set_linearised(ops, u, c->rho);
+  return run_ops(c, ops);
 }
 
 int check_finite_field(expint_ctx* c, const void* u) {
@@ -213,6 +223,8 @@ int validate_opts(const expint_opts* o) {
   if (o->mp < EXPINT_MP_NONE || o->mp > EXPINT_MP_FP16_SPLIT) return set_error(EXPINT_EINVAL, "unknown mp");
   if (o->sweeps < EXPINT_SWEEPS_AUTO || o->sweeps > EXPINT_SWEEPS_PAIRS)
     return set_error(EXPINT_EINVAL, "unknown sweeps");
+  if (o->scheme < EXPINT_SCHEME_EXP_EULER || o->scheme > EXPINT_SCHEME_LINEARISED)
+    return set_error(EXPINT_EINVAL, "unknown scheme");
   return EXPINT_OK;
 }
 
@@ -263,6 +275,10 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
     return set_error(EXPINT_EUNSUPPORTED, "split matrix-core products are for FP32 contexts");
   if (opts->sweeps == EXPINT_SWEEPS_PAIRS && !df->labels)
     return set_error(EXPINT_EUNSUPPORTED, "pair sweeps need the label form of D");
+  if (opts->scheme == EXPINT_SCHEME_LINEARISED && algo == EXPINT_ALGO_MODAL)
+    return set_error(EXPINT_EUNSUPPORTED, "the linearised operator is not separable: no modal path");
+  if (opts->scheme == EXPINT_SCHEME_LINEARISED && opts->sweeps == EXPINT_SWEEPS_PAIRS)
+    return set_error(EXPINT_EUNSUPPORTED, "the linearised scheme uses single-term sweeps");
   if (algo == EXPINT_ALGO_MODAL) {
     if (!df->labels) return set_error(EXPINT_EUNSUPPORTED, "the modal path needs the label form of D");
     if (grid->nx % 32 || grid->ny % 32 || grid->nz % 32)
@@ -284,6 +300,7 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
   c->bc = bc;
   c->algo = algo;
   c->mp = opts->mp;
+  c->scheme = opts->scheme;
   c->rho = rho;
   c->tau = opts->tau;
   default_tolerances(c->dtype, &c->tol, &c->theta_max);
@@ -376,7 +393,7 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
       return bail(set_error(EXPINT_EHIP, "autotune failed: %s", hipGetErrorString(e)));
     }
   }
-  if (c->algo != EXPINT_ALGO_MODAL) {
+  if (c->algo != EXPINT_ALGO_MODAL && c->scheme == EXPINT_SCHEME_EXP_EULER) {
     const hipError_t e = autotune_pairs(c->dtype, c->bc, c->g, c->coef(), c->y[0], c->acc[0], c->y[1], c->stream,
                                         c->tiling, opts->sweeps, &c->ptiling);
     if (e != hipSuccess) {
@@ -386,9 +403,11 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
   }
   if (c->algo == EXPINT_ALGO_MODAL && (rc = modal_setup(c))) return bail(rc);
   if (std::getenv("EXPINT_LOG"))
-    std::fprintf(stderr, "[expint] grid %dx%dx%d h=%g dtype=%s ||A||_1=%.17g nu=%.6g plan s=%d m=%d workspace %zu B\n",
-                 c->g.nx, c->g.ny, c->g.nz, c->h, c->dtype == EXPINT_F64 ? "f64" : "f32", c->norm1,
-                 c->tau * c->norm1, c->s, c->m, c->arena.bytes());
+    std::fprintf(stderr,
+                 "[expint] grid %dx%dx%d h=%g dtype=%s scheme=%s ||A||_1=%.17g nu=%.6g plan s=%d m=%d workspace %zu B\n",
+                 c->g.nx, c->g.ny, c->g.nz, c->h, c->dtype == EXPINT_F64 ? "f64" : "f32",
+                 c->scheme == EXPINT_SCHEME_LINEARISED ? "linearised" : "exp-euler", c->norm1, c->tau * plan_norm(c),
+                 c->s, c->m, c->arena.bytes());
   *out = c;
   expint::clear_error();
   return EXPINT_OK;
@@ -442,9 +461,12 @@ int expint_set_params(expint_ctx* c, double rho, const double* class_D, int32_t 
     if ((rc = upload_tables(c))) return rc;
   }
   c->rho = rho;
-  if (replan && c->labels_form) {
-    double bad = 0.0;
-    if ((rc = scan_labels(c, &bad))) return rc;
+  if (replan) {
+    // ||A||_1 changes with class_D (label form); the LINEARISED bound also with rho
+    if (c->labels_form) {
+      double bad = 0.0;
+      if ((rc = scan_labels(c, &bad))) return rc;
+    }
     if ((rc = make_plan(c))) return rc;
   }
   destroy_graphs(c->graphs);  // rho and the schedule are baked into recorded graphs
@@ -479,6 +501,19 @@ int expint_phi1(expint_ctx* c, const void* b, void* x) {
   if (rc) return rc;
   if (c->algo == EXPINT_ALGO_MODAL) return modal_phi1(c, b, x, false);
   return run_ops(c, step_schedule(c, b, x, nullptr));
+}
+
+int expint_phi1_lin(expint_ctx* c, const void* u, const void* b, void* x) {
+  CHECK_CTX(c);
+  if (!u || !b || !x) return set_error(EXPINT_EINVAL, "NULL field");
+  if (c->scheme != EXPINT_SCHEME_LINEARISED)
+    return set_error(EXPINT_EUNSUPPORTED, "phi1 of the linearised operator needs a LINEARISED context");
+  if (b == x || u == x) return set_error(EXPINT_EINVAL, "x must overlap neither u nor b");
+  int rc = ensure_device(c);
+  if (rc) return rc;
+  std::vector<TermOp> ops = step_schedule(c, b, x, nullptr);
+  set_linearised(ops, u, c->rho);
+  return run_ops(c, ops);
 }
 
 int expint_step(expint_ctx* c, void* u) {
@@ -564,7 +599,8 @@ int expint_profile(expint_ctx* c, int32_t kernel, int32_t reps, double* ms) {
   // 0 = pair-flush term (src y0, running sum updated in place, y1 written),
   // 1 = skip term (src y0, y1 written), 2 = right-hand side (u = acc1, b),
   // 5 = pair sweep inside a sub-step (src y0, two terms added to the running
-  // sum in place, the second term written to y1).
+  // sum in place, the second term written to y1).  LINEARISED contexts time
+  // 0 and 1 as sweeps of the linearised operator (u_n = acc1).
   TermOp op;
   op.src = c->y[0];
   op.c = c->tau / c->s / 2.0;
@@ -580,6 +616,10 @@ int expint_profile(expint_ctx* c, int32_t kernel, int32_t reps, double* ms) {
     op.c2 = c->tau / c->s / 3.0;
   } else {
     classify_term(op);
+  }
+  if ((kernel == 0 || kernel == 1) && c->scheme == EXPINT_SCHEME_LINEARISED) {
+    op.ju = c->acc[1];  // the state u_n (filled below)
+    op.jrho = c->rho;
   }
   const Coef cf = c->coef();
   ModalArgs ma;

@@ -308,6 +308,8 @@ int expint_batch_create(int32_t count, const expint_grid* grids, const expint_df
   if (!(opts->tol >= 0.0) || !(opts->theta_max >= 0.0)) return set_error(EXPINT_EINVAL, "bad tolerances");
   if (opts->algo == EXPINT_ALGO_MODAL || opts->mp != EXPINT_MP_NONE)
     return set_error(EXPINT_EUNSUPPORTED, "batches run the stencil-Taylor path only");
+  if (opts->scheme != EXPINT_SCHEME_EXP_EULER)
+    return set_error(EXPINT_EUNSUPPORTED, "batches take the EXP_EULER scheme");
   for (int i = 0; i < count; ++i) {
     const expint_grid& g = grids[i];
     const expint_dfield& d = dfields[i];

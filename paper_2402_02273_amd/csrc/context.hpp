@@ -68,6 +68,7 @@ struct expint_ctx {
   expint_bc bc = EXPINT_NOFLUX;
   expint_algo algo = EXPINT_ALGO_STENCIL_TAYLOR;
   expint_mp mp = EXPINT_MP_NONE;
+  expint_scheme scheme = EXPINT_SCHEME_EXP_EULER;
   double rho = 0.0, tau = 0.0, tol = 0.0, theta_max = 0.0;
   bool fixed_plan = false;
   int s = 1, m = 1;
@@ -161,6 +162,8 @@ int run_ops(expint_ctx* c, const std::vector<TermOp>& ops);
 // The Taylor sweeps of tau phi1(tau A) b for this context's plan: pair sweeps
 // when the context uses them, else one sweep per term (see phi1_schedule).
 std::vector<TermOp> step_schedule(expint_ctx* c, const void* b, void* x_out, void* u);
+// ||A||_1 for EXP_EULER, ||A||_1 + rho (a bound on ||J_n||_1) for LINEARISED.
+double plan_norm(const expint_ctx* c);
 int check_finite_field(expint_ctx* c, const void* u);
 // modal path (modal_host.cpp)
 int modal_setup(expint_ctx* c);

@@ -81,6 +81,11 @@ enum TermFlavor {
 };
 
 //
+// ju != NULL makes the sweep one of the linearised operator
+// J = A + rho diag(1 - 2 u_n): a = A src + jrho (1 - 2 ju) src, with ju = u_n
+// read at each voxel only (so ju may be the u the last sweep adds into).
+// Single-term sweeps only.
+//
 // A pair sweep (pair != 0, label form only) evaluates two consecutive terms:
 //   y   = c * A src + cb * bsrc                (term j, kept on chip)
 //   w   = c2 * A y                             (term j + 1)
@@ -98,6 +103,8 @@ struct TermOp {
   void* u = nullptr;
   double c = 0.0, cb = 0.0, ca = 0.0, cs = 0.0;
   double c2 = 0.0;
+  const void* ju = nullptr;
+  double jrho = 0.0;
   int flavor = kGeneric;
   int pair = 0;
 };
@@ -120,6 +127,9 @@ hipError_t launch_pair(expint_dtype dt, expint_bc bc, const Geom& g, const PairT
                        const TermOp& op, hipStream_t st);
 hipError_t launch_term(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,
                        const TermOp& op, hipStream_t st);
+// launch_term for op.ju != NULL (stencil_lin.hip)
+hipError_t launch_term_lin(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,
+                           const TermOp& op, hipStream_t st);
 hipError_t launch_rhs(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf, const void* u,
                       void* b, double rho, hipStream_t st);
 hipError_t launch_apply(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,

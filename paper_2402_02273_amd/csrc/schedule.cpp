@@ -171,4 +171,11 @@ std::vector<TermOp> phi1_schedule_pairs(const StepBuffers& ws, int s, int m, dou
   return ops;
 }
 
+void set_linearised(std::vector<TermOp>& ops, const void* un, double rho) {
+  for (TermOp& t : ops) {
+    t.ju = un;
+    t.jrho = rho;
+  }
+}
+
 }  // namespace expint

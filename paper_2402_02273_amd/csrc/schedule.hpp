@@ -40,4 +40,10 @@ std::vector<TermOp> phi1_schedule(const StepBuffers& ws, int s, int m, double ta
 std::vector<TermOp> phi1_schedule_pairs(const StepBuffers& ws, int s, int m, double tau, const void* b,
                                         void* x_out, void* u);
 
+// Turns every sweep of a schedule into a sweep of the linearised operator
+// J = A + rho diag(1 - 2 u_n) (TermOp::ju), so the schedule evaluates
+// x = tau phi1(tau J) b.  un is read at each voxel by the sweep that writes
+// that voxel only, so it may be the u the last sweep adds into.
+void set_linearised(std::vector<TermOp>& ops, const void* un, double rho);
+
 }  // namespace expint

@@ -43,8 +43,12 @@ __device__ __forceinline__ int xcd_remap(int L, int nb) {
   return L;
 }
 
-enum SweepKind { kTerm = 0, kRhs = 1, kApply = 2, kAdjRhs = 3 };
+// kTermJ is a Taylor-term sweep of the linearised operator
+// J = A + rho diag(1 - 2 u_n) (TermOp::ju, TermOp::jrho): the diagonal term is
+// added to the stencil result before the term's outputs are formed.
+enum SweepKind { kTerm = 0, kRhs = 1, kApply = 2, kAdjRhs = 3, kTermJ = 4 };
 constexpr int kRuntimeFlavor = -1;
+__host__ __device__ constexpr bool is_term(int kind) { return kind == kTerm || kind == kTermJ; }
 
 struct SweepArgs {
   TermOp op;          // kTerm
@@ -105,7 +109,7 @@ __device__ __forceinline__ void sweep_column(const Geom& g, const Coef& cf, cons
   const int dym = j > 0 ? -g.nz : 0, dyp = j < g.ny - 1 ? g.nz : 0;
   const int dzm = k > 0 ? -1 : 0, dzp = k < g.nz - 1 ? 1 : 0;
   const int wall_yz = BC ? (j == 0) + (j == g.ny - 1) + (k == 0) + (k == g.nz - 1) : 0;
-  const T* __restrict__ x = static_cast<const T*>(KIND == kTerm ? a.op.src : a.x);
+  const T* __restrict__ x = static_cast<const T*>(is_term(KIND) ? a.op.src : a.x);
   const uint8_t* __restrict__ lab = cf.labels;
   const T* __restrict__ fx = static_cast<const T*>(cf.fx);
   const T* __restrict__ fy = static_cast<const T*>(cf.fy);
@@ -145,7 +149,12 @@ __device__ __forceinline__ void sweep_column(const Geom& g, const Coef& cf, cons
       if (BC) ax -= static_cast<const T*>(cf.wallv)[q] * xc * T(wall_yz + (i == 0) + (i == g.nx - 1));
       km = kp;
     }
-    if (KIND == kTerm) {
+    if (KIND == kTermJ) {
+      // u_n at this voxel only; a last sweep that adds into u_n reads it first
+      const T d = static_cast<T>(a.op.jrho) * (T(1) - T(2) * static_cast<const T*>(a.op.ju)[q]);
+      ax += d * xc;
+    }
+    if (is_term(KIND)) {
       if (FL == kRuntimeFlavor) term_store_runtime<T>(a.op, q, ax, xc);
       else term_store<T, FL>(a.op, q, ax, xc);
     } else if (KIND == kRhs) {
@@ -276,14 +285,15 @@ __device__ __forceinline__ void sweep_column4(const Geom& g, const uint8_t* lab,
   const bool wall_lo = k4 == 0, wall_hi = k4 == nz4 - 1;          // z walls
   const bool edge_lo = !wall_lo && kq == 0, edge_hi = !wall_hi && kq == rw - 1;  // segment edges in the row
   const int wall_y = BC ? (j == 0) + (j == g.ny - 1) : 0;
-  const T* __restrict__ x = static_cast<const T*>(KIND == kTerm ? a.op.src : a.x);
+  const T* __restrict__ x = static_cast<const T*>(is_term(KIND) ? a.op.src : a.x);
   const uint32_t* __restrict__ l4 = reinterpret_cast<const uint32_t*>(lab);
   int q = (i0 * g.ny + j) * nz4 + k4;
   const int qm0 = i0 > 0 ? q - sx4 : q;
   Vec4<T> xm = ld4<T>(x, qm0), xc = ld4<T>(x, q);
   uint32_t lm = l4[qm0], lc = l4[q];
   // loads of the plane computed next: +x neighbour, lateral neighbours
-  Vec4<T> fxn, fya, fyb;
+  // (kTermJ: and u_n of the plane itself)
+  Vec4<T> fxn, fya, fyb, fun;
   uint32_t fln, fla, flb;
   auto fetch = [&](int i, int qq) {
     const int qn = i < g.nx - 1 ? qq + sx4 : qq;
@@ -293,6 +303,7 @@ __device__ __forceinline__ void sweep_column4(const Geom& g, const uint8_t* lab,
     fyb = ld4<T>(x, qq + dyp);
     fla = l4[qq + dym];
     flb = l4[qq + dyp];
+    if (KIND == kTermJ) fun = ld4<T>(a.op.ju, qq);
   };
   fetch(i0, q);
   ready();
@@ -300,7 +311,7 @@ __device__ __forceinline__ void sweep_column4(const Geom& g, const uint8_t* lab,
   for (int sp = 0; sp < LP; ++sp) {
     const int i = i0 + sp;
     if (i >= g.nx) break;
-    const Vec4<T> xn = fxn, ya = fya, yb = fyb;
+    const Vec4<T> xn = fxn, ya = fya, yb = fyb, un = fun;
     const uint32_t ln = fln, la = fla, lb = flb;
     if (sp + 1 < LP && i + 1 < g.nx) fetch(i + 1, q + sx4);
     // z neighbours of voxels 0 and 3
@@ -338,8 +349,12 @@ __device__ __forceinline__ void sweep_column4(const Geom& g, const uint8_t* lab,
         const int nw = wall_x + (e == 0 && wall_lo) + (e == 3 && wall_hi);
         ax[e] -= s.wall[le] * v * T(nw);
       }
+      if (KIND == kTermJ) {
+        const T d = static_cast<T>(a.op.jrho) * (T(1) - T(2) * un.v[e]);
+        ax[e] += d * v;
+      }
     }
-    if (KIND == kTerm) {
+    if (is_term(KIND)) {
       term_store4<T, FL>(a.op, q, ax, xc);
     } else if (KIND == kRhs) {
       Vec4<T> o;

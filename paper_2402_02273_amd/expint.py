@@ -22,6 +22,7 @@ _BCS = {"noflux": N.NOFLUX, "dirichlet0": N.DIRICHLET0}
 _ALGOS = {"auto": N.ALGO_AUTO, "stencil_taylor": N.ALGO_STENCIL_TAYLOR, "modal": N.ALGO_MODAL}
 _MPS = {"none": N.MP_NONE, "bf16_split": N.MP_BF16_SPLIT, "fp16_split": N.MP_FP16_SPLIT}
 _SWEEPS = {"auto": N.SWEEPS_AUTO, "single": N.SWEEPS_SINGLE, "pairs": N.SWEEPS_PAIRS}
+_SCHEMES = {"exp_euler": N.SCHEME_EXP_EULER, "linearised": N.SCHEME_LINEARISED}
 
 
 @dataclass
@@ -47,7 +48,11 @@ def _as_device(x, device, dtype):
 
 
 class ExpInt:
-    """One exponential-Euler integrator context on one GPU."""
+    """One exponential integrator context on one GPU.
+
+    scheme="exp_euler" steps u + tau phi1(tau A)(A u + f(u)); scheme="linearised"
+    takes the paper's splitting of the reaction, u + tau phi1(tau J_n)(A u + f(u))
+    with J_n = A + rho diag(1 - 2 u_n) (exponential Rosenbrock-Euler)."""
 
     def __init__(
         self,
@@ -69,6 +74,7 @@ class ExpInt:
         mp: str = "none",
         check_finite: bool = False,
         sweeps: str = "auto",
+        scheme: str = "exp_euler",
         device=None,
         stream=None,
     ):
@@ -124,6 +130,8 @@ class ExpInt:
         opts.m = int(m)
         opts.check_finite = int(bool(check_finite))
         opts.sweeps = _SWEEPS[sweeps]
+        opts.scheme = _SCHEMES[scheme]
+        self.scheme = scheme
         with torch.cuda.device(self.device):
             opts.stream = _stream_handle(stream, self.device)
             N.check(
@@ -220,6 +228,13 @@ class ExpInt:
     def phi1(self, b, out=None):
         out = self.empty() if out is None else out
         N.check(self.lib.expint_phi1(self._ctx, self._field(b, "b"), self._field(out, "out")))
+        return out
+
+    def phi1_lin(self, u, b, out=None):
+        """tau phi1(tau J) b with J = A + rho diag(1 - 2 u) (linearised contexts)."""
+        out = self.empty() if out is None else out
+        N.check(self.lib.expint_phi1_lin(self._ctx, self._field(u, "u"), self._field(b, "b"),
+                                         self._field(out, "out")))
         return out
 
     def step(self, u):

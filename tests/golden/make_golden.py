@@ -4,6 +4,7 @@ Calls only ``oracle/`` (FP64, CPU) on inputs from ``workloads``.  Run from
 the repository root:
 
     python tests/golden/make_golden.py c2      # 128^3 head, 100 steps (~12 min)
+    python tests/golden/make_golden.py c2l     # the same with the linearised step (~13 min)
     python tests/golden/make_golden.py c4      # 96^3 gradients, 50 steps (~15 min)
 
 Each file records the plan, the input hashes and the oracle result.
@@ -19,7 +20,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from oracle import adjoint, integrator, operator, plan  # noqa: E402
+from oracle import adjoint, integrator, operator, plan, rosenbrock  # noqa: E402
 from workloads import c2_head, c4_adjoint  # noqa: E402
 from workloads.configs import c4_synthetic_target  # noqa: E402
 
@@ -43,6 +44,35 @@ def make_c2(n=128, nsteps=100):
 
     u = integrator.advance(op, w.u0, w.rho, w.tau, s, m, nsteps, callback=progress)
     out = os.path.join(HERE, f"c2_head_{n}_u{nsteps}_f64.npz")
+    np.savez_compressed(
+        out,
+        u=u,
+        s=s,
+        m=m,
+        norm1=op.norm1(),
+        labels_sha256=digest(w.labels),
+        u0_sha256=digest(w.u0),
+        rho=w.rho,
+        tau=w.tau,
+        class_D=np.asarray(w.class_D),
+    )
+    print("wrote", out, "plan", (s, m), "seconds", round(time.time() - t0, 1))
+
+
+def make_c2l(n=128, nsteps=100):
+    """The headline head run with the linearised step (section 2.1's
+    splitting), plan chosen for tau (||A||_1 + rho)."""
+    w = c2_head(n=n, nsteps=nsteps)
+    op = operator.Operator(w.h, labels=w.labels, class_D=w.class_D)
+    s, m = plan.for_dtype(w.tau * rosenbrock.norm1_bound(op.norm1(), w.rho), "f64")
+    t0 = time.time()
+
+    def progress(k, u):
+        if k % 10 == 0:
+            print(f"step {k}/{nsteps}  {time.time() - t0:.0f}s", flush=True)
+
+    u = rosenbrock.advance(op, w.u0, w.rho, w.tau, s, m, nsteps, callback=progress)
+    out = os.path.join(HERE, f"c2l_head_{n}_u{nsteps}_f64.npz")
     np.savez_compressed(
         out,
         u=u,
@@ -86,6 +116,8 @@ if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "c2"
     if which == "c2":
         make_c2()
+    elif which == "c2l":
+        make_c2l()
     elif which == "c4":
         make_c4()
     else:

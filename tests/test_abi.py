@@ -62,6 +62,7 @@ def _labels_df():
         (lambda g, d, o: d.__setattr__("D", 99), "exactly one"),
         (lambda g, d, o: o.__setitem__("dtype", 7), "dtype"),
         (lambda g, d, o: o.__setitem__("sweeps", 3), "sweeps"),
+        (lambda g, d, o: o.__setitem__("scheme", 2), "scheme"),
     ],
 )
 def test_create_rejects_invalid_arguments(change, needle):
@@ -104,8 +105,29 @@ def test_pair_sweeps_need_label_form():
     assert rc == N.EUNSUPPORTED and "label form" in N.last_error()
 
 
+def test_linearised_scheme_limits_rejected_before_hip():
+    df, cd = _labels_df()
+    lin = N.SCHEME_LINEARISED
+    rc, _ = _create(N.Grid(32, 32, 32, 1.0), df, algo=N.ALGO_MODAL, scheme=lin)
+    assert rc == N.EUNSUPPORTED and "separable" in N.last_error()
+    rc, _ = _create(N.Grid(8, 8, 8, 1.0), df, sweeps=N.SWEEPS_PAIRS, scheme=lin)
+    assert rc == N.EUNSUPPORTED and "single-term" in N.last_error()
+    L = N.lib()
+    o = N.Opts()
+    L.expint_opts_default(ctypes.byref(o))
+    assert o.scheme == N.SCHEME_EXP_EULER
+    o.scheme = lin
+    grids = (N.Grid * 1)(N.Grid(8, 8, 8, 1.0))
+    dfs = (N.DField * 1)(df)
+    rho = (ctypes.c_double * 1)(0.025)
+    b = ctypes.c_void_p()
+    assert L.expint_batch_create(1, grids, dfs, rho, N.NOFLUX, ctypes.byref(o), ctypes.byref(b)) == N.EUNSUPPORTED
+    assert "EXP_EULER" in N.last_error()
+
+
 def test_null_context_calls():
     L = N.lib()
+    assert L.expint_phi1_lin(None, None, None, None) == N.EINVAL
     assert L.expint_step(None, None) == N.EINVAL
     assert L.expint_advance(None, None, 1) == N.EINVAL
     assert L.expint_get_plan(None, None, None, None) == N.EINVAL

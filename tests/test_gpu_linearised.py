@@ -1,0 +1,253 @@
+"""GPU parity of the linearised step (section 2.1's splitting of the reaction,
+J_n = A + rho diag(1 - 2 u_n), stepped by section 2.2's phi1 scheme) against
+the FP64 oracle.
+
+Both sweep shapes are covered: EXPINT_TILE=scalar forces the scalar sweep,
+EXPINT_TILE=vec the z-vectorised one (shapes with nz % 4 == 0).  Shapes have
+ragged tails in every axis, nz > 256 gives two z-segments per row, and
+(1, 1, 4) is the smallest grid the vectorised sweep takes.
+"""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import operator as oop
+from oracle import plan as oplan
+from oracle import rosenbrock as orb
+from workloads import c2_head
+from workloads.configs import make_ragged, random_field, random_labels
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+CLASS_D = (0.0, 0.13, 0.013)
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+SHAPES = [(1, 1, 4), (5, 7, 12), (17, 33, 68), (9, 130, 20), (3, 5, 264), (6, 3, 520)]
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
+
+
+@pytest.fixture(params=["scalar", "vec"])
+def tile(request, monkeypatch):
+    monkeypatch.setenv("EXPINT_TILE", request.param)
+    return request.param
+
+
+def make_ctx(labels, class_D, dtype, tile=None, **kw):
+    from paper_2402_02273_amd.expint import ExpInt
+
+    ctx = ExpInt(labels.shape, labels=labels, class_D=class_D, dtype=dtype, device=DEV, scheme="linearised", **kw)
+    info = ctx.launch_info()
+    print(f"[case] shape={labels.shape} dtype={dtype} {kw} plan={(ctx.plan.s, ctx.plan.m)} launch={info}", flush=True)
+    assert info["sweeps"] == 1  # single-term sweeps
+    if tile is not None:
+        assert info["vec"] == (1 if tile == "vec" else 0)
+    return ctx
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("bc", ["noflux", "dirichlet0"])
+def test_phi1_lin_vs_oracle(native, tile, shape, bc):
+    labels = random_labels(shape, 3, seed=sum(shape) + 3)
+    u = random_field(shape, seed=4)
+    b = random_field(shape, seed=5, lo=-1, hi=1)
+    op = oop.Operator(0.8, bc=bc, labels=labels, class_D=CLASS_D)
+    rho, tau = 0.05, 7.3
+    for dtype, tol in ((torch.float64, 1e-13), (torch.float32, 2e-6)):
+        ctx = make_ctx(labels, CLASS_D, dtype, tile, bc=bc, rho=rho, tau=tau, h=0.8)
+        p = ctx.plan
+        ref = orb.phi1_action(op, u, b, rho, tau, p.s, p.m)
+        got = ctx.phi1_lin(dev(u, dtype), dev(b, dtype)).cpu().numpy()
+        assert rel_l2(got, ref) < tol
+        # u and b may be the same field
+        ref_same = orb.phi1_action(op, u, u, rho, tau, p.s, p.m)
+        uu = dev(u, dtype)
+        got_same = ctx.phi1_lin(uu, uu).cpu().numpy()
+        assert rel_l2(got_same, ref_same) < tol
+
+
+@pytest.mark.parametrize("shape", [(5, 7, 12), (20, 17, 36), (7, 40, 264)])
+@pytest.mark.parametrize("sm", [(1, 1), (1, 2), (1, 5), (2, 1), (3, 4)])
+def test_fixed_plans_same_polynomial(native, tile, shape, sm):
+    # every schedule shape (the m = 1 and m = 2 shortcuts included) with the
+    # diagonal term in each sweep
+    labels = random_labels(shape, 3, seed=13)
+    u = random_field(shape, seed=14)
+    b = random_field(shape, seed=15, lo=-1, hi=1)
+    ctx = make_ctx(labels, CLASS_D, torch.float64, tile, tau=7.3, rho=0.2, s=sm[0], m=sm[1])
+    op = oop.Operator(1.0, labels=labels, class_D=CLASS_D)
+    ref = orb.phi1_action(op, u, b, 0.2, 7.3, sm[0], sm[1])
+    got = ctx.phi1_lin(dev(u, torch.float64), dev(b, torch.float64)).cpu().numpy()
+    assert rel_l2(got, ref) < 1e-13
+    uref = orb.step(op, u, 0.2, 7.3, sm[0], sm[1])
+    ut = dev(u, torch.float64)
+    ctx.step(ut)
+    assert rel_l2(ut.cpu().numpy(), uref) < 1e-13
+
+
+@pytest.mark.parametrize("shape", [(20, 17, 36), (7, 40, 264), (13, 9, 30)])
+@pytest.mark.parametrize("bc", ["noflux", "dirichlet0"])
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-11), (torch.float32, 1e-5)])
+def test_advance_vs_oracle(native, tile, shape, bc, dtype, tol):
+    if tile == "vec" and shape[2] % 4:
+        pytest.skip("the vectorised sweep needs nz % 4 == 0")
+    w = make_ragged(shape, seed=21, nsteps=4)
+    op = oop.Operator(w.h, bc=bc, labels=w.labels, class_D=w.class_D)
+    ctx = make_ctx(w.labels, w.class_D, dtype, tile, bc=bc, tau=w.tau, rho=w.rho)
+    p = ctx.plan
+    ref = orb.advance(op, w.u0, w.rho, w.tau, p.s, p.m, w.nsteps)
+    u = dev(w.u0, dtype)
+    ctx.advance(u, w.nsteps)  # recorded graph
+    assert rel_l2(u.cpu().numpy(), ref) < tol
+    u2 = dev(w.u0, dtype)
+    for _ in range(w.nsteps):  # direct launches
+        ctx.step(u2)
+    assert rel_l2(u2.cpu().numpy(), ref) < tol
+
+
+def test_plan_rule_uses_norm_bound(native):
+    # the plan is the rule applied to tau (||A||_1 + rho), in both precisions
+    shape = (12, 10, 16)
+    labels = random_labels(shape, 3, seed=31)
+    op = oop.Operator(1.0, labels=labels, class_D=CLASS_D)
+    for dtype, key in ((torch.float64, "f64"), (torch.float32, "f32")):
+        for rho, tau in ((0.025, 7.3), (0.9, 7.3), (2.0, 30.0)):
+            ctx = make_ctx(labels, CLASS_D, dtype, rho=rho, tau=tau)
+            p = ctx.plan
+            assert p.norm_A1 == pytest.approx(op.norm1(), rel=1e-12)
+            assert (p.s, p.m) == oplan.for_dtype(tau * orb.norm1_bound(op.norm1(), rho), key)
+    # a large rho changes the plan against the plain step's
+    from paper_2402_02273_amd.expint import ExpInt
+
+    lin = make_ctx(labels, CLASS_D, torch.float64, rho=2.0, tau=30.0)
+    plain = ExpInt(shape, labels=labels, class_D=CLASS_D, dtype=torch.float64, device=DEV, rho=2.0, tau=30.0)
+    assert (lin.plan.s, lin.plan.m) != (plain.plan.s, plain.plan.m)
+    # set_params replans with the new rho
+    lin.set_params(rho=0.025)
+    assert (lin.plan.s, lin.plan.m) == oplan.for_dtype(30.0 * orb.norm1_bound(op.norm1(), 0.025), "f64")
+
+
+def test_rho_zero_equals_plain_step(native, tile, monkeypatch):
+    # J = A when rho = 0: the linearised and plain contexts take the same step,
+    # up to rounding (the two run different kernel instantiations, so the
+    # compiler's fused multiply-adds need not match bit for bit)
+    from paper_2402_02273_amd.expint import ExpInt
+
+    monkeypatch.setenv("EXPINT_AUTOTUNE", "0")  # the same launch shape for both
+    w = make_ragged((11, 14, 20), seed=41, nsteps=3)
+    lin = make_ctx(w.labels, w.class_D, torch.float64, tile, rho=0.0, tau=w.tau)
+    plain = ExpInt(w.shape, labels=w.labels, class_D=w.class_D, dtype=torch.float64, device=DEV, rho=0.0, tau=w.tau,
+                   sweeps="single")
+    assert (lin.plan.s, lin.plan.m) == (plain.plan.s, plain.plan.m)
+    a = dev(w.u0, torch.float64)
+    b = dev(w.u0, torch.float64)
+    assert lin.launch_info() == plain.launch_info()
+    lin.advance(a, 3)
+    plain.advance(b, 3)
+    err = rel_l2(a.cpu().numpy(), b.cpu().numpy())
+    print(f"[result] rho = 0: linearised vs plain rel-L2 {err:.3e} (bitwise equal: {torch.equal(a, b)})", flush=True)
+    assert err < 1e-15
+
+
+def test_dense_D_vs_oracle(native):
+    shape = (9, 11, 13)
+    D = 0.02 + 0.1 * random_field(shape, seed=51)
+    u0 = random_field(shape, seed=52)
+    from paper_2402_02273_amd.expint import ExpInt
+
+    op = oop.Operator(1.0, D=D)
+    for dtype, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+        ctx = ExpInt(shape, D=D, dtype=dtype, device=DEV, rho=0.03, tau=7.3, scheme="linearised")
+        p = ctx.plan
+        ref = orb.advance(op, u0, 0.03, 7.3, p.s, p.m, 3)
+        u = dev(u0, dtype)
+        ctx.advance(u, 3)
+        assert rel_l2(u.cpu().numpy(), ref) < tol
+
+
+def test_misaligned_state_takes_scalar_sweep(native, monkeypatch):
+    # a state view one value into its buffer is not 16-byte aligned: the
+    # sweeps that read it fall back to the scalar form
+    monkeypatch.setenv("EXPINT_TILE", "vec")
+    w = make_ragged((6, 9, 40), seed=61, nsteps=2)
+    op = oop.Operator(w.h, labels=w.labels, class_D=w.class_D)
+    ctx = make_ctx(w.labels, w.class_D, torch.float32, "vec", rho=w.rho, tau=w.tau)
+    p = ctx.plan
+    ref = orb.advance(op, w.u0, w.rho, w.tau, p.s, p.m, 2)
+    buf = torch.zeros(w.labels.size + 1, dtype=torch.float32, device=DEV)
+    uv = buf[1:].view(w.shape)
+    uv.copy_(dev(w.u0, torch.float32))
+    ctx.advance(uv, 2)
+    assert rel_l2(uv.cpu().numpy(), ref) < 1e-5
+    assert buf[0].item() == 0.0
+
+
+def test_unsupported_uses(native):
+    from paper_2402_02273_amd import _native as N
+    from paper_2402_02273_amd.expint import ExpInt
+
+    shape = (8, 8, 8)
+    labels = random_labels(shape, 3, seed=71)
+    lin = make_ctx(labels, CLASS_D, torch.float32)
+    u = dev(random_field(shape, seed=72), torch.float32)
+    with pytest.raises(RuntimeError, match="EXP_EULER"):
+        lin.grad(u, 2, u.clone(), ckpt_every=1)
+    plain = ExpInt(shape, labels=labels, class_D=CLASS_D, dtype=torch.float32, device=DEV)
+    with pytest.raises(RuntimeError, match="LINEARISED"):
+        plain.phi1_lin(u, u)
+    # x must not alias the state
+    L = N.lib()
+    assert L.expint_phi1_lin(lin._ctx, u.data_ptr(), u.data_ptr(), u.data_ptr()) == N.EINVAL
+
+
+def test_more_accurate_than_plain_step(native):
+    # the second-order step against a fine-step reference (the linearised step
+    # at tau / 16) on a small head: the plain step's error is many times larger
+    from paper_2402_02273_amd.expint import ExpInt
+
+    w = c2_head(n=32, nsteps=25)
+    kw = dict(labels=w.labels, class_D=w.class_D, rho=w.rho, dtype=torch.float64, device=DEV)
+    fine = ExpInt(w.shape, tau=w.tau / 16, scheme="linearised", **kw)
+    uf = dev(w.u0, torch.float64)
+    fine.advance(uf, 16 * w.nsteps)
+    errs = {}
+    for scheme in ("exp_euler", "linearised"):
+        ctx = ExpInt(w.shape, tau=w.tau, scheme=scheme, **kw)
+        u = dev(w.u0, torch.float64)
+        ctx.advance(u, w.nsteps)
+        errs[scheme] = rel_l2(u.cpu().numpy(), uf.cpu().numpy())
+    print(f"[result] rel-L2 vs tau/16 after {w.nsteps} steps: {errs}", flush=True)
+    assert errs["linearised"] < 0.1 * errs["exp_euler"]
+
+
+def test_head_128_f32_vs_stored_oracle(native):
+    # the headline head at full size, 100 FP32 steps, against the stored FP64
+    # oracle run of the linearised step
+    path = os.path.join(GOLDEN, "c2l_head_128_u100_f64.npz")
+    g = np.load(path)
+    w = c2_head()
+    from paper_2402_02273_amd.expint import ExpInt
+
+    ctx = ExpInt(w.shape, labels=w.labels, class_D=w.class_D, rho=w.rho, tau=w.tau, dtype=torch.float32, device=DEV,
+                 scheme="linearised")
+    assert ctx.plan.norm_A1 == pytest.approx(float(g["norm1"]), rel=1e-12)
+    u = dev(w.u0, torch.float32)
+    ctx.advance(u, w.nsteps)
+    err = rel_l2(u.cpu().numpy(), g["u"])
+    print(f"[result] 128^3 linearised FP32 100 steps rel-L2 {err:.3e} plan {(ctx.plan.s, ctx.plan.m)}", flush=True)
+    assert err < 1e-5
+    # the oracle's own invariants at full size: CSF stays empty, 0 <= u <= 1
+    uh = u.cpu().numpy()
+    assert np.all(uh[w.labels == 0] == 0.0)
+    assert uh.min() >= -1e-6 and uh.max() <= 1 + 1e-6
