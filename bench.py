@@ -97,6 +97,18 @@ def step_bytes_per_voxel(w, s, m, linearised=False):
     return total, len(ops) + 1
 
 
+def step_bytes_per_voxel_exprk2(w, s, m):
+    """The second-order exponential Runge-Kutta step: the right-hand side,
+    the phi1 schedule of stage 1 (its last sweep stores X instead of adding
+    into u: one read fewer), the reaction increment d = f(u + X) - f(u) (reads
+    u and X, writes d), and the stage-2 schedule, the plain step's sweeps with
+    d read by two sweeps of each sub-step but the first (one there)."""
+    plain, nl = step_bytes_per_voxel(w, s, m)
+    d_reads = (2 * s - 1) * w if m >= 2 else (s - 1) * w
+    total = 2 * plain - RHS_BYTES(w) - w + 3 * w + d_reads
+    return total, 2 * (nl - 1) + 2
+
+
 def step_bytes_per_voxel_pairs(w, s, m):
     """The same for the pair schedule (m >= 2): per sub-step the Taylor terms
     two at a time, (1, 2), (3, 4), ... ((2, 3), (4, 5), ... in sub-step 1,
@@ -138,13 +150,16 @@ def load_traffic(kernel_key, kernel):
 def cpu_baseline(w, nsteps, scheme="exp_euler"):
     import numpy as np
 
-    from oracle import integrator, operator, plan, rosenbrock
+    from oracle import exprk2, integrator, operator, plan, rosenbrock
 
     op = operator.Operator(w.h, labels=w.labels, class_D=w.class_D)
     t0 = time.perf_counter()
     if scheme == "linearised":
         s, m = plan.for_dtype(w.tau * rosenbrock.norm1_bound(op.norm1(), w.rho), "f64")
         u = rosenbrock.advance(op, w.u0, w.rho, w.tau, s, m, nsteps)
+    elif scheme == "exprk2":
+        s, m = plan.for_dtype(w.tau * op.norm1(), "f64", m_min=exprk2.M_MIN)
+        u = exprk2.advance(op, w.u0, w.rho, w.tau, s, m, nsteps)
     else:
         s, m = plan.for_dtype(w.tau * op.norm1(), "f64")
         u = integrator.advance(op, w.u0, w.rho, w.tau, s, m, nsteps)
@@ -172,8 +187,9 @@ def run_c2(args):
     w_bytes = 4 if args.dtype == "f32" else 8
     w = c2_head(n=args.n)
     lin = args.scheme == "linearised"
+    erk = args.scheme == "exprk2"
     ctx = ExpInt(w.shape, w.h, labels=w.labels, class_D=w.class_D, rho=w.rho, tau=w.tau, dtype=dtype, device=dev,
-                 sweeps="single" if lin else args.sweeps, scheme=args.scheme)
+                 sweeps="single" if (lin or erk) else args.sweeps, scheme=args.scheme)
     plan = ctx.plan
     sweeps, ptiling = ctx.sweeps()
     launch = ctx.launch_info()
@@ -202,8 +218,10 @@ def run_c2(args):
     value = w.nvox * args.steps / (ms / 1e3)
 
     rel = None
-    if args.n == 128 and args.steps == 100:
-        gname = "c2l_head_128_u100_f64.npz" if lin else "c2_head_128_u100_f64.npz"
+    gsteps = 20 if erk else 100
+    if args.n == 128 and args.steps == gsteps:
+        gname = {"linearised": "c2l_head_128_u100_f64.npz", "exprk2": "c2e_head_128_u20_f64.npz"}.get(
+            args.scheme, "c2_head_128_u100_f64.npz")
         gpath = os.path.join(ROOT, "tests", "golden", gname)
         if os.path.exists(gpath):
             g = np.load(gpath)
@@ -235,13 +253,20 @@ def run_c2(args):
         tb = FLUSH_BYTES(w_bytes) * w.nvox
         ms_dom = ms_flush
         traffic = load_traffic(f"flush_{args.dtype}_{args.n}", "k_sweep4" if launch["vec"] else "k_sweep")
-        sbv, nlaunch = step_bytes_per_voxel(w_bytes, plan.s, plan.m)
+        if erk:
+            sbv, nlaunch = step_bytes_per_voxel_exprk2(w_bytes, plan.s, plan.m)
+        else:
+            sbv, nlaunch = step_bytes_per_voxel(w_bytes, plan.s, plan.m)
     achieved = tb / (ms_dom * 1e-3) / 1e9
     from paper_2402_02273_amd.expint import probe_peaks
 
     peaks = probe_peaks(dev)
     sb = sbv * w.nvox
     sweep_model = 4 * w_bytes + LABEL_BYTES  # one read/write of y and the sum per term
+    model_pv = RHS_BYTES(w_bytes) + (plan.s * plan.m - 1) * sweep_model
+    if erk:  # two schedules, the increment kernel and the reads of d
+        model_pv = RHS_BYTES(w_bytes) + 2 * (plan.s * plan.m - 1) * sweep_model + 3 * w_bytes \
+            + (2 * plan.s - 1) * w_bytes
     out = {
         "metric": METRIC,
         "value": value,
@@ -258,7 +283,8 @@ def run_c2(args):
         "config": {
             "workload": f"{args.n}^3 synthetic head seed 2402, D 0.13/0.013/0 mm^2/day, rho 0.025/day, "
             f"tau 7.3 d, no-flux, stencil-Taylor"
-            + (", linearised step (J_n = A + rho diag(1 - 2 u_n))" if lin else ""),
+            + (", linearised step (J_n = A + rho diag(1 - 2 u_n))" if lin else "")
+            + (", second-order exponential Runge-Kutta step (phi1 + phi2)" if erk else ""),
             "scheme": args.scheme,
             "grid": [args.n] * 3,
             "plan_s_m": [plan.s, plan.m],
@@ -283,9 +309,8 @@ def run_c2(args):
             "algorithmic_bytes_per_step": sb,
             "achieved_GBs": sb / (ms_per_step * 1e-3) / 1e9,
             "frac_of_hbm_peak": sb / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "sweep_model_bytes_per_step": (RHS_BYTES(w_bytes) + (plan.s * plan.m - 1) * sweep_model) * w.nvox,
-            "sweep_model_frac_of_hbm_peak": (RHS_BYTES(w_bytes) + (plan.s * plan.m - 1) * sweep_model)
-            * w.nvox / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "sweep_model_bytes_per_step": model_pv * w.nvox,
+            "sweep_model_frac_of_hbm_peak": model_pv * w.nvox / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "sweeps": sweeps,
             "launch": launch,
             "ms_flush_per_launch": ms_flush,
@@ -531,8 +556,9 @@ def main():
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
     ap.add_argument("--cpu-steps", type=int, default=8)
-    ap.add_argument("--scheme", choices=["exp_euler", "linearised"], default="exp_euler",
-                    help="c2: the plain exponential Euler step, or the paper's linearised step")
+    ap.add_argument("--scheme", choices=["exp_euler", "linearised", "exprk2"], default="exp_euler",
+                    help="c2: the plain exponential Euler step, the paper's linearised step, or the "
+                    "second-order exponential Runge-Kutta step")
     ap.add_argument("--sweeps", choices=["auto", "single", "pairs"], default="auto",
                     help="Taylor terms per stencil sweep (auto: timed at context creation)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

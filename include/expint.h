@@ -94,6 +94,15 @@ typedef enum {
 /* The step a context takes.
  * EXP_EULER: u <- u + tau phi1(tau A)(A u + f(u)), f(u) = rho u (1 - u): the
  *   reaction frozen at u_n over the step (section 2.2).
+ * EXPRK2: the second-order exponential Runge-Kutta step, the higher-order
+ *   extension section 1 mentions, with phi2 from section 2.2's augmented
+ *   matrix with both columns of its omega block in use:
+ *   U = u + tau phi1(tau A)(A u + f(u)), then
+ *   u <- u + tau phi1(tau A)(A u + f(u)) + tau phi2(tau A)(f(U) - f(u)).
+ *   Two phi evaluations per step.  The plan rule takes m >= 2 (the phi2
+ *   vector enters the series through its degree-2 term).  Stencil-Taylor
+ *   with single-term sweeps only; batches and gradients give
+ *   EXPINT_EUNSUPPORTED.
  * LINEARISED: the paper's splitting of the reaction (section 2.1, the
  *   rewritten F and the new F after it).  The part linear in the new state
  *   moves into the matrix, J_n = A + rho diag(1 - 2 u_n), leaving the source
@@ -107,7 +116,8 @@ typedef enum {
  *   and gradients give EXPINT_EUNSUPPORTED. */
 typedef enum {
   EXPINT_SCHEME_EXP_EULER = 0,
-  EXPINT_SCHEME_LINEARISED = 1
+  EXPINT_SCHEME_LINEARISED = 1,
+  EXPINT_SCHEME_EXPRK2 = 2
 } expint_scheme;
 
 typedef struct {
@@ -159,9 +169,10 @@ int expint_opts_default(expint_opts* opts);
  * Errors: EINVAL (NULL pointer, dims < 1, h <= 0, tau <= 0, rho < 0 or not
  * finite, n_classes outside 1..8, class_D < 0 or not finite, a label >=
  * n_classes, D < 0 or not finite, s/m partly set), EUNSUPPORTED (MODAL with a
- * non-uniform D, mp without MODAL F32, LINEARISED with MODAL or PAIRS), ENOMEM,
- * EHIP.  A LINEARISED context plans for tau*(||A||_1 + rho) in place of
- * tau*||A||_1.  *out is NULL on error. */
+ * non-uniform D, mp without MODAL F32, LINEARISED or EXPRK2 with MODAL or
+ * PAIRS), ENOMEM, EHIP.  A LINEARISED context plans for tau*(||A||_1 + rho) in
+ * place of tau*||A||_1; an EXPRK2 context plans with m >= 2.  *out is NULL on
+ * error. */
 int expint_create(const expint_grid* grid, const expint_dfield* dfield, double rho,
                   expint_bc bc, const expint_opts* opts, expint_ctx** out);
 
@@ -202,6 +213,14 @@ int expint_rhs(expint_ctx* ctx, const void* u, void* b);
  * MODAL algorithm, exactly in the mode basis.  b and x must not overlap. */
 int expint_phi1(expint_ctx* ctx, const void* b, void* x);
 
+/* x = tau phi1(tau A) b + tau phi2(tau A) d (section 2.2's augmented matrix
+ * with omega = [d / tau, b] next to the nilpotent 2 x 2 block), by the scaled
+ * Taylor series with the context's plan (phi2 needs m >= 2 to appear; EXPRK2
+ * contexts plan with it).  Stencil-Taylor contexts of the EXP_EULER or
+ * EXPRK2 scheme (else EXPINT_EUNSUPPORTED).  b, d: device fields, read only;
+ * x: device field, written, overlapping neither. */
+int expint_phi12(expint_ctx* ctx, const void* b, const void* d, void* x);
+
 /* x = tau phi1(tau J) b with J = A + rho diag(1 - 2 u), the linearised
  * operator of section 2.1 at the state u, by the scaled Taylor series of
  * section 2.2 with the context's plan.  LINEARISED contexts only (else
@@ -211,8 +230,9 @@ int expint_phi1_lin(expint_ctx* ctx, const void* u, const void* b, void* x);
 
 /* One step in place, of the context's scheme: EXP_EULER
  * u <- u + tau phi1(tau A)(A u + f(u)); LINEARISED
- * u <- u + tau phi1(tau J_n)(A u + f(u)).  u: device field owned by the
- * caller.  ENONFINITE with check_finite set. */
+ * u <- u + tau phi1(tau J_n)(A u + f(u)); EXPRK2 as described at
+ * expint_scheme.  u: device field owned by the caller.  ENONFINITE with
+ * check_finite set. */
 int expint_step(expint_ctx* ctx, void* u);
 
 /* nsteps >= 0 steps in place.  The first call for a given u records the step
@@ -231,7 +251,7 @@ int expint_reduce(expint_ctx* ctx, int32_t op, const void* x, const void* y, dou
  * loss, grad_rho: host scalars; grad_class_D: host array of n_classes
  * (label form only; dense form gives EINVAL).  u is checkpointed every
  * ckpt_every steps (>= 1) and recomputed in between.  EXP_EULER contexts
- * only (LINEARISED: EXPINT_EUNSUPPORTED). */
+ * only (other schemes: EXPINT_EUNSUPPORTED). */
 int expint_grad(expint_ctx* ctx, const void* u0, int32_t nsteps, const void* u_target,
                 int32_t ckpt_every, double* loss, void* grad_u0, double* grad_rho,
                 double* grad_class_D);
@@ -247,7 +267,7 @@ typedef struct expint_batch expint_batch;
 /* count instances, each with its own grid, label field, class table and rho
  * (arrays of length count; dfield entries must use the label form).  Shared
  * bc and opts (dtype, tau, tol, theta_max).  Every instance gets its own
- * plan.  Errors as expint_create; the LINEARISED scheme gives
+ * plan.  Errors as expint_create; schemes other than EXP_EULER give
  * EXPINT_EUNSUPPORTED. */
 int expint_batch_create(int32_t count, const expint_grid* grids, const expint_dfield* dfields,
                         const double* rho, expint_bc bc, const expint_opts* opts,

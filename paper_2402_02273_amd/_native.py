@@ -36,7 +36,7 @@ NOFLUX, DIRICHLET0 = 0, 1
 ALGO_AUTO, ALGO_STENCIL_TAYLOR, ALGO_MODAL = 0, 1, 2
 MP_NONE, MP_BF16_SPLIT, MP_FP16_SPLIT = 0, 1, 2
 SWEEPS_AUTO, SWEEPS_SINGLE, SWEEPS_PAIRS = 0, 1, 2
-SCHEME_EXP_EULER, SCHEME_LINEARISED = 0, 1
+SCHEME_EXP_EULER, SCHEME_LINEARISED, SCHEME_EXPRK2 = 0, 1, 2
 MAX_CLASSES = 8
 
 
@@ -110,6 +110,7 @@ SIGNATURES = {
     "expint_rhs": (_I, [_P, _P, _P]),
     "expint_phi1": (_I, [_P, _P, _P]),
     "expint_phi1_lin": (_I, [_P, _P, _P, _P]),
+    "expint_phi12": (_I, [_P, _P, _P, _P]),
     "expint_step": (_I, [_P, _P]),
     "expint_advance": (_I, [_P, _P, _I32]),
     "expint_reduce": (_I, [_P, _I32, _P, _P, _DP]),

@@ -182,7 +182,7 @@ int vjp_core(expint_ctx* c, const void* u0, int32_t nsteps, const void* cot, boo
   if (ckpt_every < 1) return set_error(EXPINT_EINVAL, "ckpt_every must be >= 1");
   if (!c->labels_form) return set_error(EXPINT_EINVAL, "gradients need the label form of D");
   if (c->scheme != EXPINT_SCHEME_EXP_EULER)
-    return set_error(EXPINT_EUNSUPPORTED, "gradients are for the EXP_EULER scheme");
+    return set_error(EXPINT_EUNSUPPORTED, "gradients are for the EXP_EULER scheme");  // LINEARISED, EXPRK2
   int rc = ensure_device(c);
   if (rc) return rc;
   const int nck = nsteps > 0 ? (nsteps + ckpt_every - 1) / ckpt_every : 0;

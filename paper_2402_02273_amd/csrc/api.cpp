@@ -152,7 +152,8 @@ int make_plan(expint_ctx* c) {
   if (c->fixed_plan) return EXPINT_OK;
   int s = 0, m = 0;
   const double nu = c->tau * plan_norm(c);
-  if (!choose_plan(nu, c->tol, c->theta_max, &s, &m))
+  const int m_min = c->scheme == EXPINT_SCHEME_EXPRK2 ? 2 : 1;
+  if (!choose_plan(nu, c->tol, c->theta_max, &s, &m, m_min))
     return set_error(EXPINT_EINVAL, "no admissible plan for nu = %g (tol %g, theta_max %g)", nu, c->tol,
                      c->theta_max);
   c->s = s;
@@ -192,6 +193,15 @@ std::vector<TermOp> step_schedule(expint_ctx* c, const void* b, void* x_out, voi
 int enqueue_step(expint_ctx* c, void* u) {
   HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, c->tiling, c->coef(), u, c->b, c->rho, c->stream));
   if (c->algo == EXPINT_ALGO_MODAL) return modal_phi1(c, c->b, u, true);
+  if (c->scheme == EXPINT_SCHEME_EXPRK2) {
+    // stage 1: X = tau phi1(tau A) b; d = f(u + X) - f(u); stage 2 adds
+    // tau phi1(tau A) b + tau phi2(tau A) d into u (phi1 b recomputed: the
+    // phi2 part needs the same sweeps, d enters two of them per sub-step)
+    int rc = run_ops(c, phi1_schedule(step_buffers(c), c->s, c->m, c->tau, c->b, c->stage, nullptr));
+    if (rc) return rc;
+    HIP_TRY(c, launch_reaction_increment(c->dtype, c->g.n, c->rho, u, c->stage, c->dvec, c->stream));
+    return run_ops(c, phi1_schedule(step_buffers(c), c->s, c->m, c->tau, c->b, nullptr, u, c->dvec));
+  }
   std::vector<TermOp> ops = step_schedule(c, c->b, nullptr, u);
   if (c->scheme == EXPINT_SCHEME_LINEARISED) set_linearised(ops, u, c->rho);
   return run_ops(c, ops);
@@ -223,7 +233,7 @@ int validate_opts(const expint_opts* o) {
   if (o->mp < EXPINT_MP_NONE || o->mp > EXPINT_MP_FP16_SPLIT) return set_error(EXPINT_EINVAL, "unknown mp");
   if (o->sweeps < EXPINT_SWEEPS_AUTO || o->sweeps > EXPINT_SWEEPS_PAIRS)
     return set_error(EXPINT_EINVAL, "unknown sweeps");
-  if (o->scheme < EXPINT_SCHEME_EXP_EULER || o->scheme > EXPINT_SCHEME_LINEARISED)
+  if (o->scheme < EXPINT_SCHEME_EXP_EULER || o->scheme > EXPINT_SCHEME_EXPRK2)
     return set_error(EXPINT_EINVAL, "unknown scheme");
   return EXPINT_OK;
 }
@@ -277,8 +287,10 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
     return set_error(EXPINT_EUNSUPPORTED, "pair sweeps need the label form of D");
   if (opts->scheme == EXPINT_SCHEME_LINEARISED && algo == EXPINT_ALGO_MODAL)
     return set_error(EXPINT_EUNSUPPORTED, "the linearised operator is not separable: no modal path");
-  if (opts->scheme == EXPINT_SCHEME_LINEARISED && opts->sweeps == EXPINT_SWEEPS_PAIRS)
-    return set_error(EXPINT_EUNSUPPORTED, "the linearised scheme uses single-term sweeps");
+  if (opts->scheme == EXPINT_SCHEME_EXPRK2 && algo == EXPINT_ALGO_MODAL)
+    return set_error(EXPINT_EUNSUPPORTED, "the EXPRK2 scheme runs on the stencil-Taylor path");
+  if (opts->scheme != EXPINT_SCHEME_EXP_EULER && opts->sweeps == EXPINT_SWEEPS_PAIRS)
+    return set_error(EXPINT_EUNSUPPORTED, "the LINEARISED and EXPRK2 schemes use single-term sweeps");
   if (algo == EXPINT_ALGO_MODAL) {
     if (!df->labels) return set_error(EXPINT_EUNSUPPORTED, "the modal path needs the label form of D");
     if (grid->nx % 32 || grid->ny % 32 || grid->nz % 32)
@@ -381,6 +393,10 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
   if ((rc = make_plan(c))) return bail(rc);
 
   if ((rc = c->arena.alloc(&c->b, fb))) return bail(rc);
+  if (c->scheme == EXPINT_SCHEME_EXPRK2) {
+    if ((rc = c->arena.alloc(&c->stage, fb))) return bail(rc);
+    if ((rc = c->arena.alloc(&c->dvec, fb))) return bail(rc);
+  }
   for (int i = 0; i < 2; ++i) {
     if ((rc = c->arena.alloc(&c->y[i], fb))) return bail(rc);
     if ((rc = c->arena.alloc(&c->acc[i], fb))) return bail(rc);
@@ -406,7 +422,10 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
     std::fprintf(stderr,
                  "[expint] grid %dx%dx%d h=%g dtype=%s scheme=%s ||A||_1=%.17g nu=%.6g plan s=%d m=%d workspace %zu B\n",
                  c->g.nx, c->g.ny, c->g.nz, c->h, c->dtype == EXPINT_F64 ? "f64" : "f32",
-                 c->scheme == EXPINT_SCHEME_LINEARISED ? "linearised" : "exp-euler", c->norm1, c->tau * plan_norm(c),
+                 c->scheme == EXPINT_SCHEME_LINEARISED ? "linearised"
+                 : c->scheme == EXPINT_SCHEME_EXPRK2  ? "exprk2"
+                                                      : "exp-euler",
+                 c->norm1, c->tau * plan_norm(c),
                  c->s, c->m, c->arena.bytes());
   *out = c;
   expint::clear_error();
@@ -501,6 +520,17 @@ int expint_phi1(expint_ctx* c, const void* b, void* x) {
   if (rc) return rc;
   if (c->algo == EXPINT_ALGO_MODAL) return modal_phi1(c, b, x, false);
   return run_ops(c, step_schedule(c, b, x, nullptr));
+}
+
+int expint_phi12(expint_ctx* c, const void* b, const void* d, void* x) {
+  CHECK_CTX(c);
+  if (!b || !d || !x) return set_error(EXPINT_EINVAL, "NULL field");
+  if (c->algo == EXPINT_ALGO_MODAL || c->scheme == EXPINT_SCHEME_LINEARISED)
+    return set_error(EXPINT_EUNSUPPORTED, "phi1 + phi2 needs a stencil-Taylor EXP_EULER or EXPRK2 context");
+  if (b == x || d == x) return set_error(EXPINT_EINVAL, "x must overlap neither b nor d");
+  int rc = ensure_device(c);
+  if (rc) return rc;
+  return run_ops(c, phi1_schedule(step_buffers(c), c->s, c->m, c->tau, b, x, nullptr, d));
 }
 
 int expint_phi1_lin(expint_ctx* c, const void* u, const void* b, void* x) {

@@ -95,6 +95,8 @@ struct expint_ctx {
   void* wallv = nullptr;
 
   void* b = nullptr;  // step workspace
+  void* stage = nullptr;  // EXPRK2: tau phi1(tau A) b of the first stage
+  void* dvec = nullptr;   // EXPRK2: f(U) - f(u)
   void* y[2] = {nullptr, nullptr};
   void* acc[2] = {nullptr, nullptr};
   double* partial = nullptr;  // reduction partials (see expint_create)

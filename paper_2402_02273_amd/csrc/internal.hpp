@@ -81,6 +81,10 @@ enum TermFlavor {
 };
 
 //
+// bsrc2 != NULL adds a second source vector to the term, y += cb2 * bsrc2
+// (the phi2 vector of the augmented matrix with both omega columns); such
+// sweeps take the generic flavour.  Single-term sweeps only.
+//
 // ju != NULL makes the sweep one of the linearised operator
 // J = A + rho diag(1 - 2 u_n): a = A src + jrho (1 - 2 ju) src, with ju = u_n
 // read at each voxel only (so ju may be the u the last sweep adds into).
@@ -105,6 +109,8 @@ struct TermOp {
   double c2 = 0.0;
   const void* ju = nullptr;
   double jrho = 0.0;
+  const void* bsrc2 = nullptr;  // a second source: y += cb2 * bsrc2 (generic flavour)
+  double cb2 = 0.0;
   int flavor = kGeneric;
   int pair = 0;
 };
@@ -179,5 +185,9 @@ hipError_t launch_copy(expint_dtype dt, int64_t n, const void* x, void* y, hipSt
 hipError_t launch_axpby(expint_dtype dt, int64_t n, double a, const void* x, double b, const void* y, void* out,
                         hipStream_t st);  // out = a x + b y
 hipError_t launch_fill(expint_dtype dt, int64_t n, double v, void* y, hipStream_t st);
+// d = f(u + x) - f(u) for f(v) = rho v (1 - v), evaluated as rho x (1 - 2u - x)
+// (the same polynomial without the cancellation of the difference).
+hipError_t launch_reaction_increment(expint_dtype dt, int64_t n, double rho, const void* u, const void* x, void* d,
+                                     hipStream_t st);
 
 }  // namespace expint

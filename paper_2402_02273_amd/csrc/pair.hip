@@ -278,7 +278,7 @@ bool pair_grid_ok(const Geom& g, expint_dtype dt) {
 
 hipError_t launch_pair(expint_dtype dt, expint_bc bc, const Geom& g, const PairTiling& tl, const Coef& cf,
                        const TermOp& op, hipStream_t st) {
-  if (!pair_tiling_valid(tl) || !cf.labels_form || !op.pair || !op.src || op.ju || !pair_grid_ok(g, dt))
+  if (!pair_tiling_valid(tl) || !cf.labels_form || !op.pair || !op.src || op.ju || op.bsrc2 || !pair_grid_ok(g, dt))
     return hipErrorInvalidValue;
   if (op.y_out == op.src || op.acc_out == op.src || op.u == op.src) return hipErrorInvalidValue;
   if (op.bsrc && (op.y_out == op.bsrc || op.acc_out == op.bsrc || op.u == op.bsrc)) return hipErrorInvalidValue;

@@ -10,6 +10,10 @@
 // Lagrange remainder of the degree-m Taylor polynomial of e^z on [-theta, 0]
 // is at most theta^(m+1)/(m+1)! per factor; (ii) caps the growth of the
 // partial sums (about e^theta) and with it the rounding error.
+//
+// m_min: a degree floor.  The augmented matrix that also carries phi2 (both
+// columns of the omega block next to the nilpotent 2 x 2 block) reaches the
+// phi2 vector only through (hB)^2 / 2, so schemes that need phi2 ask for m >= 2.
 
 #include <cmath>
 
@@ -23,11 +27,12 @@ static double remainder_bound(int s, int m, double theta) {
   return t;
 }
 
-bool choose_plan(double nu, double tol, double theta_max, int* s_out, int* m_out) {
+bool choose_plan(double nu, double tol, double theta_max, int* s_out, int* m_out, int m_min) {
   if (!(nu >= 0.0) || std::isinf(nu) || !(tol > 0.0) || !(theta_max > 0.0)) return false;
+  if (m_min < 1 || m_min > kPlanMaxDegree) return false;
   if (nu == 0.0) {
     *s_out = 1;
-    *m_out = 1;
+    *m_out = m_min;
     return true;
   }
   long s = static_cast<long>(std::ceil(nu / theta_max));
@@ -38,7 +43,7 @@ bool choose_plan(double nu, double tol, double theta_max, int* s_out, int* m_out
   for (;; ++s) {
     if (s > 100000) return false;
     const double theta = nu / static_cast<double>(s);
-    for (int m = 1; m <= kPlanMaxDegree; ++m) {
+    for (int m = m_min; m <= kPlanMaxDegree; ++m) {
       if (remainder_bound(static_cast<int>(s), m, theta) <= tol) {
         const long cost = s * m;
         if (best_cost < 0 || cost < best_cost) {

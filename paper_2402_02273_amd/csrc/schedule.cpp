@@ -4,7 +4,7 @@ namespace expint {
 
 void classify_term(TermOp& op) {
   op.flavor = kGeneric;
-  if (op.u) return;
+  if (op.u || op.bsrc2) return;
   if (!op.bsrc && !op.acc_in && !op.acc_out && op.y_out) {
     op.flavor = kSkip;
   } else if (!op.bsrc && op.acc_in && op.ca == 1.0 && op.acc_out) {
@@ -15,7 +15,7 @@ void classify_term(TermOp& op) {
 }
 
 std::vector<TermOp> phi1_schedule(const StepBuffers& ws, int s, int m, double tau, const void* b, void* x_out,
-                                  void* u) {
+                                  void* u, const void* d) {
   enum class X { Zero, HB, Buf };
   std::vector<TermOp> ops;
   const double h = tau / s;
@@ -33,10 +33,15 @@ std::vector<TermOp> phi1_schedule(const StepBuffers& ws, int s, int m, double ta
         xk = X::HB;
         continue;
       }
-      // y_1 = h b is not stored; y_2 = (h/2) A (h b)
+      // y_1 = h b is not stored (eta = (0, 1): no d yet); y_2 = (h/2) A (h b),
+      // plus (h^2 / (2 tau)) d
       TermOp t;
       t.src = b;
       t.c = h * h / 2.0;
+      if (d) {
+        t.bsrc2 = d;
+        t.cb2 = h * h / (2.0 * tau);
+      }
       if (m == 2) {
         t.acc_out = A;
         t.cs = h;  // h b + y_2
@@ -51,12 +56,16 @@ std::vector<TermOp> phi1_schedule(const StepBuffers& ws, int s, int m, double ta
       pend_hb = true;
       j0 = 3;
     } else {
-      // y_1 = h (A x + b), sum = x + y_1
+      // y_1 = h (A x + b) (+ h (k h / tau) d in sub-step k + 1), sum = x + y_1
       TermOp t;
       t.src = (xk == X::HB) ? b : ws.acc[xa];
       t.bsrc = b;
       t.c = (xk == X::HB) ? h * h : h;  // x = h b: h A (h b)
       t.cb = h;
+      if (d) {
+        t.bsrc2 = d;
+        t.cb2 = h * (sig - 1) * h / tau;
+      }
       t.cs = (xk == X::HB) ? h : 1.0;
       t.acc_out = A;
       t.y_out = m >= 2 ? ws.y[0] : nullptr;
@@ -69,6 +78,10 @@ std::vector<TermOp> phi1_schedule(const StepBuffers& ws, int s, int m, double ta
       TermOp t;
       t.src = ws.y[ycur];
       t.c = h / j;
+      if (d && j == 2) {  // y_2 = (h/2) A y_1 + (h^2 / (2 tau)) d
+        t.bsrc2 = d;
+        t.cb2 = h * h / (2.0 * tau);
+      }
       const bool last = j == m;
       if (pend || last) {
         if (pend_hb) {

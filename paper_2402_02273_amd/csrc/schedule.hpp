@@ -13,6 +13,16 @@
 //   - if m == 1, sub-step 1 leaves x = h b and sub-step 2 computes
 //     y_1 = h^2 A b + h b with the sum started at h b.
 // The last sweep either adds the sum into u (the step u + x) or stores it.
+//
+// With a second vector d the same sweeps evaluate
+// x = tau phi1(tau A) b + tau phi2(tau A) d: the augmented matrix then fills
+// both columns of its omega block, [d / tau, b], next to the nilpotent block
+// J = [[0, 1], [0, 0]], and the augmented unit vector starts at eta = (0, 1).
+// eta after k sub-steps is (k h, 1), so one sub-step's terms become
+//   y_1 = h (A x + b + (k h / tau) d),   y_2 = (h/2) A y_1 + (h^2 / (2 tau)) d,
+//   y_j = (h / j) A y_{j-1} (j >= 3);
+// d enters two sweeps per sub-step as a second source (TermOp::bsrc2).  With
+// m = 1 the phi2 part is truncated away entirely.
 #pragma once
 
 #include <vector>
@@ -27,10 +37,11 @@ struct StepBuffers {
   void* acc[2] = {nullptr, nullptr};
 };
 
-// b: the vector phi1 acts on.  Exactly one of x_out (store the result) and
-// u (add the result into u) is non-NULL.
+// b: the vector phi1 acts on; d (may be NULL): the vector phi2 acts on.
+// Exactly one of x_out (store the result) and u (add the result into u) is
+// non-NULL.
 std::vector<TermOp> phi1_schedule(const StepBuffers& ws, int s, int m, double tau, const void* b, void* x_out,
-                                  void* u);
+                                  void* u, const void* d = nullptr);
 
 // The same polynomial with the terms of every sub-step taken two at a time
 // by pair sweeps (TermOp::pair; label form, m >= 2): sub-step terms

@@ -281,6 +281,17 @@ __global__ __launch_bounds__(kBlock) void k_copy(int64_t n, const T* __restrict_
   if (p < n) y[p] = x[p];
 }
 
+// d = f(u + x) - f(u), f(v) = rho v (1 - v), as rho x (1 - 2u - x)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_reaction_increment(int64_t n, T rho, const T* __restrict__ u,
+                                                               const T* __restrict__ x, T* __restrict__ d) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (p < n) {
+    const T xv = x[p];
+    d[p] = rho * xv * (T(1) - T(2) * u[p] - xv);
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fill(int64_t n, T v, T* __restrict__ y) {
   const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
@@ -424,6 +435,18 @@ hipError_t launch_copy(expint_dtype dt, int64_t n, const void* x, void* y, hipSt
     k_copy<double><<<grid, block, 0, st>>>(n, static_cast<const double*>(x), static_cast<double*>(y));
   else
     k_copy<float><<<grid, block, 0, st>>>(n, static_cast<const float*>(x), static_cast<float*>(y));
+  return hipGetLastError();
+}
+
+hipError_t launch_reaction_increment(expint_dtype dt, int64_t n, double rho, const void* u, const void* x, void* d,
+                                     hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>((n + kBlock - 1) / kBlock)), block(kBlock);
+  if (dt == EXPINT_F64)
+    k_reaction_increment<double><<<grid, block, 0, st>>>(n, rho, static_cast<const double*>(u),
+                                                         static_cast<const double*>(x), static_cast<double*>(d));
+  else
+    k_reaction_increment<float><<<grid, block, 0, st>>>(n, static_cast<float>(rho), static_cast<const float*>(u),
+                                                        static_cast<const float*>(x), static_cast<float*>(d));
   return hipGetLastError();
 }
 

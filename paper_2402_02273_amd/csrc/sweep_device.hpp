@@ -76,6 +76,7 @@ __device__ __forceinline__ void term_store(const TermOp& op, int q, T ax, T xc) 
   } else {
     T y = c * ax;
     if (op.bsrc) y += static_cast<T>(op.cb) * static_cast<const T*>(op.bsrc)[q];
+    if (op.bsrc2) y += static_cast<T>(op.cb2) * static_cast<const T*>(op.bsrc2)[q];
     T v = static_cast<T>(op.cs) * xc + y;
     if (op.acc_in) v += static_cast<T>(op.ca) * static_cast<const T*>(op.acc_in)[q];
     if (op.u) {
@@ -242,6 +243,12 @@ __device__ __forceinline__ void term_store4(const TermOp& op, int q4, const T (&
       const T cb = static_cast<T>(op.cb);
 #pragma unroll
       for (int e = 0; e < 4; ++e) y.v[e] += cb * b.v[e];
+    }
+    if (op.bsrc2) {
+      const Vec4<T> b2 = ld4<T>(op.bsrc2, q4);
+      const T cb2 = static_cast<T>(op.cb2);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) y.v[e] += cb2 * b2.v[e];
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) v.v[e] = cs * xc.v[e] + y.v[e];

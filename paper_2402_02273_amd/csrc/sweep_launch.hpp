@@ -99,7 +99,7 @@ inline bool vec_aligned(int kind, const SweepArgs& a, const Coef& cf, expint_dty
   if ((reinterpret_cast<uintptr_t>(cf.labels) & 3) != 0) return false;
   if (is_term(kind))
     return ok(a.op.src) && ok(a.op.bsrc) && ok(a.op.acc_in) && ok(a.op.y_out) && ok(a.op.acc_out) && ok(a.op.u) &&
-           ok(a.op.ju);
+           ok(a.op.ju) && ok(a.op.bsrc2);
   return ok(a.x) && ok(a.out) && ok(a.aux0) && ok(a.aux1);
 }
 

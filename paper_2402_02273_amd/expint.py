@@ -22,7 +22,7 @@ _BCS = {"noflux": N.NOFLUX, "dirichlet0": N.DIRICHLET0}
 _ALGOS = {"auto": N.ALGO_AUTO, "stencil_taylor": N.ALGO_STENCIL_TAYLOR, "modal": N.ALGO_MODAL}
 _MPS = {"none": N.MP_NONE, "bf16_split": N.MP_BF16_SPLIT, "fp16_split": N.MP_FP16_SPLIT}
 _SWEEPS = {"auto": N.SWEEPS_AUTO, "single": N.SWEEPS_SINGLE, "pairs": N.SWEEPS_PAIRS}
-_SCHEMES = {"exp_euler": N.SCHEME_EXP_EULER, "linearised": N.SCHEME_LINEARISED}
+_SCHEMES = {"exp_euler": N.SCHEME_EXP_EULER, "linearised": N.SCHEME_LINEARISED, "exprk2": N.SCHEME_EXPRK2}
 
 
 @dataclass
@@ -52,7 +52,8 @@ class ExpInt:
 
     scheme="exp_euler" steps u + tau phi1(tau A)(A u + f(u)); scheme="linearised"
     takes the paper's splitting of the reaction, u + tau phi1(tau J_n)(A u + f(u))
-    with J_n = A + rho diag(1 - 2 u_n) (exponential Rosenbrock-Euler)."""
+    with J_n = A + rho diag(1 - 2 u_n) (exponential Rosenbrock-Euler);
+    scheme="exprk2" the second-order exponential Runge-Kutta step with phi2."""
 
     def __init__(
         self,
@@ -228,6 +229,12 @@ class ExpInt:
     def phi1(self, b, out=None):
         out = self.empty() if out is None else out
         N.check(self.lib.expint_phi1(self._ctx, self._field(b, "b"), self._field(out, "out")))
+        return out
+
+    def phi12(self, b, d, out=None):
+        """tau phi1(tau A) b + tau phi2(tau A) d."""
+        out = self.empty() if out is None else out
+        N.check(self.lib.expint_phi12(self._ctx, self._field(b, "b"), self._field(d, "d"), self._field(out, "out")))
         return out
 
     def phi1_lin(self, u, b, out=None):

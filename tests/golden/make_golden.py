@@ -5,6 +5,7 @@ the repository root:
 
     python tests/golden/make_golden.py c2      # 128^3 head, 100 steps (~12 min)
     python tests/golden/make_golden.py c2l     # the same with the linearised step (~13 min)
+    python tests/golden/make_golden.py c2e     # 20 second-order exponential Runge-Kutta steps (~6 min)
     python tests/golden/make_golden.py c4      # 96^3 gradients, 50 steps (~15 min)
 
 Each file records the plan, the input hashes and the oracle result.
@@ -20,7 +21,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from oracle import adjoint, integrator, operator, plan, rosenbrock  # noqa: E402
+from oracle import adjoint, exprk2, integrator, operator, plan, rosenbrock  # noqa: E402
 from workloads import c2_head, c4_adjoint  # noqa: E402
 from workloads.configs import c4_synthetic_target  # noqa: E402
 
@@ -88,6 +89,34 @@ def make_c2l(n=128, nsteps=100):
     print("wrote", out, "plan", (s, m), "seconds", round(time.time() - t0, 1))
 
 
+def make_c2e(n=128, nsteps=20):
+    """The headline head with the second-order exponential Runge-Kutta step
+    (phi2 from the augmented matrix), plan with the degree floor m >= 2."""
+    w = c2_head(n=n, nsteps=nsteps)
+    op = operator.Operator(w.h, labels=w.labels, class_D=w.class_D)
+    s, m = plan.for_dtype(w.tau * op.norm1(), "f64", m_min=exprk2.M_MIN)
+    t0 = time.time()
+
+    def progress(k, u):
+        print(f"step {k}/{nsteps}  {time.time() - t0:.0f}s", flush=True)
+
+    u = exprk2.advance(op, w.u0, w.rho, w.tau, s, m, nsteps, callback=progress)
+    out = os.path.join(HERE, f"c2e_head_{n}_u{nsteps}_f64.npz")
+    np.savez_compressed(
+        out,
+        u=u,
+        s=s,
+        m=m,
+        norm1=op.norm1(),
+        labels_sha256=digest(w.labels),
+        u0_sha256=digest(w.u0),
+        rho=w.rho,
+        tau=w.tau,
+        class_D=np.asarray(w.class_D),
+    )
+    print("wrote", out, "plan", (s, m), "seconds", round(time.time() - t0, 1))
+
+
 def make_c4(n=96, nsteps=50, ckpt=10):
     """Oracle loss and gradients at the evaluation parameters of the
     calibration workload, against the synthetic (model-free) target."""
@@ -118,6 +147,8 @@ if __name__ == "__main__":
         make_c2()
     elif which == "c2l":
         make_c2l()
+    elif which == "c2e":
+        make_c2e()
     elif which == "c4":
         make_c4()
     else:

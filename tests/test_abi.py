@@ -62,7 +62,7 @@ def _labels_df():
         (lambda g, d, o: d.__setattr__("D", 99), "exactly one"),
         (lambda g, d, o: o.__setitem__("dtype", 7), "dtype"),
         (lambda g, d, o: o.__setitem__("sweeps", 3), "sweeps"),
-        (lambda g, d, o: o.__setitem__("scheme", 2), "scheme"),
+        (lambda g, d, o: o.__setitem__("scheme", 3), "scheme"),
     ],
 )
 def test_create_rejects_invalid_arguments(change, needle):
@@ -105,12 +105,16 @@ def test_pair_sweeps_need_label_form():
     assert rc == N.EUNSUPPORTED and "label form" in N.last_error()
 
 
-def test_linearised_scheme_limits_rejected_before_hip():
+def test_scheme_limits_rejected_before_hip():
     df, cd = _labels_df()
     lin = N.SCHEME_LINEARISED
     rc, _ = _create(N.Grid(32, 32, 32, 1.0), df, algo=N.ALGO_MODAL, scheme=lin)
     assert rc == N.EUNSUPPORTED and "separable" in N.last_error()
     rc, _ = _create(N.Grid(8, 8, 8, 1.0), df, sweeps=N.SWEEPS_PAIRS, scheme=lin)
+    assert rc == N.EUNSUPPORTED and "single-term" in N.last_error()
+    rc, _ = _create(N.Grid(32, 32, 32, 1.0), df, algo=N.ALGO_MODAL, scheme=N.SCHEME_EXPRK2)
+    assert rc == N.EUNSUPPORTED and "stencil-Taylor" in N.last_error()
+    rc, _ = _create(N.Grid(8, 8, 8, 1.0), df, sweeps=N.SWEEPS_PAIRS, scheme=N.SCHEME_EXPRK2)
     assert rc == N.EUNSUPPORTED and "single-term" in N.last_error()
     L = N.lib()
     o = N.Opts()
@@ -123,11 +127,14 @@ def test_linearised_scheme_limits_rejected_before_hip():
     b = ctypes.c_void_p()
     assert L.expint_batch_create(1, grids, dfs, rho, N.NOFLUX, ctypes.byref(o), ctypes.byref(b)) == N.EUNSUPPORTED
     assert "EXP_EULER" in N.last_error()
+    o.scheme = N.SCHEME_EXPRK2
+    assert L.expint_batch_create(1, grids, dfs, rho, N.NOFLUX, ctypes.byref(o), ctypes.byref(b)) == N.EUNSUPPORTED
 
 
 def test_null_context_calls():
     L = N.lib()
     assert L.expint_phi1_lin(None, None, None, None) == N.EINVAL
+    assert L.expint_phi12(None, None, None, None) == N.EINVAL
     assert L.expint_step(None, None) == N.EINVAL
     assert L.expint_advance(None, None, 1) == N.EINVAL
     assert L.expint_get_plan(None, None, None, None) == N.EINVAL
