@@ -29,9 +29,13 @@ Plain, slow, obviously-correct NumPy/SciPy in float64:
                  with both columns of its omega block (section 2.2), and the
                  second-order exponential Runge-Kutta step built on it (the
                  higher-order extension section 1 mentions);
+* ``diagnostics`` labels from 8-bit scan intensities (section 3.1 thresholds,
+                 sampled at the stencil points as in section 3.5), the tumour
+                 volume (section 3.5) and the largest distance between tumour
+                 points (section 3.2);
 * ``adjoint``    discrete adjoint (gradients of 0.5||u_T - u_target||^2 with
                  respect to u0, rho and the class diffusivities) and central
                  finite differences.
 """
 
-from . import operator, plan, integrator, reference, adjoint, rosenbrock, exprk2  # noqa: F401
+from . import operator, plan, integrator, reference, adjoint, rosenbrock, exprk2, diagnostics  # noqa: F401
