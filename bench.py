@@ -348,7 +348,10 @@ def run_c3(args):
     insts, nsteps = c3_batch()
     steps = args.steps if args.steps_given else nsteps
     dicts = [{"labels": i.labels, "class_D": i.class_D, "rho": i.rho} for i in insts]
-    b = ExpIntBatch(dicts, tau=7.3, dtype=torch.float32, device="cuda:0")
+    lin = args.scheme == "linearised"
+    if args.scheme == "exprk2":
+        raise SystemExit("c3 runs the exp_euler or linearised scheme")
+    b = ExpIntBatch(dicts, tau=7.3, dtype=torch.float32, device="cuda:0", scheme=args.scheme)
     u0 = [torch.as_tensor(i.u0, dtype=torch.float32, device="cuda:0").contiguous() for i in insts]
     us = [u.clone() for u in u0]
     if args.warmup > 0:
@@ -358,7 +361,7 @@ def run_c3(args):
     ms = _timed(lambda: b.advance(us, steps), None)
     vox = sum(int(i.labels.size) for i in insts)
     plans = b.plans
-    step_bytes = sum(step_bytes_per_voxel(4, p.s, p.m)[0] * int(i.labels.size) for p, i in zip(plans, insts))
+    step_bytes = sum(step_bytes_per_voxel(4, p.s, p.m, lin)[0] * int(i.labels.size) for p, i in zip(plans, insts))
     achieved = step_bytes * steps / (ms * 1e-3) / 1e9
     out = {
         "metric": "voxel-updates/s, 64 batched scenarios (sum of N^3 x steps / time)",
@@ -375,7 +378,8 @@ def run_c3(args):
         "data": "synthetic",
         "config": {
             "workload": "64 synthetic heads, N in {48,64,96,128}, rho~U[0.01,0.05], D_w~U[0.05,0.2], D_g=D_w/10, "
-            "tau 7.3 d, one HIP graph per step",
+            "tau 7.3 d, one HIP graph per step" + (", linearised step" if lin else ""),
+            "scheme": args.scheme,
             "voxels": vox,
             "terms_per_step": [min(p.s * p.m for p in plans), max(p.s * p.m for p in plans)],
             "launches_per_step": 1 + max(step_bytes_per_voxel(4, p.s, p.m)[1] - 1 for p in plans),
@@ -546,13 +550,80 @@ def run_c5(args):
     print(json.dumps(out), flush=True)
 
 
+def run_diag(args):
+    """The pipeline around the step, on the headline head: labels from a
+    29 x 565 x 532 8-bit scan onto the 128^3 grid, the tumour volume after
+    every step of a 100-step run, and the tumour size (largest distance
+    between points with u > 1e-3) at the end."""
+    import numpy as np
+    import torch
+
+    from oracle import diagnostics as odg
+    from paper_2402_02273_amd.expint import ExpInt, labels_from_intensity
+    from workloads import c2_head
+    from workloads.mri import SCAN_SHAPE, synthetic_scan
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    scan = synthetic_scan(SCAN_SHAPE, seed=2402)
+    img = torch.as_tensor(scan, device=dev)
+    lab = labels_from_intensity(img, (n, n, n))
+    torch.cuda.synchronize()
+    assert np.array_equal(lab.cpu().numpy(), odg.labels_from_intensity(scan, (n, n, n)))
+    reps = 200
+    ms_lab = _timed(lambda: [labels_from_intensity(img, (n, n, n), out=lab) for _ in range(reps)], True) / reps
+
+    w = c2_head(n=n)
+    ctx = ExpInt(w.shape, w.h, labels=w.labels, class_D=w.class_D, rho=w.rho, tau=w.tau, dtype=torch.float32,
+                 device=dev)
+    u0 = torch.as_tensor(w.u0, dtype=torch.float32, device=dev)
+    u = u0.clone()
+    ctx.advance(u, args.warmup)  # records the step graph
+    u.copy_(u0)
+    ms_plain = _timed(lambda: ctx.advance(u, args.steps), True)
+    u.copy_(u0)
+    t0 = time.perf_counter()
+    vols = ctx.advance_volumes(u, args.steps)
+    ms_vol = (time.perf_counter() - t0) * 1e3
+    ms_size = _timed(lambda: ctx.tumour_size(u, 1e-3), True)
+    d2, pair = ctx.tumour_size(u, 1e-3)
+    size_mm = w.h * float(np.sqrt(d2))
+    lab_bytes = 2 * n**3  # one gathered scan byte in, one label out per point
+    out = {
+        "metric": "diagnostics around the step (ms)",
+        "value": ms_vol / args.steps,
+        "unit": "ms per step with the volume recorded",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_vol / args.steps,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"29x565x532 synthetic scan -> {n}^3 labels; {n}^3 head, {args.steps} steps, "
+                   f"volume every step; tumour size at u > 1e-3"},
+        "labels_ms_per_launch": ms_lab,
+        "labels_GBs": lab_bytes / (ms_lab * 1e-3) / 1e9,
+        "step_ms_plain": ms_plain / args.steps,
+        "step_ms_with_volume": ms_vol / args.steps,
+        "volume_first_last": [float(vols[0]), float(vols[-1])],
+        "tumour_size_ms": ms_size,
+        "tumour_size_mm": size_mm,
+        "tumour_size_pair": list(pair),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2",
-                    help="c2: 128^3 head (default, the headline); c3: 64 batched heads; c4: gradient; c5: 256^3 modal")
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5", "diag"], default="c2",
+                    help="c2: 128^3 head (default, the headline); c3: 64 batched heads; c4: gradient; c5: 256^3 "
+                    "modal; diag: label ingestion, volume per step and tumour size around the c2 run")
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
     ap.add_argument("--cpu-steps", type=int, default=8)
@@ -573,7 +644,7 @@ def main():
     args.steps_given = args.steps is not None
     if args.steps is None:
         args.steps = 100
-    {"c2": run_c2, "c3": run_c3, "c4": run_c4, "c5": run_c5}[args.workload](args)
+    {"c2": run_c2, "c3": run_c3, "c4": run_c4, "c5": run_c5, "diag": run_diag}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -48,6 +48,7 @@ extern "C" {
 #define EXPINT_EHIP (-4)         /* a HIP runtime call failed; context poisoned */
 #define EXPINT_ENONFINITE (-5)   /* check_finite found a NaN/Inf in the state */
 #define EXPINT_ESTATE (-6)       /* context poisoned by an earlier EXPINT_EHIP */
+#define EXPINT_EIO (-7)          /* a file could not be written */
 
 #define EXPINT_MAX_CLASSES 8
 
@@ -112,8 +113,8 @@ typedef enum {
  *   this is exponential Rosenbrock-Euler, second order in tau.  The plan is
  *   chosen for tau (||A||_1 + rho), which bounds tau ||J_n||_1 for every
  *   state with 0 <= u <= 1 (the tolerance is not guaranteed outside that
- *   range).  Stencil-Taylor algorithm with single-term sweeps only; batches
- *   and gradients give EXPINT_EUNSUPPORTED. */
+ *   range).  Stencil-Taylor algorithm with single-term sweeps only;
+ *   gradients give EXPINT_EUNSUPPORTED. */
 typedef enum {
   EXPINT_SCHEME_EXP_EULER = 0,
   EXPINT_SCHEME_LINEARISED = 1,
@@ -267,8 +268,8 @@ typedef struct expint_batch expint_batch;
 /* count instances, each with its own grid, label field, class table and rho
  * (arrays of length count; dfield entries must use the label form).  Shared
  * bc and opts (dtype, tau, tol, theta_max).  Every instance gets its own
- * plan.  Errors as expint_create; schemes other than EXP_EULER give
- * EXPINT_EUNSUPPORTED. */
+ * plan (LINEARISED: for tau (||A||_1 + rho_i)).  Errors as expint_create;
+ * EXPRK2 gives EXPINT_EUNSUPPORTED. */
 int expint_batch_create(int32_t count, const expint_grid* grids, const expint_dfield* dfields,
                         const double* rho, expint_bc bc, const expint_opts* opts,
                         expint_batch** out);
@@ -321,6 +322,50 @@ int expint_probe_copy(const void* src, void* dst, int64_t bytes, int32_t reps, i
  * per instruction) to *tflops.  sink: device buffer of blocks * 256 floats
  * that receives the accumulator sums (overwritten).  Synchronises. */
 int expint_probe_mfma(int32_t f16, int32_t iters, int32_t blocks, void* sink, void* stream, double* tflops);
+
+/* ---- Label ingestion, diagnostics and output (sections 3.1, 3.2, 3.5). ---- */
+
+/* Labels on the stencil grid nx x ny x nz from an 8-bit scan volume
+ * ni x nj x nk (device, uint8, z fastest like the fields).  Section 3.5 takes
+ * the scan values at the stencil points; read as: stencil point i of n along
+ * an axis of N samples takes sample floor((2i + 1) N / (2n)).  Section 3.1
+ * assigns materials by intensity thresholds; the label is the number of
+ * thresholds strictly below the intensity (the paper's thresholds 1, 115,
+ * 240 give 0 air, 1 white, 2 gray, 3 skull).  thresholds: host array of
+ * n_thresholds (1..7) strictly increasing values.  labels: device, nx*ny*nz
+ * bytes, written.  Asynchronous on `stream` (hipStream_t, NULL = null
+ * stream).  EXPINT_EINVAL for bad arguments or overlapping buffers,
+ * EXPINT_EUNSUPPORTED for nx or ny above 65535. */
+int expint_labels_from_intensity(const uint8_t* image, int32_t ni, int32_t nj, int32_t nk,
+                                 const int32_t* thresholds, int32_t n_thresholds, int32_t nx,
+                                 int32_t ny, int32_t nz, uint8_t* labels, void* stream);
+
+/* nsteps steps of the context's scheme, in place, recording the tumour
+ * volume of section 3.5 after each: volumes[k] = (sum of u after step k + 1)
+ * / (number of voxels), by the fixed-order FP64 reduction.  volumes: host
+ * array of nsteps doubles.  Synchronises once at the end.  Errors as
+ * expint_advance. */
+int expint_advance_volumes(expint_ctx* ctx, void* u, int32_t nsteps, double* volumes);
+
+/* The tumour size of section 3.2, the largest distance between two grid
+ * points holding tumour, here the points with u > threshold: *d2 = the
+ * largest squared distance in grid steps (h * sqrt(*d2) in length units);
+ * -1 without such points, 0 for one.  pair (may be NULL): the linear indices
+ * (i * ny + j) * nz + k of the pair reaching it that is smallest in
+ * (first, second) order with first < second (the point twice for one point).
+ * u: device field of the context's dtype and grid.  The comparison u >
+ * threshold is made in FP64.  Synchronises.  EXPINT_EUNSUPPORTED for grids
+ * whose y-z cross-section exceeds 2^27 points. */
+int expint_tumour_size(expint_ctx* ctx, const void* u, double threshold, int64_t* d2, int64_t* pair);
+
+/* Writes a legacy VTK file (STRUCTURED_POINTS, binary, big-endian) for
+ * ParaView, the viewer of section 3.3: the field (host, nx*ny*nz values of
+ * dtype, the library's layout) as scalars `name` (1..64 letters, digits or
+ * '_'), and the labels (host, may be NULL) as scalars "labels".  The
+ * library's axis i is VTK's x axis; spacing h, origin 0.  Host only, no
+ * device call.  EXPINT_EINVAL for bad arguments, EXPINT_EIO for file errors. */
+int expint_write_vtk(const char* path, int32_t nx, int32_t ny, int32_t nz, double h, const void* field,
+                     expint_dtype dtype, const char* name, const uint8_t* labels);
 
 /* Message for the last failed call on this thread ("" if none). */
 const char* expint_last_error(void);

@@ -22,6 +22,7 @@ ENOMEM = -3
 EHIP = -4
 ENONFINITE = -5
 ESTATE = -6
+EIO = -7
 ERROR_NAMES = {
     EINVAL: "EINVAL",
     EUNSUPPORTED: "EUNSUPPORTED",
@@ -29,6 +30,7 @@ ERROR_NAMES = {
     EHIP: "EHIP",
     ENONFINITE: "ENONFINITE",
     ESTATE: "ESTATE",
+    EIO: "EIO",
 }
 
 F64, F32 = 0, 1
@@ -127,6 +129,10 @@ SIGNATURES = {
     "expint_profile": (_I, [_P, _I32, _I32, _DP]),
     "expint_probe_copy": (_I, [_P, _P, ctypes.c_int64, _I32, _I32, _P, _DP]),
     "expint_probe_mfma": (_I, [_I32, _I32, _I32, _P, _P, _DP]),
+    "expint_labels_from_intensity": (_I, [_P, _I32, _I32, _I32, _P, _I32, _I32, _I32, _I32, _P, _P]),
+    "expint_advance_volumes": (_I, [_P, _P, _I32, _DP]),
+    "expint_tumour_size": (_I, [_P, _P, _D, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "expint_write_vtk": (_I, [ctypes.c_char_p, _I32, _I32, _I32, _D, _P, _I, ctypes.c_char_p, _P]),
     "expint_last_error": (ctypes.c_char_p, []),
 }
 

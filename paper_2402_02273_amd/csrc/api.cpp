@@ -563,10 +563,49 @@ int expint_advance(expint_ctx* c, void* u, int32_t nsteps) {
   int rc = ensure_device(c);
   if (rc) return rc;
   if (nsteps == 0) return EXPINT_OK;
+  if ((rc = run_steps(c, u, nsteps))) return rc;
+  if (c->check_finite) return check_finite_field(c, u);
+  return EXPINT_OK;
+}
+
+int expint_advance_volumes(expint_ctx* c, void* u, int32_t nsteps, double* volumes) {
+  CHECK_CTX(c);
+  if (!u || (nsteps > 0 && !volumes)) return set_error(EXPINT_EINVAL, "NULL argument");
+  if (nsteps < 0) return set_error(EXPINT_EINVAL, "nsteps must be >= 0");
+  int rc = ensure_device(c);
+  if (rc) return rc;
+  if (nsteps == 0) return EXPINT_OK;
+  auto& d = c->diag;
+  if (d.vol_cap < nsteps) {
+    c->arena.release(d.vol);
+    d.vol = nullptr;
+    d.vol_cap = 0;
+    if ((rc = c->arena.alloc(reinterpret_cast<void**>(&d.vol), static_cast<size_t>(nsteps) * sizeof(double))))
+      return rc;
+    d.vol_cap = nsteps;
+  }
+  // each step, then sum u (fixed-order FP64 reduction) into slot k
+  for (int32_t k = 0; k < nsteps; ++k) {
+    if ((rc = run_steps(c, u, 1))) return rc;
+    HIP_TRY(c, launch_reduce(c->dtype, 0, u, nullptr, c->g.n, c->partial, d.vol + k, c->stream));
+  }
+  HIP_TRY(c, hipMemcpyAsync(volumes, d.vol, static_cast<size_t>(nsteps) * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int32_t k = 0; k < nsteps; ++k) volumes[k] /= static_cast<double>(c->g.n);
+  if (c->check_finite) return check_finite_field(c, u);
+  return EXPINT_OK;
+}
+
+}  // extern "C"
+
+namespace expint {
+
+int run_steps(expint_ctx* c, void* u, int32_t nsteps) {
+  int rc = EXPINT_OK;
   if (!c->use_graph) {
     for (int32_t i = 0; i < nsteps; ++i)
       if ((rc = enqueue_step(c, u))) return rc;
-    if (c->check_finite) return check_finite_field(c, u);
     return EXPINT_OK;
   }
   GraphEntry* ge = nullptr;
@@ -599,9 +638,12 @@ int expint_advance(expint_ctx* c, void* u, int32_t nsteps) {
     ge = &c->graphs.back();
   }
   for (int32_t i = 0; i < nsteps; ++i) HIP_TRY(c, hipGraphLaunch(ge->exec, c->stream));
-  if (c->check_finite) return check_finite_field(c, u);
   return EXPINT_OK;
 }
+
+}  // namespace expint
+
+extern "C" {
 
 int expint_reduce(expint_ctx* c, int32_t op, const void* x, const void* y, double* out) {
   CHECK_CTX(c);

@@ -66,6 +66,7 @@ struct Launch {
 struct expint_batch {
   expint_dtype dtype = EXPINT_F32;
   expint_bc bc = EXPINT_NOFLUX;
+  expint_scheme scheme = EXPINT_SCHEME_EXP_EULER;
   double tau = 0.0;
   int device = 0;
   hipStream_t stream = nullptr;
@@ -164,6 +165,7 @@ int build_schedule(expint_batch* b, void* const* u) {
   for (int i = 0; i < count; ++i) {
     Inst& in = b->inst[i];
     per[i] = phi1_schedule(in.ws, in.s, in.m, b->tau, in.ws.b, nullptr, u[i]);
+    if (b->scheme == EXPINT_SCHEME_LINEARISED) set_linearised(per[i], u[i], in.rho);
     tl[i] = in.tiling;
     if (tl[i].vec && (reinterpret_cast<uintptr_t>(u[i]) & vmask) != 0) tl[i] = default_tiling(in.g);
   }
@@ -275,8 +277,8 @@ int build_schedule(expint_batch* b, void* const* u) {
   hipError_t err = hipSuccess;
   for (const Launch& L : b->launches) {
     const void* tb = static_cast<const char*>(b->d_tables) + static_cast<size_t>(L.offset) * (kTab + kMaxClasses) * w;
-    err = launch_batch(b->dtype, b->bc, L.rhs, L.flavor, L.lp, b->d_items + L.offset, tb, L.nitems, L.total, L.grid,
-                       b->stream);
+    err = launch_batch(b->dtype, b->bc, L.rhs, b->scheme == EXPINT_SCHEME_LINEARISED, L.flavor, L.lp,
+                       b->d_items + L.offset, tb, L.nitems, L.total, L.grid, b->stream);
     if (err != hipSuccess) break;
   }
   hipGraph_t gr = nullptr;
@@ -308,8 +310,8 @@ int expint_batch_create(int32_t count, const expint_grid* grids, const expint_df
   if (!(opts->tol >= 0.0) || !(opts->theta_max >= 0.0)) return set_error(EXPINT_EINVAL, "bad tolerances");
   if (opts->algo == EXPINT_ALGO_MODAL || opts->mp != EXPINT_MP_NONE)
     return set_error(EXPINT_EUNSUPPORTED, "batches run the stencil-Taylor path only");
-  if (opts->scheme != EXPINT_SCHEME_EXP_EULER)
-    return set_error(EXPINT_EUNSUPPORTED, "batches take the EXP_EULER scheme");
+  if (opts->scheme != EXPINT_SCHEME_EXP_EULER && opts->scheme != EXPINT_SCHEME_LINEARISED)
+    return set_error(EXPINT_EUNSUPPORTED, "batches take the EXP_EULER or LINEARISED scheme");
   for (int i = 0; i < count; ++i) {
     const expint_grid& g = grids[i];
     const expint_dfield& d = dfields[i];
@@ -332,6 +334,7 @@ int expint_batch_create(int32_t count, const expint_grid* grids, const expint_df
   };
   b->dtype = opts->dtype;
   b->bc = bc;
+  b->scheme = opts->scheme;
   b->tau = opts->tau;
   double tol, theta_max;
   default_tolerances(b->dtype, &tol, &theta_max);
@@ -373,7 +376,8 @@ int expint_batch_create(int32_t count, const expint_grid* grids, const expint_df
     if (opts->s > 0) {
       in.s = opts->s;
       in.m = opts->m;
-    } else if (!choose_plan(b->tau * in.norm1, tol, theta_max, &in.s, &in.m)) {
+    } else if (!choose_plan(b->tau * (in.norm1 + (b->scheme == EXPINT_SCHEME_LINEARISED ? in.rho : 0.0)), tol,
+                            theta_max, &in.s, &in.m)) {
       return bail(set_error(EXPINT_EINVAL, "instance %d: no admissible plan", i));
     }
   }

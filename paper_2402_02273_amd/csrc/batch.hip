@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchItem* __restrict__ 
       cf.labels_form = true;
       cf.labels = it.labels;
       SweepArgs a{};
-      if (KIND == kTerm) {
+      if (is_term(KIND)) {
         a.op = it.op;
       } else {
         a.x = it.op.src;
@@ -101,32 +101,37 @@ static void batch_lp(int lp, const BatchItem* items, const void* tables, int n, 
   }
 }
 
-template <typename T, int BC>
-static void batch_typed(bool rhs, int flavor, int lp, const BatchItem* items, const void* tables, int n, int total,
-                        dim3 g, hipStream_t st) {
-  if (rhs) {
-    batch_lp<T, BC, kRhs, kGeneric>(lp, items, tables, n, total, g, st);
-    return;
-  }
+template <typename T, int BC, int KIND>
+static void batch_terms(int flavor, int lp, const BatchItem* items, const void* tables, int n, int total, dim3 g,
+                        hipStream_t st) {
   switch (flavor) {
-    case kSkip: batch_lp<T, BC, kTerm, kSkip>(lp, items, tables, n, total, g, st); break;
-    case kFlushY: batch_lp<T, BC, kTerm, kFlushY>(lp, items, tables, n, total, g, st); break;
-    case kFlushNoY: batch_lp<T, BC, kTerm, kFlushNoY>(lp, items, tables, n, total, g, st); break;
-    case kFirst: batch_lp<T, BC, kTerm, kFirst>(lp, items, tables, n, total, g, st); break;
-    default: batch_lp<T, BC, kTerm, kGeneric>(lp, items, tables, n, total, g, st); break;
+    case kSkip: batch_lp<T, BC, KIND, kSkip>(lp, items, tables, n, total, g, st); break;
+    case kFlushY: batch_lp<T, BC, KIND, kFlushY>(lp, items, tables, n, total, g, st); break;
+    case kFlushNoY: batch_lp<T, BC, KIND, kFlushNoY>(lp, items, tables, n, total, g, st); break;
+    case kFirst: batch_lp<T, BC, KIND, kFirst>(lp, items, tables, n, total, g, st); break;
+    default: batch_lp<T, BC, KIND, kGeneric>(lp, items, tables, n, total, g, st); break;
   }
 }
 
-hipError_t launch_batch(expint_dtype dt, expint_bc bc, bool rhs, int flavor, int lp, const BatchItem* items,
-                        const void* tables, int nitems, int total_blocks, int grid, hipStream_t st) {
+template <typename T, int BC>
+static void batch_typed(bool rhs, bool lin, int flavor, int lp, const BatchItem* items, const void* tables, int n,
+                        int total, dim3 g, hipStream_t st) {
+  if (rhs) batch_lp<T, BC, kRhs, kGeneric>(lp, items, tables, n, total, g, st);
+  else if (lin) batch_terms<T, BC, kTermJ>(flavor, lp, items, tables, n, total, g, st);
+  else batch_terms<T, BC, kTerm>(flavor, lp, items, tables, n, total, g, st);
+}
+
+hipError_t launch_batch(expint_dtype dt, expint_bc bc, bool rhs, bool lin, int flavor, int lp,
+                        const BatchItem* items, const void* tables, int nitems, int total_blocks, int grid,
+                        hipStream_t st) {
   if (nitems < 1 || nitems > kBatchMaxOps) return hipErrorInvalidValue;
   const dim3 g(grid);
   if (dt == EXPINT_F64) {
-    if (bc == EXPINT_NOFLUX) batch_typed<double, 0>(rhs, flavor, lp, items, tables, nitems, total_blocks, g, st);
-    else batch_typed<double, 1>(rhs, flavor, lp, items, tables, nitems, total_blocks, g, st);
+    if (bc == EXPINT_NOFLUX) batch_typed<double, 0>(rhs, lin, flavor, lp, items, tables, nitems, total_blocks, g, st);
+    else batch_typed<double, 1>(rhs, lin, flavor, lp, items, tables, nitems, total_blocks, g, st);
   } else {
-    if (bc == EXPINT_NOFLUX) batch_typed<float, 0>(rhs, flavor, lp, items, tables, nitems, total_blocks, g, st);
-    else batch_typed<float, 1>(rhs, flavor, lp, items, tables, nitems, total_blocks, g, st);
+    if (bc == EXPINT_NOFLUX) batch_typed<float, 0>(rhs, lin, flavor, lp, items, tables, nitems, total_blocks, g, st);
+    else batch_typed<float, 1>(rhs, lin, flavor, lp, items, tables, nitems, total_blocks, g, st);
   }
   return hipGetLastError();
 }

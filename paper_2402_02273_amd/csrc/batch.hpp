@@ -22,10 +22,12 @@ struct BatchItem {
 };
 
 // One launch over items[0 .. nitems) (nitems <= kBatchMaxOps): all of them
-// right-hand sides (rhs) or all Taylor terms of the given flavour; every
-// instance involved uses lp planes per thread.  tables: per item the class
-// table (64 values) followed by the wall table (8 values), in the dtype.
-hipError_t launch_batch(expint_dtype dt, expint_bc bc, bool rhs, int flavor, int lp, const BatchItem* items,
-                        const void* tables, int nitems, int total_blocks, int grid, hipStream_t st);
+// right-hand sides (rhs) or all Taylor terms of the given flavour (lin: of
+// the linearised operator, TermOp::ju set in every item); every instance
+// involved uses lp planes per thread.  tables: per item the class table (64
+// values) followed by the wall table (8 values), in the dtype.
+hipError_t launch_batch(expint_dtype dt, expint_bc bc, bool rhs, bool lin, int flavor, int lp,
+                        const BatchItem* items, const void* tables, int nitems, int total_blocks, int grid,
+                        hipStream_t st);
 
 }  // namespace expint

@@ -131,6 +131,17 @@ struct expint_ctx {
     double* dwall = nullptr;  // 8 x 8 wall weights
   } adj;
 
+  // tumour diagnostics workspace: allocated on first use
+  struct Diag {
+    int* ext = nullptr;  // x lo/hi, y lo/hi, z lo/hi line extents, back to back
+    int* cand = nullptr;  // candidate points (linear indices), up to 2 per x-line
+    int* count = nullptr;  // candidate count; best d2 and pair key follow
+    unsigned long long* best = nullptr;
+    unsigned long long* key = nullptr;
+    double* vol = nullptr;  // per-step sums of u
+    int64_t vol_cap = 0;
+  } diag;
+
   std::vector<expint::GraphEntry> graphs;
   bool use_graph = true;  // EXPINT_GRAPH=0: advance launches each step directly
   bool poisoned = false;
@@ -160,6 +171,9 @@ double harmonic_mean(double a, double b);
 int ensure_device(expint_ctx* c);
 int upload_tables(expint_ctx* c);
 int enqueue_step(expint_ctx* c, void* u);
+// nsteps steps on the stream: replays (recording on first use) the step graph
+// for u, or launches each step when graphs are off.  No synchronisation.
+int run_steps(expint_ctx* c, void* u, int32_t nsteps);
 int run_ops(expint_ctx* c, const std::vector<TermOp>& ops);
 // The Taylor sweeps of tau phi1(tau A) b for this context's plan: pair sweeps
 // when the context uses them, else one sweep per term (see phi1_schedule).

@@ -10,6 +10,7 @@ arithmetic happens in the HIP library.
 from __future__ import annotations
 
 import ctypes
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -248,6 +249,22 @@ class ExpInt:
         N.check(self.lib.expint_step(self._ctx, self._field(u, "u")))
         return u
 
+    def advance_volumes(self, u, nsteps: int) -> np.ndarray:
+        """nsteps steps in place; the tumour volume sum(u) / N after each."""
+        vol = np.zeros(max(int(nsteps), 0), dtype=np.float64)
+        ptr = vol.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if len(vol) else None
+        N.check(self.lib.expint_advance_volumes(self._ctx, self._field(u, "u"), int(nsteps), ptr))
+        return vol
+
+    def tumour_size(self, u, threshold: float):
+        """(d2, (a, b)): the largest squared distance in grid steps between
+        two points with u > threshold and the smallest pair of linear indices
+        reaching it."""
+        d2 = ctypes.c_int64()
+        pair = (ctypes.c_int64 * 2)()
+        N.check(self.lib.expint_tumour_size(self._ctx, self._field(u, "u"), float(threshold), ctypes.byref(d2), pair))
+        return int(d2.value), (int(pair[0]), int(pair[1]))
+
     def advance(self, u, nsteps: int):
         N.check(self.lib.expint_advance(self._ctx, self._field(u, "u"), int(nsteps)))
         return u
@@ -334,6 +351,7 @@ class ExpIntBatch:
         theta_max: float = 0.0,
         s: int = 0,
         m: int = 0,
+        scheme: str = "exp_euler",
         device=None,
         stream=None,
     ):
@@ -345,6 +363,7 @@ class ExpIntBatch:
         if dtype not in _DTYPES:
             raise ValueError("dtype must be torch.float32 or torch.float64")
         self.dtype = dtype
+        self.scheme = scheme
         count = len(instances)
         if count < 1:
             raise ValueError("empty batch")
@@ -374,6 +393,7 @@ class ExpIntBatch:
         opts.theta_max = float(theta_max)
         opts.s = int(s)
         opts.m = int(m)
+        opts.scheme = _SCHEMES[scheme]
         self._b = ctypes.c_void_p()
         with torch.cuda.device(device):
             opts.stream = _stream_handle(stream, device)
@@ -417,6 +437,44 @@ class ExpIntBatch:
             ptrs[i] = u.data_ptr()
         N.check(self.lib.expint_batch_advance(self._b, ptrs, int(nsteps)))
         return us
+
+
+def labels_from_intensity(image, shape, thresholds=(1, 115, 240), stream=None, out=None):
+    """uint8 labels on the stencil grid `shape` from a uint8 scan volume on a
+    GPU (the thresholds of section 3.1 by default), into `out` if given."""
+    if not isinstance(image, torch.Tensor) or image.dtype != torch.uint8 or image.dim() != 3:
+        raise TypeError("image must be a 3-D torch.uint8 tensor")
+    if image.device.type != "cuda":
+        raise ValueError("image must be on a GPU")
+    image = image.contiguous()
+    shape = tuple(int(v) for v in shape)
+    lab = torch.empty(shape, dtype=torch.uint8, device=image.device) if out is None else out
+    if lab.dtype != torch.uint8 or tuple(lab.shape) != shape or not lab.is_contiguous() or lab.device != image.device:
+        raise ValueError("out must be a contiguous uint8 tensor of the grid's shape on the image's device")
+    th = (ctypes.c_int32 * len(thresholds))(*[int(v) for v in thresholds])
+    lib = N.lib()
+    with torch.cuda.device(image.device):
+        st = _stream_handle(stream, image.device)
+        N.check(lib.expint_labels_from_intensity(image.data_ptr(), *image.shape, th, len(thresholds), *shape,
+                                                 lab.data_ptr(), st))
+    return lab
+
+
+def write_vtk(path, field, h: float = 1.0, name: str = "u", labels=None):
+    """Writes `field` (and optionally `labels`) as a legacy VTK file for ParaView."""
+    f = field.detach().cpu().numpy() if isinstance(field, torch.Tensor) else np.asarray(field)
+    if f.ndim != 3 or f.dtype not in (np.float32, np.float64):
+        raise TypeError("field must be a 3-D float32 or float64 array")
+    f = np.ascontiguousarray(f)
+    lab = None
+    if labels is not None:
+        lab = labels.detach().cpu().numpy() if isinstance(labels, torch.Tensor) else np.asarray(labels)
+        if lab.shape != f.shape or lab.dtype != np.uint8:
+            raise TypeError("labels must be uint8 with the field's shape")
+        lab = np.ascontiguousarray(lab)
+    dt = N.F64 if f.dtype == np.float64 else N.F32
+    N.check(N.lib().expint_write_vtk(os.fsencode(path), *f.shape, float(h), f.ctypes.data, dt, name.encode(),
+                                     None if lab is None else lab.ctypes.data))
 
 
 def probe_peaks(device=None, hbm_bytes=1 << 30, cache_bytes=32 << 20, mfma_blocks=2048, mfma_iters=2048):

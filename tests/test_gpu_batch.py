@@ -147,3 +147,31 @@ def test_batch_sweep_shapes_vs_oracle(native, monkeypatch, tile):
         for i, inst in enumerate(insts):
             ref, _ = oracle_run(inst, tau, K)
             assert rel(us[i].cpu().numpy(), ref) < tol, (dtype, i)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-5)])
+def test_small_batch_linearised_vs_oracle(native, dtype, tol):
+    # the paper's linearised step in every instance: per-instance plans for
+    # tau (||A||_1 + rho_i) and the diagonal rho_i (1 - 2 u_n) in every sweep
+    from oracle import rosenbrock as orb
+    from paper_2402_02273_amd.expint import ExpInt, ExpIntBatch
+
+    insts = small_instances()
+    tau, K = 7.3, 3
+    print(f"[case] small linearised batch {dtype}", flush=True)
+    b = ExpIntBatch(insts, tau=tau, dtype=dtype, device=DEV, scheme="linearised")
+    us = [dev(i["u0"], dtype) for i in insts]
+    b.advance(us, 2)
+    b.advance(us, 1)
+    key = "f64" if dtype == torch.float64 else "f32"
+    for i, inst in enumerate(insts):
+        op = oop.Operator(1.0, labels=inst["labels"], class_D=inst["class_D"])
+        p = b.plan(i)
+        assert (p.s, p.m) == oplan.for_dtype(tau * orb.norm1_bound(op.norm1(), inst["rho"]), key)
+        ref = orb.advance(op, inst["u0"], inst["rho"], tau, p.s, p.m, K)
+        assert rel(us[i].cpu().numpy(), ref) < tol, i
+        single = ExpInt(inst["labels"].shape, labels=inst["labels"], class_D=inst["class_D"], rho=inst["rho"],
+                        tau=tau, dtype=dtype, device=DEV, scheme="linearised")
+        v = dev(inst["u0"], dtype)
+        single.advance(v, K)
+        assert rel(us[i].cpu().numpy(), v.double().cpu().numpy()) < (1e-14 if dtype == torch.float64 else 1e-6)
