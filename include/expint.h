@@ -144,7 +144,7 @@ typedef struct {
   expint_dtype dtype;   /* arithmetic of the fields */
   double tau;           /* time step (> 0) */
   double tol;           /* plan tolerance; 0 = 1e-13 (F64) / 1e-6 (F32) */
-  double theta_max;     /* plan cap on tau*||A||_1/s; 0 = ln 1024 (F64) / ln 16 (F32) */
+  double theta_max;     /* plan cap on tau*||A||_1/s; 0 = ln 1024 (F64) / ln 64 (F32) */
   expint_algo algo;
   expint_mp mp;
   int32_t s, m;         /* both > 0: use this plan; both 0: choose it */
