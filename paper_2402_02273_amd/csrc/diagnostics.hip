@@ -241,12 +241,23 @@ int expint_tumour_size(expint_ctx* c, const void* u, double threshold, int64_t* 
     return set_error(EXPINT_EUNSUPPORTED, "grid cross-section too large for the tumour size pass");
   auto& w = c->diag;
   if (!w.ext) {
-    if ((rc = c->arena.alloc(reinterpret_cast<void**>(&w.ext), 2 * (lx + ly + lz) * sizeof(int)))) return rc;
-    if ((rc = c->arena.alloc(reinterpret_cast<void**>(&w.cand), cmax * sizeof(int)))) return rc;
-    if ((rc = c->arena.alloc(reinterpret_cast<void**>(&w.count), 64))) return rc;
+    // all or nothing: a failed allocation leaves the workspace unset
+    void *ext = nullptr, *cand = nullptr, *cnt = nullptr;
+    rc = c->arena.alloc(&ext, 2 * (lx + ly + lz) * sizeof(int));
+    if (!rc) rc = c->arena.alloc(&cand, cmax * sizeof(int));
+    if (!rc) rc = c->arena.alloc(&cnt, 64);
+    if (rc) {
+      c->arena.release(ext);
+      c->arena.release(cand);
+      c->arena.release(cnt);
+      return rc;
+    }
+    w.cand = static_cast<int*>(cand);
+    w.count = static_cast<int*>(cnt);
     // best and key are adjacent: the host reads both in one copy
-    w.best = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(w.count) + 16);
+    w.best = reinterpret_cast<unsigned long long*>(static_cast<char*>(cnt) + 16);
     w.key = w.best + 1;
+    w.ext = static_cast<int*>(ext);
   }
   int* xlo = w.ext;
   int* xhi = xlo + lx;
