@@ -117,7 +117,7 @@ def test_class_derivative_mutant_caught(monkeypatch):
     def dK(la, lb, class_D, c):
         return 0.5 * ((la == c).astype(float) + (lb == c).astype(float))
     monkeypatch.setattr(oop, "_dK_dDc", dK)
-    assert caught(T_op.test_class_derivative_by_difference, lambda: T_adj.test_gradients_vs_central_fd(2))
+    assert caught(T_op.test_class_derivative_by_difference, lambda: T_adj.test_gradients_vs_central_fd(2, "exp_euler"))
 
 
 # ---- mutants of the integrator (section 2.2) ----
@@ -201,7 +201,7 @@ def test_theta_cap_ignored_caught(monkeypatch):
 
 def test_adjoint_reaction_derivative_sign_caught(monkeypatch):
     monkeypatch.setattr(oadj, "reaction_prime", lambda u, rho: rho * (1.0 + 2.0 * u))
-    assert caught(lambda: T_adj.test_gradients_vs_central_fd(2), T_adj.test_taylor_remainder_second_order)
+    assert caught(lambda: T_adj.test_gradients_vs_central_fd(2, "exp_euler"), lambda: T_adj.test_taylor_remainder_second_order("exp_euler"))
 
 
 def test_adjoint_forward_mutant_caught(monkeypatch):
