@@ -410,7 +410,10 @@ def run_c4(args):
     w, _ = c4_adjoint()
     target = c4_synthetic_target()
     dt = torch.float32 if args.dtype == "f32" else torch.float64
-    ctx = ExpInt(w.shape, labels=w.labels, class_D=w.class_D, rho=w.rho, tau=w.tau, dtype=dt, device="cuda:0")
+    if args.scheme == "exprk2":
+        raise SystemExit("c4 differentiates the exp_euler or linearised scheme")
+    ctx = ExpInt(w.shape, labels=w.labels, class_D=w.class_D, rho=w.rho, tau=w.tau, dtype=dt, device="cuda:0",
+                 scheme=args.scheme)
     u0 = torch.as_tensor(w.u0, dtype=dt, device="cuda:0").contiguous()
     tg = torch.as_tensor(target, dtype=dt, device="cuda:0").contiguous()
     ctx.grad(u0, w.nsteps, tg, ckpt_every=10)
@@ -422,7 +425,7 @@ def run_c4(args):
     ms = _timed(go, None)
     errs = None
     gpath = os.path.join(ROOT, "tests", "golden", "c4_adjoint_96_k50_f64.npz")
-    if os.path.exists(gpath):
+    if os.path.exists(gpath) and args.scheme == "exp_euler":
         g = np.load(gpath)
         loss, gu, grho, gD = res["g"]
         errs = {
@@ -445,7 +448,9 @@ def run_c4(args):
         "vs_baseline": None,
         "dtype": args.dtype,
         "data": "synthetic",
-        "config": {"workload": "96^3 head seed 2404, gradient wrt u0, rho, D per class, ckpt 10", "plan": [ctx.plan.s, ctx.plan.m]},
+        "config": {"workload": "96^3 head seed 2404, gradient wrt u0, rho, D per class, ckpt 10"
+                   + (", linearised step" if args.scheme == "linearised" else ""),
+                   "scheme": args.scheme, "plan": [ctx.plan.s, ctx.plan.m]},
         "errors_vs_oracle": errs,
     }
     print(json.dumps(out), flush=True)

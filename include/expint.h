@@ -113,8 +113,7 @@ typedef enum {
  *   this is exponential Rosenbrock-Euler, second order in tau.  The plan is
  *   chosen for tau (||A||_1 + rho), which bounds tau ||J_n||_1 for every
  *   state with 0 <= u <= 1 (the tolerance is not guaranteed outside that
- *   range).  Stencil-Taylor algorithm with single-term sweeps only;
- *   gradients give EXPINT_EUNSUPPORTED. */
+ *   range).  Stencil-Taylor algorithm with single-term sweeps only. */
 typedef enum {
   EXPINT_SCHEME_EXP_EULER = 0,
   EXPINT_SCHEME_LINEARISED = 1,
@@ -251,8 +250,9 @@ int expint_reduce(expint_ctx* ctx, int32_t op, const void* x, const void* y, dou
  * u0, u_target: device fields (read only); grad_u0: device field (written);
  * loss, grad_rho: host scalars; grad_class_D: host array of n_classes
  * (label form only; dense form gives EINVAL).  u is checkpointed every
- * ckpt_every steps (>= 1) and recomputed in between.  EXP_EULER contexts
- * only (other schemes: EXPINT_EUNSUPPORTED). */
+ * ckpt_every steps (>= 1) and recomputed in between.  EXP_EULER and
+ * LINEARISED contexts (the latter differentiates J_n's diagonal too); EXPRK2
+ * gives EXPINT_EUNSUPPORTED. */
 int expint_grad(expint_ctx* ctx, const void* u0, int32_t nsteps, const void* u_target,
                 int32_t ckpt_every, double* loss, void* grad_u0, double* grad_rho,
                 double* grad_class_D);

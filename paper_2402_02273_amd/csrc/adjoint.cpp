@@ -14,6 +14,13 @@
 //   dL/dD_c += <g, A_c u_n> + sum_sigma [h <ybar_1, A_c x_{sigma-1}> + sum_{j>=2} (h/j) <ybar_j, A_c y_{j-1}>],
 // with A_c = dA/dD_c.  u is checkpointed every ckpt_every steps and recomputed
 // inside a segment; each step's Taylor terms are recomputed once and kept.
+//
+// The LINEARISED scheme (section 2.1's splitting) runs every recurrence with
+// J_n = A + diag(d_n), d_n = rho (1 - 2 u_n), in place of A (J_n is
+// symmetric as well); the diagonal's adjoint
+//   dbar = sum_sigma [h ybar_1 * x_{sigma-1} + sum_{j>=2} (h/j) ybar_j * y_{j-1}]
+// (pointwise, the pairs of the class terms) adds lambda_n += -2 rho dbar and
+// dL/drho += <dbar, 1 - 2 u_n>.
 
 #include <algorithm>
 #include <cmath>
@@ -42,16 +49,34 @@ int ensure_adj(expint_ctx* c, int nck, int seg) {
   const size_t fb = c->field_bytes();
   int rc;
   if (!a.lam) {
-    void** singles[] = {&a.lam, &a.gb, &a.work, &a.xb[0], &a.xb[1], &a.yb[0], &a.yb[1]};
-    for (void** p : singles)
-      if ((rc = c->arena.alloc(p, fb))) return rc;
-    if ((rc = c->arena.alloc(reinterpret_cast<void**>(&a.fpart),
-                             static_cast<size_t>(faceprod_slots(c->g, c->tiling)) * kMaxClasses * sizeof(double))))
-      return rc;
-    if ((rc = c->arena.alloc(reinterpret_cast<void**>(&a.dev), 16 * sizeof(double)))) return rc;
-    if ((rc = c->arena.alloc(reinterpret_cast<void**>(&a.dtab), kMaxClasses * kTab * sizeof(double)))) return rc;
-    if ((rc = c->arena.alloc(reinterpret_cast<void**>(&a.dwall), kMaxClasses * kMaxClasses * sizeof(double))))
-      return rc;
+    // all or nothing, lam last: it marks the set as complete
+    struct Want {
+      void** p;
+      size_t bytes;
+    } want[] = {
+        {&a.gb, fb},
+        {&a.work, fb},
+        {&a.xb[0], fb},
+        {&a.xb[1], fb},
+        {&a.yb[0], fb},
+        {&a.yb[1], fb},
+        {&a.dbar, fb},
+        {reinterpret_cast<void**>(&a.fpart),
+         static_cast<size_t>(faceprod_slots(c->g, c->tiling)) * kMaxClasses * sizeof(double)},
+        {reinterpret_cast<void**>(&a.dev), 16 * sizeof(double)},
+        {reinterpret_cast<void**>(&a.dtab), kMaxClasses * kTab * sizeof(double)},
+        {reinterpret_cast<void**>(&a.dwall), kMaxClasses * kMaxClasses * sizeof(double)},
+        {&a.lam, fb},
+    };
+    for (const Want& wnt : want) {
+      if ((rc = c->arena.alloc(wnt.p, wnt.bytes))) {
+        for (const Want& q : want) {
+          c->arena.release(*q.p);
+          *q.p = nullptr;
+        }
+        return rc;
+      }
+    }
   }
   if ((rc = grow(c, a.ckpt, static_cast<size_t>(nck)))) return rc;
   if ((rc = grow(c, a.segs, static_cast<size_t>(seg)))) return rc;
@@ -87,13 +112,22 @@ int upload_weights(expint_ctx* c) {
 }
 
 // Adds w <ybar, (dA/dD_c) y> for every class into the face-product slots.
-int faceprod(expint_ctx* c, const void* ybar, const void* y, double w) {
+// For a Taylor term (taylor) of the LINEARISED scheme also dbar += w ybar * y:
+// the term applied the diagonal to y as well.
+int faceprod(expint_ctx* c, const void* ybar, const void* y, double w, bool taylor) {
   HIP_TRY(c, launch_faceprod(c->dtype, c->bc, c->g, c->tiling, c->labels, c->nclass, c->adj.dtab, c->adj.dwall, ybar,
                              y, w, c->adj.fpart, c->stream));
+  if (taylor && c->scheme == EXPINT_SCHEME_LINEARISED)
+    HIP_TRY(c, launch_diag_accumulate(c->dtype, c->g.n, w, ybar, y, c->adj.dbar, c->stream));
   return EXPINT_OK;
 }
 
-int term(expint_ctx* c, TermOp op) {
+// One Taylor sweep of the step's matrix: A, or J_n at the state un.
+int term(expint_ctx* c, TermOp op, const void* un) {
+  if (c->scheme == EXPINT_SCHEME_LINEARISED) {
+    op.ju = un;
+    op.jrho = c->rho;
+  }
   classify_term(op);
   HIP_TRY(c, launch_term(c->dtype, c->bc, c->g, c->tiling, c->coef(), op, c->stream));
   return EXPINT_OK;
@@ -118,7 +152,7 @@ int reverse_step(expint_ctx* c, const void* un) {
     t1.cs = 1.0;
     t1.acc_out = a.xs[sig];
     t1.y_out = m >= 2 ? T[0] : nullptr;
-    if ((rc = term(c, t1))) return rc;
+    if ((rc = term(c, t1, un))) return rc;
     for (int j = 2; j <= m; ++j) {
       TermOp t;
       t.src = T[j - 2];
@@ -127,21 +161,23 @@ int reverse_step(expint_ctx* c, const void* un) {
       t.ca = 1.0;
       t.acc_out = a.xs[sig];
       t.y_out = j < m ? T[j - 1] : nullptr;
-      if ((rc = term(c, t))) return rc;
+      if ((rc = term(c, t, un))) return rc;
     }
   }
   // reverse through the sub-steps
   int xi = 0;
   HIP_TRY(c, launch_copy(c->dtype, n, a.lam, a.xb[0], c->stream));
   HIP_TRY(c, launch_fill(c->dtype, n, 0.0, a.gb, c->stream));
+  const bool lin = c->scheme == EXPINT_SCHEME_LINEARISED;
+  if (lin) HIP_TRY(c, launch_fill(c->dtype, n, 0.0, a.dbar, c->stream));
   for (int sig = s; sig >= 1; --sig) {
     void** T = &a.tape[static_cast<size_t>(sig - 1) * m];
     const void* xprev = a.xs[sig - 1];
     const void* ynext = a.xb[xi];  // ybar_m = xbar
     if (m >= 2) {
-      if ((rc = faceprod(c, ynext, T[m - 2], h / m))) return rc;
+      if ((rc = faceprod(c, ynext, T[m - 2], h / m, true))) return rc;
     } else {
-      if ((rc = faceprod(c, ynext, xprev, h))) return rc;
+      if ((rc = faceprod(c, ynext, xprev, h, true))) return rc;
     }
     int yi = 0;
     for (int j = m - 1; j >= 1; --j) {
@@ -151,10 +187,10 @@ int reverse_step(expint_ctx* c, const void* un) {
       t.cb = 1.0;
       t.c = h / (j + 1);
       t.y_out = a.yb[yi];
-      if ((rc = term(c, t))) return rc;
+      if ((rc = term(c, t, un))) return rc;
       ynext = a.yb[yi];
       yi ^= 1;
-      if ((rc = faceprod(c, ynext, j >= 2 ? T[j - 2] : xprev, j >= 2 ? h / j : h))) return rc;
+      if ((rc = faceprod(c, ynext, j >= 2 ? T[j - 2] : xprev, j >= 2 ? h / j : h, true))) return rc;
     }
     // bbar += h ybar_1;  xbar <- xbar + h A ybar_1
     HIP_TRY(c, launch_axpby(c->dtype, n, 1.0, a.gb, h, ynext, a.gb, c->stream));
@@ -164,13 +200,17 @@ int reverse_step(expint_ctx* c, const void* un) {
     t.cb = 1.0;
     t.c = h;
     t.y_out = a.xb[1 - xi];
-    if ((rc = term(c, t))) return rc;
+    if ((rc = term(c, t, un))) return rc;
     xi ^= 1;
   }
   // g = bbar: rho and D contributions of b_n = A u_n + f(u_n), then lambda_n
   HIP_TRY(c, launch_reduce(c->dtype, 4, a.gb, un, n, c->partial, a.dev + 8, c->stream, true));
-  if ((rc = faceprod(c, a.gb, un, 1.0))) return rc;
+  if ((rc = faceprod(c, a.gb, un, 1.0, false))) return rc;  // b_n = A u_n + f(u_n): no diagonal
   HIP_TRY(c, launch_adj_rhs(c->dtype, c->bc, c->g, c->tiling, c->coef(), a.gb, un, a.lam, a.lam, c->rho, c->stream));
+  if (lin) {  // the diagonal rho (1 - 2 u_n): d/drho and d/du_n
+    HIP_TRY(c, launch_reduce(c->dtype, 6, a.dbar, un, n, c->partial, a.dev + 8, c->stream, true));
+    HIP_TRY(c, launch_axpy(c->dtype, n, -2.0 * c->rho, a.dbar, a.lam, c->stream));
+  }
   return EXPINT_OK;
 }
 
@@ -181,8 +221,8 @@ int vjp_core(expint_ctx* c, const void* u0, int32_t nsteps, const void* cot, boo
   if (nsteps < 0) return set_error(EXPINT_EINVAL, "nsteps must be >= 0");
   if (ckpt_every < 1) return set_error(EXPINT_EINVAL, "ckpt_every must be >= 1");
   if (!c->labels_form) return set_error(EXPINT_EINVAL, "gradients need the label form of D");
-  if (c->scheme != EXPINT_SCHEME_EXP_EULER)
-    return set_error(EXPINT_EUNSUPPORTED, "gradients are for the EXP_EULER scheme");  // LINEARISED, EXPRK2
+  if (c->scheme == EXPINT_SCHEME_EXPRK2)
+    return set_error(EXPINT_EUNSUPPORTED, "gradients are for the EXP_EULER and LINEARISED schemes");
   int rc = ensure_device(c);
   if (rc) return rc;
   const int nck = nsteps > 0 ? (nsteps + ckpt_every - 1) / ckpt_every : 0;

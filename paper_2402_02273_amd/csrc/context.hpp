@@ -125,6 +125,7 @@ struct expint_ctx {
     void* work = nullptr;     // forward state
     void* xb[2] = {nullptr, nullptr};
     void* yb[2] = {nullptr, nullptr};
+    void* dbar = nullptr;     // LINEARISED: adjoint of the diagonal rho (1 - 2 u_n)
     double* fpart = nullptr;  // face-product slots, faceprod_slots(g, tiling) * 8
     double* dev = nullptr;    // [0..7] class sums, [8] d/drho, [9] loss
     double* dtab = nullptr;   // 8 x 64 face weights

@@ -151,7 +151,8 @@ hipError_t launch_scan_dense(expint_dtype dt, expint_bc bc, const Geom& g, const
                              void* fy, void* fz, void* wallv, double* partial, double* out, hipStream_t st);
 
 // Deterministic two-pass FP64 reductions: op 0 sum x, 1 sum x*y, 2 max|x|,
-// 3 count of non-finite x, 4 sum x*y*(1-y), 5 sum (x-y)^2.  partial:
+// 3 count of non-finite x, 4 sum x*y*(1-y), 5 sum (x-y)^2,
+// 6 sum x*(1-2y).  partial:
 // kReduceBlocks doubles; out: 1 double, overwritten or (accumulate) added to.
 hipError_t launch_reduce(expint_dtype dt, int op, const void* x, const void* y, int64_t n, double* partial,
                          double* out, hipStream_t st, bool accumulate = false);
@@ -185,6 +186,9 @@ hipError_t launch_copy(expint_dtype dt, int64_t n, const void* x, void* y, hipSt
 hipError_t launch_axpby(expint_dtype dt, int64_t n, double a, const void* x, double b, const void* y, void* out,
                         hipStream_t st);  // out = a x + b y
 hipError_t launch_fill(expint_dtype dt, int64_t n, double v, void* y, hipStream_t st);
+// d += w ybar y pointwise (the adjoint of the linearised operator's diagonal)
+hipError_t launch_diag_accumulate(expint_dtype dt, int64_t n, double w, const void* ybar, const void* y, void* d,
+                                  hipStream_t st);
 // d = f(u + x) - f(u) for f(v) = rho v (1 - v), evaluated as rho x (1 - 2u - x)
 // (the same polynomial without the cancellation of the difference).
 hipError_t launch_reaction_increment(expint_dtype dt, int64_t n, double rho, const void* u, const void* x, void* d,

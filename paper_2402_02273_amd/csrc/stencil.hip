@@ -248,6 +248,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const T* __restrict__ x, cons
       const double d = v - static_cast<double>(y[p]);
       acc += d * d;
     }
+    if (OP == 6) acc += v * (1.0 - 2.0 * static_cast<double>(y[p]));
   }
   acc = block_reduce<OP>(acc);
   if (threadIdx.x == 0) partial[blockIdx.x] = acc;
@@ -279,6 +280,14 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_copy(int64_t n, const T* __restrict__ x, T* __restrict__ y) {
   const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (p < n) y[p] = x[p];
+}
+
+// d += w ybar y, pointwise
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_diag_accumulate(int64_t n, T w, const T* __restrict__ ybar,
+                                                            const T* __restrict__ y, T* __restrict__ d) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (p < n) d[p] += w * ybar[p] * y[p];
 }
 
 // d = f(u + x) - f(u), f(v) = rho v (1 - v), as rho x (1 - 2u - x)
@@ -391,7 +400,8 @@ static void reduce_typed(int op, const T* x, const T* y, int64_t n, double* part
     case 2: reduce_op<T, 2>(x, y, n, partial, out, acc, st); break;
     case 3: reduce_op<T, 3>(x, y, n, partial, out, acc, st); break;
     case 4: reduce_op<T, 4>(x, y, n, partial, out, acc, st); break;
-    default: reduce_op<T, 5>(x, y, n, partial, out, acc, st); break;
+    case 5: reduce_op<T, 5>(x, y, n, partial, out, acc, st); break;
+    default: reduce_op<T, 6>(x, y, n, partial, out, acc, st); break;
   }
 }
 
@@ -447,6 +457,18 @@ hipError_t launch_reaction_increment(expint_dtype dt, int64_t n, double rho, con
   else
     k_reaction_increment<float><<<grid, block, 0, st>>>(n, static_cast<float>(rho), static_cast<const float*>(u),
                                                         static_cast<const float*>(x), static_cast<float*>(d));
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_accumulate(expint_dtype dt, int64_t n, double w, const void* ybar, const void* y, void* d,
+                                  hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>((n + kBlock - 1) / kBlock)), block(kBlock);
+  if (dt == EXPINT_F64)
+    k_diag_accumulate<double><<<grid, block, 0, st>>>(n, w, static_cast<const double*>(ybar),
+                                                      static_cast<const double*>(y), static_cast<double*>(d));
+  else
+    k_diag_accumulate<float><<<grid, block, 0, st>>>(n, static_cast<float>(w), static_cast<const float*>(ybar),
+                                                     static_cast<const float*>(y), static_cast<float*>(d));
   return hipGetLastError();
 }
 

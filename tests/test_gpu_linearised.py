@@ -201,8 +201,6 @@ def test_unsupported_uses(native):
     labels = random_labels(shape, 3, seed=71)
     lin = make_ctx(labels, CLASS_D, torch.float32)
     u = dev(random_field(shape, seed=72), torch.float32)
-    with pytest.raises(RuntimeError, match="EXP_EULER"):
-        lin.grad(u, 2, u.clone(), ckpt_every=1)
     plain = ExpInt(shape, labels=labels, class_D=CLASS_D, dtype=torch.float32, device=DEV)
     with pytest.raises(RuntimeError, match="LINEARISED"):
         plain.phi1_lin(u, u)
