@@ -135,6 +135,15 @@ __device__ __forceinline__ float phi1_times_tau(float z, float tau) {
   return z == 0.f ? tau : tau * expm1f(z) / z;
 }
 
+// tau phi1(z) for z = zr + zc <= 0 from er = exp(zr) and ec = exp(zc):
+// e^z - 1 by one FP64 fma (its relative error stays near 1e-12 down to the
+// smallest nonzero |z| of a grid), then the FP32 quotient.
+__device__ __forceinline__ float phi1_sep(double zr, double er, double zc, double ec, float tau) {
+  const float z = static_cast<float>(zr + zc);
+  const float num = static_cast<float>(fma(er, ec, -1.0));
+  return z == 0.f ? tau : tau * num * __builtin_amdgcn_rcpf(z);
+}
+
 // One 64 x 64 output tile of a mode product.
 //   SIDE 0 (left):  out[p][m][q] = sum_k Qop[m][k] in[p][k][q]   (view pre, n, post)
 //   SIDE 1 (right): out[p][m]    = sum_k in[p][k] Qop[m][k]     (view pre, n)
@@ -723,14 +732,66 @@ __global__ __launch_bounds__(64 * TMW * TNW) void k_mode_gemm(ModalArgs a) {
   };
   load_chunk(0, pend0);
   load_chunk(min(1, nchunks - 1) * GK, pend1);
+  // phi1 multiplier: exp(z) is separable, exp(z_row + z_col) =
+  // exp(z_row) exp(z_col), so each row's tauD lambda_x and its exponential are
+  // formed once per tile (FP64, LDS) and each column's once per lane; per
+  // element the multiplier is then tau (e_row e_col - 1) / z.  z <= 0, and
+  // z == 0 only for the constant mode, where e_row e_col - 1 is exactly 0 too.
+  __shared__ double rowv[SIDE == 0 && EPI == kEpiMul ? 2 * GM : 1];
+  if (SIDE == 0 && EPI == kEpiMul && tid < GM) {
+    const long row = m0 + tid;
+    const double zr = row < mrows ? a.tauD * a.lam_x[row] : 0.0;
+    rowv[tid] = zr;
+    rowv[GM + tid] = exp(zr);
+  }
   store_chunk(pend0, 0);
-  __syncthreads();
+  __syncthreads();  // also publishes rowv
   for (int c = 0; c < nchunks; c += 2) {
     iteration(c, std::integral_constant<int, 0>{});
     if (c + 1 < nchunks) iteration(c + 1, std::integral_constant<int, 1>{});
   }
 
   // epilogue: D[row][col], col = lane % 32, row = 8 (r / 4) + 4 (lane / 32) + r % 4
+  const long rs = SIDE == 0 ? a.post : n;  // row stride of the output
+  float* const obase = out + (SIDE == 0 ? static_cast<long>(p) * n * a.post : 0);
+  if (m0 + GM <= mrows && c0 + GN <= ncols && rs * GM < (1L << 31)) {
+    // interior tile: no per-element bounds, a uniform base per 32 x 32 block
+    // and a 32-bit offset per element
+    const int irs = static_cast<int>(rs);
+    const int lane_off = 4 * (lane >> 5) * irs + fr;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        float* const tb = obase + (m0 + wm + 32 * t) * rs + c0 + wn + 32 * u;
+        double zc = 0.0, ec = 1.0;  // kEpiMul: tauD (lambda_y + lambda_z) of this lane's column, its exp
+        if (SIDE == 0 && EPI == kEpiMul) {
+          const long col = c0 + wn + 32 * u + fr;
+          zc = a.tauD * (a.lam_y[col / a.nz] + a.lam_z[col % a.nz]);
+          ec = exp(zc);
+        }
+        // add into u: all 16 loads of the block before its stores (a load
+        // after a store to the same buffer would wait for the store's address)
+        float old[16];
+        if (SIDE == 1 && EPI == kEpiAddU) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) old[r] = tb[(8 * (r >> 2) + (r & 3)) * irs + lane_off];
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int off = (8 * (r >> 2) + (r & 3)) * irs + lane_off;
+          float v = acc[t][u][r];
+          if (two_acc) v += accx[two_acc ? t : 0][two_acc ? u : 0][r] * (1.0f / kF16LoScale);
+          if (SIDE == 0 && EPI == kEpiMul) {
+            const int rl = wm + 32 * t + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            v *= phi1_sep(rowv[rl], rowv[GM + rl], zc, ec, static_cast<float>(a.tau));
+          }
+          if (SIDE == 1 && EPI == kEpiAddU) tb[off] = old[r] + v;
+          else tb[off] = v;
+        }
+      }
+    return;
+  }
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -745,9 +806,9 @@ __global__ __launch_bounds__(64 * TMW * TNW) void k_mode_gemm(ModalArgs a) {
         if (two_acc) v += accx[two_acc ? t : 0][two_acc ? u : 0][r] * (1.0f / kF16LoScale);
         if (SIDE == 0) {
           if (EPI == kEpiMul) {
-            const int jj = static_cast<int>(col / a.nz), kk = static_cast<int>(col % a.nz);
-            const float z = static_cast<float>(a.tauD * (a.lam_x[row] + a.lam_y[jj] + a.lam_z[kk]));
-            v *= phi1_times_tau(z, static_cast<float>(a.tau));
+            const int rl = static_cast<int>(row - m0);
+            const double zc = a.tauD * (a.lam_y[col / a.nz] + a.lam_z[col % a.nz]);
+            v *= phi1_sep(rowv[rl], rowv[GM + rl], zc, exp(zc), static_cast<float>(a.tau));
           }
           out[static_cast<long>(p) * n * a.post + row * a.post + col] = v;
         } else {
