@@ -621,14 +621,91 @@ def run_diag(args):
     print(json.dumps(out), flush=True)
 
 
+def run_shard(args):
+    """One GPU's share of the headline step if the 128^3 head were split into
+    x-slabs over G GPUs (G = 2, 4, 8): the step on a slab of 128/G owned
+    planes plus its halo planes (one on each side of an interior slab, one for
+    G = 2), with the whole grid's plan.  Only
+    the compute on the share is timed.  The halo exchange between GPUs is not
+    built, and the slab's outer planes are plain walls here, so the result is
+    a timing of the kernel shape, not a solution of the split problem."""
+    import torch
+
+    from paper_2402_02273_amd.expint import ExpInt
+    from workloads import c2_head
+
+    dev = torch.device("cuda:0")
+    w = c2_head(n=args.n)
+    full = ExpInt(w.shape, w.h, labels=w.labels, class_D=w.class_D, rho=w.rho, tau=w.tau, dtype=torch.float32,
+                  device=dev)
+    s, m = full.plan.s, full.plan.m
+
+    def step_ms(ctx, u0_host):
+        u0 = torch.as_tensor(u0_host, dtype=torch.float32, device=dev).contiguous()
+        u = u0.clone()
+        ctx.advance(u, args.warmup)  # records the step graph
+        u.copy_(u0)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(ctx.stream)
+        ctx.advance(u, args.steps)
+        ev1.record(ctx.stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / args.steps
+
+    ms_full = step_ms(full, w.u0)
+    del full
+    shares = []
+    n = args.n
+    for g in (2, 4, 8):
+        own = n // g
+        k = (g - 1) // 2  # an interior slab where there is one (G >= 3): a halo plane on each side
+        i0 = max(0, k * own - 1)
+        i1 = min(n, (k + 1) * own + 1)
+        ctx = ExpInt((i1 - i0, n, n), w.h, labels=w.labels[i0:i1], class_D=w.class_D, rho=w.rho, tau=w.tau,
+                     dtype=torch.float32, device=dev, s=s, m=m)
+        ms = step_ms(ctx, w.u0[i0:i1])
+        del ctx
+        torch.cuda.synchronize()
+        shares.append({
+            "gpus": g,
+            "slab": [i1 - i0, n, n],
+            "owned_planes": own,
+            "ms_per_step": ms,
+            "owned_voxel_updates_per_s": own * n * n / (ms / 1e3),
+            "speedup_vs_whole_grid": ms_full / ms,
+        })
+    out = {
+        "metric": "per-GPU share of the 128^3 step (ms)",
+        "value": shares[-1]["ms_per_step"],
+        "unit": "ms per step on the 8-way slab",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": shares[-1]["ms_per_step"],
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"x-slabs of the {n}^3 head seed 2402 (128/G owned planes + halo planes), "
+                   f"plan {s}x{m} of the whole grid; compute only, no halo exchange"},
+        "whole_grid_ms_per_step": ms_full,
+        "shares": shares,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5", "diag"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5", "diag", "shard"], default="c2",
                     help="c2: 128^3 head (default, the headline); c3: 64 batched heads; c4: gradient; c5: 256^3 "
-                    "modal; diag: label ingestion, volume per step and tumour size around the c2 run")
+                    "modal; diag: label ingestion, volume per step and tumour size around the c2 run; shard: one GPU's "
+                    "x-slab share of the c2 step for 2, 4 and 8 GPUs (compute only)")
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
     ap.add_argument("--cpu-steps", type=int, default=8)
@@ -649,7 +726,8 @@ def main():
     args.steps_given = args.steps is not None
     if args.steps is None:
         args.steps = 100
-    {"c2": run_c2, "c3": run_c3, "c4": run_c4, "c5": run_c5, "diag": run_diag}[args.workload](args)
+    {"c2": run_c2, "c3": run_c3, "c4": run_c4, "c5": run_c5, "diag": run_diag,
+     "shard": run_shard}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -149,7 +149,7 @@ typedef struct {
   int32_t s, m;         /* both > 0: use this plan; both 0: choose it */
   int32_t check_finite; /* nonzero: expint_step / expint_advance scan u for NaN/Inf */
   expint_sweeps sweeps; /* term grouping of the stencil-Taylor sweeps */
-  expint_scheme scheme; /* the step: EXP_EULER (default) or LINEARISED */
+  expint_scheme scheme; /* the step: EXP_EULER (default), LINEARISED or EXPRK2 */
   void* stream;         /* hipStream_t the context works on; NULL = null stream */
 } expint_opts;
 
@@ -279,9 +279,13 @@ int expint_batch_create(int32_t count, const expint_grid* grids, const expint_df
  * whole schedule; later calls replay it. */
 int expint_batch_advance(expint_batch* batch, void* const* u, int32_t nsteps);
 
+/* Plan of instance `index` (0 <= index < count): s, m and ||A||_1 as for
+ * expint_get_plan (host scalars; each may be NULL).  EXPINT_EINVAL for a
+ * NULL batch or an index out of range. */
 int expint_batch_get_plan(const expint_batch* batch, int32_t index, int32_t* s, int32_t* m,
                           double* norm_A1);
 
+/* Release the batch, its workspace and its recorded graph.  NULL-safe. */
 void expint_batch_destroy(expint_batch* batch);
 
 /* ---- Introspection and measurement. ---- */
