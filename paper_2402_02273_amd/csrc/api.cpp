@@ -488,7 +488,10 @@ int expint_set_params(expint_ctx* c, double rho, const double* class_D, int32_t 
     }
     if ((rc = make_plan(c))) return rc;
   }
-  destroy_graphs(c->graphs);  // rho and the schedule are baked into recorded graphs
+  // rho and the schedule are baked into recorded graphs; a launch of one may
+  // still be running on the stream
+  if (!c->graphs.empty()) HIP_TRY(c, hipStreamSynchronize(c->stream));
+  destroy_graphs(c->graphs);
   return EXPINT_OK;
 }
 
@@ -613,6 +616,8 @@ int run_steps(expint_ctx* c, void* u, int32_t nsteps) {
     if (e.key0 == u) ge = &e;
   if (!ge) {
     if (c->graphs.size() >= 4) {
+      // a launch of the evicted graph may still be running on the stream
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
       std::vector<GraphEntry> old(c->graphs.begin(), c->graphs.begin() + 1);
       destroy_graphs(old);
       c->graphs.erase(c->graphs.begin());
@@ -633,7 +638,12 @@ int run_steps(expint_ctx* c, void* u, int32_t nsteps) {
       return set_error(EXPINT_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(ec));
     }
     e.graph = gr;
-    HIP_TRY(c, hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0));
+    const hipError_t ei = hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      (void)hipGraphDestroy(e.graph);
+      c->poisoned = true;
+      return set_error(EXPINT_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+    }
     c->graphs.push_back(e);
     ge = &c->graphs.back();
   }

@@ -410,6 +410,8 @@ int expint_batch_advance(expint_batch* b, void* const* u, int32_t nsteps) {
   bool same = b->exec && static_cast<int>(b->key.size()) == count;
   for (int i = 0; same && i < count; ++i) same = b->key[i] == u[i];
   if (!same) {
+    // a launch of the graph being replaced may still be running on the stream
+    if (b->exec) BHIP(hipStreamSynchronize(b->stream));
     const int rc = build_schedule(b, u);
     if (rc) return rc;
   }
