@@ -252,7 +252,9 @@ def run_c2(args):
         kname = "k_sweep term, pair-flush flavour (stencil + Taylor term + running sum)"
         tb = FLUSH_BYTES(w_bytes) * w.nvox
         ms_dom = ms_flush
-        traffic = load_traffic(f"flush_{args.dtype}_{args.n}", "k_sweep4" if launch["vec"] else "k_sweep")
+        # the counters are per kernel variant: the vector sweep with non-temporal stores is its own
+        traffic = load_traffic(f"flush_{args.dtype}_{args.n}",
+                               ("k_sweep4_nt" if launch.get("nt") else "k_sweep4") if launch["vec"] else "k_sweep")
         if erk:
             sbv, nlaunch = step_bytes_per_voxel_exprk2(w_bytes, plan.s, plan.m)
         else:

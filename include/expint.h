@@ -192,6 +192,8 @@ typedef struct {
   int32_t bx, by;       /* scalar sweep: threads along z and y (0 if vec) */
   int32_t rw;           /* vectorised sweep: lanes per z-segment (0 if scalar) */
   int32_t lp;           /* single-term sweeps: x-planes per thread */
+  int32_t nt;           /* vectorised sweep: 1 = the Taylor terms of A store their outputs
+                         * non-temporally (autotuned; LINEARISED contexts: always 0) */
 } expint_launch_info;
 
 /* The context's launch configuration.  EXPINT_EINVAL for NULL arguments. */

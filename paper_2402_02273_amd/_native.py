@@ -71,6 +71,7 @@ class LaunchInfo(ctypes.Structure):
         ("by", ctypes.c_int32),
         ("rw", ctypes.c_int32),
         ("lp", ctypes.c_int32),
+        ("nt", ctypes.c_int32),
     ]
 
 

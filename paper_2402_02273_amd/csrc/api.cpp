@@ -463,6 +463,7 @@ int expint_get_launch(const expint_ctx* c, expint_launch_info* info) {
   info->by = c->tiling.vec ? 0 : c->tiling.by;
   info->rw = c->tiling.vec ? c->tiling.rw : 0;
   info->lp = c->tiling.lp;
+  info->nt = c->tiling.vec && c->scheme != EXPINT_SCHEME_LINEARISED ? c->tiling.nt : 0;
   return EXPINT_OK;
 }
 

@@ -21,7 +21,7 @@ std::map<Key, PairTiling> g_pair_cache;
 // choices, read when first named and appended to after every new search, so
 // that later processes (a profiled rerun, a deployment) launch exactly the
 // same shapes without timing anything.  Lines:
-//   sweep nx ny nz dtype bc flags  bx by lp vec rw
+//   sweep nx ny nz dtype bc flags  bx by lp vec rw nt
 //   pair  nx ny nz dtype bc forced ty lp
 std::string g_loaded_file;  // the tuning file last read into the caches
 
@@ -39,17 +39,18 @@ void load_tune_file() {
   FILE* f = std::fopen(path, "r");
   if (!f) return;
   char kind[16];
-  int a[6], v[5];
+  int a[6], v[6];
   while (std::fscanf(f, "%15s", kind) == 1) {
     if (std::string(kind) == "sweep" &&
-        std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d", &a[0], &a[1], &a[2], &a[3], &a[4], &a[5], &v[0], &v[1],
-                    &v[2], &v[3], &v[4]) == 11) {
+        std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d %d", &a[0], &a[1], &a[2], &a[3], &a[4], &a[5], &v[0], &v[1],
+                    &v[2], &v[3], &v[4], &v[5]) == 12) {
       Tiling t;
       t.bx = v[0];
       t.by = v[1];
       t.lp = v[2];
       t.vec = v[3];
       t.rw = v[4];
+      t.nt = v[5];
       if (tiling_valid(t)) g_cache[Key{a[0], a[1], a[2], a[3], a[4], a[5]}] = t;
     } else if (std::string(kind) == "pair" &&
                std::fscanf(f, "%d %d %d %d %d %d %d %d", &a[0], &a[1], &a[2], &a[3], &a[4], &a[5], &v[0], &v[1]) ==
@@ -275,11 +276,37 @@ hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Co
       best_t = t;
     }
   }
+  // Store policy of the chosen vector shape: non-temporal output stores
+  // finish a sweep sooner where its fields are re-read from the Infinity
+  // Cache or HBM by the next sweep anyway; kept only when clearly faster over
+  // a skip and a flush sweep (the two term flavours of the schedule).
+  if (best_t.vec) {
+    TermOp skip;
+    skip.src = f0;
+    skip.y_out = f2;
+    skip.c = 0.5;
+    classify_term(skip);
+    float t_pol[2] = {0.f, 0.f};
+    for (int nt = 0; nt < 2; ++nt) {
+      Tiling t = best_t;
+      t.nt = nt;
+      float a = 0.f, b = 0.f;
+      if ((e = time_launches([&] { return launch_term(dt, bc, g, t, cf, op, st); }, reps, st, &a)) != hipSuccess)
+        return e;
+      if ((e = time_launches([&] { return launch_term(dt, bc, g, t, cf, skip, st); }, reps, st, &b)) != hipSuccess)
+        return e;
+      t_pol[nt] = a + b;
+    }
+    best_t.nt = t_pol[1] < 0.97f * t_pol[0] ? 1 : 0;
+    if (std::getenv("EXPINT_LOG"))
+      std::fprintf(stderr, "[expint] autotune store policy: flush+skip %.2f us plain, %.2f us non-temporal -> %s\n",
+                   t_pol[0] * 1000.f, t_pol[1] * 1000.f, best_t.nt ? "non-temporal" : "plain");
+  }
   *out = best_t;
   if (std::getenv("EXPINT_LOG")) {
     if (best_t.vec)
-      std::fprintf(stderr, "[expint] autotune %dx%dx%d %s: vector sweep rw=%d lp=%d (%.2f us/sweep)\n", g.nx, g.ny,
-                   g.nz, dt == EXPINT_F64 ? "f64" : "f32", best_t.rw, best_t.lp, best * 1000.f);
+      std::fprintf(stderr, "[expint] autotune %dx%dx%d %s: vector sweep rw=%d lp=%d nt=%d (%.2f us/sweep)\n", g.nx,
+                   g.ny, g.nz, dt == EXPINT_F64 ? "f64" : "f32", best_t.rw, best_t.lp, best_t.nt, best * 1000.f);
     else
       std::fprintf(stderr, "[expint] autotune %dx%dx%d %s: bx=%d by=%d lp=%d (%.2f us/sweep)\n", g.nx, g.ny, g.nz,
                    dt == EXPINT_F64 ? "f64" : "f32", best_t.bx, best_t.by, best_t.lp, best * 1000.f);
@@ -287,8 +314,8 @@ hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Co
   std::lock_guard<std::mutex> lk(g_mu);
   g_cache[key] = best_t;
   char line[160];
-  std::snprintf(line, sizeof(line), "sweep %s %d %d %d %d %d\n", key_text(key).c_str(), best_t.bx, best_t.by, best_t.lp,
-                best_t.vec, best_t.rw);
+  std::snprintf(line, sizeof(line), "sweep %s %d %d %d %d %d %d\n", key_text(key).c_str(), best_t.bx, best_t.by,
+                best_t.lp, best_t.vec, best_t.rw, best_t.nt);
   append_tune_file(line);
   return hipSuccess;
 }

@@ -41,6 +41,7 @@ int64_t field_block_count(const Geom& g);
 struct Tiling {
   int bx = 64, by = 4, lp = 4;
   int vec = 0, rw = 64;
+  int nt = 0;  // z-vectorised Taylor-term sweeps of A: non-temporal output stores
 };
 // Whether the z-vectorised sweep handles this grid and coefficient form.
 bool vec_sweep_ok(const Geom& g, bool labels_form);

@@ -28,8 +28,8 @@ Shape choose_shape(const Geom& g) {
 
 bool tiling_valid(const Tiling& t) {
   const bool lp_ok = t.lp == 1 || t.lp == 2 || t.lp == 4;
-  if (t.vec) return (t.rw == 16 || t.rw == 32 || t.rw == 64) && lp_ok;
-  return (t.bx == 64 || t.bx == 32 || t.bx == 16) && t.by * t.bx == kBlock && lp_ok;
+  if (t.vec) return (t.rw == 16 || t.rw == 32 || t.rw == 64) && lp_ok && (t.nt == 0 || t.nt == 1);
+  return (t.bx == 64 || t.bx == 32 || t.bx == 16) && t.by * t.bx == kBlock && lp_ok && t.nt == 0;
 }
 
 bool vec_sweep_ok(const Geom& g, bool labels_form) { return labels_form && g.nz % 4 == 0; }

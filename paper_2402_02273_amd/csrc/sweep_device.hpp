@@ -198,21 +198,33 @@ __device__ __forceinline__ Vec4<T> ld4(const void* p, int q4) {
   return static_cast<const Vec4<T>*>(p)[q4];
 }
 template <typename T>
+struct NtVec {
+  typedef T type __attribute__((ext_vector_type(4)));
+};
+// NT: a non-temporal store, which streams the vector out during the sweep
+// instead of leaving it dirty in L2 (Tiling::nt).
+template <typename T, bool NT = false>
 __device__ __forceinline__ void st4(void* p, int q4, const Vec4<T>& v) {
-  static_cast<Vec4<T>*>(p)[q4] = v;
+  if (NT) {
+    const typename NtVec<T>::type w = {v.v[0], v.v[1], v.v[2], v.v[3]};
+    __builtin_nontemporal_store(w, static_cast<typename NtVec<T>::type*>(p) + q4);
+  } else {
+    static_cast<Vec4<T>*>(p)[q4] = v;
+  }
 }
 
 __device__ __forceinline__ int label_byte(uint32_t w, int e) { return static_cast<int>((w >> (8 * e)) & 255u); }
 
-// Outputs of one Taylor-term sweep on the four voxels of vector q4 (see TermOp).
-template <typename T, int FL>
+// Outputs of one Taylor-term sweep on the four voxels of vector q4 (see
+// TermOp); NT: by non-temporal stores.
+template <typename T, int FL, bool NT = false>
 __device__ __forceinline__ void term_store4(const TermOp& op, int q4, const T (&ax)[4], const Vec4<T>& xc) {
   const T c = static_cast<T>(op.c), cs = static_cast<T>(op.cs);
   Vec4<T> y;
   if (FL == kSkip) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) y.v[e] = c * ax[e];
-    st4<T>(op.y_out, q4, y);
+    st4<T, NT>(op.y_out, q4, y);
   } else if (FL == kFlushY || FL == kFlushNoY) {
     const Vec4<T> ai = ld4<T>(op.acc_in, q4);
     Vec4<T> v;
@@ -221,8 +233,8 @@ __device__ __forceinline__ void term_store4(const TermOp& op, int q4, const T (&
       y.v[e] = c * ax[e];
       v.v[e] = ai.v[e] + cs * xc.v[e] + y.v[e];
     }
-    st4<T>(op.acc_out, q4, v);
-    if (FL == kFlushY) st4<T>(op.y_out, q4, y);
+    st4<T, NT>(op.acc_out, q4, v);
+    if (FL == kFlushY) st4<T, NT>(op.y_out, q4, y);
   } else if (FL == kFirst) {
     const Vec4<T> b = ld4<T>(op.bsrc, q4);
     const T cb = static_cast<T>(op.cb);
@@ -232,8 +244,8 @@ __device__ __forceinline__ void term_store4(const TermOp& op, int q4, const T (&
       y.v[e] = c * ax[e] + cb * b.v[e];
       v.v[e] = cs * xc.v[e] + y.v[e];
     }
-    st4<T>(op.acc_out, q4, v);
-    st4<T>(op.y_out, q4, y);
+    st4<T, NT>(op.acc_out, q4, v);
+    st4<T, NT>(op.y_out, q4, y);
   } else {
     Vec4<T> v;
 #pragma unroll
@@ -262,10 +274,10 @@ __device__ __forceinline__ void term_store4(const TermOp& op, int q4, const T (&
       Vec4<T> uu = ld4<T>(op.u, q4);
 #pragma unroll
       for (int e = 0; e < 4; ++e) uu.v[e] = uu.v[e] + v.v[e];
-      st4<T>(op.u, q4, uu);
+      st4<T, NT>(op.u, q4, uu);
     } else {
-      if (op.y_out) st4<T>(op.y_out, q4, y);
-      if (op.acc_out) st4<T>(op.acc_out, q4, v);
+      if (op.y_out) st4<T, NT>(op.y_out, q4, y);
+      if (op.acc_out) st4<T, NT>(op.acc_out, q4, v);
     }
   }
 }
@@ -282,7 +294,7 @@ struct TablesReady {
 // same row and inside the grid (else the wall or segment-edge value).
 // ready() runs after the first plane's loads are issued and before the class
 // table is read: a caller that stages the table there overlaps the two.
-template <typename T, int BC, int LP, int KIND, int FL, typename Ready = TablesReady>
+template <typename T, int BC, int LP, int KIND, int FL, bool NT = false, typename Ready = TablesReady>
 __device__ __forceinline__ void sweep_column4(const Geom& g, const uint8_t* lab, const LdsCoef<T>& s,
                                               const SweepArgs& a, int i0, int j, int k4, int kq, int rw,
                                               Ready&& ready = Ready{}) {
@@ -362,7 +374,7 @@ __device__ __forceinline__ void sweep_column4(const Geom& g, const uint8_t* lab,
       }
     }
     if (is_term(KIND)) {
-      term_store4<T, FL>(a.op, q, ax, xc);
+      term_store4<T, FL, NT>(a.op, q, ax, xc);
     } else if (KIND == kRhs) {
       Vec4<T> o;
       const T rho = static_cast<T>(a.rho);

@@ -29,8 +29,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep(Geom g, int gx, int gy, Coef c
 }
 
 // The z-vectorised sweep (sweep_column4): workgroup = 256 / rw rows of one
-// z-segment of rw lanes, lp planes.
-template <typename T, int BC, int LP, int KIND, int FL>
+// z-segment of rw lanes, lp planes; NT: Taylor-term outputs by non-temporal
+// stores.
+template <typename T, int BC, int LP, int KIND, int FL, bool NT>
 __global__ __launch_bounds__(kBlock) void k_sweep4(Geom g, int gzs, int gy, int rw, Coef cf, SweepArgs a) {
   __shared__ LdsCoef<T> s;
   const int L = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep4(Geom g, int gzs, int gy, int 
     ready();
     return;
   }
-  sweep_column4<T, BC, LP, KIND, FL>(g, cf.labels, s, a, i0, j, k4, kq, rw, ready);
+  sweep_column4<T, BC, LP, KIND, FL, NT>(g, cf.labels, s, a, i0, j, k4, kq, rw, ready);
 }
 
 template <typename T, int BC, int KIND, int FL>
@@ -60,10 +61,22 @@ static void sweep_lp(const Geom& g, const Tiling& tl, const Coef& cf, const Swee
     const int rows = kBlock / tl.rw;
     const int gzs = ((g.nz >> 2) + tl.rw - 1) / tl.rw, gy = (g.ny + rows - 1) / rows;
     const dim3 grid(static_cast<unsigned>(sweep_blocks(g, tl))), block(kBlock);
+    // the store policy applies to the Taylor terms of A; those of the
+    // linearised operator were measured slower with non-temporal stores
+    if constexpr (KIND == kTerm) {
+      if (tl.nt) {
+        switch (tl.lp) {
+          case 1: k_sweep4<T, BC, 1, KIND, FL, true><<<grid, block, 0, st>>>(g, gzs, gy, tl.rw, cf, a); break;
+          case 2: k_sweep4<T, BC, 2, KIND, FL, true><<<grid, block, 0, st>>>(g, gzs, gy, tl.rw, cf, a); break;
+          default: k_sweep4<T, BC, 4, KIND, FL, true><<<grid, block, 0, st>>>(g, gzs, gy, tl.rw, cf, a); break;
+        }
+        return;
+      }
+    }
     switch (tl.lp) {
-      case 1: k_sweep4<T, BC, 1, KIND, FL><<<grid, block, 0, st>>>(g, gzs, gy, tl.rw, cf, a); break;
-      case 2: k_sweep4<T, BC, 2, KIND, FL><<<grid, block, 0, st>>>(g, gzs, gy, tl.rw, cf, a); break;
-      default: k_sweep4<T, BC, 4, KIND, FL><<<grid, block, 0, st>>>(g, gzs, gy, tl.rw, cf, a); break;
+      case 1: k_sweep4<T, BC, 1, KIND, FL, false><<<grid, block, 0, st>>>(g, gzs, gy, tl.rw, cf, a); break;
+      case 2: k_sweep4<T, BC, 2, KIND, FL, false><<<grid, block, 0, st>>>(g, gzs, gy, tl.rw, cf, a); break;
+      default: k_sweep4<T, BC, 4, KIND, FL, false><<<grid, block, 0, st>>>(g, gzs, gy, tl.rw, cf, a); break;
     }
     return;
   }

@@ -13,8 +13,10 @@ import pytest
 import torch
 
 from oracle import adjoint as oadj
+from oracle import exprk2 as oek
 from oracle import integrator as oit
 from oracle import operator as oop
+from oracle import rosenbrock as orb
 from workloads.configs import make_ragged, random_field, random_labels
 
 pytestmark = pytest.mark.gpu
@@ -152,8 +154,9 @@ def test_tune_file_pins_launch_shapes(native, monkeypatch, tmp_path):
     from paper_2402_02273_amd.expint import ExpInt
 
     path = tmp_path / "tune.txt"
-    # key: nx ny nz dtype(F32 = 1) bc(no-flux = 0) flags(label form 1 | vector ok 2 | scalar ok 4)
-    path.write_text("sweep 20 24 36 1 0 7 32 8 2 0 64\npair 20 24 36 1 0 0 0 8\n")
+    # key: nx ny nz dtype(F32 = 1) bc(no-flux = 0) flags(label form 1 | vector ok 2 | scalar ok 4),
+    # then bx by lp vec rw nt
+    path.write_text("sweep 20 24 36 1 0 7 32 8 2 0 64 0\npair 20 24 36 1 0 0 0 8\n")
     monkeypatch.setenv("EXPINT_TUNE_FILE", str(path))
     w = make_ragged((20, 24, 36), seed=2)
     ctx = ExpInt(w.shape, labels=w.labels, class_D=w.class_D, dtype=torch.float32, device=DEV)
@@ -172,3 +175,36 @@ def test_tune_file_pins_launch_shapes(native, monkeypatch, tmp_path):
     ctx.advance(u, 2)
     assert rel_l2(u.cpu().numpy(), ref) < 1e-5
     del ctx2
+
+
+@pytest.mark.parametrize("scheme", ["exp_euler", "linearised", "exprk2"])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_non_temporal_stores_change_nothing(native, monkeypatch, tmp_path, scheme, dtype):
+    # the store policy of the vectorised term sweeps, pinned by tuning files:
+    # plain and non-temporal stores give the same bits, and both the oracle
+    from paper_2402_02273_amd.expint import ExpInt
+
+    w = make_ragged((20, 24, 36), seed=5, nsteps=3)
+    dt = 1 if dtype == torch.float32 else 0
+    outs = []
+    for nt in (0, 1):
+        path = tmp_path / f"tune{nt}.txt"
+        path.write_text(f"sweep 20 24 36 {dt} 0 7 0 0 1 1 16 {nt}\npair 20 24 36 {dt} 0 0 0 8\n")
+        monkeypatch.setenv("EXPINT_TUNE_FILE", str(path))
+        ctx = ExpInt(w.shape, labels=w.labels, class_D=w.class_D, rho=w.rho, tau=w.tau, dtype=dtype, device=DEV,
+                     scheme=scheme)
+        info = ctx.launch_info()
+        # the linearised operator's sweeps keep plain stores whatever the tiling says
+        want_nt = 0 if scheme == "linearised" else nt
+        assert (info["vec"], info["rw"], info["lp"], info["nt"]) == (1, 16, 1, want_nt)
+        u = dev(w.u0, dtype)
+        ctx.advance(u, w.nsteps)
+        outs.append(u.cpu().numpy())
+        p = ctx.plan
+        del ctx
+    print(f"[case] {scheme} {dtype}: plan {p.s}x{p.m}", flush=True)
+    assert np.array_equal(outs[0], outs[1])
+    op = oop.Operator(w.h, labels=w.labels, class_D=w.class_D)
+    mod = {"exp_euler": oit, "linearised": orb, "exprk2": oek}[scheme]
+    ref = mod.advance(op, w.u0, w.rho, w.tau, p.s, p.m, w.nsteps)
+    assert rel_l2(outs[1], ref) < (1e-5 if dtype == torch.float32 else 1e-12)
