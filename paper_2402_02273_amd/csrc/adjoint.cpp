@@ -133,6 +133,23 @@ int term(expint_ctx* c, TermOp op, const void* un) {
   return EXPINT_OK;
 }
 
+// The reverse Taylor sweep op (stencil source op.src) preceded by the face
+// products w <op.src, (dA/dD_c) y>: one fused pass where it applies (plain
+// step, vectorised shape, aligned fields), else the two launches in that
+// order.
+int term_face(expint_ctx* c, TermOp op, const void* un, const void* y, double w) {
+  classify_term(op);
+  if (c->scheme != EXPINT_SCHEME_LINEARISED && op.flavor == kGeneric &&
+      sweep_face_ok(c->dtype, c->g, c->tiling, c->coef(), {op.src, op.bsrc, op.y_out, y})) {
+    HIP_TRY(c, launch_term_face(c->dtype, c->bc, c->g, c->tiling, c->coef(), op, c->nclass, y, c->adj.dtab,
+                                c->adj.dwall, w, c->adj.fpart, c->stream));
+    return EXPINT_OK;
+  }
+  int rc;
+  if ((rc = faceprod(c, op.src, y, w, true))) return rc;
+  return term(c, op, un);
+}
+
 // Reverse sweep of one step; lambda (c->adj.lam) is updated in place.
 int reverse_step(expint_ctx* c, const void* un) {
   auto& a = c->adj;
@@ -174,11 +191,10 @@ int reverse_step(expint_ctx* c, const void* un) {
     void** T = &a.tape[static_cast<size_t>(sig - 1) * m];
     const void* xprev = a.xs[sig - 1];
     const void* ynext = a.xb[xi];  // ybar_m = xbar
-    if (m >= 2) {
-      if ((rc = faceprod(c, ynext, T[m - 2], h / m, true))) return rc;
-    } else {
-      if ((rc = faceprod(c, ynext, xprev, h, true))) return rc;
-    }
+    // the face products of ybar_j pair it with y_{j-1} (x_{sigma-1} for j = 1)
+    // at weight h/j; each is taken with the next sweep, whose source is ybar_j
+    const void* fy = m >= 2 ? T[m - 2] : xprev;
+    double fw = m >= 2 ? h / m : h;
     int yi = 0;
     for (int j = m - 1; j >= 1; --j) {
       TermOp t;  // ybar_j = xbar + (h/(j+1)) A ybar_{j+1}
@@ -187,10 +203,11 @@ int reverse_step(expint_ctx* c, const void* un) {
       t.cb = 1.0;
       t.c = h / (j + 1);
       t.y_out = a.yb[yi];
-      if ((rc = term(c, t, un))) return rc;
+      if ((rc = term_face(c, t, un, fy, fw))) return rc;
       ynext = a.yb[yi];
       yi ^= 1;
-      if ((rc = faceprod(c, ynext, j >= 2 ? T[j - 2] : xprev, j >= 2 ? h / j : h, true))) return rc;
+      fy = j >= 2 ? T[j - 2] : xprev;
+      fw = j >= 2 ? h / j : h;
     }
     // bbar += h ybar_1;  xbar <- xbar + h A ybar_1
     HIP_TRY(c, launch_axpby(c->dtype, n, 1.0, a.gb, h, ynext, a.gb, c->stream));
@@ -200,13 +217,20 @@ int reverse_step(expint_ctx* c, const void* un) {
     t.cb = 1.0;
     t.c = h;
     t.y_out = a.xb[1 - xi];
-    if ((rc = term(c, t, un))) return rc;
+    if ((rc = term_face(c, t, un, fy, fw))) return rc;
     xi ^= 1;
   }
   // g = bbar: rho and D contributions of b_n = A u_n + f(u_n), then lambda_n
   HIP_TRY(c, launch_reduce(c->dtype, 4, a.gb, un, n, c->partial, a.dev + 8, c->stream, true));
-  if ((rc = faceprod(c, a.gb, un, 1.0, false))) return rc;  // b_n = A u_n + f(u_n): no diagonal
-  HIP_TRY(c, launch_adj_rhs(c->dtype, c->bc, c->g, c->tiling, c->coef(), a.gb, un, a.lam, a.lam, c->rho, c->stream));
+  // the D terms of b_n = A u_n + f(u_n) (no diagonal), then lambda_n
+  if (sweep_face_ok(c->dtype, c->g, c->tiling, c->coef(), {a.gb, un, a.lam})) {
+    HIP_TRY(c, launch_adj_rhs_face(c->dtype, c->bc, c->g, c->tiling, c->coef(), a.gb, un, a.lam, a.lam, c->rho,
+                                   c->nclass, a.dtab, a.dwall, 1.0, a.fpart, c->stream));
+  } else {
+    if ((rc = faceprod(c, a.gb, un, 1.0, false))) return rc;
+    HIP_TRY(c, launch_adj_rhs(c->dtype, c->bc, c->g, c->tiling, c->coef(), a.gb, un, a.lam, a.lam, c->rho,
+                              c->stream));
+  }
   if (lin) {  // the diagonal rho (1 - 2 u_n): d/drho and d/du_n
     HIP_TRY(c, launch_reduce(c->dtype, 6, a.dbar, un, n, c->partial, a.dev + 8, c->stream, true));
     HIP_TRY(c, launch_axpy(c->dtype, n, -2.0 * c->rho, a.dbar, a.lam, c->stream));

@@ -17,6 +17,8 @@
 // launches are stream-ordered, so results are bit-reproducible.
 
 #include <algorithm>
+#include <cstdint>
+#include <initializer_list>
 
 #include "internal.hpp"
 #include "sweep_device.hpp"
@@ -219,6 +221,136 @@ __global__ __launch_bounds__(kBlock) void k_faceprod_final(const double* __restr
   if (t < kMaxClasses) acc[t] += red[0][t];
 }
 
+// The face products of one lane, taken inside a sweep whose stencil source
+// is ybar (sweep_column4's per-plane hook): the sweep hands over ybar on the
+// lane's four voxels and their +x, +y, +z neighbours with the labels, and
+// this adds the same FP64 face terms as k_faceprod4 against y (loaded here).
+template <typename T, int BC, int NC>
+struct FaceAcc {
+  const Geom& g;
+  const FaceTables& ft;
+  const T* __restrict__ y;
+  int j, k4, kq, rw;
+  double acc[kMaxClasses];
+
+  __device__ __forceinline__ FaceAcc(const Geom& g_, const FaceTables& ft_, const T* y_, int j_, int k4_, int kq_,
+                                     int rw_)
+      : g(g_), ft(ft_), y(y_), j(j_), k4(k4_), kq(kq_), rw(rw_) {
+#pragma unroll
+    for (int c = 0; c < kMaxClasses; ++c) acc[c] = 0.0;
+  }
+
+  __device__ __forceinline__ void operator()(int i, int q, const Vec4<T>& bc, const Vec4<T>& bn, const Vec4<T>& by,
+                                             T bz, uint32_t lc, uint32_t ln, uint32_t ly, int lz) {
+    const int nz4 = g.nz >> 2, sx4 = g.ny * nz4;
+    const int qn = i < g.nx - 1 ? q + sx4 : q;
+    const int dyp = j < g.ny - 1 ? nz4 : 0;
+    const bool wall_hi = k4 == nz4 - 1, edge_hi = !wall_hi && kq == rw - 1;
+    const Vec4<T> vc = ld4<T>(y, q), vn = ld4<T>(y, qn), vy = ld4<T>(y, q + dyp);
+    T vz = __shfl_down(vc.v[0], 1, rw);
+    if (wall_hi) vz = vc.v[3];
+    else if (edge_hi) vz = y[4 * q + 4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int le = label_byte(lc, e);
+      const double bp = static_cast<double>(bc.v[e]), vp = static_cast<double>(vc.v[e]);
+      add_face<NC>(acc, ft, le, label_byte(ln, e),
+                   (bp - static_cast<double>(bn.v[e])) * (vp - static_cast<double>(vn.v[e])));
+      add_face<NC>(acc, ft, le, label_byte(ly, e),
+                   (bp - static_cast<double>(by.v[e])) * (vp - static_cast<double>(vy.v[e])));
+      const double bq = static_cast<double>(e < 3 ? bc.v[e + 1] : bz);
+      const double vq = static_cast<double>(e < 3 ? vc.v[e + 1] : vz);
+      add_face<NC>(acc, ft, le, e < 3 ? label_byte(lc, e + 1) : lz, (bp - bq) * (vp - vq));
+      if (BC) {
+        const int nw = (i == 0) + (i == g.nx - 1) + (j == 0) + (j == g.ny - 1) + (e == 0 && k4 == 0) +
+                       (e == 3 && wall_hi);
+        if (nw) {
+          const double v = bp * vp * nw;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) acc[c] += ft.wall[c * kMaxClasses + le] * v;
+        }
+      }
+    }
+  }
+};
+
+// One z-vectorised sweep of kind KIND (a Taylor term of the reverse pass, or
+// the adjoint right-hand side) with the face products of its stencil source
+// against y in the same pass: one plane per lane, workgroups as in k_sweep4
+// with lp = 1; workgroup b adds weight * (its sums) into slot b.
+template <typename T, int BC, int KIND, int NC>
+__global__ __launch_bounds__(kBlock) void k_sweep_face4(Geom g, int gzs, int gy, int rw, Coef cf, SweepArgs a,
+                                                        const T* __restrict__ y, const double* __restrict__ dtab,
+                                                        const double* __restrict__ dwall, double weight,
+                                                        double* __restrict__ partial) {
+  __shared__ LdsCoef<T> s;
+  __shared__ FaceTables ft;
+  const int L = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+  const int zs = L % gzs;
+  const int t = L / gzs;
+  const int ybk = t % gy;
+  const int i0 = t / gy;
+  const int tid = static_cast<int>(threadIdx.x);
+  const int kq = tid & (rw - 1);
+  const int j = ybk * (kBlock / rw) + tid / rw;
+  const int k4 = zs * rw + kq;
+  // both tables are staged after the first field loads are in flight; every
+  // thread passes this barrier once
+  auto ready = [&]() {
+    load_tables(s, cf, tid, kBlock);
+    load_face_tables(ft, dtab, dwall);
+    __syncthreads();
+  };
+  FaceAcc<T, BC, NC> face(g, ft, y, j, k4, kq, rw);
+  if (j < g.ny && k4 < (g.nz >> 2))
+    sweep_column4<T, BC, 1, KIND, kGeneric, false>(g, cf.labels, s, a, i0, j, k4, kq, rw, ready, face);
+  else
+    ready();
+  block_accumulate(face.acc, weight, partial);
+}
+
+// Launch shape of k_sweep_face4: the sweeps' z-segments, one plane per lane.
+Tiling sweep_face_tiling(const Tiling& tl) {
+  Tiling f = tl;
+  f.lp = 1;
+  f.nt = 0;
+  return f;
+}
+
+template <typename T, int BC, int KIND>
+hipError_t sweep_face_typed(const Geom& g, const Tiling& tl, const Coef& cf, const SweepArgs& a, int nclass,
+                            const void* y, const double* dtab, const double* dwall, double weight, double* partial,
+                            hipStream_t st) {
+  const Tiling ft = sweep_face_tiling(tl);
+  const int rows = kBlock / ft.rw;
+  const int gzs = ((g.nz >> 2) + ft.rw - 1) / ft.rw, gy = (g.ny + rows - 1) / rows;
+  const dim3 grid(static_cast<unsigned>(sweep_blocks(g, ft))), block(kBlock);
+  const T* yy = static_cast<const T*>(y);
+#define EXPINT_SWEEP_FACE(NC_) \
+  k_sweep_face4<T, BC, KIND, NC_><<<grid, block, 0, st>>>(g, gzs, gy, ft.rw, cf, a, yy, dtab, dwall, weight, partial)
+  switch (nclass) {
+    case 1: EXPINT_SWEEP_FACE(1); break;
+    case 2: EXPINT_SWEEP_FACE(2); break;
+    case 3: EXPINT_SWEEP_FACE(3); break;
+    case 4: EXPINT_SWEEP_FACE(4); break;
+    default: EXPINT_SWEEP_FACE(8); break;
+  }
+#undef EXPINT_SWEEP_FACE
+  return hipGetLastError();
+}
+
+template <int KIND>
+hipError_t sweep_face(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,
+                      const SweepArgs& a, int nclass, const void* y, const double* dtab, const double* dwall,
+                      double weight, double* partial, hipStream_t st) {
+  if (dt == EXPINT_F64) {
+    if (bc == EXPINT_NOFLUX) return sweep_face_typed<double, 0, KIND>(g, tl, cf, a, nclass, y, dtab, dwall, weight, partial, st);
+    return sweep_face_typed<double, 1, KIND>(g, tl, cf, a, nclass, y, dtab, dwall, weight, partial, st);
+  }
+  if (bc == EXPINT_NOFLUX) return sweep_face_typed<float, 0, KIND>(g, tl, cf, a, nclass, y, dtab, dwall, weight, partial, st);
+  return sweep_face_typed<float, 1, KIND>(g, tl, cf, a, nclass, y, dtab, dwall, weight, partial, st);
+}
+
 // Tiling of the vectorised face products: the z-segments of the sweeps'
 // tiling, kFaceLP planes per lane.
 Tiling face_tiling(const Tiling& tl) {
@@ -272,8 +404,46 @@ hipError_t faceprod_typed(expint_bc bc, const Geom& g, const Tiling& tl, const u
 
 int64_t faceprod_slots(const Geom& g, const Tiling& tl) {
   int64_t n = kReduceBlocks;
-  if (tl.vec && vec_sweep_ok(g, true)) n = std::max<int64_t>(n, sweep_blocks(g, face_tiling(tl)));
+  if (tl.vec && vec_sweep_ok(g, true)) {
+    n = std::max<int64_t>(n, sweep_blocks(g, face_tiling(tl)));
+    n = std::max<int64_t>(n, sweep_blocks(g, sweep_face_tiling(tl)));
+  }
   return n;
+}
+
+bool sweep_face_ok(expint_dtype dt, const Geom& g, const Tiling& tl, const Coef& cf,
+                   std::initializer_list<const void*> fields) {
+  if (!tl.vec || !cf.labels_form || !vec_sweep_ok(g, true) || !tiling_valid(sweep_face_tiling(tl))) return false;
+  if ((reinterpret_cast<uintptr_t>(cf.labels) & 3) != 0) return false;
+  const uintptr_t m = 4 * dtype_bytes(dt) - 1;
+  for (const void* p : fields)
+    if ((reinterpret_cast<uintptr_t>(p) & m) != 0) return false;
+  return true;
+}
+
+hipError_t launch_term_face(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,
+                            const TermOp& op, int nclass, const void* y, const double* dtab, const double* dwall,
+                            double weight, double* partial, hipStream_t st) {
+  if (op.ju || op.flavor != kGeneric || !sweep_face_ok(dt, g, tl, cf, {op.src, op.bsrc, op.acc_in, op.y_out,
+                                                                        op.acc_out, op.u, op.bsrc2, y}))
+    return hipErrorInvalidValue;
+  SweepArgs a{};
+  a.op = op;
+  return sweep_face<kTerm>(dt, bc, g, tl, cf, a, nclass, y, dtab, dwall, weight, partial, st);
+}
+
+hipError_t launch_adj_rhs_face(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,
+                               const void* gv, const void* u, const void* lam_in, void* lam_out, double rho,
+                               int nclass, const double* dtab, const double* dwall, double weight, double* partial,
+                               hipStream_t st) {
+  if (!sweep_face_ok(dt, g, tl, cf, {gv, u, lam_in, lam_out})) return hipErrorInvalidValue;
+  SweepArgs a{};
+  a.x = gv;
+  a.out = lam_out;
+  a.aux0 = lam_in;
+  a.aux1 = u;
+  a.rho = rho;
+  return sweep_face<kAdjRhs>(dt, bc, g, tl, cf, a, nclass, u, dtab, dwall, weight, partial, st);
 }
 
 hipError_t launch_faceprod(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const uint8_t* labels,

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <initializer_list>
 
 #include "expint.h"
 
@@ -180,6 +181,24 @@ hipError_t launch_faceprod(expint_dtype dt, expint_bc bc, const Geom& g, const T
                            int nclass, const double* dtab, const double* dwall, const void* ybar, const void* y,
                            double weight, double* partial, hipStream_t st);
 hipError_t launch_faceprod_final(const double* partial, int64_t slots, double* acc, hipStream_t st);
+
+// A sweep and the face products of its stencil source in one pass (the
+// z-vectorised shape of tl with one plane per lane; label form; every field
+// 4-value aligned: sweep_face_ok).  launch_term_face: the Taylor-term sweep op
+// (generic flavour, no linearised diagonal) plus weight <op.src, (dA/dD_c) y>;
+// launch_adj_rhs_face: launch_adj_rhs plus weight <gv, (dA/dD_c) u>.  The
+// face products go into the same slots as launch_faceprod (partial holds
+// faceprod_slots(g, tl) * 8 doubles).  hipErrorInvalidValue where the fused
+// form does not apply.
+bool sweep_face_ok(expint_dtype dt, const Geom& g, const Tiling& tl, const Coef& cf,
+                   std::initializer_list<const void*> fields);
+hipError_t launch_term_face(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,
+                            const TermOp& op, int nclass, const void* y, const double* dtab, const double* dwall,
+                            double weight, double* partial, hipStream_t st);
+hipError_t launch_adj_rhs_face(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,
+                               const void* gv, const void* u, const void* lam_in, void* lam_out, double rho,
+                               int nclass, const double* dtab, const double* dwall, double weight, double* partial,
+                               hipStream_t st);
 
 // Pointwise helpers.
 hipError_t launch_axpy(expint_dtype dt, int64_t n, double a, const void* x, void* y, hipStream_t st);  // y += a x

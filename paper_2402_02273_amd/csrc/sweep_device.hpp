@@ -287,6 +287,12 @@ struct TablesReady {
   __device__ __forceinline__ void operator()() const {}
 };
 
+// Per-plane hook of sweep_column4 that does nothing (see there).
+struct NoFace {
+  template <typename... Args>
+  __device__ __forceinline__ void operator()(Args&&...) const {}
+};
+
 // The sweep of one lane: vector k4 (voxels 4 k4 .. 4 k4 + 3) of row j,
 // planes i0 .. i0 + LP - 1 (clipped to the grid); kq is the lane's index in
 // its z-segment of rw lanes.  Lanes outside the grid need not call this: a
@@ -294,10 +300,15 @@ struct TablesReady {
 // same row and inside the grid (else the wall or segment-edge value).
 // ready() runs after the first plane's loads are issued and before the class
 // table is read: a caller that stages the table there overlaps the two.
-template <typename T, int BC, int LP, int KIND, int FL, bool NT = false, typename Ready = TablesReady>
+// face(i, q, xc, xn, xy, xz, lc, ln, ly, lz) runs once per plane with the
+// source values the stencil holds: the lane's four voxels, their +x and +y
+// neighbours, the +z neighbour of the last voxel, and the matching labels
+// (each neighbour is the voxel itself at a wall).
+template <typename T, int BC, int LP, int KIND, int FL, bool NT = false, typename Ready = TablesReady,
+          typename Face = NoFace>
 __device__ __forceinline__ void sweep_column4(const Geom& g, const uint8_t* lab, const LdsCoef<T>& s,
                                               const SweepArgs& a, int i0, int j, int k4, int kq, int rw,
-                                              Ready&& ready = Ready{}) {
+                                              Ready&& ready = Ready{}, Face&& face = Face{}) {
   const int nz4 = g.nz >> 2;
   const int sx4 = g.ny * nz4;
   const int dym = j > 0 ? -nz4 : 0, dyp = j < g.ny - 1 ? nz4 : 0;
@@ -394,6 +405,7 @@ __device__ __forceinline__ void sweep_column4(const Geom& g, const uint8_t* lab,
       for (int e = 0; e < 4; ++e) o.v[e] = ax[e];
       st4<T>(a.out, q, o);
     }
+    face(i, q, xc, xn, yb, zr, lc, ln, lb, lzr);
     xm = xc;
     xc = xn;
     lm = lc;
