@@ -225,31 +225,43 @@ __global__ __launch_bounds__(kBlock) void k_faceprod_final(const double* __restr
 // is ybar (sweep_column4's per-plane hook): the sweep hands over ybar on the
 // lane's four voxels and their +x, +y, +z neighbours with the labels, and
 // this adds the same FP64 face terms as k_faceprod4 against y (loaded here).
+// One plane per lane: load() fetches y on the lane's voxels and their +x,
+// +y, +z neighbours before the sweep starts, so these loads are in flight
+// together with the sweep's own; the hook then uses them for plane i.
 template <typename T, int BC, int NC>
 struct FaceAcc {
   const Geom& g;
   const FaceTables& ft;
-  const T* __restrict__ y;
   int j, k4, kq, rw;
+  bool wall_hi;
+  Vec4<T> vc, vn, vy;
+  T vz_edge;
   double acc[kMaxClasses];
 
-  __device__ __forceinline__ FaceAcc(const Geom& g_, const FaceTables& ft_, const T* y_, int j_, int k4_, int kq_,
-                                     int rw_)
-      : g(g_), ft(ft_), y(y_), j(j_), k4(k4_), kq(kq_), rw(rw_) {
+  __device__ __forceinline__ FaceAcc(const Geom& g_, const FaceTables& ft_, int j_, int k4_, int kq_, int rw_)
+      : g(g_), ft(ft_), j(j_), k4(k4_), kq(kq_), rw(rw_), wall_hi(k4_ == (g_.nz >> 2) - 1) {
 #pragma unroll
     for (int c = 0; c < kMaxClasses; ++c) acc[c] = 0.0;
   }
 
-  __device__ __forceinline__ void operator()(int i, int q, const Vec4<T>& bc, const Vec4<T>& bn, const Vec4<T>& by,
-                                             T bz, uint32_t lc, uint32_t ln, uint32_t ly, int lz) {
+  __device__ __forceinline__ void load(const T* __restrict__ y, int i) {
     const int nz4 = g.nz >> 2, sx4 = g.ny * nz4;
+    const int q = (i * g.ny + j) * nz4 + k4;
     const int qn = i < g.nx - 1 ? q + sx4 : q;
     const int dyp = j < g.ny - 1 ? nz4 : 0;
-    const bool wall_hi = k4 == nz4 - 1, edge_hi = !wall_hi && kq == rw - 1;
-    const Vec4<T> vc = ld4<T>(y, q), vn = ld4<T>(y, qn), vy = ld4<T>(y, q + dyp);
+    vc = ld4<T>(y, q);
+    vn = ld4<T>(y, qn);
+    vy = ld4<T>(y, q + dyp);
+    const bool edge_hi = !wall_hi && kq == rw - 1;
+    vz_edge = edge_hi ? y[4 * q + 4] : T(0);
+  }
+
+  __device__ __forceinline__ void operator()(int i, int q, const Vec4<T>& bc, const Vec4<T>& bn, const Vec4<T>& by,
+                                             T bz, uint32_t lc, uint32_t ln, uint32_t ly, int lz) {
+    const bool edge_hi = !wall_hi && kq == rw - 1;
     T vz = __shfl_down(vc.v[0], 1, rw);
     if (wall_hi) vz = vc.v[3];
-    else if (edge_hi) vz = y[4 * q + 4];
+    else if (edge_hi) vz = vz_edge;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int le = label_byte(lc, e);
@@ -301,11 +313,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep_face4(Geom g, int gzs, int gy,
     load_face_tables(ft, dtab, dwall);
     __syncthreads();
   };
-  FaceAcc<T, BC, NC> face(g, ft, y, j, k4, kq, rw);
-  if (j < g.ny && k4 < (g.nz >> 2))
+  FaceAcc<T, BC, NC> face(g, ft, j, k4, kq, rw);
+  if (j < g.ny && k4 < (g.nz >> 2)) {
+    face.load(y, i0);
     sweep_column4<T, BC, 1, KIND, kGeneric, false>(g, cf.labels, s, a, i0, j, k4, kq, rw, ready, face);
-  else
+  } else {
     ready();
+  }
   block_accumulate(face.acc, weight, partial);
 }
 
