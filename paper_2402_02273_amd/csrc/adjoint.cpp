@@ -134,15 +134,20 @@ int term(expint_ctx* c, TermOp op, const void* un) {
 }
 
 // The reverse Taylor sweep op (stencil source op.src) preceded by the face
-// products w <op.src, (dA/dD_c) y>: one fused pass where it applies (plain
-// step, vectorised shape, aligned fields), else the two launches in that
-// order.
+// products w <op.src, (dA/dD_c) y> (LINEARISED: and dbar += w op.src * y):
+// one fused pass where it applies (vectorised shape, aligned fields), else
+// the separate launches in that order.
 int term_face(expint_ctx* c, TermOp op, const void* un, const void* y, double w) {
   classify_term(op);
-  if (c->scheme != EXPINT_SCHEME_LINEARISED && op.flavor == kGeneric &&
-      sweep_face_ok(c->dtype, c->g, c->tiling, c->coef(), {op.src, op.bsrc, op.y_out, y})) {
+  const bool lin = c->scheme == EXPINT_SCHEME_LINEARISED;
+  if (op.flavor == kGeneric &&
+      sweep_face_ok(c->dtype, c->g, c->tiling, c->coef(), {op.src, op.bsrc, op.y_out, y, un, c->adj.dbar})) {
+    if (lin) {
+      op.ju = un;
+      op.jrho = c->rho;
+    }
     HIP_TRY(c, launch_term_face(c->dtype, c->bc, c->g, c->tiling, c->coef(), op, c->nclass, y, c->adj.dtab,
-                                c->adj.dwall, w, c->adj.fpart, c->stream));
+                                c->adj.dwall, w, c->adj.fpart, lin ? c->adj.dbar : nullptr, c->stream));
     return EXPINT_OK;
   }
   int rc;

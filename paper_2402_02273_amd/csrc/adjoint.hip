@@ -228,18 +228,23 @@ __global__ __launch_bounds__(kBlock) void k_faceprod_final(const double* __restr
 // One plane per lane: load() fetches y on the lane's voxels and their +x,
 // +y, +z neighbours before the sweep starts, so these loads are in flight
 // together with the sweep's own; the hook then uses them for plane i.
-template <typename T, int BC, int NC>
+// DB (a Taylor term of the linearised operator): the hook also adds
+// wd * ybar * y into dbar on the lane's voxels, the diagonal's share.
+template <typename T, int BC, int NC, bool DB>
 struct FaceAcc {
   const Geom& g;
   const FaceTables& ft;
   int j, k4, kq, rw;
   bool wall_hi;
-  Vec4<T> vc, vn, vy;
+  Vec4<T> vc, vn, vy, dv;
   T vz_edge;
+  T* dbar;
+  T wd;
   double acc[kMaxClasses];
 
-  __device__ __forceinline__ FaceAcc(const Geom& g_, const FaceTables& ft_, int j_, int k4_, int kq_, int rw_)
-      : g(g_), ft(ft_), j(j_), k4(k4_), kq(kq_), rw(rw_), wall_hi(k4_ == (g_.nz >> 2) - 1) {
+  __device__ __forceinline__ FaceAcc(const Geom& g_, const FaceTables& ft_, int j_, int k4_, int kq_, int rw_,
+                                     T* dbar_, T wd_)
+      : g(g_), ft(ft_), j(j_), k4(k4_), kq(kq_), rw(rw_), wall_hi(k4_ == (g_.nz >> 2) - 1), dbar(dbar_), wd(wd_) {
 #pragma unroll
     for (int c = 0; c < kMaxClasses; ++c) acc[c] = 0.0;
   }
@@ -254,6 +259,7 @@ struct FaceAcc {
     vy = ld4<T>(y, q + dyp);
     const bool edge_hi = !wall_hi && kq == rw - 1;
     vz_edge = edge_hi ? y[4 * q + 4] : T(0);
+    if (DB) dv = ld4<T>(dbar, q);
   }
 
   __device__ __forceinline__ void operator()(int i, int q, const Vec4<T>& bc, const Vec4<T>& bn, const Vec4<T>& by,
@@ -283,18 +289,25 @@ struct FaceAcc {
         }
       }
     }
+    if (DB) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) dv.v[e] += wd * bc.v[e] * vc.v[e];
+      st4<T>(dbar, q, dv);
+    }
   }
 };
 
-// One z-vectorised sweep of kind KIND (a Taylor term of the reverse pass, or
-// the adjoint right-hand side) with the face products of its stencil source
-// against y in the same pass: one plane per lane, workgroups as in k_sweep4
-// with lp = 1; workgroup b adds weight * (its sums) into slot b.
+// One z-vectorised sweep of kind KIND (a Taylor term of the reverse pass, of
+// A or of the linearised operator, or the adjoint right-hand side) with the
+// face products of its stencil source against y in the same pass: one plane
+// per lane, workgroups as in k_sweep4 with lp = 1; workgroup b adds
+// weight * (its sums) into slot b.  kTermJ also adds weight * ybar * y into
+// dbar.
 template <typename T, int BC, int KIND, int NC>
 __global__ __launch_bounds__(kBlock) void k_sweep_face4(Geom g, int gzs, int gy, int rw, Coef cf, SweepArgs a,
                                                         const T* __restrict__ y, const double* __restrict__ dtab,
                                                         const double* __restrict__ dwall, double weight,
-                                                        double* __restrict__ partial) {
+                                                        double* __restrict__ partial, T* __restrict__ dbar) {
   __shared__ LdsCoef<T> s;
   __shared__ FaceTables ft;
   const int L = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
@@ -313,7 +326,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_face4(Geom g, int gzs, int gy,
     load_face_tables(ft, dtab, dwall);
     __syncthreads();
   };
-  FaceAcc<T, BC, NC> face(g, ft, j, k4, kq, rw);
+  FaceAcc<T, BC, NC, KIND == kTermJ> face(g, ft, j, k4, kq, rw, dbar, static_cast<T>(weight));
   if (j < g.ny && k4 < (g.nz >> 2)) {
     face.load(y, i0);
     sweep_column4<T, BC, 1, KIND, kGeneric, false>(g, cf.labels, s, a, i0, j, k4, kq, rw, ready, face);
@@ -334,14 +347,16 @@ Tiling sweep_face_tiling(const Tiling& tl) {
 template <typename T, int BC, int KIND>
 hipError_t sweep_face_typed(const Geom& g, const Tiling& tl, const Coef& cf, const SweepArgs& a, int nclass,
                             const void* y, const double* dtab, const double* dwall, double weight, double* partial,
-                            hipStream_t st) {
+                            void* dbar, hipStream_t st) {
   const Tiling ft = sweep_face_tiling(tl);
   const int rows = kBlock / ft.rw;
   const int gzs = ((g.nz >> 2) + ft.rw - 1) / ft.rw, gy = (g.ny + rows - 1) / rows;
   const dim3 grid(static_cast<unsigned>(sweep_blocks(g, ft))), block(kBlock);
   const T* yy = static_cast<const T*>(y);
-#define EXPINT_SWEEP_FACE(NC_) \
-  k_sweep_face4<T, BC, KIND, NC_><<<grid, block, 0, st>>>(g, gzs, gy, ft.rw, cf, a, yy, dtab, dwall, weight, partial)
+  T* db = static_cast<T*>(dbar);
+#define EXPINT_SWEEP_FACE(NC_)                                                                                     \
+  k_sweep_face4<T, BC, KIND, NC_><<<grid, block, 0, st>>>(g, gzs, gy, ft.rw, cf, a, yy, dtab, dwall, weight, partial, \
+                                                         db)
   switch (nclass) {
     case 1: EXPINT_SWEEP_FACE(1); break;
     case 2: EXPINT_SWEEP_FACE(2); break;
@@ -356,13 +371,15 @@ hipError_t sweep_face_typed(const Geom& g, const Tiling& tl, const Coef& cf, con
 template <int KIND>
 hipError_t sweep_face(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,
                       const SweepArgs& a, int nclass, const void* y, const double* dtab, const double* dwall,
-                      double weight, double* partial, hipStream_t st) {
+                      double weight, double* partial, void* dbar, hipStream_t st) {
   if (dt == EXPINT_F64) {
-    if (bc == EXPINT_NOFLUX) return sweep_face_typed<double, 0, KIND>(g, tl, cf, a, nclass, y, dtab, dwall, weight, partial, st);
-    return sweep_face_typed<double, 1, KIND>(g, tl, cf, a, nclass, y, dtab, dwall, weight, partial, st);
+    if (bc == EXPINT_NOFLUX)
+      return sweep_face_typed<double, 0, KIND>(g, tl, cf, a, nclass, y, dtab, dwall, weight, partial, dbar, st);
+    return sweep_face_typed<double, 1, KIND>(g, tl, cf, a, nclass, y, dtab, dwall, weight, partial, dbar, st);
   }
-  if (bc == EXPINT_NOFLUX) return sweep_face_typed<float, 0, KIND>(g, tl, cf, a, nclass, y, dtab, dwall, weight, partial, st);
-  return sweep_face_typed<float, 1, KIND>(g, tl, cf, a, nclass, y, dtab, dwall, weight, partial, st);
+  if (bc == EXPINT_NOFLUX)
+    return sweep_face_typed<float, 0, KIND>(g, tl, cf, a, nclass, y, dtab, dwall, weight, partial, dbar, st);
+  return sweep_face_typed<float, 1, KIND>(g, tl, cf, a, nclass, y, dtab, dwall, weight, partial, dbar, st);
 }
 
 // Tiling of the vectorised face products: the z-segments of the sweeps'
@@ -437,13 +454,14 @@ bool sweep_face_ok(expint_dtype dt, const Geom& g, const Tiling& tl, const Coef&
 
 hipError_t launch_term_face(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,
                             const TermOp& op, int nclass, const void* y, const double* dtab, const double* dwall,
-                            double weight, double* partial, hipStream_t st) {
-  if (op.ju || op.flavor != kGeneric || !sweep_face_ok(dt, g, tl, cf, {op.src, op.bsrc, op.acc_in, op.y_out,
-                                                                        op.acc_out, op.u, op.bsrc2, y}))
+                            double weight, double* partial, void* dbar, hipStream_t st) {
+  if (op.flavor != kGeneric || (op.ju != nullptr) != (dbar != nullptr) ||
+      !sweep_face_ok(dt, g, tl, cf, {op.src, op.bsrc, op.acc_in, op.y_out, op.acc_out, op.u, op.bsrc2, op.ju, y, dbar}))
     return hipErrorInvalidValue;
   SweepArgs a{};
   a.op = op;
-  return sweep_face<kTerm>(dt, bc, g, tl, cf, a, nclass, y, dtab, dwall, weight, partial, st);
+  if (op.ju) return sweep_face<kTermJ>(dt, bc, g, tl, cf, a, nclass, y, dtab, dwall, weight, partial, dbar, st);
+  return sweep_face<kTerm>(dt, bc, g, tl, cf, a, nclass, y, dtab, dwall, weight, partial, nullptr, st);
 }
 
 hipError_t launch_adj_rhs_face(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,
@@ -457,7 +475,7 @@ hipError_t launch_adj_rhs_face(expint_dtype dt, expint_bc bc, const Geom& g, con
   a.aux0 = lam_in;
   a.aux1 = u;
   a.rho = rho;
-  return sweep_face<kAdjRhs>(dt, bc, g, tl, cf, a, nclass, u, dtab, dwall, weight, partial, st);
+  return sweep_face<kAdjRhs>(dt, bc, g, tl, cf, a, nclass, u, dtab, dwall, weight, partial, nullptr, st);
 }
 
 hipError_t launch_faceprod(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const uint8_t* labels,

@@ -185,16 +185,17 @@ hipError_t launch_faceprod_final(const double* partial, int64_t slots, double* a
 // A sweep and the face products of its stencil source in one pass (the
 // z-vectorised shape of tl with one plane per lane; label form; every field
 // 4-value aligned: sweep_face_ok).  launch_term_face: the Taylor-term sweep op
-// (generic flavour, no linearised diagonal) plus weight <op.src, (dA/dD_c) y>;
-// launch_adj_rhs_face: launch_adj_rhs plus weight <gv, (dA/dD_c) u>.  The
-// face products go into the same slots as launch_faceprod (partial holds
-// faceprod_slots(g, tl) * 8 doubles).  hipErrorInvalidValue where the fused
-// form does not apply.
+// (generic flavour) plus weight <op.src, (dA/dD_c) y>; for a term of the
+// linearised operator (op.ju set, dbar given) also dbar += weight op.src * y,
+// as launch_diag_accumulate; launch_adj_rhs_face: launch_adj_rhs plus
+// weight <gv, (dA/dD_c) u>.  The face products go into the same slots as
+// launch_faceprod (partial holds faceprod_slots(g, tl) * 8 doubles).
+// hipErrorInvalidValue where the fused form does not apply.
 bool sweep_face_ok(expint_dtype dt, const Geom& g, const Tiling& tl, const Coef& cf,
                    std::initializer_list<const void*> fields);
 hipError_t launch_term_face(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,
                             const TermOp& op, int nclass, const void* y, const double* dtab, const double* dwall,
-                            double weight, double* partial, hipStream_t st);
+                            double weight, double* partial, void* dbar, hipStream_t st);
 hipError_t launch_adj_rhs_face(expint_dtype dt, expint_bc bc, const Geom& g, const Tiling& tl, const Coef& cf,
                                const void* gv, const void* u, const void* lam_in, void* lam_out, double rho,
                                int nclass, const double* dtab, const double* dwall, double weight, double* partial,

@@ -210,24 +210,27 @@ def test_non_temporal_stores_change_nothing(native, monkeypatch, tmp_path, schem
     assert rel_l2(outs[1], ref) < (1e-5 if dtype == torch.float32 else 1e-12)
 
 
+@pytest.mark.parametrize("scheme", ["exp_euler", "linearised"])
 @pytest.mark.parametrize("bc", ["noflux", "dirichlet0"])
 @pytest.mark.parametrize("sm", [(1, 1), (2, 1), (1, 2), (2, 4)])
 @pytest.mark.parametrize("class_D", [(0.1,), (0.0, 0.13, 0.013), (0.02, 0.13, 0.013, 0.2, 0.05)])
-def test_adjoint_vec_fused_face_products(native, vec_env, bc, sm, class_D):
-    # the reverse sweeps that take the face products of their source in the
-    # same pass: every plan shape of the pairing (m = 1: only the last sweep
-    # of a sub-step; m = 2: one inner sweep), both walls, several class counts
+def test_adjoint_vec_fused_face_products(native, vec_env, scheme, bc, sm, class_D):
+    # the reverse sweeps that take the face products of their source (and,
+    # for the linearised operator, the diagonal's share) in the same pass:
+    # every plan shape of the pairing (m = 1: only the last sweep of a
+    # sub-step; m = 2: one inner sweep), both walls, several class counts
     shape = (6, 10, 20)
     labels = random_labels(shape, len(class_D), seed=len(class_D) + 7 * sm[1])
     u0 = random_field(shape, seed=31) * (labels != 0) if len(class_D) > 1 else random_field(shape, seed=31)
     gout = random_field(shape, seed=32, lo=-1, hi=1)
     rho, tau, K = 0.02, 3.0, 2
     op = oop.Operator(1.0, bc=bc, labels=labels, class_D=class_D)
-    gu, grho, gD = oadj.vjp(op, u0, rho, tau, sm[0], sm[1], K, gout, 1, classes=list(range(len(class_D))))
+    gu, grho, gD = oadj.vjp(op, u0, rho, tau, sm[0], sm[1], K, gout, 1, classes=list(range(len(class_D))),
+                            scheme=scheme)
     ref_D = [gD[c] for c in range(len(class_D))]
     scale = max(abs(v) for v in ref_D)
     for dtype, tol in [(torch.float64, 1e-10), (torch.float32, 2e-5)]:
-        ctx = make_ctx(labels, class_D, dtype, rho=rho, tau=tau, bc=bc, s=sm[0], m=sm[1])
+        ctx = make_ctx(labels, class_D, dtype, rho=rho, tau=tau, bc=bc, s=sm[0], m=sm[1], scheme=scheme)
         gu_g, grho_g, gD_g = ctx.vjp(dev(u0, dtype), K, dev(gout, dtype), ckpt_every=1)
         assert rel_l2(gu_g.cpu().numpy(), gu) < tol
         assert grho_g == pytest.approx(grho, rel=tol)
