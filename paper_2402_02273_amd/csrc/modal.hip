@@ -561,6 +561,12 @@ struct EV {
 
 // v if ok, else zeros; per component (a select of whole uint4 aggregates is
 // lowered to a select of their addresses, which forces them into scratch).
+typedef int i32x4_buf __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 as_uint4(i32x4_buf v) {
+  return make_uint4(static_cast<unsigned>(v.x), static_cast<unsigned>(v.y), static_cast<unsigned>(v.z),
+                    static_cast<unsigned>(v.w));
+}
+
 __device__ __forceinline__ uint4 keep_if(bool ok, const uint4& v) {
   return make_uint4(ok ? v.x : 0u, ok ? v.y : 0u, ok ? v.z : 0u, ok ? v.w : 0u);
 }
@@ -591,7 +597,6 @@ __global__ __launch_bounds__(64 * TMW * TNW) void k_mode_gemm(ModalArgs a) {
   float* __restrict__ out = static_cast<float*>(a.out);
   const E* __restrict__ qhi = static_cast<const E*>(a.q);
   const int n = a.n;
-  const E* __restrict__ qlo = qhi + static_cast<long>(n) * n;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / TNW) * 64, wn = (wave % TNW) * 64;  // the wave's block
 
@@ -626,10 +631,27 @@ __global__ __launch_bounds__(64 * TMW * TNW) void k_mode_gemm(ModalArgs a) {
   const int fk_ = SIDE == 0 ? (tid / GN) * EF : (tid % (GK / EF)) * EF;
   const long orow = (SIDE == 0 ? m0 : c0) + orow_l;
   const bool op_ok = orow < (SIDE == 0 ? mrows : ncols);
-  const long orow_c = op_ok ? orow : 0;
   const long fidx = (SIDE == 0 ? c0 : m0) + frow_l;  // field column (left) / row (right)
   const bool fld_ok = fidx < (SIDE == 0 ? ncols : mrows);
-  const long fidx_c = fld_ok ? fidx : 0;
+
+  // Loads go through buffer resources: a uniform base (the operator; this
+  // product's field slab) with a loop-invariant 32-bit byte offset per lane
+  // and the chunk's k offset in a scalar register, so a load costs no vector
+  // address arithmetic.  The host keeps every offset below 2^31 bytes.  A lane
+  // whose row or column lies outside the problem points past the resource's
+  // size, and its loads return 0: the LDS tile is zero-padded without selects.
+  constexpr uint32_t kPast = 0x80000000u;
+  constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit buffer, gfx9 family
+  const uint32_t fslab = static_cast<uint32_t>(SIDE == 0 ? static_cast<long>(n) * a.post : static_cast<long>(a.pre) * n);
+  const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<E*>(qhi), 0, static_cast<int>(2u * static_cast<uint32_t>(n) * n * sizeof(E)), kRsrcWord3);
+  const __amdgpu_buffer_rsrc_t rf =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(inp), 0, static_cast<int>(fslab * 4u), kRsrcWord3);
+  const uint32_t vo_op = op_ok ? static_cast<uint32_t>((orow * n + ok_) * sizeof(E)) : kPast;
+  const uint32_t vo_f = fld_ok ? static_cast<uint32_t>(SIDE == 0 ? (static_cast<long>(fk_) * a.post + fidx) * 4
+                                                                  : (fidx * n + fk_) * 4)
+                               : kPast;
+  const uint32_t lo_bytes = static_cast<uint32_t>(n) * n * sizeof(E);  // qlo follows qhi
 
   // Two chunks in flight between global load and LDS write.  The operator
   // part is already split; the field part stays fp32 until the LDS write
@@ -641,39 +663,37 @@ __global__ __launch_bounds__(64 * TMW * TNW) void k_mode_gemm(ModalArgs a) {
     float fld[EF];
   } pend0, pend1;  // named, not an array: a runtime index would put them in scratch
   auto load_chunk = [&](int k0, Pending& pd) __attribute__((always_inline)) {
-    const long off = orow_c * n + k0 + ok_;
+    const int sk = k0 * static_cast<int>(sizeof(E));
 #pragma unroll
     for (int i = 0; i < EO / 8; ++i) {
-      pd.op_hi.v[i] = *reinterpret_cast<const uint4*>(qhi + off + 8 * i);
-      pd.op_lo.v[i] = *reinterpret_cast<const uint4*>(qlo + off + 8 * i);
+      pd.op_hi.v[i] = as_uint4(__builtin_amdgcn_raw_buffer_load_b128(rq, vo_op + 16 * i, sk, 0));
+      pd.op_lo.v[i] = as_uint4(__builtin_amdgcn_raw_buffer_load_b128(rq, vo_op + 16 * i, sk + static_cast<int>(lo_bytes), 0));
     }
     if (SIDE == 0) {
 #pragma unroll
-      for (int e = 0; e < EF; ++e) pd.fld[e] = inp[static_cast<long>(k0 + fk_ + e) * a.post + fidx_c];
+      for (int e = 0; e < EF; ++e)
+        pd.fld[e] = __builtin_bit_cast(
+            float, __builtin_amdgcn_raw_buffer_load_b32(rf, vo_f, static_cast<int>((k0 + e) * a.post * 4), 0));
     } else {
-      const float4* src = reinterpret_cast<const float4*>(in + fidx_c * n + k0 + fk_);
 #pragma unroll
       for (int i = 0; i < EF / 4; ++i) {
-        const float4 f = src[i];
-        pd.fld[4 * i] = f.x;
-        pd.fld[4 * i + 1] = f.y;
-        pd.fld[4 * i + 2] = f.z;
-        pd.fld[4 * i + 3] = f.w;
+        const uint4 f = as_uint4(__builtin_amdgcn_raw_buffer_load_b128(rf, vo_f + 16 * i, k0 * 4, 0));
+        pd.fld[4 * i] = __builtin_bit_cast(float, f.x);
+        pd.fld[4 * i + 1] = __builtin_bit_cast(float, f.y);
+        pd.fld[4 * i + 2] = __builtin_bit_cast(float, f.z);
+        pd.fld[4 * i + 3] = __builtin_bit_cast(float, f.w);
       }
     }
   };
   auto store_chunk = [&](const Pending& pd, int buf) __attribute__((always_inline)) {
-    float fv[EF];
-#pragma unroll
-    for (int e = 0; e < EF; ++e) fv[e] = fld_ok ? pd.fld[e] : 0.f;
     EV<EF> f_hi, f_lo;
-    split_n<PREC, EF>(fv, f_hi, f_lo);
+    split_n<PREC, EF>(pd.fld, f_hi, f_lo);
     E(*ohi)[GKP] = SIDE == 0 ? s.a_hi[buf] : s.b_hi[buf];
     E(*olo)[GKP] = SIDE == 0 ? s.a_lo[buf] : s.b_lo[buf];
 #pragma unroll
     for (int i = 0; i < EO / 8; ++i) {
-      *reinterpret_cast<uint4*>(&ohi[orow_l][ok_ + 8 * i]) = keep_if(op_ok, pd.op_hi.v[i]);
-      *reinterpret_cast<uint4*>(&olo[orow_l][ok_ + 8 * i]) = keep_if(op_ok, pd.op_lo.v[i]);
+      *reinterpret_cast<uint4*>(&ohi[orow_l][ok_ + 8 * i]) = pd.op_hi.v[i];
+      *reinterpret_cast<uint4*>(&olo[orow_l][ok_ + 8 * i]) = pd.op_lo.v[i];
     }
     E(*fhi)[GKP] = SIDE == 0 ? s.b_hi[buf] : s.a_hi[buf];
     E(*flo)[GKP] = SIDE == 0 ? s.b_lo[buf] : s.a_lo[buf];
@@ -891,9 +911,16 @@ void launch_mode_mfma_nb(const ModalArgs& a, hipStream_t st) {
   else launch_mode_mfma_t<PREC, SIDE, EPI, 4, NB>(a, st);
 }
 
+// Whether the GEMM's 32-bit buffer offsets reach every byte of the operator
+// (hi and lo) and of one field slab (left: n x post, right: pre x n floats).
+bool gemm_offsets_fit(const ModalArgs& a) {
+  const long slab = a.post == 1 ? static_cast<long>(a.pre) * a.n : static_cast<long>(a.n) * a.post;
+  return slab * 4 < (1L << 31) && 4L * a.n * a.n < (1L << 31);
+}
+
 template <int PREC, int SIDE, int EPI>
 void launch_mode_mfma(const ModalArgs& a, hipStream_t st) {
-  if (modal_use_gemm()) {
+  if (modal_use_gemm() && gemm_offsets_fit(a)) {
     launch_mode_gemm<PREC, SIDE, EPI>(a, st);
     return;
   }
