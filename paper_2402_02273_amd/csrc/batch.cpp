@@ -59,6 +59,7 @@ struct Launch {
   int offset, nitems, total, grid;
   bool rhs;
   int flavor, lp;
+  int group;
 };
 
 }  // namespace
@@ -81,6 +82,12 @@ struct expint_batch {
   void* d_tables = nullptr;
   size_t items_cap = 0;
   std::vector<Launch> launches;
+  // groups are dealt round-robin to `lanes` streams inside the recorded
+  // graph (lane 0 is `stream`, the others `side` streams), so the launch
+  // chains of independent groups overlap; joined before the graph ends
+  int lanes = 2;
+  hipStream_t side[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool poisoned = false;
@@ -195,7 +202,8 @@ int build_schedule(expint_batch* b, void* const* u) {
   std::vector<BatchItem> items;
   std::vector<double> tabs;  // per item: class table + wall table
   b->launches.clear();
-  for (const std::vector<int>& grp : groups) {
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+  const std::vector<int>& grp = groups[gi];
   size_t gmax = 0;
   for (int i : grp) gmax = std::max(gmax, per[i].size());
   for (size_t t = 0; t <= gmax; ++t) {
@@ -203,11 +211,11 @@ int build_schedule(expint_batch* b, void* const* u) {
     // per launch
     for (int fl = kGeneric; fl <= kFirst; ++fl) {
       for (int lp : {1, 2, 4}) {
-        Launch L{static_cast<int>(items.size()), 0, 0, 0, t == 0, fl, lp};
+        Launch L{static_cast<int>(items.size()), 0, 0, 0, t == 0, fl, lp, static_cast<int>(gi)};
         auto close = [&]() {
           L.grid = std::min(L.total, kMaxGrid);
           if (L.nitems > 0) b->launches.push_back(L);
-          L = Launch{static_cast<int>(items.size()), 0, 0, 0, t == 0, fl, lp};
+          L = Launch{static_cast<int>(items.size()), 0, 0, 0, t == 0, fl, lp, static_cast<int>(gi)};
         };
         for (int i : grp) {
           const Inst& in = b->inst[i];
@@ -275,11 +283,23 @@ int build_schedule(expint_batch* b, void* const* u) {
   BHIP(hipStreamSynchronize(b->stream));
   BHIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   hipError_t err = hipSuccess;
+  const int lanes = std::min<int>(b->lanes, static_cast<int>(groups.size()));
+  auto lane_stream = [&](int g) { return g % lanes == 0 ? b->stream : b->side[g % lanes - 1]; };
+  if (lanes > 1) {  // fork: the side streams join the capture after the fork event
+    err = hipEventRecord(b->fork, b->stream);
+    for (int l = 1; l < lanes && err == hipSuccess; ++l) err = hipStreamWaitEvent(b->side[l - 1], b->fork, 0);
+  }
   for (const Launch& L : b->launches) {
+    if (err != hipSuccess) break;
     const void* tb = static_cast<const char*>(b->d_tables) + static_cast<size_t>(L.offset) * (kTab + kMaxClasses) * w;
     err = launch_batch(b->dtype, b->bc, L.rhs, b->scheme == EXPINT_SCHEME_LINEARISED, L.flavor, L.lp,
-                       b->d_items + L.offset, tb, L.nitems, L.total, L.grid, b->stream);
-    if (err != hipSuccess) break;
+                       b->d_items + L.offset, tb, L.nitems, L.total, L.grid, lane_stream(L.group));
+  }
+  if (lanes > 1) {  // join every side stream back into the capturing stream
+    for (int l = 1; l < lanes && err == hipSuccess; ++l) {
+      err = hipEventRecord(b->join[l - 1], b->side[l - 1]);
+      if (err == hipSuccess) err = hipStreamWaitEvent(b->stream, b->join[l - 1], 0);
+    }
   }
   hipGraph_t gr = nullptr;
   const hipError_t ec = hipStreamEndCapture(b->stream, &gr);
@@ -352,6 +372,20 @@ int expint_batch_create(int32_t count, const expint_grid* grids, const expint_df
       return bail(set_error(EXPINT_EHIP, "hipStreamCreate failed"));
     }
     b->own_stream = true;
+  }
+  // lanes of the recorded step (default 2; EXPINT_BATCH_LANES, 1..4): side
+  // streams (default priority) and the fork / join events of the capture
+  if (const char* env = std::getenv("EXPINT_BATCH_LANES")) b->lanes = std::max(1, std::min(4, std::atoi(env)));
+  for (int l = 1; l < b->lanes; ++l) {
+    if (hipStreamCreateWithFlags(&b->side[l - 1], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join[l - 1], hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return bail(set_error(EXPINT_EHIP, "side stream creation failed"));
+    }
+  }
+  if (b->lanes > 1 && hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(set_error(EXPINT_EHIP, "event creation failed"));
   }
   int64_t max_parts = kReduceBlocks;
   b->inst.resize(count);
@@ -433,6 +467,11 @@ void expint_batch_destroy(expint_batch* b) {
   if (!b) return;
   if (b->stream && !b->poisoned) (void)hipStreamSynchronize(b->stream);
   destroy_graph(b);
+  for (int l = 0; l < 3; ++l) {
+    if (b->side[l]) (void)hipStreamDestroy(b->side[l]);
+    if (b->join[l]) (void)hipEventDestroy(b->join[l]);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
 }

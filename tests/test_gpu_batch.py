@@ -84,6 +84,31 @@ def test_batch_matches_single_contexts(native):
             assert float((u - us[i]).abs().max()) <= tol * float(u.abs().max()), (dtype, i)
 
 
+@pytest.mark.parametrize("lanes", ["1", "2", "3"])
+def test_group_lanes_change_nothing(native, monkeypatch, lanes):
+    # a tiny group budget puts every instance in a group of its own, and the
+    # groups are dealt to 1, 2 or 3 concurrent streams inside the graph: the
+    # results are the same bits whatever the lanes
+    from paper_2402_02273_amd.expint import ExpIntBatch
+
+    insts = small_instances()
+    monkeypatch.setenv("EXPINT_BATCH_GROUP_BYTES", "1")
+    outs = {}
+    for ln in ("1", lanes):
+        monkeypatch.setenv("EXPINT_BATCH_LANES", ln)
+        b = ExpIntBatch(insts, tau=7.3, dtype=torch.float32, device=DEV)
+        us = [dev(i["u0"], torch.float32) for i in insts]
+        b.advance(us, 3)
+        b.advance(us, 2)  # graph replay
+        torch.cuda.synchronize()
+        outs[ln] = [u.cpu().numpy() for u in us]
+        del b
+    for a, c in zip(outs["1"], outs[lanes]):
+        assert np.array_equal(a, c)
+    ref, _ = oracle_run(insts[3], 7.3, 5, key="f32")
+    assert rel(outs[lanes][3], ref) < 1e-5
+
+
 def test_c3_full_batch(native):
     """All 64 scenarios of the batched workload, 50 steps, FP32: plans match the
     oracle rule, every instance matches a single-grid context, and the three
