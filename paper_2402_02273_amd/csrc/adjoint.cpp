@@ -80,9 +80,27 @@ int ensure_adj(expint_ctx* c, int nck, int seg) {
   }
   if ((rc = grow(c, a.ckpt, static_cast<size_t>(nck)))) return rc;
   if ((rc = grow(c, a.segs, static_cast<size_t>(seg)))) return rc;
-  if ((rc = grow(c, a.xs, static_cast<size_t>(c->s) + 1))) return rc;
-  if ((rc = grow(c, a.tape, static_cast<size_t>(c->s) * c->m))) return rc;
+  if ((rc = grow(c, a.xs, 2 * (static_cast<size_t>(c->s) + 1)))) return rc;
+  if ((rc = grow(c, a.tape, 2 * static_cast<size_t>(c->s) * c->m))) return rc;
+  for (int p = 0; p < 2; ++p)
+    if (!a.bt[p] && (rc = c->arena.alloc(&a.bt[p], fb))) return rc;
+  if (!a.side) {
+    // the tape stream and its events (default priority, like every stream here)
+    hipStream_t st = nullptr;
+    HIP_TRY(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    a.side = st;
+    for (int p = 0; p < 2; ++p) {
+      HIP_TRY(c, hipEventCreateWithFlags(&a.ev_tape[p], hipEventDisableTiming));
+      HIP_TRY(c, hipEventCreateWithFlags(&a.ev_rev[p], hipEventDisableTiming));
+    }
+    HIP_TRY(c, hipEventCreateWithFlags(&a.ev_seg, hipEventDisableTiming));
+  }
   return EXPINT_OK;
+}
+
+void* xs_at(expint_ctx* c, int p, int sig) { return c->adj.xs[static_cast<size_t>(p) * (c->s + 1) + sig]; }
+void** tape_of(expint_ctx* c, int p, int sig) {
+  return &c->adj.tape[(static_cast<size_t>(p) * c->s + (sig - 1)) * c->m];
 }
 
 // Face weights -dK(D_a, D_b)/dD_c / h^2 and wall weights -[a == c] / h^2.
@@ -123,13 +141,13 @@ int faceprod(expint_ctx* c, const void* ybar, const void* y, double w, bool tayl
 }
 
 // One Taylor sweep of the step's matrix: A, or J_n at the state un.
-int term(expint_ctx* c, TermOp op, const void* un) {
+int term(expint_ctx* c, TermOp op, const void* un, hipStream_t st) {
   if (c->scheme == EXPINT_SCHEME_LINEARISED) {
     op.ju = un;
     op.jrho = c->rho;
   }
   classify_term(op);
-  HIP_TRY(c, launch_term(c->dtype, c->bc, c->g, c->tiling, c->coef(), op, c->stream));
+  HIP_TRY(c, launch_term(c->dtype, c->bc, c->g, c->tiling, c->coef(), op, st));
   return EXPINT_OK;
 }
 
@@ -152,40 +170,51 @@ int term_face(expint_ctx* c, TermOp op, const void* un, const void* y, double w)
   }
   int rc;
   if ((rc = faceprod(c, op.src, y, w, true))) return rc;
-  return term(c, op, un);
+  return term(c, op, un, c->stream);
 }
 
 // Reverse sweep of one step; lambda (c->adj.lam) is updated in place.
-int reverse_step(expint_ctx* c, const void* un) {
+// The forward tape of step n at the state un into tape set p, on stream st:
+// b_n, the sub-step states and every Taylor term.
+int tape_step(expint_ctx* c, const void* un, int p, hipStream_t st) {
+  auto& a = c->adj;
+  const int s = c->s, m = c->m;
+  const double h = c->tau / s;
+  int rc;
+  HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, c->tiling, c->coef(), un, a.bt[p], c->rho, st));
+  for (int sig = 1; sig <= s; ++sig) {
+    void** T = tape_of(c, p, sig);
+    TermOp t1;
+    t1.src = xs_at(c, p, sig - 1);
+    t1.bsrc = a.bt[p];
+    t1.c = h;
+    t1.cb = h;
+    t1.cs = 1.0;
+    t1.acc_out = xs_at(c, p, sig);
+    t1.y_out = m >= 2 ? T[0] : nullptr;
+    if ((rc = term(c, t1, un, st))) return rc;
+    for (int j = 2; j <= m; ++j) {
+      TermOp t;
+      t.src = T[j - 2];
+      t.c = h / j;
+      t.acc_in = xs_at(c, p, sig);
+      t.ca = 1.0;
+      t.acc_out = xs_at(c, p, sig);
+      t.y_out = j < m ? T[j - 1] : nullptr;
+      if ((rc = term(c, t, un, st))) return rc;
+    }
+  }
+  return EXPINT_OK;
+}
+
+// The reverse sweeps of step n from tape set p, on the context stream;
+// lambda (c->adj.lam) is updated in place.
+int reverse_step(expint_ctx* c, const void* un, int p) {
   auto& a = c->adj;
   const int s = c->s, m = c->m;
   const double h = c->tau / s;
   const int64_t n = c->g.n;
   int rc;
-  // b_n and the Taylor tape of every sub-step
-  HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, c->tiling, c->coef(), un, c->b, c->rho, c->stream));
-  for (int sig = 1; sig <= s; ++sig) {
-    void** T = &a.tape[static_cast<size_t>(sig - 1) * m];
-    TermOp t1;
-    t1.src = a.xs[sig - 1];
-    t1.bsrc = c->b;
-    t1.c = h;
-    t1.cb = h;
-    t1.cs = 1.0;
-    t1.acc_out = a.xs[sig];
-    t1.y_out = m >= 2 ? T[0] : nullptr;
-    if ((rc = term(c, t1, un))) return rc;
-    for (int j = 2; j <= m; ++j) {
-      TermOp t;
-      t.src = T[j - 2];
-      t.c = h / j;
-      t.acc_in = a.xs[sig];
-      t.ca = 1.0;
-      t.acc_out = a.xs[sig];
-      t.y_out = j < m ? T[j - 1] : nullptr;
-      if ((rc = term(c, t, un))) return rc;
-    }
-  }
   // reverse through the sub-steps
   int xi = 0;
   HIP_TRY(c, launch_copy(c->dtype, n, a.lam, a.xb[0], c->stream));
@@ -193,8 +222,8 @@ int reverse_step(expint_ctx* c, const void* un) {
   const bool lin = c->scheme == EXPINT_SCHEME_LINEARISED;
   if (lin) HIP_TRY(c, launch_fill(c->dtype, n, 0.0, a.dbar, c->stream));
   for (int sig = s; sig >= 1; --sig) {
-    void** T = &a.tape[static_cast<size_t>(sig - 1) * m];
-    const void* xprev = a.xs[sig - 1];
+    void** T = tape_of(c, p, sig);
+    const void* xprev = xs_at(c, p, sig - 1);
     const void* ynext = a.xb[xi];  // ybar_m = xbar
     // the face products of ybar_j pair it with y_{j-1} (x_{sigma-1} for j = 1)
     // at weight h/j; each is taken with the next sweep, whose source is ybar_j
@@ -263,7 +292,9 @@ int vjp_core(expint_ctx* c, const void* u0, int32_t nsteps, const void* cot, boo
   const int64_t slots = faceprod_slots(c->g, c->tiling);
   HIP_TRY(c, launch_fill(EXPINT_F64, 16, 0.0, a.dev, c->stream));
   HIP_TRY(c, launch_fill(EXPINT_F64, slots * kMaxClasses, 0.0, a.fpart, c->stream));
-  HIP_TRY(c, launch_fill(c->dtype, n, 0.0, a.xs[0], c->stream));
+  for (int p = 0; p < 2; ++p) HIP_TRY(c, launch_fill(c->dtype, n, 0.0, xs_at(c, p, 0), c->stream));
+  // both tape sets start free
+  for (int p = 0; p < 2; ++p) HIP_TRY(c, hipEventRecord(a.ev_rev[p], c->stream));
 
   // forward with checkpoints
   HIP_TRY(c, launch_copy(c->dtype, n, u0, a.work, c->stream));
@@ -286,8 +317,26 @@ int vjp_core(expint_ctx* c, const void* u0, int32_t nsteps, const void* cot, boo
       HIP_TRY(c, launch_copy(c->dtype, n, a.segs[k - start], a.segs[k - start + 1], c->stream));
       if ((rc = enqueue_step(c, a.segs[k - start + 1]))) return rc;
     }
-    for (int k = stop - 1; k >= start; --k)
-      if ((rc = reverse_step(c, a.segs[k - start]))) return rc;
+    // the tapes run on the side stream one step ahead of the reverse sweeps:
+    // tape k - 1 into the other set while step k reverses
+    HIP_TRY(c, hipEventRecord(a.ev_seg, c->stream));
+    HIP_TRY(c, hipStreamWaitEvent(a.side, a.ev_seg, 0));
+    auto issue_tape = [&](int k) -> int {
+      const int p = k & 1;
+      HIP_TRY(c, hipStreamWaitEvent(a.side, a.ev_rev[p], 0));
+      const int r = tape_step(c, a.segs[k - start], p, a.side);
+      if (r) return r;
+      HIP_TRY(c, hipEventRecord(a.ev_tape[p], a.side));
+      return EXPINT_OK;
+    };
+    if ((rc = issue_tape(stop - 1))) return rc;
+    for (int k = stop - 1; k >= start; --k) {
+      if (k - 1 >= start && (rc = issue_tape(k - 1))) return rc;
+      const int p = k & 1;
+      HIP_TRY(c, hipStreamWaitEvent(c->stream, a.ev_tape[p], 0));
+      if ((rc = reverse_step(c, a.segs[k - start], p))) return rc;
+      HIP_TRY(c, hipEventRecord(a.ev_rev[p], c->stream));
+    }
   }
   HIP_TRY(c, launch_copy(c->dtype, n, a.lam, grad_u0, c->stream));
   HIP_TRY(c, launch_faceprod_final(a.fpart, slots, a.dev, c->stream));

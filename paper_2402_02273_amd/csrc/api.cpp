@@ -438,6 +438,13 @@ void expint_destroy(expint_ctx* c) {
   if (hipGetDevice(&cur) == hipSuccess && cur != c->device) (void)hipSetDevice(c->device);
   if (c->stream && !c->poisoned) (void)hipStreamSynchronize(c->stream);
   destroy_graphs(c->graphs);
+  auto& a = c->adj;
+  if (a.side) {
+    if (!c->poisoned) (void)hipStreamSynchronize(a.side);
+    (void)hipStreamDestroy(a.side);
+  }
+  for (hipEvent_t e : {a.ev_tape[0], a.ev_tape[1], a.ev_rev[0], a.ev_rev[1], a.ev_seg})
+    if (e) (void)hipEventDestroy(e);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   const int dev = c->device;
   delete c;  // the arena frees the device buffers

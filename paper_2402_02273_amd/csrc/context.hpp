@@ -118,8 +118,17 @@ struct expint_ctx {
   struct Adj {
     std::vector<void*> ckpt;  // u every ckpt_every steps
     std::vector<void*> segs;  // states of one checkpoint segment
-    std::vector<void*> xs;    // sub-step states x_0 .. x_s of one step
-    std::vector<void*> tape;  // Taylor terms y_1 .. y_m of every sub-step
+    // Two tape sets: the tape of step n - 1 is recomputed on `side` while
+    // step n reverses on the context stream.  Set p holds b_n (bt[p]), the
+    // sub-step states x_0 .. x_s (xs[p (s + 1) ..]) and the Taylor terms
+    // y_1 .. y_m of every sub-step (tape[p s m ..]).
+    std::vector<void*> xs;
+    std::vector<void*> tape;
+    void* bt[2] = {nullptr, nullptr};
+    hipStream_t side = nullptr;
+    hipEvent_t ev_tape[2] = {nullptr, nullptr};  // tape set p written
+    hipEvent_t ev_rev[2] = {nullptr, nullptr};   // tape set p no longer read
+    hipEvent_t ev_seg = nullptr;                 // states of a segment recomputed
     void* lam = nullptr;      // adjoint state
     void* gb = nullptr;       // adjoint of b (= P(A) lambda)
     void* work = nullptr;     // forward state
