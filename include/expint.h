@@ -252,10 +252,12 @@ int expint_reduce(expint_ctx* ctx, int32_t op, const void* x, const void* y, dou
  * u0, u_target: device fields (read only); grad_u0: device field (written);
  * loss, grad_rho: host scalars; grad_class_D: host array of n_classes
  * (label form only; dense form gives EINVAL).  u is checkpointed every
- * ckpt_every steps (>= 1) and recomputed in between.  Each step's Taylor
- * tape is recomputed on a second stream the context creates (default
- * priority), one step ahead of the reverse sweeps on the context stream;
- * the call synchronises both before it returns.  EXP_EULER and
+ * ckpt_every steps (>= 1) and recomputed in between.  Stencil-Taylor
+ * contexts only (MODAL gives EXPINT_EUNSUPPORTED).  The context creates two
+ * more streams for it (default priority): one recomputes each step's Taylor
+ * tape one step ahead of the reverse sweeps on the context stream, the
+ * other the states of the next checkpoint segment one segment ahead.  The
+ * call synchronises all three before it returns.  EXP_EULER and
  * LINEARISED contexts (the latter differentiates J_n's diagonal too); EXPRK2
  * gives EXPINT_EUNSUPPORTED. */
 int expint_grad(expint_ctx* ctx, const void* u0, int32_t nsteps, const void* u_target,

@@ -80,6 +80,7 @@ int ensure_adj(expint_ctx* c, int nck, int seg) {
   }
   if ((rc = grow(c, a.ckpt, static_cast<size_t>(nck)))) return rc;
   if ((rc = grow(c, a.segs, static_cast<size_t>(seg)))) return rc;
+  if ((rc = grow(c, a.segs2, static_cast<size_t>(seg)))) return rc;
   if ((rc = grow(c, a.xs, 2 * (static_cast<size_t>(c->s) + 1)))) return rc;
   if ((rc = grow(c, a.tape, 2 * static_cast<size_t>(c->s) * c->m))) return rc;
   for (int p = 0; p < 2; ++p)
@@ -93,7 +94,13 @@ int ensure_adj(expint_ctx* c, int nck, int seg) {
       HIP_TRY(c, hipEventCreateWithFlags(&a.ev_tape[p], hipEventDisableTiming));
       HIP_TRY(c, hipEventCreateWithFlags(&a.ev_rev[p], hipEventDisableTiming));
     }
-    HIP_TRY(c, hipEventCreateWithFlags(&a.ev_seg, hipEventDisableTiming));
+    HIP_TRY(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    a.rec = st;
+    HIP_TRY(c, hipEventCreateWithFlags(&a.ev_fwd, hipEventDisableTiming));
+    for (int q = 0; q < 2; ++q) {
+      HIP_TRY(c, hipEventCreateWithFlags(&a.ev_seg[q], hipEventDisableTiming));
+      HIP_TRY(c, hipEventCreateWithFlags(&a.ev_segfree[q], hipEventDisableTiming));
+    }
   }
   return EXPINT_OK;
 }
@@ -281,6 +288,8 @@ int vjp_core(expint_ctx* c, const void* u0, int32_t nsteps, const void* cot, boo
   if (!c->labels_form) return set_error(EXPINT_EINVAL, "gradients need the label form of D");
   if (c->scheme == EXPINT_SCHEME_EXPRK2)
     return set_error(EXPINT_EUNSUPPORTED, "gradients are for the EXP_EULER and LINEARISED schemes");
+  if (c->algo == EXPINT_ALGO_MODAL)  // the reverse pass is that of the Taylor map, not of the mode products
+    return set_error(EXPINT_EUNSUPPORTED, "gradients are for the stencil-Taylor algorithm");
   int rc = ensure_device(c);
   if (rc) return rc;
   const int nck = nsteps > 0 ? (nsteps + ckpt_every - 1) / ckpt_every : 0;
@@ -293,13 +302,18 @@ int vjp_core(expint_ctx* c, const void* u0, int32_t nsteps, const void* cot, boo
   HIP_TRY(c, launch_fill(EXPINT_F64, 16, 0.0, a.dev, c->stream));
   HIP_TRY(c, launch_fill(EXPINT_F64, slots * kMaxClasses, 0.0, a.fpart, c->stream));
   for (int p = 0; p < 2; ++p) HIP_TRY(c, launch_fill(c->dtype, n, 0.0, xs_at(c, p, 0), c->stream));
-  // both tape sets start free
+  // both tape sets and both segment-state sets start free
   for (int p = 0; p < 2; ++p) HIP_TRY(c, hipEventRecord(a.ev_rev[p], c->stream));
+  for (int q = 0; q < 2; ++q) HIP_TRY(c, hipEventRecord(a.ev_segfree[q], c->stream));
 
-  // forward with checkpoints
+  // Segment sgi keeps its states in set sgi & 1.
+  auto seg_states = [&](int sgi) -> std::vector<void*>& { return (sgi & 1) ? a.segs2 : a.segs; };
+  // forward with checkpoints; the last segment's states are kept as they pass
   HIP_TRY(c, launch_copy(c->dtype, n, u0, a.work, c->stream));
+  const int last_start = (nck - 1) * ckpt_every;
   for (int k = 0; k < nsteps; ++k) {
     if (k % ckpt_every == 0) HIP_TRY(c, launch_copy(c->dtype, n, a.work, a.ckpt[k / ckpt_every], c->stream));
+    if (k >= last_start) HIP_TRY(c, launch_copy(c->dtype, n, a.work, seg_states(nck - 1)[k - last_start], c->stream));
     if ((rc = enqueue_step(c, a.work))) return rc;
   }
   if (cot_is_target) {
@@ -309,22 +323,41 @@ int vjp_core(expint_ctx* c, const void* u0, int32_t nsteps, const void* cot, boo
     HIP_TRY(c, launch_copy(c->dtype, n, cot, a.lam, c->stream));
   }
 
+  // Three streams from here on: the states of segment sgi - 1 are recomputed
+  // on `rec` while segment sgi reverses on the context stream, and within a
+  // segment the tape of step k - 1 is recomputed on `side` while step k
+  // reverses.  Segment sgi uses state set sgi & 1, step k tape set k & 1.
+  HIP_TRY(c, hipEventRecord(a.ev_fwd, c->stream));
+  HIP_TRY(c, hipStreamWaitEvent(a.rec, a.ev_fwd, 0));
+  auto recompute = [&](int sgi) -> int {
+    const int q = sgi & 1;
+    const int start = sgi * ckpt_every;
+    const int stop = std::min(start + ckpt_every, nsteps);
+    std::vector<void*>& sv = seg_states(sgi);
+    HIP_TRY(c, hipStreamWaitEvent(a.rec, a.ev_segfree[q], 0));
+    HIP_TRY(c, launch_copy(c->dtype, n, a.ckpt[sgi], sv[0], a.rec));
+    for (int k = start; k < stop - 1; ++k) {
+      HIP_TRY(c, launch_copy(c->dtype, n, sv[k - start], sv[k - start + 1], a.rec));
+      const int r = enqueue_step_on(c, sv[k - start + 1], a.rec);
+      if (r) return r;
+    }
+    HIP_TRY(c, hipEventRecord(a.ev_seg[q], a.rec));
+    return EXPINT_OK;
+  };
+  // the last segment's states came from the forward pass
+  if (nck > 0) HIP_TRY(c, hipEventRecord(a.ev_seg[(nck - 1) & 1], c->stream));
   for (int sgi = nck - 1; sgi >= 0; --sgi) {
     const int start = sgi * ckpt_every;
     const int stop = std::min(start + ckpt_every, nsteps);
-    HIP_TRY(c, launch_copy(c->dtype, n, a.ckpt[sgi], a.segs[0], c->stream));
-    for (int k = start; k < stop - 1; ++k) {
-      HIP_TRY(c, launch_copy(c->dtype, n, a.segs[k - start], a.segs[k - start + 1], c->stream));
-      if ((rc = enqueue_step(c, a.segs[k - start + 1]))) return rc;
-    }
-    // the tapes run on the side stream one step ahead of the reverse sweeps:
-    // tape k - 1 into the other set while step k reverses
-    HIP_TRY(c, hipEventRecord(a.ev_seg, c->stream));
-    HIP_TRY(c, hipStreamWaitEvent(a.side, a.ev_seg, 0));
+    const int q = sgi & 1;
+    std::vector<void*>& sv = seg_states(sgi);
+    if (sgi >= 1 && (rc = recompute(sgi - 1))) return rc;
+    HIP_TRY(c, hipStreamWaitEvent(a.side, a.ev_seg[q], 0));
+    HIP_TRY(c, hipStreamWaitEvent(c->stream, a.ev_seg[q], 0));
     auto issue_tape = [&](int k) -> int {
       const int p = k & 1;
       HIP_TRY(c, hipStreamWaitEvent(a.side, a.ev_rev[p], 0));
-      const int r = tape_step(c, a.segs[k - start], p, a.side);
+      const int r = tape_step(c, sv[k - start], p, a.side);
       if (r) return r;
       HIP_TRY(c, hipEventRecord(a.ev_tape[p], a.side));
       return EXPINT_OK;
@@ -334,9 +367,11 @@ int vjp_core(expint_ctx* c, const void* u0, int32_t nsteps, const void* cot, boo
       if (k - 1 >= start && (rc = issue_tape(k - 1))) return rc;
       const int p = k & 1;
       HIP_TRY(c, hipStreamWaitEvent(c->stream, a.ev_tape[p], 0));
-      if ((rc = reverse_step(c, a.segs[k - start], p))) return rc;
+      if ((rc = reverse_step(c, sv[k - start], p))) return rc;
       HIP_TRY(c, hipEventRecord(a.ev_rev[p], c->stream));
     }
+    // every read of this state set (tapes included) is behind this event
+    HIP_TRY(c, hipEventRecord(a.ev_segfree[q], c->stream));
   }
   HIP_TRY(c, launch_copy(c->dtype, n, a.lam, grad_u0, c->stream));
   HIP_TRY(c, launch_faceprod_final(a.fpart, slots, a.dev, c->stream));

@@ -161,14 +161,16 @@ int make_plan(expint_ctx* c) {
   return EXPINT_OK;
 }
 
-int run_ops(expint_ctx* c, const std::vector<TermOp>& ops) {
+int run_ops(expint_ctx* c, const std::vector<TermOp>& ops, hipStream_t st) {
   const Coef cf = c->coef();
   for (const TermOp& op : ops) {
-    if (op.pair) HIP_TRY(c, launch_pair(c->dtype, c->bc, c->g, c->ptiling, cf, op, c->stream));
-    else HIP_TRY(c, launch_term(c->dtype, c->bc, c->g, c->tiling, cf, op, c->stream));
+    if (op.pair) HIP_TRY(c, launch_pair(c->dtype, c->bc, c->g, c->ptiling, cf, op, st));
+    else HIP_TRY(c, launch_term(c->dtype, c->bc, c->g, c->tiling, cf, op, st));
   }
   return EXPINT_OK;
 }
+
+int run_ops(expint_ctx* c, const std::vector<TermOp>& ops) { return run_ops(c, ops, c->stream); }
 
 StepBuffers step_buffers(expint_ctx* c) {
   StepBuffers sb;
@@ -186,12 +188,15 @@ std::vector<TermOp> step_schedule(expint_ctx* c, const void* b, void* x_out, voi
   return phi1_schedule(step_buffers(c), c->s, c->m, c->tau, b, x_out, u);
 }
 
-// Launches of one step on c->stream (no synchronisation).  The right-hand
-// side is A u + f(u) for both schemes (for LINEARISED it is J_n u_n + rho u_n^2,
-// the same field); LINEARISED applies phi1 to J_n, taken at u before the last
-// sweep adds the result into it.
-int enqueue_step(expint_ctx* c, void* u) {
-  HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, c->tiling, c->coef(), u, c->b, c->rho, c->stream));
+// Launches of one step on stream st (no synchronisation); the context's step
+// buffers are its workspace.  The right-hand side is A u + f(u) for both
+// schemes (for LINEARISED it is J_n u_n + rho u_n^2, the same field);
+// LINEARISED applies phi1 to J_n, taken at u before the last sweep adds the
+// result into it.  The modal and EXPRK2 forms run on the context stream only.
+int enqueue_step_on(expint_ctx* c, void* u, hipStream_t st) {
+  if (st != c->stream && (c->algo == EXPINT_ALGO_MODAL || c->scheme == EXPINT_SCHEME_EXPRK2))
+    return set_error(EXPINT_EUNSUPPORTED, "this step runs on the context stream only");
+  HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, c->tiling, c->coef(), u, c->b, c->rho, st));
   if (c->algo == EXPINT_ALGO_MODAL) return modal_phi1(c, c->b, u, true);
   if (c->scheme == EXPINT_SCHEME_EXPRK2) {
     // stage 1: X = tau phi1(tau A) b; d = f(u + X) - f(u); stage 2 adds
@@ -204,8 +209,10 @@ int enqueue_step(expint_ctx* c, void* u) {
   }
   std::vector<TermOp> ops = step_schedule(c, c->b, nullptr, u);
   if (c->scheme == EXPINT_SCHEME_LINEARISED) set_linearised(ops, u, c->rho);
-  return run_ops(c, ops);
+  return run_ops(c, ops, st);
 }
+
+int enqueue_step(expint_ctx* c, void* u) { return enqueue_step_on(c, u, c->stream); }
 
 int check_finite_field(expint_ctx* c, const void* u) {
   HIP_TRY(c, launch_reduce(c->dtype, 3, u, nullptr, c->g.n, c->partial, c->red, c->stream));
@@ -439,11 +446,13 @@ void expint_destroy(expint_ctx* c) {
   if (c->stream && !c->poisoned) (void)hipStreamSynchronize(c->stream);
   destroy_graphs(c->graphs);
   auto& a = c->adj;
-  if (a.side) {
-    if (!c->poisoned) (void)hipStreamSynchronize(a.side);
-    (void)hipStreamDestroy(a.side);
+  for (hipStream_t st : {a.side, a.rec}) {
+    if (!st) continue;
+    if (!c->poisoned) (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
   }
-  for (hipEvent_t e : {a.ev_tape[0], a.ev_tape[1], a.ev_rev[0], a.ev_rev[1], a.ev_seg})
+  for (hipEvent_t e : {a.ev_tape[0], a.ev_tape[1], a.ev_rev[0], a.ev_rev[1], a.ev_fwd, a.ev_seg[0], a.ev_seg[1],
+                       a.ev_segfree[0], a.ev_segfree[1]})
     if (e) (void)hipEventDestroy(e);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   const int dev = c->device;

@@ -128,7 +128,14 @@ struct expint_ctx {
     hipStream_t side = nullptr;
     hipEvent_t ev_tape[2] = {nullptr, nullptr};  // tape set p written
     hipEvent_t ev_rev[2] = {nullptr, nullptr};   // tape set p no longer read
-    hipEvent_t ev_seg = nullptr;                 // states of a segment recomputed
+    // Two segment-state sets: the states of segment k - 1 are recomputed on
+    // `rec` (with the context's step buffers, which nothing else uses after
+    // the forward pass) while segment k reverses.
+    std::vector<void*> segs2;                    // second set, like segs
+    hipStream_t rec = nullptr;
+    hipEvent_t ev_fwd = nullptr;                 // forward pass with checkpoints done
+    hipEvent_t ev_seg[2] = {nullptr, nullptr};   // segment-state set q recomputed
+    hipEvent_t ev_segfree[2] = {nullptr, nullptr};  // set q no longer read
     void* lam = nullptr;      // adjoint state
     void* gb = nullptr;       // adjoint of b (= P(A) lambda)
     void* work = nullptr;     // forward state
@@ -181,6 +188,7 @@ double harmonic_mean(double a, double b);
 int ensure_device(expint_ctx* c);
 int upload_tables(expint_ctx* c);
 int enqueue_step(expint_ctx* c, void* u);
+int enqueue_step_on(expint_ctx* c, void* u, hipStream_t st);
 // nsteps steps on the stream: replays (recording on first use) the step graph
 // for u, or launches each step when graphs are off.  No synchronisation.
 int run_steps(expint_ctx* c, void* u, int32_t nsteps);

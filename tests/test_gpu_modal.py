@@ -132,3 +132,16 @@ def test_c5_full_size_one_step_elementwise(native):
         print(f"[result] c5 256^3 one step {dtype} {mp}: rel-L2 {err:.2e}", flush=True)
         assert err < tol
         ctx.close()
+
+
+def test_modal_gradient_rejected(native):
+    # the reverse pass is the adjoint of the Taylor map, not of the mode
+    # products, so modal contexts give no gradients
+    from paper_2402_02273_amd import ExpIntError
+
+    ctx = modal_ctx((32, 32, 32), torch.float64)
+    u0 = dev(random_field((32, 32, 32), seed=5), torch.float64)
+    with pytest.raises(ExpIntError, match="EUNSUPPORTED"):
+        ctx.grad(u0, 2, u0, ckpt_every=1)
+    with pytest.raises(ExpIntError, match="EUNSUPPORTED"):
+        ctx.vjp(u0, 2, u0, ckpt_every=1)
