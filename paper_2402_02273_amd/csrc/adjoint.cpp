@@ -28,6 +28,7 @@
 
 #include "context.hpp"
 #include "internal.hpp"
+#include "schedule.hpp"
 
 using namespace expint;
 
@@ -85,6 +86,8 @@ int ensure_adj(expint_ctx* c, int nck, int seg) {
   if ((rc = grow(c, a.tape, 2 * static_cast<size_t>(c->s) * c->m))) return rc;
   for (int p = 0; p < 2; ++p)
     if (!a.bt[p] && (rc = c->arena.alloc(&a.bt[p], fb))) return rc;
+  for (void*& r : a.rb)
+    if (!r && (rc = c->arena.alloc(&r, fb))) return rc;
   if (!a.side) {
     // the tape stream and its events (default priority, like every stream here)
     hipStream_t st = nullptr;
@@ -313,6 +316,8 @@ int vjp_core(expint_ctx* c, const void* u0, int32_t nsteps, const void* cot, boo
   const int last_start = (nck - 1) * ckpt_every;
   for (int k = 0; k < nsteps; ++k) {
     if (k % ckpt_every == 0) HIP_TRY(c, launch_copy(c->dtype, n, a.work, a.ckpt[k / ckpt_every], c->stream));
+    // the recompute of the segments before the last may start from here on
+    if (k == last_start - ckpt_every) HIP_TRY(c, hipEventRecord(a.ev_fwd, c->stream));
     if (k >= last_start) HIP_TRY(c, launch_copy(c->dtype, n, a.work, seg_states(nck - 1)[k - last_start], c->stream));
     if ((rc = enqueue_step(c, a.work))) return rc;
   }
@@ -327,8 +332,8 @@ int vjp_core(expint_ctx* c, const void* u0, int32_t nsteps, const void* cot, boo
   // on `rec` while segment sgi reverses on the context stream, and within a
   // segment the tape of step k - 1 is recomputed on `side` while step k
   // reverses.  Segment sgi uses state set sgi & 1, step k tape set k & 1.
-  HIP_TRY(c, hipEventRecord(a.ev_fwd, c->stream));
-  HIP_TRY(c, hipStreamWaitEvent(a.rec, a.ev_fwd, 0));
+  if (nck >= 2) HIP_TRY(c, hipStreamWaitEvent(a.rec, a.ev_fwd, 0));
+  const StepBuffers rsb{a.rb[0], {a.rb[1], a.rb[2]}, {a.rb[3], a.rb[4]}};
   auto recompute = [&](int sgi) -> int {
     const int q = sgi & 1;
     const int start = sgi * ckpt_every;
@@ -338,7 +343,7 @@ int vjp_core(expint_ctx* c, const void* u0, int32_t nsteps, const void* cot, boo
     HIP_TRY(c, launch_copy(c->dtype, n, a.ckpt[sgi], sv[0], a.rec));
     for (int k = start; k < stop - 1; ++k) {
       HIP_TRY(c, launch_copy(c->dtype, n, sv[k - start], sv[k - start + 1], a.rec));
-      const int r = enqueue_step_on(c, sv[k - start + 1], a.rec);
+      const int r = enqueue_step_on(c, sv[k - start + 1], a.rec, &rsb);
       if (r) return r;
     }
     HIP_TRY(c, hipEventRecord(a.ev_seg[q], a.rec));

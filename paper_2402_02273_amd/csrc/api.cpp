@@ -182,21 +182,24 @@ StepBuffers step_buffers(expint_ctx* c) {
   return sb;
 }
 
-std::vector<TermOp> step_schedule(expint_ctx* c, const void* b, void* x_out, void* u) {
+std::vector<TermOp> step_schedule(expint_ctx* c, const void* b, void* x_out, void* u, const StepBuffers* sb) {
+  const StepBuffers ws = sb ? *sb : step_buffers(c);
   if (c->ptiling.ty != 0 && c->labels_form && c->m >= 2)
-    return phi1_schedule_pairs(step_buffers(c), c->s, c->m, c->tau, b, x_out, u);
-  return phi1_schedule(step_buffers(c), c->s, c->m, c->tau, b, x_out, u);
+    return phi1_schedule_pairs(ws, c->s, c->m, c->tau, b, x_out, u);
+  return phi1_schedule(ws, c->s, c->m, c->tau, b, x_out, u);
 }
 
-// Launches of one step on stream st (no synchronisation); the context's step
-// buffers are its workspace.  The right-hand side is A u + f(u) for both
-// schemes (for LINEARISED it is J_n u_n + rho u_n^2, the same field);
-// LINEARISED applies phi1 to J_n, taken at u before the last sweep adds the
-// result into it.  The modal and EXPRK2 forms run on the context stream only.
-int enqueue_step_on(expint_ctx* c, void* u, hipStream_t st) {
-  if (st != c->stream && (c->algo == EXPINT_ALGO_MODAL || c->scheme == EXPINT_SCHEME_EXPRK2))
+// Launches of one step on stream st (no synchronisation), with the step
+// buffers sb as workspace (NULL: the context's).  The right-hand side is
+// A u + f(u) for both schemes (for LINEARISED it is J_n u_n + rho u_n^2, the
+// same field); LINEARISED applies phi1 to J_n, taken at u before the last
+// sweep adds the result into it.  The modal and EXPRK2 forms run on the
+// context stream with the context's buffers only.
+int enqueue_step_on(expint_ctx* c, void* u, hipStream_t st, const StepBuffers* sb) {
+  if ((st != c->stream || sb) && (c->algo == EXPINT_ALGO_MODAL || c->scheme == EXPINT_SCHEME_EXPRK2))
     return set_error(EXPINT_EUNSUPPORTED, "this step runs on the context stream only");
-  HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, c->tiling, c->coef(), u, c->b, c->rho, st));
+  void* const bv = sb ? sb->b : c->b;
+  HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, c->tiling, c->coef(), u, bv, c->rho, st));
   if (c->algo == EXPINT_ALGO_MODAL) return modal_phi1(c, c->b, u, true);
   if (c->scheme == EXPINT_SCHEME_EXPRK2) {
     // stage 1: X = tau phi1(tau A) b; d = f(u + X) - f(u); stage 2 adds
@@ -207,12 +210,12 @@ int enqueue_step_on(expint_ctx* c, void* u, hipStream_t st) {
     HIP_TRY(c, launch_reaction_increment(c->dtype, c->g.n, c->rho, u, c->stage, c->dvec, c->stream));
     return run_ops(c, phi1_schedule(step_buffers(c), c->s, c->m, c->tau, c->b, nullptr, u, c->dvec));
   }
-  std::vector<TermOp> ops = step_schedule(c, c->b, nullptr, u);
+  std::vector<TermOp> ops = step_schedule(c, bv, nullptr, u, sb);
   if (c->scheme == EXPINT_SCHEME_LINEARISED) set_linearised(ops, u, c->rho);
   return run_ops(c, ops, st);
 }
 
-int enqueue_step(expint_ctx* c, void* u) { return enqueue_step_on(c, u, c->stream); }
+int enqueue_step(expint_ctx* c, void* u) { return enqueue_step_on(c, u, c->stream, nullptr); }
 
 int check_finite_field(expint_ctx* c, const void* u) {
   HIP_TRY(c, launch_reduce(c->dtype, 3, u, nullptr, c->g.n, c->partial, c->red, c->stream));
@@ -539,7 +542,7 @@ int expint_phi1(expint_ctx* c, const void* b, void* x) {
   int rc = ensure_device(c);
   if (rc) return rc;
   if (c->algo == EXPINT_ALGO_MODAL) return modal_phi1(c, b, x, false);
-  return run_ops(c, step_schedule(c, b, x, nullptr));
+  return run_ops(c, step_schedule(c, b, x, nullptr, nullptr));
 }
 
 int expint_phi12(expint_ctx* c, const void* b, const void* d, void* x) {
@@ -561,7 +564,7 @@ int expint_phi1_lin(expint_ctx* c, const void* u, const void* b, void* x) {
   if (b == x || u == x) return set_error(EXPINT_EINVAL, "x must overlap neither u nor b");
   int rc = ensure_device(c);
   if (rc) return rc;
-  std::vector<TermOp> ops = step_schedule(c, b, x, nullptr);
+  std::vector<TermOp> ops = step_schedule(c, b, x, nullptr, nullptr);
   set_linearised(ops, u, c->rho);
   return run_ops(c, ops);
 }

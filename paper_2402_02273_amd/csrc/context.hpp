@@ -129,9 +129,10 @@ struct expint_ctx {
     hipEvent_t ev_tape[2] = {nullptr, nullptr};  // tape set p written
     hipEvent_t ev_rev[2] = {nullptr, nullptr};   // tape set p no longer read
     // Two segment-state sets: the states of segment k - 1 are recomputed on
-    // `rec` (with the context's step buffers, which nothing else uses after
-    // the forward pass) while segment k reverses.
+    // `rec`, with step buffers of its own, while segment k reverses (the
+    // first of them while the forward pass still runs).
     std::vector<void*> segs2;                    // second set, like segs
+    void* rb[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // rec's step buffers: b, y0, y1, acc0, acc1
     hipStream_t rec = nullptr;
     hipEvent_t ev_fwd = nullptr;                 // forward pass with checkpoints done
     hipEvent_t ev_seg[2] = {nullptr, nullptr};   // segment-state set q recomputed
@@ -188,14 +189,14 @@ double harmonic_mean(double a, double b);
 int ensure_device(expint_ctx* c);
 int upload_tables(expint_ctx* c);
 int enqueue_step(expint_ctx* c, void* u);
-int enqueue_step_on(expint_ctx* c, void* u, hipStream_t st);
+int enqueue_step_on(expint_ctx* c, void* u, hipStream_t st, const StepBuffers* sb);
 // nsteps steps on the stream: replays (recording on first use) the step graph
 // for u, or launches each step when graphs are off.  No synchronisation.
 int run_steps(expint_ctx* c, void* u, int32_t nsteps);
 int run_ops(expint_ctx* c, const std::vector<TermOp>& ops);
 // The Taylor sweeps of tau phi1(tau A) b for this context's plan: pair sweeps
 // when the context uses them, else one sweep per term (see phi1_schedule).
-std::vector<TermOp> step_schedule(expint_ctx* c, const void* b, void* x_out, void* u);
+std::vector<TermOp> step_schedule(expint_ctx* c, const void* b, void* x_out, void* u, const StepBuffers* sb);
 // ||A||_1 for EXP_EULER, ||A||_1 + rho (a bound on ||J_n||_1) for LINEARISED.
 double plan_norm(const expint_ctx* c);
 int check_finite_field(expint_ctx* c, const void* u);
