@@ -216,6 +216,16 @@ __global__ __launch_bounds__(256) void k_mode(ModalArgs a) {
           accx = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, accx, 0, 0, 0);
         }
       }
+    } else if constexpr (PREC == kPrecF32) {
+      // FP32 on the matrix cores: v_mfma_f32_32x32x2_f32, lane l holding
+      // A[l % 32][k + l / 32] and B[k + l / 32][l % 32]; FP32 products and sums
+      const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+#pragma unroll
+      for (int ks = 0; ks < KC; ks += 2) {
+        const float av = s.a_hi[wm + (lane & 31)][ks + (lane >> 5)];
+        const float bv = s.b_hi[wn + (lane & 31)][ks + (lane >> 5)];
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+      }
     } else {
       const int rm = (threadIdx.x >> 4) * 4, rn = (threadIdx.x & 15) * 4;
 #pragma unroll 8
@@ -254,9 +264,9 @@ __global__ __launch_bounds__(256) void k_mode(ModalArgs a) {
       else out[idx] = v;
     }
   };
-  if (is_split<PREC>()) {
+  if (is_split<PREC>() || PREC == kPrecF32) {
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    const float xs = PREC == kPrecF16 ? 1.0f / kF16LoScale : 1.0f;
+    const float xs = PREC == kPrecF16 ? 1.0f / kF16LoScale : (PREC == kPrecF32 ? 0.0f : 1.0f);  // F32: no accx
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int row = wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
