@@ -393,7 +393,8 @@ def run_c3(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            # per step, like achieved: the counters cover the exp_euler batch
+            "traffic": None if lin else load_traffic("batch_c3_step_f32", "k_batch"),
             "bytes_per_step": step_bytes,
         },
     }
@@ -541,7 +542,7 @@ def run_c5(args):
             "peak": HBM_PEAK_GBS if intensity < ridge else peaks[head],
             "unit": "GB/s" if intensity < ridge else "TFLOP/s",
             "frac": x["GBs"] / HBM_PEAK_GBS if intensity < ridge else x["executed_TFLOPs"] / peaks[head],
-            "traffic": None,
+            "traffic": load_traffic(f"gemm_fp16_x_{n}", "k_mode_gemm"),
             "intensity_flop_per_byte": intensity,
             "ridge_flop_per_byte": ridge,
             "mfma_TFLOPs_executed": x["executed_TFLOPs"],
