@@ -237,3 +237,28 @@ def test_adjoint_vec_fused_face_products(native, vec_env, scheme, bc, sm, class_
         for c in range(len(class_D)):
             assert abs(gD_g[c] - ref_D[c]) <= tol * scale, (dtype, c, gD_g[c], ref_D[c])
         del ctx
+
+
+@pytest.mark.parametrize("scheme", ["exp_euler", "linearised"])
+@pytest.mark.parametrize("bc", ["noflux", "dirichlet0"])
+def test_adjoint_vec_fused_segment_edges(native, vec_env, scheme, bc):
+    # nz = 264: 66 four-voxel vectors per row, so the 64-lane z-segments of
+    # the default shape end inside a row; the +z face of a segment's last lane
+    # then comes from a load, not a shuffle (the fused face products included)
+    shape = (3, 5, 264)
+    class_D = (0.02, 0.13, 0.013)
+    labels = random_labels(shape, len(class_D), seed=77)
+    u0 = random_field(shape, seed=78)
+    gout = random_field(shape, seed=79, lo=-1, hi=1)
+    rho, tau, K, sm = 0.02, 3.0, 2, (2, 4)
+    op = oop.Operator(1.0, bc=bc, labels=labels, class_D=class_D)
+    gu, grho, gD = oadj.vjp(op, u0, rho, tau, sm[0], sm[1], K, gout, 1, classes=[0, 1, 2], scheme=scheme)
+    scale = max(abs(gD[c]) for c in range(3))
+    for dtype, tol in [(torch.float64, 1e-10), (torch.float32, 2e-5)]:
+        ctx = make_ctx(labels, class_D, dtype, rho=rho, tau=tau, bc=bc, s=sm[0], m=sm[1], scheme=scheme)
+        gu_g, grho_g, gD_g = ctx.vjp(dev(u0, dtype), K, dev(gout, dtype), ckpt_every=1)
+        assert rel_l2(gu_g.cpu().numpy(), gu) < tol
+        assert grho_g == pytest.approx(grho, rel=tol)
+        for c in range(3):
+            assert abs(gD_g[c] - gD[c]) <= tol * scale, (dtype, c, gD_g[c], gD[c])
+        del ctx
