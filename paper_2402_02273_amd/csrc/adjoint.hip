@@ -327,12 +327,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep_face4(Geom g, int gzs, int gy,
     __syncthreads();
   };
   FaceAcc<T, BC, NC, KIND == kTermJ> face(g, ft, j, k4, kq, rw, dbar, static_cast<T>(weight));
-  if (j < g.ny && k4 < (g.nz >> 2)) {
-    face.load(y, i0);
-    sweep_column4<T, BC, 1, KIND, kGeneric, false>(g, cf.labels, s, a, i0, j, k4, kq, rw, ready, face);
-  } else {
-    ready();
-  }
+  const bool live = j < g.ny && k4 < (g.nz >> 2);
+  if (live) face.load(y, i0);
+  sweep_column4<T, BC, 1, KIND, kGeneric, false>(g, cf.labels, s, a, i0, j, k4, kq, rw, live, ready, face);
   block_accumulate(face.acc, weight, partial);
 }
 

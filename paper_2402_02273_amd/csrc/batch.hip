@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchItem* __restrict__ 
         a.out = it.op.y_out;
         a.rho = it.rho;
       }
-      if (it.vec) sweep_column4<T, BC, LP, KIND, FL>(g, it.labels, st[lo], a, i0, j, k, kq, it.bx);
+      if (it.vec) sweep_column4<T, BC, LP, KIND, FL>(g, it.labels, st[lo], a, i0, j, k, kq, it.bx, true);
       else sweep_column<T, BC, LP, KIND, FL>(g, cf, st[lo], a, i0, j, k, LP);
     }
   }

@@ -295,11 +295,16 @@ struct NoFace {
 
 // The sweep of one lane: vector k4 (voxels 4 k4 .. 4 k4 + 3) of row j,
 // planes i0 .. i0 + LP - 1 (clipped to the grid); kq is the lane's index in
-// its z-segment of rw lanes.  Lanes outside the grid need not call this: a
-// lane only uses a neighbour's shuffled values when that neighbour is in the
-// same row and inside the grid (else the wall or segment-edge value).
+// its z-segment of rw lanes.  live: the lane's vector is inside the grid.
+// Every lane of the workgroup calls this; a lane that is not live issues no
+// loads or stores and returns after ready(), and a live lane only uses a
+// neighbour's shuffled values when that neighbour is in the same row and
+// inside the grid (else the wall or segment-edge value).
 // ready() runs after the first plane's loads are issued and before the class
-// table is read: a caller that stages the table there overlaps the two.
+// table is read, in control flow that every lane of the workgroup reaches: a
+// caller that stages the table there with a workgroup barrier overlaps the
+// two (a barrier reached on two divergent paths of one wave would be passed
+// twice by that wave and pair with a later barrier of the others).
 // face(i, q, xc, xn, xy, xz, lc, ln, ly, lz) runs once per plane with the
 // source values the stencil holds: the lane's four voxels, their +x and +y
 // neighbours, the +z neighbour of the last voxel, and the matching labels
@@ -308,7 +313,7 @@ template <typename T, int BC, int LP, int KIND, int FL, bool NT = false, typenam
           typename Face = NoFace>
 __device__ __forceinline__ void sweep_column4(const Geom& g, const uint8_t* lab, const LdsCoef<T>& s,
                                               const SweepArgs& a, int i0, int j, int k4, int kq, int rw,
-                                              Ready&& ready = Ready{}, Face&& face = Face{}) {
+                                              bool live, Ready&& ready = Ready{}, Face&& face = Face{}) {
   const int nz4 = g.nz >> 2;
   const int sx4 = g.ny * nz4;
   const int dym = j > 0 ? -nz4 : 0, dyp = j < g.ny - 1 ? nz4 : 0;
@@ -318,13 +323,12 @@ __device__ __forceinline__ void sweep_column4(const Geom& g, const uint8_t* lab,
   const T* __restrict__ x = static_cast<const T*>(is_term(KIND) ? a.op.src : a.x);
   const uint32_t* __restrict__ l4 = reinterpret_cast<const uint32_t*>(lab);
   int q = (i0 * g.ny + j) * nz4 + k4;
-  const int qm0 = i0 > 0 ? q - sx4 : q;
-  Vec4<T> xm = ld4<T>(x, qm0), xc = ld4<T>(x, q);
-  uint32_t lm = l4[qm0], lc = l4[q];
+  Vec4<T> xm, xc;
+  uint32_t lm = 0, lc = 0;
   // loads of the plane computed next: +x neighbour, lateral neighbours
   // (kTermJ: and u_n of the plane itself)
   Vec4<T> fxn, fya, fyb, fun;
-  uint32_t fln, fla, flb;
+  uint32_t fln = 0, fla = 0, flb = 0;
   auto fetch = [&](int i, int qq) {
     const int qn = i < g.nx - 1 ? qq + sx4 : qq;
     fxn = ld4<T>(x, qn);
@@ -335,8 +339,16 @@ __device__ __forceinline__ void sweep_column4(const Geom& g, const uint8_t* lab,
     flb = l4[qq + dyp];
     if (KIND == kTermJ) fun = ld4<T>(a.op.ju, qq);
   };
-  fetch(i0, q);
+  if (live) {
+    const int qm0 = i0 > 0 ? q - sx4 : q;
+    xm = ld4<T>(x, qm0);
+    xc = ld4<T>(x, q);
+    lm = l4[qm0];
+    lc = l4[q];
+    fetch(i0, q);
+  }
   ready();
+  if (!live) return;
 #pragma unroll
   for (int sp = 0; sp < LP; ++sp) {
     const int i = i0 + sp;

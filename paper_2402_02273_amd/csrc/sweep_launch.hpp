@@ -48,11 +48,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep4(Geom g, int gzs, int gy, int 
     load_tables(s, cf, tid, kBlock);
     __syncthreads();
   };
-  if (j >= g.ny || k4 >= (g.nz >> 2)) {
-    ready();
-    return;
-  }
-  sweep_column4<T, BC, LP, KIND, FL, NT>(g, cf.labels, s, a, i0, j, k4, kq, rw, ready);
+  const bool live = j < g.ny && k4 < (g.nz >> 2);
+  sweep_column4<T, BC, LP, KIND, FL, NT>(g, cf.labels, s, a, i0, j, k4, kq, rw, live, ready);
 }
 
 template <typename T, int BC, int KIND, int FL>

@@ -262,3 +262,46 @@ def test_adjoint_vec_fused_segment_edges(native, vec_env, scheme, bc):
         for c in range(3):
             assert abs(gD_g[c] - gD[c]) <= tol * scale, (dtype, c, gD_g[c], gD[c])
         del ctx
+
+
+@pytest.mark.parametrize("rw", [16, 32])
+@pytest.mark.parametrize("scheme", ["exp_euler", "linearised"])
+@pytest.mark.parametrize("bc", ["noflux", "dirichlet0"])
+def test_waves_with_rows_past_the_grid(native, monkeypatch, tmp_path, rw, scheme, bc):
+    # rw = 16 or 32 packs 4 or 2 rows into a wave; with ny = 5 one wave of each
+    # workgroup holds row 4 and rows past the grid, and nz / 4 = 66 leaves a
+    # partial last segment: the class-table barrier of the sweeps and the
+    # workgroup sums of the fused face products must still see every lane
+    from paper_2402_02273_amd.expint import ExpInt
+
+    shape = (3, 5, 264)
+    class_D = (0.02, 0.13, 0.013)
+    labels = random_labels(shape, len(class_D), seed=81)
+    u0 = random_field(shape, seed=82)
+    gout = random_field(shape, seed=83, lo=-1, hi=1)
+    rho, tau, K, sm = 0.02, 3.0, 2, (2, 4)
+    op = oop.Operator(1.0, bc=bc, labels=labels, class_D=class_D)
+    mod = {"exp_euler": oit, "linearised": orb}[scheme]
+    ref = mod.advance(op, u0, rho, tau, sm[0], sm[1], K)
+    gu, grho, gD = oadj.vjp(op, u0, rho, tau, sm[0], sm[1], K, gout, 1, classes=[0, 1, 2], scheme=scheme)
+    scale = max(abs(gD[c]) for c in range(3))
+    bcode = 0 if bc == "noflux" else 1
+    for dtype, tol in [(torch.float64, 1e-10), (torch.float32, 2e-5)]:
+        dt = 1 if dtype == torch.float32 else 0
+        path = tmp_path / f"tune_{dt}.txt"
+        path.write_text(f"sweep 3 5 264 {dt} {bcode} 7 0 0 1 1 {rw} 0\npair 3 5 264 {dt} {bcode} 0 0 8\n")
+        monkeypatch.setenv("EXPINT_TUNE_FILE", str(path))
+        ctx = ExpInt(shape, labels=labels, class_D=class_D, dtype=dtype, device=DEV, sweeps="single", rho=rho,
+                     tau=tau, bc=bc, s=sm[0], m=sm[1], scheme=scheme)
+        info = ctx.launch_info()
+        print(f"[case] rw={rw} {scheme} {bc} {dtype} launch={info}", flush=True)
+        assert (info["vec"], info["rw"], info["lp"]) == (1, rw, 1)
+        u = dev(u0, dtype)
+        ctx.advance(u, K)
+        assert rel_l2(u.cpu().numpy(), ref) < tol
+        gu_g, grho_g, gD_g = ctx.vjp(dev(u0, dtype), K, dev(gout, dtype), ckpt_every=1)
+        assert rel_l2(gu_g.cpu().numpy(), gu) < tol
+        assert grho_g == pytest.approx(grho, rel=tol)
+        for c in range(3):
+            assert abs(gD_g[c] - gD[c]) <= tol * scale, (dtype, c, gD_g[c], gD[c])
+        del ctx
