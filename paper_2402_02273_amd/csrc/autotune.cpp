@@ -286,36 +286,48 @@ hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Co
     }
   }
   // Store policy of the chosen vector shape: non-temporal output stores
-  // finish a sweep sooner where its fields are re-read from the Infinity
-  // Cache or HBM by the next sweep anyway; kept when at least 2% faster over
-  // a skip and a flush sweep (the two term flavours of the schedule).
+  // finish a sweep sooner, but whether the step gains depends on how the next
+  // sweep then reads those terms back.  So it is timed on a dependent chain
+  // as in a step: a skip sweep writes a term, a flush sweep reads it as its
+  // source.  Non-temporal stores are kept when at least 2% faster, on the
+  // best of three alternating rounds (one short timing can lose a difference
+  // of a few percent in noise).
   if (best_t.vec) {
-    TermOp skip;
+    TermOp skip;  // f0 -> f2
     skip.src = f0;
     skip.y_out = f2;
     skip.c = 0.5;
     classify_term(skip);
-    // three alternating rounds, the best round of each policy: a single short
-    // timing can lose a difference of a few percent in noise
+    TermOp flush;  // source f2, sum f1, term -> f0
+    flush.src = f2;
+    flush.acc_in = f1;
+    flush.ca = 1.0;
+    flush.cs = 1.0;
+    flush.acc_out = f1;
+    flush.y_out = f0;
+    flush.c = 0.5;
+    classify_term(flush);
     const int reps_pol = std::max(reps, 16);
     float t_pol[2] = {-1.f, -1.f};
     for (int round = 0; round < 3; ++round) {
       for (int nt = 0; nt < 2; ++nt) {
         Tiling t = best_t;
         t.nt = nt;
-        float a = 0.f, b = 0.f;
-        if ((e = time_launches([&] { return launch_term(dt, bc, g, t, cf, op, st); }, reps_pol, st, &a)) !=
-            hipSuccess)
+        if ((e = launch_fill(dt, g.n, 0.25, f0, st)) != hipSuccess) return e;
+        float ms = 0.f;
+        if ((e = time_launches(
+                 [&] {
+                   const hipError_t r = launch_term(dt, bc, g, t, cf, skip, st);
+                   return r != hipSuccess ? r : launch_term(dt, bc, g, t, cf, flush, st);
+                 },
+                 reps_pol, st, &ms)) != hipSuccess)
           return e;
-        if ((e = time_launches([&] { return launch_term(dt, bc, g, t, cf, skip, st); }, reps_pol, st, &b)) !=
-            hipSuccess)
-          return e;
-        if (t_pol[nt] < 0.f || a + b < t_pol[nt]) t_pol[nt] = a + b;
+        if (t_pol[nt] < 0.f || ms < t_pol[nt]) t_pol[nt] = ms;
       }
     }
     best_t.nt = t_pol[1] < 0.98f * t_pol[0] ? 1 : 0;
     if (std::getenv("EXPINT_LOG"))
-      std::fprintf(stderr, "[expint] autotune store policy: flush+skip %.2f us plain, %.2f us non-temporal -> %s\n",
+      std::fprintf(stderr, "[expint] autotune store policy: skip -> flush chain %.2f us plain, %.2f us non-temporal -> %s\n",
                    t_pol[0] * 1000.f, t_pol[1] * 1000.f, best_t.nt ? "non-temporal" : "plain");
   }
   *out = best_t;
