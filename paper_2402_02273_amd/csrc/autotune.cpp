@@ -285,13 +285,17 @@ hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Co
       best_t = cands[i];
     }
   }
-  // Store policy of the chosen vector shape: non-temporal output stores
-  // finish a sweep sooner, but whether the step gains depends on how the next
-  // sweep then reads those terms back.  So it is timed on a dependent chain
-  // as in a step: a skip sweep writes a term, a flush sweep reads it as its
-  // source.  Non-temporal stores are kept when at least 2% faster, on the
-  // best of three alternating rounds (one short timing can lose a difference
-  // of a few percent in noise).
+  // Vector winner: the final choice of shape and store policy is timed on a
+  // dependent chain as in a step, a skip sweep writing a term and a flush
+  // sweep reading it back as its source.  The pass above times the flush
+  // flavour alone, but a step runs as many skip sweeps, and a shape or a
+  // store policy that helps one flavour can cost the other; non-temporal
+  // stores finish a sweep sooner, yet the next sweep then reads the term from
+  // further away.  Every vector shape within 10% of the best single sweep is
+  // a finalist, with plain and with non-temporal stores; best of three
+  // alternating rounds (one short timing can lose a difference of a few
+  // percent in noise).  Non-temporal stores must win by at least 2%.
+  float chain = -1.f;
   if (best_t.vec) {
     TermOp skip;  // f0 -> f2
     skip.src = f0;
@@ -307,12 +311,20 @@ hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Co
     flush.y_out = f0;
     flush.c = 0.5;
     classify_term(flush);
-    const int reps_pol = std::max(reps, 16);
-    float t_pol[2] = {-1.f, -1.f};
-    for (int round = 0; round < 3; ++round) {
+    std::vector<Tiling> fin;
+    for (size_t i = 0; i < cands.size(); ++i) {
+      if (!cands[i].vec || t_c[i] > 1.10f * best) continue;
       for (int nt = 0; nt < 2; ++nt) {
-        Tiling t = best_t;
+        Tiling t = cands[i];
         t.nt = nt;
+        fin.push_back(t);
+      }
+    }
+    const int reps_pol = std::max(reps, 16);
+    std::vector<float> t_f(fin.size(), -1.f);
+    for (int round = 0; round < 3; ++round) {
+      for (size_t k = 0; k < fin.size(); ++k) {
+        const Tiling& t = fin[k];
         if ((e = launch_fill(dt, g.n, 0.25, f0, st)) != hipSuccess) return e;
         float ms = 0.f;
         if ((e = time_launches(
@@ -322,19 +334,30 @@ hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Co
                  },
                  reps_pol, st, &ms)) != hipSuccess)
           return e;
-        if (t_pol[nt] < 0.f || ms < t_pol[nt]) t_pol[nt] = ms;
+        if (t_f[k] < 0.f || ms < t_f[k]) t_f[k] = ms;
       }
     }
-    best_t.nt = t_pol[1] < 0.98f * t_pol[0] ? 1 : 0;
+    float best_e = -1.f;
+    for (size_t k = 0; k < fin.size(); ++k) {
+      const float eff = fin[k].nt ? t_f[k] / 0.98f : t_f[k];
+      if (best_e < 0.f || eff < best_e) {
+        best_e = eff;
+        best_t = fin[k];
+        chain = t_f[k];
+      }
+    }
     if (std::getenv("EXPINT_LOG"))
-      std::fprintf(stderr, "[expint] autotune store policy: skip -> flush chain %.2f us plain, %.2f us non-temporal -> %s\n",
-                   t_pol[0] * 1000.f, t_pol[1] * 1000.f, best_t.nt ? "non-temporal" : "plain");
+      for (size_t k = 0; k < fin.size(); ++k)
+        std::fprintf(stderr, "[expint] autotune skip -> flush chain: rw=%d lp=%d nt=%d %.2f us\n", fin[k].rw,
+                     fin[k].lp, fin[k].nt, t_f[k] * 1000.f);
   }
   *out = best_t;
   if (std::getenv("EXPINT_LOG")) {
     if (best_t.vec)
-      std::fprintf(stderr, "[expint] autotune %dx%dx%d %s: vector sweep rw=%d lp=%d nt=%d (%.2f us/sweep)\n", g.nx,
-                   g.ny, g.nz, dt == EXPINT_F64 ? "f64" : "f32", best_t.rw, best_t.lp, best_t.nt, best * 1000.f);
+      std::fprintf(stderr,
+                   "[expint] autotune %dx%dx%d %s: vector sweep rw=%d lp=%d nt=%d (%.2f us per skip -> flush chain)\n",
+                   g.nx, g.ny, g.nz, dt == EXPINT_F64 ? "f64" : "f32", best_t.rw, best_t.lp, best_t.nt,
+                   chain * 1000.f);
     else
       std::fprintf(stderr, "[expint] autotune %dx%dx%d %s: bx=%d by=%d lp=%d (%.2f us/sweep)\n", g.nx, g.ny, g.nz,
                    dt == EXPINT_F64 ? "f64" : "f32", best_t.bx, best_t.by, best_t.lp, best * 1000.f);

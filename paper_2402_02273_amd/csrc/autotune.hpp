@@ -11,11 +11,12 @@ namespace expint {
 // boundary and coefficient form on `st` -- (bx, lp) of the scalar sweep and,
 // if allow_vec and the grid qualifies, (rw, lp) of the z-vectorised sweep --
 // using the three scratch fields (each g.n values of dtype; their contents are
-// overwritten), and returns the fastest.  For a z-vectorised winner it also
-// times plain against non-temporal output stores of the Taylor terms on a
-// dependent pair (a skip sweep writes a term, a flush sweep reads it back;
-// best of three alternating rounds) and keeps non-temporal ones if they are
-// at least 2% faster (Tiling::nt).
+// overwritten), and returns the fastest.  For a z-vectorised winner the final
+// choice is made on a dependent pair as in a step (a skip sweep writes a term,
+// a flush sweep reads it back): every vector shape within 10% of the best,
+// with plain and with non-temporal output stores of the Taylor terms (best of
+// three alternating rounds); non-temporal stores must be at least 2% faster
+// (Tiling::nt).
 // Results are cached per (grid, dtype, bc, form, candidate set) for the
 // process.  EXPINT_AUTOTUNE=0 in the
 // environment skips the search (default_tiling); EXPINT_TILE=scalar or vec
