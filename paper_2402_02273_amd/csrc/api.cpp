@@ -412,8 +412,9 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
     if ((rc = c->arena.alloc(&c->acc[i], fb))) return bail(rc);
   }
   {
+    const bool lin = c->scheme == EXPINT_SCHEME_LINEARISED;
     const hipError_t e = autotune_sweep(c->dtype, c->bc, c->g, c->coef(), c->y[0], c->acc[0], c->y[1], c->stream,
-                                        true, &c->tiling);
+                                        true, &c->tiling, lin ? c->acc[1] : nullptr, c->rho);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return bail(set_error(EXPINT_EHIP, "autotune failed: %s", hipGetErrorString(e)));

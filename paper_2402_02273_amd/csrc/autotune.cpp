@@ -198,7 +198,7 @@ hipError_t autotune_pairs(expint_dtype dt, expint_bc bc, const Geom& g, const Co
 }
 
 hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Coef& cf, void* f0, void* f1, void* f2,
-                          hipStream_t st, bool allow_vec, Tiling* out) {
+                          hipStream_t st, bool allow_vec, Tiling* out, void* ju, double jrho) {
   *out = default_tiling(g);
   // EXPINT_TILE=scalar / vec restricts the candidates to one sweep shape
   const char* shape = std::getenv("EXPINT_TILE");
@@ -216,7 +216,7 @@ hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Co
     return hipSuccess;
   }
   const Key key{g.nx, g.ny, g.nz, static_cast<int>(dt), static_cast<int>(bc),
-                (cf.labels_form ? 1 : 0) | (vec_ok ? 2 : 0) | (scalar_ok ? 4 : 0)};
+                (cf.labels_form ? 1 : 0) | (vec_ok ? 2 : 0) | (scalar_ok ? 4 : 0) | (ju ? 8 : 0)};
   {
     std::lock_guard<std::mutex> lk(g_mu);
     load_tune_file();
@@ -230,8 +230,11 @@ hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Co
   hipError_t e;
   if ((e = launch_fill(dt, g.n, 0.25, f0, st)) != hipSuccess) return e;
   if ((e = launch_fill(dt, g.n, 0.0, f1, st)) != hipSuccess) return e;
+  if (ju && (e = launch_fill(dt, g.n, 0.5, ju, st)) != hipSuccess) return e;
   // the flush sweep with a y output: the heaviest flavour of the schedule
   TermOp op;
+  op.ju = ju;
+  op.jrho = jrho;
   op.src = f0;
   op.acc_in = f1;
   op.ca = 1.0;
@@ -298,11 +301,15 @@ hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Co
   float chain = -1.f;
   if (best_t.vec) {
     TermOp skip;  // f0 -> f2
+    skip.ju = ju;
+    skip.jrho = jrho;
     skip.src = f0;
     skip.y_out = f2;
     skip.c = 0.5;
     classify_term(skip);
     TermOp flush;  // source f2, sum f1, term -> f0
+    flush.ju = ju;
+    flush.jrho = jrho;
     flush.src = f2;
     flush.acc_in = f1;
     flush.ca = 1.0;
@@ -314,7 +321,8 @@ hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Co
     std::vector<Tiling> fin;
     for (size_t i = 0; i < cands.size(); ++i) {
       if (!cands[i].vec || t_c[i] > 1.10f * best) continue;
-      for (int nt = 0; nt < 2; ++nt) {
+      // the linearised operator's sweeps always store plainly
+      for (int nt = 0; nt < (ju ? 1 : 2); ++nt) {
         Tiling t = cands[i];
         t.nt = nt;
         fin.push_back(t);

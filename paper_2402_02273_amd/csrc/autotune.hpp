@@ -22,8 +22,12 @@ namespace expint {
 // environment skips the search (default_tiling); EXPINT_TILE=scalar or vec
 // restricts the candidates to one sweep shape; EXPINT_TUNE_FILE=path keeps
 // the choices in a text file that later processes read instead of timing.
+// ju (n values of dtype, overwritten) selects the Taylor sweeps of the
+// linearised operator J = A + jrho diag(1 - 2 ju) instead, which a linearised
+// step runs: those read u_n as well and keep plain stores, so they are tuned
+// apart (their own cache and tuning-file key: flags bit 8).
 hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Coef& cf, void* f0, void* f1, void* f2,
-                          hipStream_t st, bool allow_vec, Tiling* out);
+                          hipStream_t st, bool allow_vec, Tiling* out, void* ju = nullptr, double jrho = 0.0);
 
 // Decides whether the step takes its Taylor terms two at a time (pair
 // sweeps, label form only) and with which tiling.  mode SINGLE: never (ty = 0

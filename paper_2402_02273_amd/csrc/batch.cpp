@@ -148,8 +148,9 @@ int setup_instance(expint_batch* b, Inst& in, const uint8_t* labels_src) {
   BHIP(hipStreamSynchronize(b->stream));  // also retires the host-array copies above
   if (out[1] != 0.0) return set_error(EXPINT_EINVAL, "a label is >= n_classes (%d)", in.nclass);
   in.norm1 = out[0];
+  const bool lin = b->scheme == EXPINT_SCHEME_LINEARISED;
   BHIP(autotune_sweep(b->dtype, b->bc, in.g, in.coef(), in.ws.y[0], in.ws.acc[0], in.ws.y[1], b->stream, true,
-                      &in.tiling));
+                      &in.tiling, lin ? in.ws.acc[1] : nullptr, in.rho));
   return EXPINT_OK;
 }
 

@@ -154,8 +154,8 @@ def test_tune_file_pins_launch_shapes(native, monkeypatch, tmp_path):
     from paper_2402_02273_amd.expint import ExpInt
 
     path = tmp_path / "tune.txt"
-    # key: nx ny nz dtype(F32 = 1) bc(no-flux = 0) flags(label form 1 | vector ok 2 | scalar ok 4),
-    # then bx by lp vec rw nt
+    # key: nx ny nz dtype(F32 = 1) bc(no-flux = 0) flags(label form 1 | vector ok 2 | scalar ok 4 |
+    # linearised step 8), then bx by lp vec rw nt
     path.write_text("sweep 20 24 36 1 0 7 32 8 2 0 64 0\npair 20 24 36 1 0 0 0 8\n")
     monkeypatch.setenv("EXPINT_TUNE_FILE", str(path))
     w = make_ragged((20, 24, 36), seed=2)
@@ -189,7 +189,9 @@ def test_non_temporal_stores_change_nothing(native, monkeypatch, tmp_path, schem
     outs = []
     for nt in (0, 1):
         path = tmp_path / f"tune{nt}.txt"
-        path.write_text(f"sweep 20 24 36 {dt} 0 7 0 0 1 1 16 {nt}\npair 20 24 36 {dt} 0 0 0 8\n")
+        # flags 7, and 15 for the linearised step, whose sweeps are tuned apart
+        fl = 15 if scheme == "linearised" else 7
+        path.write_text(f"sweep 20 24 36 {dt} 0 {fl} 0 0 1 1 16 {nt}\npair 20 24 36 {dt} 0 0 0 8\n")
         monkeypatch.setenv("EXPINT_TUNE_FILE", str(path))
         ctx = ExpInt(w.shape, labels=w.labels, class_D=w.class_D, rho=w.rho, tau=w.tau, dtype=dtype, device=DEV,
                      scheme=scheme)
@@ -289,7 +291,8 @@ def test_waves_with_rows_past_the_grid(native, monkeypatch, tmp_path, rw, scheme
     for dtype, tol in [(torch.float64, 1e-10), (torch.float32, 2e-5)]:
         dt = 1 if dtype == torch.float32 else 0
         path = tmp_path / f"tune_{dt}.txt"
-        path.write_text(f"sweep 3 5 264 {dt} {bcode} 7 0 0 1 1 {rw} 0\npair 3 5 264 {dt} {bcode} 0 0 8\n")
+        fl = 15 if scheme == "linearised" else 7
+        path.write_text(f"sweep 3 5 264 {dt} {bcode} {fl} 0 0 1 1 {rw} 0\npair 3 5 264 {dt} {bcode} 0 0 8\n")
         monkeypatch.setenv("EXPINT_TUNE_FILE", str(path))
         ctx = ExpInt(shape, labels=labels, class_D=class_D, dtype=dtype, device=DEV, sweeps="single", rho=rho,
                      tau=tau, bc=bc, s=sm[0], m=sm[1], scheme=scheme)
@@ -338,7 +341,8 @@ def test_every_tiling_same_step(native, monkeypatch, tmp_path, shape, scheme):
     plan = None
     for i, (bx, by, lp, vec, rw, nt) in enumerate(_tilings()):
         path = tmp_path / f"tune{i}.txt"
-        path.write_text(f"sweep {nx} {ny} {nz} 1 1 7 {bx} {by} {lp} {vec} {rw} {nt}\npair {nx} {ny} {nz} 1 1 0 0 8\n")
+        fl = 15 if scheme == "linearised" else 7
+        path.write_text(f"sweep {nx} {ny} {nz} 1 1 {fl} {bx} {by} {lp} {vec} {rw} {nt}\npair {nx} {ny} {nz} 1 1 0 0 8\n")
         monkeypatch.setenv("EXPINT_TUNE_FILE", str(path))
         ctx = ExpInt(shape, labels=labels, class_D=class_D, dtype=torch.float32, device=DEV, sweeps="single",
                      rho=rho, tau=tau, bc="dirichlet0", scheme=scheme)
