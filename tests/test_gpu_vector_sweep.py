@@ -323,9 +323,10 @@ def _tilings():
     return out
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 @pytest.mark.parametrize("scheme", ["exp_euler", "linearised"])
 @pytest.mark.parametrize("shape", [(3, 5, 264), (5, 7, 12), (9, 13, 68)])
-def test_every_tiling_same_step(native, monkeypatch, tmp_path, shape, scheme):
+def test_every_tiling_same_step(native, monkeypatch, tmp_path, shape, scheme, dtype):
     # the tuned shape differs from one machine to the next, so each one is
     # pinned here through a tuning file: a step is bit-identical over all
     # z-vectorised shapes and over all scalar shapes, and both match the oracle
@@ -342,15 +343,17 @@ def test_every_tiling_same_step(native, monkeypatch, tmp_path, shape, scheme):
     for i, (bx, by, lp, vec, rw, nt) in enumerate(_tilings()):
         path = tmp_path / f"tune{i}.txt"
         fl = 15 if scheme == "linearised" else 7
-        path.write_text(f"sweep {nx} {ny} {nz} 1 1 {fl} {bx} {by} {lp} {vec} {rw} {nt}\npair {nx} {ny} {nz} 1 1 0 0 8\n")
+        dt = 1 if dtype == torch.float32 else 0
+        path.write_text(f"sweep {nx} {ny} {nz} {dt} 1 {fl} {bx} {by} {lp} {vec} {rw} {nt}\n"
+                        f"pair {nx} {ny} {nz} {dt} 1 0 0 8\n")
         monkeypatch.setenv("EXPINT_TUNE_FILE", str(path))
-        ctx = ExpInt(shape, labels=labels, class_D=class_D, dtype=torch.float32, device=DEV, sweeps="single",
+        ctx = ExpInt(shape, labels=labels, class_D=class_D, dtype=dtype, device=DEV, sweeps="single",
                      rho=rho, tau=tau, bc="dirichlet0", scheme=scheme)
         info = ctx.launch_info()
-        print(f"[case] {shape} {scheme} tiling={(bx, by, lp, vec, rw, nt)} launch={info}", flush=True)
+        print(f"[case] {shape} {scheme} {dtype} tiling={(bx, by, lp, vec, rw, nt)} launch={info}", flush=True)
         assert (info["vec"], info["lp"]) == (vec, lp)
         assert (info["rw"] if vec else info["bx"]) == (rw if vec else bx)
-        u = dev(u0, torch.float32)
+        u = dev(u0, dtype)
         ctx.advance(u, K)
         outs[vec].append(u.cpu().numpy())
         plan = (ctx.plan.s, ctx.plan.m)
@@ -360,5 +363,6 @@ def test_every_tiling_same_step(native, monkeypatch, tmp_path, shape, scheme):
             assert np.array_equal(o, outs[vec][0]), vec
     mod = {"exp_euler": oit, "linearised": orb}[scheme]
     ref = mod.advance(op, u0, rho, tau, plan[0], plan[1], K)
+    tol = 1e-5 if dtype == torch.float32 else 1e-12
     for vec in (0, 1):
-        assert rel_l2(outs[vec][0], ref) < 1e-5, vec
+        assert rel_l2(outs[vec][0], ref) < tol, vec
