@@ -200,3 +200,37 @@ def test_small_batch_linearised_vs_oracle(native, dtype, tol):
         v = dev(inst["u0"], dtype)
         single.advance(v, K)
         assert rel(us[i].cpu().numpy(), v.double().cpu().numpy()) < (1e-14 if dtype == torch.float64 else 1e-6)
+
+
+def test_batch_mixed_pinned_shapes_vs_oracle(native, monkeypatch, tmp_path):
+    # each instance pinned to a different sweep shape and plane count through
+    # a tuning file: the batch splits its launches by plane count and mixes
+    # the scalar and z-vectorised shapes inside a launch
+    from paper_2402_02273_amd.expint import ExpIntBatch
+
+    shapes = [(9, 10, 12), (6, 33, 68), (17, 5, 264), (12, 12, 20)]
+    # bx by lp vec rw nt per shape
+    tiles = [(16, 16, 2, 0, 64, 0), (0, 0, 2, 1, 16, 1), (0, 0, 4, 1, 32, 0), (0, 0, 1, 1, 64, 0)]
+    insts = []
+    for i, shape in enumerate(shapes):
+        labels = random_labels(shape, 3, seed=170 + i)
+        insts.append({"labels": labels, "class_D": (0.0, 0.1 + 0.02 * i, 0.01), "rho": 0.02,
+                      "u0": random_field(shape, seed=180 + i) * (labels != 0)})
+    tau = 7.3
+    for dtype, tol in ((torch.float64, 1e-10), (torch.float32, 1e-5)):
+        dt = 1 if dtype == torch.float32 else 0
+        path = tmp_path / f"tune{dt}.txt"
+        lines = [f"sweep {nx} {ny} {nz} {dt} 0 7 " + " ".join(map(str, t)) for (nx, ny, nz), t in zip(shapes, tiles)]
+        path.write_text("\n".join(lines) + "\n")
+        monkeypatch.setenv("EXPINT_TUNE_FILE", str(path))
+        print(f"[case] batch pinned shapes {dtype}", flush=True)
+        b = ExpIntBatch(insts, tau=tau, dtype=dtype, device=DEV)
+        # every instance found its line: nothing was timed and appended
+        assert path.read_text().splitlines() == lines
+        us = [dev(i["u0"], dtype) for i in insts]
+        b.advance(us, 2)  # records the graph
+        b.advance(us, 1)  # replays it
+        for i, inst in enumerate(insts):
+            ref, _ = oracle_run(inst, tau, 3)
+            assert rel(us[i].cpu().numpy(), ref) < tol, (dtype, i)
+        del b
