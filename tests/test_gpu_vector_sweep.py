@@ -366,3 +366,39 @@ def test_every_tiling_same_step(native, monkeypatch, tmp_path, shape, scheme, dt
     tol = 1e-5 if dtype == torch.float32 else 1e-12
     for vec in (0, 1):
         assert rel_l2(outs[vec][0], ref) < tol, vec
+
+
+@pytest.mark.parametrize("tile", [(0, 0, 2, 1, 32, 1), (0, 0, 4, 1, 16, 0), (32, 8, 2, 0, 64, 0)])
+@pytest.mark.parametrize("scheme", ["exp_euler", "linearised"])
+def test_gradient_with_pinned_planes_per_lane(native, monkeypatch, tmp_path, tile, scheme):
+    # the forward and tape sweeps follow the context's tiling (here 2 or 4
+    # planes per lane, vector or scalar) while the fused reverse sweeps take
+    # one plane per lane: the gradient must not depend on it
+    from paper_2402_02273_amd.expint import ExpInt
+
+    shape = (7, 6, 36)
+    class_D = (0.02, 0.13, 0.013)
+    labels = random_labels(shape, len(class_D), seed=191)
+    u0 = random_field(shape, seed=192)
+    gout = random_field(shape, seed=193, lo=-1, hi=1)
+    rho, tau, K, sm = 0.02, 3.0, 3, (2, 4)
+    op = oop.Operator(1.0, bc="dirichlet0", labels=labels, class_D=class_D)
+    gu, grho, gD = oadj.vjp(op, u0, rho, tau, sm[0], sm[1], K, gout, 2, classes=[0, 1, 2], scheme=scheme)
+    scale = max(abs(gD[c]) for c in range(3))
+    fl = 15 if scheme == "linearised" else 7
+    for dtype, tol in [(torch.float64, 1e-10), (torch.float32, 2e-5)]:
+        dt = 1 if dtype == torch.float32 else 0
+        path = tmp_path / f"tune_{dt}.txt"
+        path.write_text(f"sweep 7 6 36 {dt} 1 {fl} " + " ".join(map(str, tile)) + "\n")
+        monkeypatch.setenv("EXPINT_TUNE_FILE", str(path))
+        ctx = ExpInt(shape, labels=labels, class_D=class_D, dtype=dtype, device=DEV, sweeps="single", rho=rho,
+                     tau=tau, bc="dirichlet0", s=sm[0], m=sm[1], scheme=scheme)
+        info = ctx.launch_info()
+        print(f"[case] tile={tile} {scheme} {dtype} launch={info}", flush=True)
+        assert (info["vec"], info["lp"]) == (tile[3], tile[2])
+        gu_g, grho_g, gD_g = ctx.vjp(dev(u0, dtype), K, dev(gout, dtype), ckpt_every=2)
+        assert rel_l2(gu_g.cpu().numpy(), gu) < tol
+        assert grho_g == pytest.approx(grho, rel=tol)
+        for c in range(3):
+            assert abs(gD_g[c] - gD[c]) <= tol * scale, (dtype, c, gD_g[c], gD[c])
+        del ctx
