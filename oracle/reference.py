@@ -15,7 +15,10 @@ These do not use the Taylor scheme; they pin it:
 * ``modal_phi1`` - for uniform D on a box, A is a Kronecker sum of 1D
   operators whose eigenvectors are DCT-II (no-flux) or DST-I (zero Dirichlet)
   modes, so tau phi1(tau A) b is a diagonal scaling in that basis
-  (``scipy.fft.dctn/dstn`` with orthonormal scaling).
+  (``scipy.fft.dctn/dstn`` with orthonormal scaling);
+* ``modal_apply_A``, ``modal_expm``, ``modal_step``, ``modal_advance`` - the
+  operator, exp(t A), the exponential Euler step with the exact phi1 and its
+  repetition in the same basis.
 
 phi1(z) = (e^z - 1)/z is evaluated as expm1(z)/z with phi1(0) = 1 (section
 2.2 defines phi1 through A^{-1}(e^{tau A} - I); the series sum_k z^k/(k+1)!
@@ -62,11 +65,6 @@ def dense_phi1_paper_augmented(A, b, tau):
 def eigh_phi1(A, b, tau):
     lam, Q = np.linalg.eigh(A)
     return Q @ (tau * phi1_scalar(tau * lam) * (Q.T @ np.ravel(b)))
-
-
-def eigh_expm(A, v, t):
-    lam, Q = np.linalg.eigh(A)
-    return Q @ (np.exp(t * lam) * (Q.T @ np.ravel(v)))
 
 
 # ---------------------------------------------------------------------------
