@@ -151,18 +151,31 @@ def test_gpu_gradient_vs_central_differences(native):
     assert float((gu * v).sum()) == pytest.approx(rich(fu), rel=1e-7)
 
 
-def _golden_c4():
-    path = os.path.join(GOLDEN, "c4_adjoint_96_k50_f64.npz")
+def _golden_c4(target):
+    name = {"model": "c4m_adjoint_96_k50_f64.npz", "blob": "c4_adjoint_96_k50_f64.npz"}[target]
+    path = os.path.join(GOLDEN, name)
     if not os.path.exists(path):
-        pytest.skip("stored oracle gradient missing (tests/golden/make_golden.py c4)")
+        pytest.skip(f"stored oracle gradient missing ({name}, tests/golden/make_golden.py)")
     return np.load(path)
 
 
+@pytest.mark.parametrize("target_kind", ["model", "blob"])
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, 1e-4)])
-def test_c4_full_size_vs_stored_oracle(native, dtype, tol):
-    g = _golden_c4()
+def test_c4_full_size_vs_stored_oracle(native, dtype, tol, target_kind):
+    # model: the configured target, the forward model at the hidden
+    # parameters plus noise (stored with the oracle gradients); blob: a
+    # model-free target of the same size
+    g = _golden_c4(target_kind)
     w, _ = c4_adjoint()
-    target = c4_synthetic_target()
+    if target_kind == "model":
+        import hashlib
+
+        assert hashlib.sha256(w.labels.tobytes()).hexdigest() == str(g["labels_sha256"])
+        assert hashlib.sha256(w.u0.tobytes()).hexdigest() == str(g["u0_sha256"])
+        target = g["target"].astype(np.float64)
+    else:
+        target = c4_synthetic_target()
+    print(f"[case] c4 96^3 x50 {dtype} target={target_kind}", flush=True)
     ctx = make_ctx(w.labels, w.class_D, dtype, rho=w.rho, tau=w.tau)
     if dtype == torch.float64:
         assert (ctx.plan.s, ctx.plan.m) == (int(g["s"]), int(g["m"]))
@@ -170,7 +183,7 @@ def test_c4_full_size_vs_stored_oracle(native, dtype, tol):
     err_u = rel(gu.cpu().numpy(), g["grad_u0"])
     ref_D = {c: float(v) for c, v in enumerate(g["grad_D"])}
     print(
-        f"[result] c4 96^3 x50 {dtype}: loss {abs(loss - float(g['loss'])) / float(g['loss']):.2e} "
+        f"[result] c4 96^3 x50 {dtype} {target_kind}: loss {abs(loss - float(g['loss'])) / float(g['loss']):.2e} "
         f"grad_u0 {err_u:.2e} rho {abs(grho - float(g['grad_rho'])) / abs(float(g['grad_rho'])):.2e} "
         f"D {[abs(gD[c] - ref_D[c]) / max(abs(v) for v in ref_D.values()) for c in range(3)]}",
         flush=True,

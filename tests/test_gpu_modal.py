@@ -124,13 +124,17 @@ def test_c5_full_size_pure_diffusion_exact(native, dtype, mp, tol):
 def test_c5_full_size_one_step_elementwise(native):
     w = c5_separable()
     ref = oref.modal_step(w.u0, 0.1, 1.0, w.rho, w.tau)
-    for dtype, mp, tol in ((torch.float64, "none", 1e-13), (torch.float32, "bf16_split", 1e-5)):
+    for dtype, mp, tol in ((torch.float64, "none", 1e-13), (torch.float32, "bf16_split", 1e-5),
+                           (torch.float32, "fp16_split", 1e-6)):
         ctx = modal_ctx(w.shape, dtype, mp=mp, rho=w.rho, tau=w.tau)
         u = dev(w.u0, dtype)
         ctx.step(u)
-        err = rel(u.cpu().numpy(), ref)
-        print(f"[result] c5 256^3 one step {dtype} {mp}: rel-L2 {err:.2e}", flush=True)
+        got = u.cpu().numpy()
+        err = rel(got, ref)
+        emax = float(np.abs(got - ref).max() / np.abs(ref).max())
+        print(f"[result] c5 256^3 one step {dtype} {mp}: rel-L2 {err:.2e}, max-abs/max {emax:.2e}", flush=True)
         assert err < tol
+        assert emax < tol  # voxel by voxel, relative to the field's largest value
         ctx.close()
 
 
