@@ -31,6 +31,11 @@
  *  - A context is not thread-safe; use one context per stream.  After an
  *    EXPINT_EHIP failure the context is poisoned and every later call on it
  *    returns EXPINT_ESTATE (expint_destroy still works).
+ *  - Environment: EXPINT_MAX_BYTES=N caps the device memory of a context;
+ *    expint_create gives EXPINT_ENOMEM, before touching the device, when the
+ *    field buffers alone exceed it.  EXPINT_FAIL_NTH_HIP=N (for tests of the
+ *    error paths) makes a context created with it report its N-th checked
+ *    HIP call after creation as failed.
  */
 #ifndef EXPINT_H
 #define EXPINT_H

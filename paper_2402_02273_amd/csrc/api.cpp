@@ -341,6 +341,17 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
   }
 
   if (field_block_count(c->g) > (int64_t(1) << 31) - 1) return bail(set_error(EXPINT_EINVAL, "grid too large"));
+  {
+    // The field buffers every context needs (b, two terms, two running sums;
+    // the stage and increment of EXPRK2; the labels or the four dense face
+    // fields) against EXPINT_MAX_BYTES, before the device is touched.
+    const size_t fb = c->field_bytes();
+    size_t need = (c->scheme == EXPINT_SCHEME_EXPRK2 ? 7 : 5) * fb;
+    need += c->labels_form ? static_cast<size_t>(n) : 4 * fb;
+    if (c->arena.cap() && need > c->arena.cap())
+      return bail(set_error(EXPINT_ENOMEM, "the workspace needs at least %zu bytes, above EXPINT_MAX_BYTES=%zu", need,
+                            c->arena.cap()));
+  }
   if (hipGetDevice(&c->device) != hipSuccess) {
     (void)hipGetLastError();
     return bail(set_error(EXPINT_EHIP, "no HIP device"));
@@ -438,6 +449,7 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
                                                       : "exp-euler",
                  c->norm1, c->tau * plan_norm(c),
                  c->s, c->m, c->arena.bytes());
+  if (const char* f = std::getenv("EXPINT_FAIL_NTH_HIP")) c->fail_countdown = std::strtoll(f, nullptr, 10);
   *out = c;
   expint::clear_error();
   return EXPINT_OK;

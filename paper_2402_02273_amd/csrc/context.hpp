@@ -24,6 +24,8 @@ class Arena {
   // frees one allocation made by this arena (no-op for NULL)
   void release(void* p);
   size_t bytes() const { return bytes_; }
+  // the EXPINT_MAX_BYTES cap read at construction (0 = none)
+  size_t cap() const { return cap_; }
 
  private:
   std::vector<std::pair<void*, size_t>> ptrs_;
@@ -44,9 +46,14 @@ size_t dtype_size(expint_dtype dt);
 
 }  // namespace expint
 
+// A checked HIP call.  A context created with EXPINT_FAIL_NTH_HIP=N counts
+// its checked calls and reports the N-th one as failed (after making it), so
+// that the poisoned-context path can be driven from the host.
 #define HIP_TRY(ctxp, call)                                                                          \
   do {                                                                                               \
-    const hipError_t e_ = (call);                                                                    \
+    hipError_t e_ = (call);                                                                          \
+    if (e_ == hipSuccess && (ctxp)->fail_countdown > 0 && --(ctxp)->fail_countdown == 0)             \
+      e_ = hipErrorUnknown;                                                                          \
     if (e_ != hipSuccess) {                                                                          \
       (ctxp)->poisoned = true;                                                                       \
       return set_error(EXPINT_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
@@ -163,6 +170,7 @@ struct expint_ctx {
   std::vector<expint::GraphEntry> graphs;
   bool use_graph = true;  // EXPINT_GRAPH=0: advance launches each step directly
   bool poisoned = false;
+  int64_t fail_countdown = 0;  // EXPINT_FAIL_NTH_HIP (see HIP_TRY)
 
   expint::Coef coef() const {
     expint::Coef c{};

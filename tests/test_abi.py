@@ -150,3 +150,18 @@ def test_probes_reject_bad_arguments():
     assert L.expint_probe_copy(16, 512, 1024, 1, 0, None, ctypes.byref(ms)) == N.EINVAL  # overlapping
     assert L.expint_probe_copy(16, 1 << 40, 1 << 45, 1, 1, None, ctypes.byref(ms)) == N.EINVAL  # beyond one launch
     assert L.expint_probe_mfma(0, 0, 1, 16, None, ctypes.byref(ms)) == N.EINVAL
+
+
+@pytest.mark.parametrize("scheme,fields", [(0, 5), (2, 7)])
+def test_workspace_cap_gives_enomem_before_hip(monkeypatch, scheme, fields):
+    # EXPINT_MAX_BYTES below the field buffers a context needs: EXPINT_ENOMEM
+    # and a NULL context, decided before any HIP call (so it holds here too)
+    n = 16
+    need = fields * n**3 * 4 + n**3  # FP32 fields plus the uint8 labels
+    grid = N.Grid(n, n, n, 1.0)
+    df, cd = _labels_df()
+    monkeypatch.setenv("EXPINT_MAX_BYTES", str(need - 1))
+    rc, ctx = _create(grid, df, scheme=scheme)
+    assert rc == N.ENOMEM
+    assert ctx.value is None
+    assert "EXPINT_MAX_BYTES" in N.last_error() and str(need) in N.last_error()
