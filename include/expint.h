@@ -377,6 +377,26 @@ int expint_advance_volumes(expint_ctx* ctx, void* u, int32_t nsteps, double* vol
  * whose y-z cross-section exceeds 2^27 points. */
 int expint_tumour_size(expint_ctx* ctx, const void* u, double threshold, int64_t* d2, int64_t* pair);
 
+/* Bytes of the static device workspace of expint_tumour_size_static. */
+#define EXPINT_STATIC_SCRATCH_BYTES (4 << 20)
+
+/* expint_tumour_size without a context and without any allocation, for
+ * callers that cannot allocate device memory (code running while a HIP graph
+ * is captured, tight serving loops, hosts that forbid hipMalloc).  Same
+ * result as expint_tumour_size for the same field.  u: device field of nx *
+ * ny * nz values of `dtype` (expint_dtype), z fastest; d2 and pair (may be
+ * NULL) as there.  Runs on `stream` (hipStream_t, NULL = null stream) and
+ * synchronises it.  The pass's workspace (line extents, candidates and
+ * counters, 8 (ny nz + nx nz + nx ny) + 8 ny nz bytes plus 320) lives in a
+ * static device array of EXPINT_STATIC_SCRATCH_BYTES on each device the
+ * library runs on, held until the process ends; grids needing more give
+ * EXPINT_EINVAL (up to 362^3 for cubes).  All calls on one device share that
+ * array: calls that overlap in time on one device race and must not be
+ * made.  EXPINT_EUNSUPPORTED as expint_tumour_size; EXPINT_EHIP on a HIP
+ * error. */
+int expint_tumour_size_static(const void* u, int32_t dtype, int32_t nx, int32_t ny, int32_t nz, double threshold,
+                              int64_t* d2, int64_t* pair, void* stream);
+
 /* Writes a legacy VTK file (STRUCTURED_POINTS, binary, big-endian) for
  * ParaView, the viewer of section 3.3: the field (host, nx*ny*nz values of
  * dtype, the library's layout) as scalars `name` (1..64 letters, digits or

@@ -133,6 +133,8 @@ SIGNATURES = {
     "expint_labels_from_intensity": (_I, [_P, _I32, _I32, _I32, _P, _I32, _I32, _I32, _I32, _P, _P]),
     "expint_advance_volumes": (_I, [_P, _P, _I32, _DP]),
     "expint_tumour_size": (_I, [_P, _P, _D, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "expint_tumour_size_static": (_I, [_P, _I32, _I32, _I32, _I32, _D, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_int64), _P]),
     "expint_write_vtk": (_I, [ctypes.c_char_p, _I32, _I32, _I32, _D, _P, _I, ctypes.c_char_p, _P]),
     "expint_last_error": (ctypes.c_char_p, []),
 }

@@ -18,9 +18,16 @@
 
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 
 #include "context.hpp"
 #include "internal.hpp"
+
+// The static workspace of expint_tumour_size_static: one copy per device,
+// held until the process ends.  Host code never passes `scratch` itself to a
+// kernel (that name is a host-side stand-in): it passes the device address
+// that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[EXPINT_STATIC_SCRATCH_BYTES];
 
 namespace expint {
 
@@ -185,6 +192,133 @@ __global__ void k_pairs_init(int* count, unsigned long long* best, unsigned long
 
 unsigned grid_of(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
 
+// Workspace of one tumour-size pass: line extents (two ints per line of each
+// axis), candidates (up to two per x-line), the candidate count and the
+// 64-bit best distance and pair key.
+struct SizeWork {
+  int* ext;
+  int* cand;
+  int* count;
+  unsigned long long* best;  // best and key adjacent: one read-back copy
+  unsigned long long* key;
+};
+
+struct SizeDims {
+  int64_t lx, ly, lz, cmax, pgy;
+};
+
+// Line counts of the grid; EXPINT_EUNSUPPORTED when the pair pass cannot
+// cover its cross-section.
+int size_dims(int nx, int ny, int nz, SizeDims* d) {
+  d->lx = static_cast<int64_t>(ny) * nz;
+  d->ly = static_cast<int64_t>(nx) * nz;
+  d->lz = static_cast<int64_t>(nx) * ny;
+  d->cmax = 2 * d->lx;  // at most two candidates per x-line
+  d->pgy = (d->cmax + kPairChunk - 1) / kPairChunk;
+  if (d->cmax > INT32_MAX || d->pgy > 65535)
+    return set_error(EXPINT_EUNSUPPORTED, "grid cross-section too large for the tumour size pass");
+  return EXPINT_OK;
+}
+
+// Bytes of SizeWork laid out back to back from a 256-byte aligned base:
+// extents, candidates, then 64 bytes of counters.
+size_t size_work_bytes(const SizeDims& d) {
+  const size_t ints = static_cast<size_t>(2 * (d.lx + d.ly + d.lz) + d.cmax);
+  return ((ints * sizeof(int) + 255) / 256) * 256 + 64;
+}
+
+SizeWork size_work_at(void* base, const SizeDims& d) {
+  SizeWork w;
+  char* p = static_cast<char*>(base);
+  w.ext = reinterpret_cast<int*>(p);
+  w.cand = w.ext + 2 * (d.lx + d.ly + d.lz);
+  const size_t ints = static_cast<size_t>(2 * (d.lx + d.ly + d.lz) + d.cmax);
+  char* cnt = p + ((ints * sizeof(int) + 255) / 256) * 256;
+  w.count = reinterpret_cast<int*>(cnt);
+  w.best = reinterpret_cast<unsigned long long*>(cnt + 16);
+  w.key = w.best + 1;
+  return w;
+}
+
+// The kernels of one pass on stream st; every workspace word the pass reads
+// is written by it first (the counters by k_pairs_init).
+hipError_t enqueue_size_pass(expint_dtype dt, int nx, int ny, int nz, const void* u, double threshold,
+                             const SizeDims& d, const SizeWork& w, hipStream_t st) {
+  int* xlo = w.ext;
+  int* xhi = xlo + d.lx;
+  int* ylo = xhi + d.lx;
+  int* yhi = ylo + d.ly;
+  int* zlo = yhi + d.ly;
+  int* zhi = zlo + d.lz;
+  k_pairs_init<<<1, 1, 0, st>>>(w.count, w.best, w.key);
+  if (dt == EXPINT_F64) {
+    const double* f = static_cast<const double*>(u);
+    k_line_extent<double, 0><<<grid_of(d.lx), kBlock, 0, st>>>(f, nx, ny, nz, threshold, xlo, xhi);
+    k_line_extent<double, 1><<<grid_of(d.ly), kBlock, 0, st>>>(f, nx, ny, nz, threshold, ylo, yhi);
+    k_line_extent<double, 2><<<grid_of(d.lz), kBlock, 0, st>>>(f, nx, ny, nz, threshold, zlo, zhi);
+  } else {
+    const float* f = static_cast<const float*>(u);
+    k_line_extent<float, 0><<<grid_of(d.lx), kBlock, 0, st>>>(f, nx, ny, nz, threshold, xlo, xhi);
+    k_line_extent<float, 1><<<grid_of(d.ly), kBlock, 0, st>>>(f, nx, ny, nz, threshold, ylo, yhi);
+    k_line_extent<float, 2><<<grid_of(d.lz), kBlock, 0, st>>>(f, nx, ny, nz, threshold, zlo, zhi);
+  }
+  k_candidates<<<grid_of(d.lx), kBlock, 0, st>>>(nx, ny, nz, xlo, xhi, ylo, yhi, zlo, zhi, w.count, w.cand);
+  // sized for the largest candidate count; workgroups past the actual count
+  // return at once
+  const dim3 pgrid(grid_of(d.cmax), static_cast<unsigned>(d.pgy));
+  k_pairs<0><<<pgrid, kBlock, 0, st>>>(w.cand, w.count, ny, nz, w.best, w.key);
+  k_pairs<1><<<pgrid, kBlock, 0, st>>>(w.cand, w.count, ny, nz, w.best, w.key);
+  return hipGetLastError();
+}
+
+// Reads the pass's result back (synchronises st) into *d2 and pair.
+hipError_t read_size_result(const SizeWork& w, hipStream_t st, int64_t* d2, int64_t* pair) {
+  int count = 0;
+  unsigned long long out[2] = {0, 0};
+  int first = -1;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(&count, w.count, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(out, w.best, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st)) != hipSuccess)
+    return e;
+  if ((e = hipMemcpyAsync(&first, w.cand, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  if (count == 0) {
+    *d2 = -1;
+    if (pair) pair[0] = pair[1] = -1;
+  } else if (count == 1) {
+    *d2 = 0;
+    if (pair) pair[0] = pair[1] = first;
+  } else {
+    *d2 = static_cast<int64_t>(out[0]);
+    if (pair) {
+      pair[0] = static_cast<int64_t>(out[1] >> 32);
+      pair[1] = static_cast<int64_t>(out[1] & 0xffffffffull);
+    }
+  }
+  return hipSuccess;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch`, looked up once per device.
+int static_scratch(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return set_error(EXPINT_EUNSUPPORTED, "device index %d", device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return set_error(EXPINT_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    }
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return EXPINT_OK;
+}
+
 }  // namespace
 
 }  // namespace expint
@@ -233,77 +367,55 @@ int expint_tumour_size(expint_ctx* c, const void* u, double threshold, int64_t* 
   int rc = ensure_device(c);
   if (rc) return rc;
   const Geom& g = c->g;
-  const int64_t lx = static_cast<int64_t>(g.ny) * g.nz, ly = static_cast<int64_t>(g.nx) * g.nz,
-                lz = static_cast<int64_t>(g.nx) * g.ny;
-  const int64_t cmax = 2 * lx;  // at most two candidates per x-line
-  const int64_t pgy = (cmax + kPairChunk - 1) / kPairChunk;
-  if (cmax > INT32_MAX || pgy > 65535)
-    return set_error(EXPINT_EUNSUPPORTED, "grid cross-section too large for the tumour size pass");
+  SizeDims d;
+  if ((rc = size_dims(g.nx, g.ny, g.nz, &d))) return rc;
   auto& w = c->diag;
   if (!w.ext) {
-    // all or nothing: a failed allocation leaves the workspace unset
-    void *ext = nullptr, *cand = nullptr, *cnt = nullptr;
-    rc = c->arena.alloc(&ext, 2 * (lx + ly + lz) * sizeof(int));
-    if (!rc) rc = c->arena.alloc(&cand, cmax * sizeof(int));
-    if (!rc) rc = c->arena.alloc(&cnt, 64);
-    if (rc) {
-      c->arena.release(ext);
-      c->arena.release(cand);
-      c->arena.release(cnt);
-      return rc;
-    }
-    w.cand = static_cast<int*>(cand);
-    w.count = static_cast<int*>(cnt);
-    // best and key are adjacent: the host reads both in one copy
-    w.best = reinterpret_cast<unsigned long long*>(static_cast<char*>(cnt) + 16);
-    w.key = w.best + 1;
-    w.ext = static_cast<int*>(ext);
+    // allocated on first use; all or nothing
+    void* base = nullptr;
+    if ((rc = c->arena.alloc(&base, size_work_bytes(d)))) return rc;
+    const SizeWork sw = size_work_at(base, d);
+    w.ext = sw.ext;
+    w.cand = sw.cand;
+    w.count = sw.count;
+    w.best = sw.best;
+    w.key = sw.key;
   }
-  int* xlo = w.ext;
-  int* xhi = xlo + lx;
-  int* ylo = xhi + lx;
-  int* yhi = ylo + ly;
-  int* zlo = yhi + ly;
-  int* zhi = zlo + lz;
-  hipStream_t st = c->stream;
-  k_pairs_init<<<1, 1, 0, st>>>(w.count, w.best, w.key);
-  if (c->dtype == EXPINT_F64) {
-    const double* f = static_cast<const double*>(u);
-    k_line_extent<double, 0><<<grid_of(lx), kBlock, 0, st>>>(f, g.nx, g.ny, g.nz, threshold, xlo, xhi);
-    k_line_extent<double, 1><<<grid_of(ly), kBlock, 0, st>>>(f, g.nx, g.ny, g.nz, threshold, ylo, yhi);
-    k_line_extent<double, 2><<<grid_of(lz), kBlock, 0, st>>>(f, g.nx, g.ny, g.nz, threshold, zlo, zhi);
-  } else {
-    const float* f = static_cast<const float*>(u);
-    k_line_extent<float, 0><<<grid_of(lx), kBlock, 0, st>>>(f, g.nx, g.ny, g.nz, threshold, xlo, xhi);
-    k_line_extent<float, 1><<<grid_of(ly), kBlock, 0, st>>>(f, g.nx, g.ny, g.nz, threshold, ylo, yhi);
-    k_line_extent<float, 2><<<grid_of(lz), kBlock, 0, st>>>(f, g.nx, g.ny, g.nz, threshold, zlo, zhi);
+  const SizeWork sw{w.ext, w.cand, w.count, w.best, w.key};
+  HIP_TRY(c, enqueue_size_pass(c->dtype, g.nx, g.ny, g.nz, u, threshold, d, sw, c->stream));
+  HIP_TRY(c, read_size_result(sw, c->stream, d2, pair));
+  return EXPINT_OK;
+}
+
+int expint_tumour_size_static(const void* u, int32_t dtype, int32_t nx, int32_t ny, int32_t nz, double threshold,
+                              int64_t* d2, int64_t* pair, void* stream) {
+  if (!u || !d2) return set_error(EXPINT_EINVAL, "NULL argument");
+  if (dtype != EXPINT_F32 && dtype != EXPINT_F64) return set_error(EXPINT_EINVAL, "dtype must be F32 or F64");
+  if (nx < 1 || ny < 1 || nz < 1) return set_error(EXPINT_EINVAL, "grid dims must be >= 1");
+  if (std::isnan(threshold)) return set_error(EXPINT_EINVAL, "threshold is NaN");
+  SizeDims d;
+  int rc = size_dims(nx, ny, nz, &d);
+  if (rc) return rc;
+  const size_t need = size_work_bytes(d);
+  if (need > static_cast<size_t>(EXPINT_STATIC_SCRATCH_BYTES))
+    return set_error(EXPINT_EINVAL,
+                     "grid %dx%dx%d needs %zu bytes of workspace, above the %d-byte static workspace of "
+                     "expint_tumour_size_static",
+                     nx, ny, nz, need, EXPINT_STATIC_SCRATCH_BYTES);
+  int device = -1;
+  if (hipGetDevice(&device) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(EXPINT_EHIP, "no HIP device");
   }
-  k_candidates<<<grid_of(lx), kBlock, 0, st>>>(g.nx, g.ny, g.nz, xlo, xhi, ylo, yhi, zlo, zhi, w.count, w.cand);
-  // sized for the largest candidate count; workgroups past the actual count
-  // return at once
-  const dim3 pgrid(grid_of(cmax), static_cast<unsigned>(pgy));
-  k_pairs<0><<<pgrid, kBlock, 0, st>>>(w.cand, w.count, g.ny, g.nz, w.best, w.key);
-  k_pairs<1><<<pgrid, kBlock, 0, st>>>(w.cand, w.count, g.ny, g.nz, w.best, w.key);
-  HIP_TRY(c, hipGetLastError());
-  int count = 0;
-  unsigned long long out[2] = {0, 0};
-  int first = -1;
-  HIP_TRY(c, hipMemcpyAsync(&count, w.count, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_TRY(c, hipMemcpyAsync(out, w.best, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-  HIP_TRY(c, hipMemcpyAsync(&first, w.cand, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_TRY(c, hipStreamSynchronize(st));
-  if (count == 0) {
-    *d2 = -1;
-    if (pair) pair[0] = pair[1] = -1;
-  } else if (count == 1) {
-    *d2 = 0;
-    if (pair) pair[0] = pair[1] = first;
-  } else {
-    *d2 = static_cast<int64_t>(out[0]);
-    if (pair) {
-      pair[0] = static_cast<int64_t>(out[1] >> 32);
-      pair[1] = static_cast<int64_t>(out[1] & 0xffffffffull);
-    }
+  void* base = nullptr;
+  if ((rc = static_scratch(device, &base))) return rc;
+  const SizeWork w = size_work_at(base, d);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = enqueue_size_pass(static_cast<expint_dtype>(dtype), nx, ny, nz, u, threshold, d, w, st);
+  if (e == hipSuccess) e = read_size_result(w, st, d2, pair);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(EXPINT_EHIP, "tumour size pass failed: %s", hipGetErrorString(e));
   }
   return EXPINT_OK;
 }
