@@ -231,7 +231,8 @@ int check_finite_field(expint_ctx* c, const void* u) {
 namespace {
 
 int validate_opts(const expint_opts* o) {
-  if (o->dtype != EXPINT_F64 && o->dtype != EXPINT_F32) return set_error(EXPINT_EINVAL, "unknown dtype %d", o->dtype);
+  const int dt = enum_value(o->dtype);
+  if (dt != EXPINT_F64 && dt != EXPINT_F32) return set_error(EXPINT_EINVAL, "unknown dtype %d", dt);
   if (!(o->tau > 0.0) || !std::isfinite(o->tau)) return set_error(EXPINT_EINVAL, "tau must be finite and > 0");
   if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return set_error(EXPINT_EINVAL, "tol must be finite and >= 0");
   if (!(o->theta_max >= 0.0) || !std::isfinite(o->theta_max))
@@ -239,11 +240,12 @@ int validate_opts(const expint_opts* o) {
   if ((o->s > 0) != (o->m > 0) || o->s < 0 || o->m < 0)
     return set_error(EXPINT_EINVAL, "give both s and m (> 0) or neither");
   if (o->m > kPlanMaxDegree) return set_error(EXPINT_EINVAL, "m must be <= %d", kPlanMaxDegree);
-  if (o->algo < EXPINT_ALGO_AUTO || o->algo > EXPINT_ALGO_MODAL) return set_error(EXPINT_EINVAL, "unknown algo");
-  if (o->mp < EXPINT_MP_NONE || o->mp > EXPINT_MP_FP16_SPLIT) return set_error(EXPINT_EINVAL, "unknown mp");
-  if (o->sweeps < EXPINT_SWEEPS_AUTO || o->sweeps > EXPINT_SWEEPS_PAIRS)
-    return set_error(EXPINT_EINVAL, "unknown sweeps");
-  if (o->scheme < EXPINT_SCHEME_EXP_EULER || o->scheme > EXPINT_SCHEME_EXPRK2)
+  const int algo = enum_value(o->algo), mp = enum_value(o->mp), sw = enum_value(o->sweeps);
+  const int scheme = enum_value(o->scheme);
+  if (algo < EXPINT_ALGO_AUTO || algo > EXPINT_ALGO_MODAL) return set_error(EXPINT_EINVAL, "unknown algo");
+  if (mp < EXPINT_MP_NONE || mp > EXPINT_MP_FP16_SPLIT) return set_error(EXPINT_EINVAL, "unknown mp");
+  if (sw < EXPINT_SWEEPS_AUTO || sw > EXPINT_SWEEPS_PAIRS) return set_error(EXPINT_EINVAL, "unknown sweeps");
+  if (scheme < EXPINT_SCHEME_EXP_EULER || scheme > EXPINT_SCHEME_EXPRK2)
     return set_error(EXPINT_EINVAL, "unknown scheme");
   return EXPINT_OK;
 }
@@ -272,15 +274,16 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
     return set_error(EXPINT_EINVAL, "grid dims must be >= 1 (got %d %d %d)", grid->nx, grid->ny, grid->nz);
   if (!(grid->h > 0.0) || !std::isfinite(grid->h)) return set_error(EXPINT_EINVAL, "h must be finite and > 0");
   if (!finite_nonneg(rho)) return set_error(EXPINT_EINVAL, "rho must be finite and >= 0");
-  if (bc != EXPINT_NOFLUX && bc != EXPINT_DIRICHLET0) return set_error(EXPINT_EINVAL, "unknown bc %d", bc);
+  if (enum_value(bc) != EXPINT_NOFLUX && enum_value(bc) != EXPINT_DIRICHLET0)
+    return set_error(EXPINT_EINVAL, "unknown bc %d", enum_value(bc));
   int rc = validate_opts(opts);
   if (rc) return rc;
   if ((df->labels == nullptr) == (df->D == nullptr))
     return set_error(EXPINT_EINVAL, "give exactly one of labels and D");
-  const int64_t n = static_cast<int64_t>(grid->nx) * grid->ny * grid->nz;
   // 32-bit voxel indices, with room for the sweeps' one-past-the-chunk offsets
-  if ((static_cast<int64_t>(grid->nx) + 16) * grid->ny * grid->nz > (int64_t(1) << 31) - 1)
-    return set_error(EXPINT_EINVAL, "grid too large (%lld voxels)", (long long)n);
+  if (product_within(static_cast<int64_t>(grid->nx) + 16, grid->ny, grid->nz, (int64_t(1) << 31) - 1) < 0)
+    return set_error(EXPINT_EINVAL, "grid too large (%d x %d x %d)", grid->nx, grid->ny, grid->nz);
+  const int64_t n = static_cast<int64_t>(grid->nx) * grid->ny * grid->nz;
   if (df->labels) {
     if (df->n_classes < 1 || df->n_classes > EXPINT_MAX_CLASSES)
       return set_error(EXPINT_EINVAL, "n_classes must be in 1..%d", EXPINT_MAX_CLASSES);

@@ -323,22 +323,30 @@ int expint_batch_create(int32_t count, const expint_grid* grids, const expint_df
                         expint_bc bc, const expint_opts* opts, expint_batch** out) {
   if (out) *out = nullptr;
   if (count < 1 || !grids || !dfields || !rho || !opts || !out) return set_error(EXPINT_EINVAL, "NULL argument or count < 1");
-  if (bc != EXPINT_NOFLUX && bc != EXPINT_DIRICHLET0) return set_error(EXPINT_EINVAL, "unknown bc %d", bc);
-  if (opts->dtype != EXPINT_F64 && opts->dtype != EXPINT_F32) return set_error(EXPINT_EINVAL, "unknown dtype");
+  if (enum_value(bc) != EXPINT_NOFLUX && enum_value(bc) != EXPINT_DIRICHLET0)
+    return set_error(EXPINT_EINVAL, "unknown bc %d", enum_value(bc));
+  if (enum_value(opts->dtype) != EXPINT_F64 && enum_value(opts->dtype) != EXPINT_F32)
+    return set_error(EXPINT_EINVAL, "unknown dtype");
   if (!(opts->tau > 0.0) || !std::isfinite(opts->tau)) return set_error(EXPINT_EINVAL, "tau must be finite and > 0");
   if ((opts->s > 0) != (opts->m > 0) || opts->s < 0 || opts->m < 0 || opts->m > kPlanMaxDegree)
     return set_error(EXPINT_EINVAL, "give both s and m (m <= %d) or neither", kPlanMaxDegree);
   if (!(opts->tol >= 0.0) || !(opts->theta_max >= 0.0)) return set_error(EXPINT_EINVAL, "bad tolerances");
-  if (opts->algo == EXPINT_ALGO_MODAL || opts->mp != EXPINT_MP_NONE)
-    return set_error(EXPINT_EUNSUPPORTED, "batches run the stencil-Taylor path only");
-  if (opts->scheme != EXPINT_SCHEME_EXP_EULER && opts->scheme != EXPINT_SCHEME_LINEARISED)
-    return set_error(EXPINT_EUNSUPPORTED, "batches take the EXP_EULER or LINEARISED scheme");
+  {
+    const int algo = enum_value(opts->algo), mp = enum_value(opts->mp), scheme = enum_value(opts->scheme);
+    if (algo < EXPINT_ALGO_AUTO || algo > EXPINT_ALGO_MODAL || mp < EXPINT_MP_NONE || mp > EXPINT_MP_FP16_SPLIT ||
+        scheme < EXPINT_SCHEME_EXP_EULER || scheme > EXPINT_SCHEME_EXPRK2)
+      return set_error(EXPINT_EINVAL, "unknown algo, mp or scheme");
+    if (algo == EXPINT_ALGO_MODAL || mp != EXPINT_MP_NONE)
+      return set_error(EXPINT_EUNSUPPORTED, "batches run the stencil-Taylor path only");
+    if (scheme != EXPINT_SCHEME_EXP_EULER && scheme != EXPINT_SCHEME_LINEARISED)
+      return set_error(EXPINT_EUNSUPPORTED, "batches take the EXP_EULER or LINEARISED scheme");
+  }
   for (int i = 0; i < count; ++i) {
     const expint_grid& g = grids[i];
     const expint_dfield& d = dfields[i];
     if (g.nx < 1 || g.ny < 1 || g.nz < 1 || !(g.h > 0.0) || !std::isfinite(g.h))
       return set_error(EXPINT_EINVAL, "instance %d: bad grid", i);
-    if ((static_cast<int64_t>(g.nx) + 16) * g.ny * g.nz > (int64_t(1) << 31) - 1)
+    if (product_within(static_cast<int64_t>(g.nx) + 16, g.ny, g.nz, (int64_t(1) << 31) - 1) < 0)
       return set_error(EXPINT_EINVAL, "instance %d: grid too large", i);
     if (!d.labels || d.D) return set_error(EXPINT_EINVAL, "instance %d: batches need the label form", i);
     if (d.n_classes < 1 || d.n_classes > EXPINT_MAX_CLASSES || !d.class_D)

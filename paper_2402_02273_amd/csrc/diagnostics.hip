@@ -341,9 +341,10 @@ int expint_labels_from_intensity(const uint8_t* image, int32_t ni, int32_t nj, i
     th.t[q] = thresholds[q];
     if (q > 0 && th.t[q] <= th.t[q - 1]) return set_error(EXPINT_EINVAL, "thresholds must increase");
   }
-  const int64_t n = static_cast<int64_t>(nx) * ny * nz;
-  const int64_t nimg = static_cast<int64_t>(ni) * nj * nk;
-  if (n > (int64_t(1) << 31) * kBlock) return set_error(EXPINT_EINVAL, "grid too large");
+  const int64_t n = product_within(nx, ny, nz, (int64_t(1) << 31) * kBlock);
+  const int64_t nimg = product_within(ni, nj, nk, INT64_MAX);
+  if (n < 0) return set_error(EXPINT_EINVAL, "grid too large");
+  if (nimg < 0) return set_error(EXPINT_EINVAL, "image too large");
   const char* a = reinterpret_cast<const char*>(image);
   const char* b = reinterpret_cast<const char*>(labels);
   if (a < b + n && b < a + nimg) return set_error(EXPINT_EINVAL, "image and labels overlap");

@@ -16,6 +16,27 @@ constexpr int kTab = kMaxClasses * kMaxClasses;
 constexpr int kBlock = 256;        // threads per workgroup of the field kernels
 constexpr int kReduceBlocks = 1024;  // fixed partial count -> deterministic reductions
 
+// a * b * c if it is at most `limit` (all of them >= 0), else -1: element
+// counts of grids from 32-bit dimensions without signed overflow.
+inline int64_t product_within(int64_t a, int64_t b, int64_t c, int64_t limit) {
+  if (a < 0 || b < 0 || c < 0) return -1;
+  if (b != 0 && a > limit / b) return -1;
+  const int64_t ab = a * b;
+  if (c != 0 && ab > limit / c) return -1;
+  return ab * c;
+}
+
+// The int a C caller stored in an enumeration field or argument.  A C caller
+// may store any int there; reading it as the enumeration type before it is
+// validated would be undefined, so validation reads it through this.
+template <typename E>
+inline int enum_value(const E& e) {
+  static_assert(sizeof(E) == sizeof(int), "C enumerations are int-sized");
+  int v;
+  __builtin_memcpy(&v, &e, sizeof v);
+  return v;
+}
+
 inline constexpr int dtype_bytes(expint_dtype dt) { return dt == EXPINT_F64 ? 8 : 4; }
 
 struct Geom {

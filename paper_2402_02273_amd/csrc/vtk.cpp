@@ -41,9 +41,11 @@ int expint_write_vtk(const char* path, int32_t nx, int32_t ny, int32_t nz, doubl
   if (!path || !field) return set_error(EXPINT_EINVAL, "NULL argument");
   if (nx < 1 || ny < 1 || nz < 1) return set_error(EXPINT_EINVAL, "grid dims must be >= 1");
   if (!(h > 0.0) || !std::isfinite(h)) return set_error(EXPINT_EINVAL, "h must be finite and > 0");
-  if (dtype != EXPINT_F32 && dtype != EXPINT_F64) return set_error(EXPINT_EINVAL, "unknown dtype");
+  if (enum_value(dtype) != EXPINT_F32 && enum_value(dtype) != EXPINT_F64)
+    return set_error(EXPINT_EINVAL, "unknown dtype");
   if (!valid_name(name)) return set_error(EXPINT_EINVAL, "name must be 1..64 letters, digits or '_'");
-  const int64_t n = static_cast<int64_t>(nx) * ny * nz;
+  const int64_t n = product_within(nx, ny, nz, INT64_MAX / 8);
+  if (n < 0) return set_error(EXPINT_EINVAL, "grid too large");
   const int w = dtype == EXPINT_F64 ? 8 : 4;
   std::FILE* f = std::fopen(path, "wb");
   if (!f) return set_error(EXPINT_EIO, "cannot open %s for writing", path);
