@@ -35,16 +35,19 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Sums acc over the workgroup (fixed order) and adds weight * sum into
-// partial[blockIdx.x * 8 + c].  Every thread of the workgroup must call it.
+// partial[blockIdx.x * 8 + c] for the NC classes of the grid (the slots of
+// the other classes stay as filled, zero).  Every thread of the workgroup
+// must call it.
+template <int NC>
 __device__ __forceinline__ void block_accumulate(double (&acc)[kMaxClasses], double weight, double* partial) {
   __shared__ double red[kBlock / 64][kMaxClasses];
 #pragma unroll
-  for (int c = 0; c < kMaxClasses; ++c) {
+  for (int c = 0; c < NC; ++c) {
     const double v = wave_sum(acc[c]);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][c] = v;
   }
   __syncthreads();
-  if (threadIdx.x < kMaxClasses) {
+  if (threadIdx.x < NC) {
     double v = 0.0;
     for (int w = 0; w < kBlock / 64; ++w) v += red[w][threadIdx.x];
     double* slot = partial + static_cast<size_t>(blockIdx.x) * kMaxClasses + threadIdx.x;
@@ -57,9 +60,18 @@ struct FaceTables {
   double wall[kMaxClasses * kMaxClasses];  // [c][a]
 };
 
+// Stages the entries a grid of NC classes can reach (class c, labels a, b
+// below NC), in the tables' own layout.
+template <int NC>
 __device__ __forceinline__ void load_face_tables(FaceTables& ft, const double* dtab, const double* dwall) {
-  for (int t = threadIdx.x; t < kMaxClasses * kTab; t += kBlock) ft.tab[t] = dtab[t];
-  if (threadIdx.x < kMaxClasses * kMaxClasses) ft.wall[threadIdx.x] = dwall[threadIdx.x];
+  for (int t = threadIdx.x; t < NC * NC * NC; t += kBlock) {
+    const int o = (t / (NC * NC)) * kTab + ((t / NC) % NC) * kMaxClasses + t % NC;
+    ft.tab[o] = dtab[o];
+  }
+  if (threadIdx.x < NC * NC) {
+    const int o = (threadIdx.x / NC) * kMaxClasses + threadIdx.x % NC;
+    ft.wall[o] = dwall[o];
+  }
 }
 
 template <int NC>
@@ -77,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_faceprod(Geom g, const uint8_t* __re
                                                      const T* __restrict__ yb, const T* __restrict__ y, double weight,
                                                      double* __restrict__ partial) {
   __shared__ FaceTables ft;
-  load_face_tables(ft, dtab, dwall);
+  load_face_tables<NC>(ft, dtab, dwall);
   __syncthreads();
   double acc[kMaxClasses];
 #pragma unroll
@@ -106,7 +118,7 @@ __global__ __launch_bounds__(kBlock) void k_faceprod(Geom g, const uint8_t* __re
       }
     }
   }
-  block_accumulate(acc, weight, partial);
+  block_accumulate<NC>(acc, weight, partial);
 }
 
 // z-vectorised form (nz % 4 == 0, 4-value aligned fields): the z-segments of
@@ -120,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void k_faceprod4(Geom g, int gzs, int gy, i
                                                       const T* __restrict__ y, double weight,
                                                       double* __restrict__ partial) {
   __shared__ FaceTables ft;
-  load_face_tables(ft, dtab, dwall);
+  load_face_tables<NC>(ft, dtab, dwall);
   __syncthreads();
   double acc[kMaxClasses];
 #pragma unroll
@@ -193,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_faceprod4(Geom g, int gzs, int gy, i
       q += sx4;
     }
   }
-  block_accumulate(acc, weight, partial);
+  block_accumulate<NC>(acc, weight, partial);
 }
 
 // acc[c] += sum over slots b of partial[b][c]: thread t sums the slots
@@ -225,41 +237,53 @@ __global__ __launch_bounds__(kBlock) void k_faceprod_final(const double* __restr
 // is ybar (sweep_column4's per-plane hook): the sweep hands over ybar on the
 // lane's four voxels and their +x, +y, +z neighbours with the labels, and
 // this adds the same FP64 face terms as k_faceprod4 against y (loaded here).
-// One plane per lane: load() fetches y on the lane's voxels and their +x,
-// +y, +z neighbours before the sweep starts, so these loads are in flight
-// together with the sweep's own; the hook then uses them for plane i.
+// load() fetches y on the lane's voxels of its first plane and their +x, +y,
+// +z neighbours before the sweep starts, so these loads are in flight
+// together with the sweep's own; the hook uses them for plane i and then
+// fetches the next plane's (the +x values become the centre values), which
+// the sweep's work on that plane covers.
 // DB (a Taylor term of the linearised operator): the hook also adds
 // wd * ybar * y into dbar on the lane's voxels, the diagonal's share.
 template <typename T, int BC, int NC, bool DB>
 struct FaceAcc {
   const Geom& g;
   const FaceTables& ft;
-  int j, k4, kq, rw;
+  int j, k4, kq, rw, i_end;
   bool wall_hi;
   Vec4<T> vc, vn, vy, dv;
   T vz_edge;
+  const T* yf;
   T* dbar;
   T wd;
   double acc[kMaxClasses];
 
   __device__ __forceinline__ FaceAcc(const Geom& g_, const FaceTables& ft_, int j_, int k4_, int kq_, int rw_,
-                                     T* dbar_, T wd_)
-      : g(g_), ft(ft_), j(j_), k4(k4_), kq(kq_), rw(rw_), wall_hi(k4_ == (g_.nz >> 2) - 1), dbar(dbar_), wd(wd_) {
+                                     int i_end_, T* dbar_, T wd_)
+      : g(g_), ft(ft_), j(j_), k4(k4_), kq(kq_), rw(rw_), i_end(i_end_), wall_hi(k4_ == (g_.nz >> 2) - 1),
+        yf(nullptr), dbar(dbar_), wd(wd_) {
 #pragma unroll
     for (int c = 0; c < kMaxClasses; ++c) acc[c] = 0.0;
   }
 
-  __device__ __forceinline__ void load(const T* __restrict__ y, int i) {
+  // y on plane i: the +x and +y neighbours and the z segment edge (the
+  // centre values are already held), and dbar
+  __device__ __forceinline__ void fetch(int i) {
     const int nz4 = g.nz >> 2, sx4 = g.ny * nz4;
     const int q = (i * g.ny + j) * nz4 + k4;
     const int qn = i < g.nx - 1 ? q + sx4 : q;
     const int dyp = j < g.ny - 1 ? nz4 : 0;
-    vc = ld4<T>(y, q);
-    vn = ld4<T>(y, qn);
-    vy = ld4<T>(y, q + dyp);
+    vn = ld4<T>(yf, qn);
+    vy = ld4<T>(yf, q + dyp);
     const bool edge_hi = !wall_hi && kq == rw - 1;
-    vz_edge = edge_hi ? y[4 * q + 4] : T(0);
+    vz_edge = edge_hi ? yf[4 * q + 4] : T(0);
     if (DB) dv = ld4<T>(dbar, q);
+  }
+
+  __device__ __forceinline__ void load(const T* __restrict__ y, int i) {
+    const int nz4 = g.nz >> 2;
+    yf = y;
+    vc = ld4<T>(y, (i * g.ny + j) * nz4 + k4);
+    fetch(i);
   }
 
   __device__ __forceinline__ void operator()(int i, int q, const Vec4<T>& bc, const Vec4<T>& bn, const Vec4<T>& by,
@@ -294,6 +318,10 @@ struct FaceAcc {
       for (int e = 0; e < 4; ++e) dv.v[e] += wd * bc.v[e] * vc.v[e];
       st4<T>(dbar, q, dv);
     }
+    if (i + 1 < i_end) {
+      vc = vn;
+      fetch(i + 1);
+    }
   }
 };
 
@@ -303,7 +331,7 @@ struct FaceAcc {
 // per lane, workgroups as in k_sweep4 with lp = 1; workgroup b adds
 // weight * (its sums) into slot b.  kTermJ also adds weight * ybar * y into
 // dbar.
-template <typename T, int BC, int KIND, int NC>
+template <typename T, int BC, int KIND, int NC, int LP>
 __global__ __launch_bounds__(kBlock) void k_sweep_face4(Geom g, int gzs, int gy, int rw, Coef cf, SweepArgs a,
                                                         const T* __restrict__ y, const double* __restrict__ dtab,
                                                         const double* __restrict__ dwall, double weight,
@@ -314,7 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_face4(Geom g, int gzs, int gy,
   const int zs = L % gzs;
   const int t = L / gzs;
   const int ybk = t % gy;
-  const int i0 = t / gy;
+  const int i0 = (t / gy) * LP;
   const int tid = static_cast<int>(threadIdx.x);
   const int kq = tid & (rw - 1);
   const int j = ybk * (kBlock / rw) + tid / rw;
@@ -323,20 +351,21 @@ __global__ __launch_bounds__(kBlock) void k_sweep_face4(Geom g, int gzs, int gy,
   // thread passes this barrier once
   auto ready = [&]() {
     load_tables(s, cf, tid, kBlock);
-    load_face_tables(ft, dtab, dwall);
+    load_face_tables<NC>(ft, dtab, dwall);
     __syncthreads();
   };
-  FaceAcc<T, BC, NC, KIND == kTermJ> face(g, ft, j, k4, kq, rw, dbar, static_cast<T>(weight));
+  FaceAcc<T, BC, NC, KIND == kTermJ> face(g, ft, j, k4, kq, rw, min(i0 + LP, g.nx), dbar, static_cast<T>(weight));
   const bool live = j < g.ny && k4 < (g.nz >> 2);
   if (live) face.load(y, i0);
-  sweep_column4<T, BC, 1, KIND, kGeneric, false>(g, cf.labels, s, a, i0, j, k4, kq, rw, live, ready, face);
-  block_accumulate(face.acc, weight, partial);
+  sweep_column4<T, BC, LP, KIND, kGeneric, false>(g, cf.labels, s, a, i0, j, k4, kq, rw, live, ready, face);
+  block_accumulate<NC>(face.acc, weight, partial);
 }
 
-// Launch shape of k_sweep_face4: the sweeps' z-segments, one plane per lane.
+// Launch shape of k_sweep_face4: the sweeps' z-segments, Tiling::flp planes
+// per lane.
 Tiling sweep_face_tiling(const Tiling& tl) {
   Tiling f = tl;
-  f.lp = 1;
+  f.lp = (tl.flp == 2 || tl.flp == 4) ? tl.flp : 1;
   f.nt = 0;
   return f;
 }
@@ -351,16 +380,23 @@ hipError_t sweep_face_typed(const Geom& g, const Tiling& tl, const Coef& cf, con
   const dim3 grid(static_cast<unsigned>(sweep_blocks(g, ft))), block(kBlock);
   const T* yy = static_cast<const T*>(y);
   T* db = static_cast<T*>(dbar);
-#define EXPINT_SWEEP_FACE(NC_)                                                                                     \
-  k_sweep_face4<T, BC, KIND, NC_><<<grid, block, 0, st>>>(g, gzs, gy, ft.rw, cf, a, yy, dtab, dwall, weight, partial, \
-                                                         db)
-  switch (nclass) {
-    case 1: EXPINT_SWEEP_FACE(1); break;
-    case 2: EXPINT_SWEEP_FACE(2); break;
-    case 3: EXPINT_SWEEP_FACE(3); break;
-    case 4: EXPINT_SWEEP_FACE(4); break;
-    default: EXPINT_SWEEP_FACE(8); break;
+#define EXPINT_SWEEP_FACE(NC_, LP_)                                                                     \
+  k_sweep_face4<T, BC, KIND, NC_, LP_><<<grid, block, 0, st>>>(g, gzs, gy, ft.rw, cf, a, yy, dtab, dwall, weight, \
+                                                              partial, db)
+#define EXPINT_SWEEP_FACE_LP(NC_)                     \
+  switch (ft.lp) {                                    \
+    case 1: EXPINT_SWEEP_FACE(NC_, 1); break;         \
+    case 2: EXPINT_SWEEP_FACE(NC_, 2); break;         \
+    default: EXPINT_SWEEP_FACE(NC_, 4); break;        \
   }
+  switch (nclass) {
+    case 1: EXPINT_SWEEP_FACE_LP(1); break;
+    case 2: EXPINT_SWEEP_FACE_LP(2); break;
+    case 3: EXPINT_SWEEP_FACE_LP(3); break;
+    case 4: EXPINT_SWEEP_FACE_LP(4); break;
+    default: EXPINT_SWEEP_FACE_LP(8); break;
+  }
+#undef EXPINT_SWEEP_FACE_LP
 #undef EXPINT_SWEEP_FACE
   return hipGetLastError();
 }

@@ -434,6 +434,11 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
       return bail(set_error(EXPINT_EHIP, "autotune failed: %s", hipGetErrorString(e)));
     }
   }
+  if (const char* f = std::getenv("EXPINT_FACE_LP")) {
+    // planes per lane of the adjoint's fused reverse sweeps (default 1)
+    const int v = std::atoi(f);
+    if (v == 1 || v == 2 || v == 4) c->tiling.flp = v;
+  }
   if (c->algo != EXPINT_ALGO_MODAL && c->scheme == EXPINT_SCHEME_EXP_EULER) {
     const hipError_t e = autotune_pairs(c->dtype, c->bc, c->g, c->coef(), c->y[0], c->acc[0], c->y[1], c->stream,
                                         c->tiling, opts->sweeps, &c->ptiling);

@@ -64,6 +64,9 @@ struct Tiling {
   int bx = 64, by = 4, lp = 4;
   int vec = 0, rw = 64;
   int nt = 0;  // z-vectorised Taylor-term sweeps of A: non-temporal output stores
+  // x-planes per lane of the adjoint's fused reverse sweeps (1, 2 or 4); set
+  // per context, not by the sweep autotuner
+  int flp = 1;
 };
 // Whether the z-vectorised sweep handles this grid and coefficient form.
 bool vec_sweep_ok(const Geom& g, bool labels_form);

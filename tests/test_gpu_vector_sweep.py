@@ -373,7 +373,7 @@ def test_every_tiling_same_step(native, monkeypatch, tmp_path, shape, scheme, dt
 def test_gradient_with_pinned_planes_per_lane(native, monkeypatch, tmp_path, tile, scheme):
     # the forward and tape sweeps follow the context's tiling (here 2 or 4
     # planes per lane, vector or scalar) while the fused reverse sweeps take
-    # one plane per lane: the gradient must not depend on it
+    # their own planes per lane: the gradient must not depend on it
     from paper_2402_02273_amd.expint import ExpInt
 
     shape = (7, 6, 36)
@@ -396,6 +396,39 @@ def test_gradient_with_pinned_planes_per_lane(native, monkeypatch, tmp_path, til
         info = ctx.launch_info()
         print(f"[case] tile={tile} {scheme} {dtype} launch={info}", flush=True)
         assert (info["vec"], info["lp"]) == (tile[3], tile[2])
+        gu_g, grho_g, gD_g = ctx.vjp(dev(u0, dtype), K, dev(gout, dtype), ckpt_every=2)
+        assert rel_l2(gu_g.cpu().numpy(), gu) < tol
+        assert grho_g == pytest.approx(grho, rel=tol)
+        for c in range(3):
+            assert abs(gD_g[c] - gD[c]) <= tol * scale, (dtype, c, gD_g[c], gD[c])
+        del ctx
+
+
+@pytest.mark.parametrize("flp", ["1", "2", "4"])
+@pytest.mark.parametrize("scheme", ["exp_euler", "linearised"])
+def test_gradient_fused_reverse_sweep_planes(native, monkeypatch, flp, scheme):
+    # the fused reverse sweeps (a Taylor term of the reverse pass plus the
+    # class face products) with 1, 2 or 4 x-planes per lane, on a grid whose
+    # x extent is not a multiple of 4 and whose rows leave lanes past the
+    # grid, against the FP64 oracle adjoint
+    from paper_2402_02273_amd.expint import ExpInt
+
+    shape = (11, 5, 40)
+    class_D = (0.0, 0.13, 0.013)
+    labels = random_labels(shape, len(class_D), seed=301)
+    u0 = random_field(shape, seed=302) * (labels != 0)
+    gout = random_field(shape, seed=303, lo=-1, hi=1)
+    rho, tau, K, sm = 0.025, 7.3, 4, (2, 9)
+    op = oop.Operator(1.0, labels=labels, class_D=class_D)
+    gu, grho, gD = oadj.vjp(op, u0, rho, tau, sm[0], sm[1], K, gout, 2, classes=[0, 1, 2], scheme=scheme)
+    scale = max(abs(gD[c]) for c in range(3))
+    monkeypatch.setenv("EXPINT_FACE_LP", flp)
+    monkeypatch.setenv("EXPINT_TILE", "vec")  # the fused sweeps need the z-vectorised shape
+    for dtype, tol in [(torch.float64, 1e-10), (torch.float32, 2e-5)]:
+        print(f"[case] fused reverse sweep planes={flp} {scheme} {dtype}", flush=True)
+        ctx = ExpInt(shape, labels=labels, class_D=class_D, dtype=dtype, device=DEV, sweeps="single", rho=rho,
+                     tau=tau, s=sm[0], m=sm[1], scheme=scheme)
+        assert ctx.launch_info()["vec"] == 1
         gu_g, grho_g, gD_g = ctx.vjp(dev(u0, dtype), K, dev(gout, dtype), ckpt_every=2)
         assert rel_l2(gu_g.cpu().numpy(), gu) < tol
         assert grho_g == pytest.approx(grho, rel=tol)
