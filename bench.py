@@ -133,9 +133,11 @@ def step_bytes_per_voxel_pairs(w, s, m):
     return RHS_BYTES(w) + sum(sweep_bytes(w, r, wr) for r, wr in ops), len(ops) + 1
 
 
-def load_traffic(kernel_key, kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprof counter
-    summary, or None if there is none for this kernel and workload."""
+def load_profile_entry(kernel_key, kernel):
+    """The committed rocprof figures of `kernel` on one workload
+    (profiles/traffic.json): HBM bytes per launch from the FETCH_SIZE and
+    WRITE_SIZE counters, and the kernel trace's average duration; None if
+    there is no entry for this kernel and workload."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -146,7 +148,23 @@ def load_traffic(kernel_key, kernel):
         return None
     if not entry or entry.get("kernel") != kernel:
         return None
-    return entry.get("bytes_per_launch")
+    return entry
+
+
+def load_traffic(kernel_key, kernel):
+    """HBM bytes per launch of `kernel` from the committed counters, or None."""
+    entry = load_profile_entry(kernel_key, kernel)
+    return entry.get("bytes_per_launch") if entry else None
+
+
+def rocprof_frac(kernel_key, kernel, alg_bytes, peak_gbs):
+    """Algorithmic bytes per launch over the committed rocprof average
+    duration of the same kernel, as a fraction of peak_gbs (None without a
+    committed trace)."""
+    entry = load_profile_entry(kernel_key, kernel)
+    if not entry or not entry.get("rocprof_avg_us"):
+        return None
+    return alg_bytes / (entry["rocprof_avg_us"] * 1e-6) / 1e9 / peak_gbs
 
 
 def cpu_baseline(w, nsteps, scheme="exp_euler"):
@@ -229,6 +247,7 @@ def run_c2(args):
     ms_skip = ctx.profile("skip", reps=200)
     ms_rhs = ctx.profile("rhs", reps=200)
     ms_pair = ctx.profile("pair", reps=200) if pairs else None
+    pkey = pkern = None
     if pairs:
         kname = f"k_pair (two Taylor terms per sweep, stencil twice + running sum), ty={ptiling[0]} lp={ptiling[1]}"
         tb = PAIR_BYTES(w_bytes) * w.nvox
@@ -239,15 +258,17 @@ def run_c2(args):
         kname = "k_sweep term of the linearised operator, pair-flush flavour (stencil + diagonal + Taylor term + sum)"
         tb = FLUSH_BYTES_LIN(w_bytes) * w.nvox
         ms_dom = ms_flush
-        traffic = load_traffic(f"flush_lin_{args.dtype}_{args.n}", "k_sweep4" if launch["vec"] else "k_sweep")
+        pkey, pkern = f"flush_lin_{args.dtype}_{args.n}", "k_sweep4" if launch["vec"] else "k_sweep"
+        traffic = load_traffic(pkey, pkern)
         sbv, nlaunch = step_bytes_per_voxel(w_bytes, plan.s, plan.m, linearised=True)
     else:
         kname = "k_sweep term, pair-flush flavour (stencil + Taylor term + running sum)"
         tb = FLUSH_BYTES(w_bytes) * w.nvox
         ms_dom = ms_flush
         # the counters are per kernel variant: the vector sweep with non-temporal stores is its own
-        traffic = load_traffic(f"flush_{args.dtype}_{args.n}",
-                               ("k_sweep4_nt" if launch.get("nt") else "k_sweep4") if launch["vec"] else "k_sweep")
+        pkey = f"flush_{args.dtype}_{args.n}"
+        pkern = ("k_sweep4_nt" if launch.get("nt") else "k_sweep4") if launch["vec"] else "k_sweep"
+        traffic = load_traffic(pkey, pkern)
         if erk:
             sbv, nlaunch = step_bytes_per_voxel_exprk2(w_bytes, plan.s, plan.m)
         else:
@@ -299,6 +320,12 @@ def run_c2(args):
             "ms_per_launch": ms_dom,
             "measured_peak": peaks["copy_hbm_GBs"],
             "frac_of_measured_peak": achieved / peaks["copy_hbm_GBs"],
+            # the same bytes over the committed rocprof kernel trace's average
+            # duration of this kernel (the profiler serialises dispatches,
+            # which lengthens each; the live figure above is back to back)
+            "frac_rocprof": rocprof_frac(pkey, pkern, tb, HBM_PEAK_GBS) if pkey else None,
+            "working_set_note": "the 128^3 fields (~52 MB) stay in the 256 MB Infinity Cache between sweeps: "
+            "bytes come from the Infinity Cache / fabric, not HBM" if args.n <= 128 else "HBM-resident",
         },
         "measured_peaks": peaks,
         "step_rates": {
