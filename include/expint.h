@@ -289,7 +289,7 @@ int expint_batch_create(int32_t count, const expint_grid* grids, const expint_df
 /* Advance every instance by nsteps: u[i] is instance i's device field.  The
  * first call for a given set of pointers records one HIP graph holding the
  * whole schedule; later calls replay it.  Inside the graph, groups of
- * instances sized for the Infinity Cache run on two streams concurrently
+ * instances sized for the Infinity Cache run on three streams concurrently
  * (EXPINT_BATCH_LANES=1..4 in the environment at expint_batch_create sets
  * the count); results do not depend on it. */
 int expint_batch_advance(expint_batch* batch, void* const* u, int32_t nsteps);

@@ -84,6 +84,10 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         tmp,
         *objs,
         f"-Wl,--version-script={os.path.join(CSRC, 'exports.map')}",
+        # named phase ranges for the profiler's marker trace
+        "-L/opt/rocm/lib",
+        "-lrocprofiler-sdk-roctx",
+        "-Wl,-rpath,/opt/rocm/lib",
     ]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -22,6 +22,7 @@
 #include "context.hpp"
 #include "plan.hpp"
 #include "schedule.hpp"
+#include "trace.hpp"
 
 using namespace expint;
 
@@ -85,7 +86,7 @@ struct expint_batch {
   // groups are dealt round-robin to `lanes` streams inside the recorded
   // graph (lane 0 is `stream`, the others `side` streams), so the launch
   // chains of independent groups overlap; joined before the graph ends
-  int lanes = 2;
+  int lanes = 3;
   hipStream_t side[3] = {nullptr, nullptr, nullptr};
   hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
   hipGraph_t graph = nullptr;
@@ -187,7 +188,7 @@ int build_schedule(expint_batch* b, void* const* u) {
     return sweep_blocks(b->inst[a].g, tl[a]) > sweep_blocks(b->inst[c].g, tl[c]);
   });
   const size_t w = dtype_size(b->dtype);
-  size_t budget = static_cast<size_t>(224) << 20;
+  size_t budget = static_cast<size_t>(128) << 20;
   if (const char* env = std::getenv("EXPINT_BATCH_GROUP_BYTES")) budget = std::strtoull(env, nullptr, 10);
   std::vector<std::vector<int>> groups;
   size_t used = 0;
@@ -282,6 +283,7 @@ int build_schedule(expint_batch* b, void* const* u) {
   BHIP(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice, b->stream));
   BHIP(hipMemcpyAsync(b->d_tables, tsrc, tabs.size() * w, hipMemcpyHostToDevice, b->stream));
   BHIP(hipStreamSynchronize(b->stream));
+  PhaseRange range("record batch graph");
   BHIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   hipError_t err = hipSuccess;
   const int lanes = std::min<int>(b->lanes, static_cast<int>(groups.size()));
@@ -321,6 +323,7 @@ extern "C" {
 
 int expint_batch_create(int32_t count, const expint_grid* grids, const expint_dfield* dfields, const double* rho,
                         expint_bc bc, const expint_opts* opts, expint_batch** out) {
+  PhaseRange range("expint_batch_create");
   if (out) *out = nullptr;
   if (count < 1 || !grids || !dfields || !rho || !opts || !out) return set_error(EXPINT_EINVAL, "NULL argument or count < 1");
   if (enum_value(bc) != EXPINT_NOFLUX && enum_value(bc) != EXPINT_DIRICHLET0)
@@ -382,7 +385,7 @@ int expint_batch_create(int32_t count, const expint_grid* grids, const expint_df
     }
     b->own_stream = true;
   }
-  // lanes of the recorded step (default 2; EXPINT_BATCH_LANES, 1..4): side
+  // lanes of the recorded step (default 3; EXPINT_BATCH_LANES, 1..4): side
   // streams (default priority) and the fork / join events of the capture
   if (const char* env = std::getenv("EXPINT_BATCH_LANES")) b->lanes = std::max(1, std::min(4, std::atoi(env)));
   for (int l = 1; l < b->lanes; ++l) {
@@ -439,6 +442,7 @@ int expint_batch_create(int32_t count, const expint_grid* grids, const expint_df
 }
 
 int expint_batch_advance(expint_batch* b, void* const* u, int32_t nsteps) {
+  PhaseRange range("expint_batch_advance");
   if (!b) return set_error(EXPINT_EINVAL, "batch is NULL");
   if (b->poisoned) return set_error(EXPINT_ESTATE, "batch poisoned by an earlier HIP error");
   if (!u) return set_error(EXPINT_EINVAL, "u is NULL");

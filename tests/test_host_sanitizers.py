@@ -65,7 +65,7 @@ def _build():
     for p in procs:
         out = p.communicate()[0].decode()
         assert p.returncode == 0, out
-    r = subprocess.run([clangxx, "-fsanitize=address,undefined", *objs, *hip_objs, "-L/opt/rocm/lib", "-lamdhip64",
+    r = subprocess.run([clangxx, "-fsanitize=address,undefined", *objs, *hip_objs, "-L/opt/rocm/lib", "-lamdhip64", "-lrocprofiler-sdk-roctx",
                         "-Wl,-rpath,/opt/rocm/lib", "-o", exe], capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
     return exe
