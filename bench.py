@@ -190,8 +190,8 @@ def cpu_baseline(w, nsteps, scheme="exp_euler"):
         "unit": "voxel-updates/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"{nsteps} FP64 oracle steps ({scheme}) of the same 128^3 workload (plan {s}x{m}), NumPy on 1 host "
-        f"thread, {dt:.1f} s",
+        "sample": f"{nsteps} FP64 oracle steps ({scheme}) of the same {w.shape[0]}^3 workload (plan {s}x{m}), NumPy "
+        f"on 1 host thread, {dt:.1f} s",
     }
 
 
@@ -500,13 +500,14 @@ def run_c4(args):
                  scheme=args.scheme)
     u0 = torch.as_tensor(w.u0, dtype=dt, device="cuda:0").contiguous()
     tg = torch.as_tensor(target, dtype=dt, device="cuda:0").contiguous()
-    ctx.grad(u0, w.nsteps, tg, ckpt_every=10)
     res = {}
 
     def go():
         res["g"] = ctx.grad(u0, w.nsteps, tg, ckpt_every=10)
 
-    ms = _timed(go, None)
+    # the first call also allocates the gradient workspace
+    ms_first = _timed(go, None)
+    ms = min(_timed(go, None) for _ in range(3))
     errs = None
     if os.path.exists(gpath) and args.scheme == "exp_euler":
         g = np.load(gpath)
@@ -526,6 +527,7 @@ def run_c4(args):
         "warmup": 1,
         "ms_per_step": ms / w.nsteps,
         "ms_per_gradient": ms,
+        "ms_first_call": ms_first,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

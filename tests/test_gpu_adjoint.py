@@ -209,3 +209,45 @@ def test_autograd_function_matches_oracle(native):
     assert float(loss.detach()) == pytest.approx(L, rel=1e-12)
     assert rel(u0t.grad.cpu().numpy(), gu) < 1e-10
     check_scalars(float(rt.grad), [float(v) for v in ct.grad], grho, gD, 1e-10)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-4)])
+def test_repeated_gradients(native, dtype, tol):
+    # Repeated calls on one context (three streams, workspace reused) give the
+    # same bits with new u0 / target buffers each time; a new target, a
+    # general cotangent and new parameters give the oracle's new gradients.
+    labels, u0, target = case_small(n=14, seed=5)
+    cd, rho, tau, K, ck = (0.0, 0.10, 0.010), 0.02, 7.3, 5, 2
+    L, gu, grho, gD = oracle_grad(labels, cd, rho, tau, u0, target, K, ck)
+    ctx = make_ctx(labels, cd, dtype, rho=rho, tau=tau)
+    outs = [ctx.grad(dev(u0, dtype), K, dev(target, dtype), ckpt_every=ck) for _ in range(4)]
+    for o in outs[1:]:
+        assert o[0] == outs[0][0] and o[2] == outs[0][2] and o[3] == outs[0][3]
+        assert torch.equal(o[1], outs[0][1])
+    assert outs[0][0] == pytest.approx(L, rel=tol)
+    assert rel(outs[0][1].cpu().numpy(), gu) < tol
+    check_scalars(outs[0][2], outs[0][3], grho, gD, tol)
+    # another target
+    target2 = np.clip(target * 0.7 + 0.05, 0, 1) * (labels != 0)
+    L2, gu2, grho2, gD2 = oracle_grad(labels, cd, rho, tau, u0, target2, K, ck)
+    loss2, g2, r2, d2 = ctx.grad(dev(u0, dtype), K, dev(target2, dtype), ckpt_every=ck)
+    assert loss2 == pytest.approx(L2, rel=tol)
+    assert rel(g2.cpu().numpy(), gu2) < tol
+    check_scalars(r2, d2, grho2, gD2, tol)
+    # a general cotangent (vjp)
+    cot = 0.25 * (labels != 0).astype(np.float64)
+    op = oop.Operator(1.0, labels=labels, class_D=cd)
+    s, m = oplan.for_dtype(tau * op.norm1(), "f64")
+    gv, rv, dv = oadj.vjp(op, u0, rho, tau, s, m, K, cot, ck, classes=[0, 1, 2])
+    for _ in range(3):
+        g3, r3, d3 = ctx.vjp(dev(u0, dtype), K, dev(cot, dtype), ckpt_every=ck)
+        assert rel(g3.cpu().numpy(), gv) < tol
+        check_scalars(r3, d3, rv, {c: dv[c] for c in range(3)}, tol)
+    # new rho (plan kept)
+    ctx.set_params(rho=0.03, replan=False)
+    L4, gu4, grho4, gD4 = oracle_grad(labels, cd, 0.03, tau, u0, target, K, ck, s=s, m=m)
+    for _ in range(3):
+        loss4, g4, r4, d4 = ctx.grad(dev(u0, dtype), K, dev(target, dtype), ckpt_every=ck)
+        assert loss4 == pytest.approx(L4, rel=tol)
+        assert rel(g4.cpu().numpy(), gu4) < tol
+        check_scalars(r4, d4, grho4, gD4, tol)
