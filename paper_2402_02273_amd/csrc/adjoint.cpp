@@ -29,6 +29,7 @@
 #include "context.hpp"
 #include "internal.hpp"
 #include "schedule.hpp"
+#include "trace.hpp"
 
 using namespace expint;
 
@@ -79,24 +80,19 @@ int ensure_adj(expint_ctx* c, int nck, int seg) {
       }
     }
   }
+  // the most steps per segment any call asked for (slot t's buffers do not
+  // depend on it, so a larger value only adds slots)
+  if (seg > a.seg) a.seg = seg;
+  const size_t slots = 2 * static_cast<size_t>(a.seg);
   if ((rc = grow(c, a.ckpt, static_cast<size_t>(nck)))) return rc;
-  if ((rc = grow(c, a.segs, static_cast<size_t>(seg)))) return rc;
-  if ((rc = grow(c, a.segs2, static_cast<size_t>(seg)))) return rc;
-  if ((rc = grow(c, a.xs, 2 * (static_cast<size_t>(c->s) + 1)))) return rc;
-  if ((rc = grow(c, a.tape, 2 * static_cast<size_t>(c->s) * c->m))) return rc;
-  for (int p = 0; p < 2; ++p)
-    if (!a.bt[p] && (rc = c->arena.alloc(&a.bt[p], fb))) return rc;
-  for (void*& r : a.rb)
-    if (!r && (rc = c->arena.alloc(&r, fb))) return rc;
-  if (!a.side) {
-    // the tape stream and its events (default priority, like every stream here)
+  if ((rc = grow(c, a.segs, static_cast<size_t>(a.seg)))) return rc;
+  if ((rc = grow(c, a.segs2, static_cast<size_t>(a.seg)))) return rc;
+  if ((rc = grow(c, a.xs, slots * (static_cast<size_t>(c->s) + 1)))) return rc;
+  if ((rc = grow(c, a.tape, slots * static_cast<size_t>(c->s) * c->m))) return rc;
+  if ((rc = grow(c, a.bts, slots))) return rc;
+  if (!a.rec) {
+    // the segment stream and its events (default priority, like every stream here)
     hipStream_t st = nullptr;
-    HIP_TRY(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    a.side = st;
-    for (int p = 0; p < 2; ++p) {
-      HIP_TRY(c, hipEventCreateWithFlags(&a.ev_tape[p], hipEventDisableTiming));
-      HIP_TRY(c, hipEventCreateWithFlags(&a.ev_rev[p], hipEventDisableTiming));
-    }
     HIP_TRY(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     a.rec = st;
     HIP_TRY(c, hipEventCreateWithFlags(&a.ev_fwd, hipEventDisableTiming));
@@ -108,9 +104,10 @@ int ensure_adj(expint_ctx* c, int nck, int seg) {
   return EXPINT_OK;
 }
 
-void* xs_at(expint_ctx* c, int p, int sig) { return c->adj.xs[static_cast<size_t>(p) * (c->s + 1) + sig]; }
-void** tape_of(expint_ctx* c, int p, int sig) {
-  return &c->adj.tape[(static_cast<size_t>(p) * c->s + (sig - 1)) * c->m];
+// Tape slot t: the sub-step state x_sig, the Taylor terms of sub-step sig.
+void* xs_at(expint_ctx* c, int t, int sig) { return c->adj.xs[static_cast<size_t>(t) * (c->s + 1) + sig]; }
+void** tape_of(expint_ctx* c, int t, int sig) {
+  return &c->adj.tape[(static_cast<size_t>(t) * c->s + (sig - 1)) * c->m];
 }
 
 // Face weights -dK(D_a, D_b)/dD_c / h^2 and wall weights -[a == c] / h^2.
@@ -184,19 +181,19 @@ int term_face(expint_ctx* c, TermOp op, const void* un, const void* y, double w)
 }
 
 // Reverse sweep of one step; lambda (c->adj.lam) is updated in place.
-// The forward tape of step n at the state un into tape set p, on stream st:
+// The forward tape of step n at the state un into tape slot p, on stream st:
 // b_n, the sub-step states and every Taylor term.
 int tape_step(expint_ctx* c, const void* un, int p, hipStream_t st) {
   auto& a = c->adj;
   const int s = c->s, m = c->m;
   const double h = c->tau / s;
   int rc;
-  HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, c->tiling, c->coef(), un, a.bt[p], c->rho, st));
+  HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, c->tiling, c->coef(), un, a.bts[p], c->rho, st));
   for (int sig = 1; sig <= s; ++sig) {
     void** T = tape_of(c, p, sig);
     TermOp t1;
     t1.src = xs_at(c, p, sig - 1);
-    t1.bsrc = a.bt[p];
+    t1.bsrc = a.bts[p];
     t1.c = h;
     t1.cb = h;
     t1.cs = 1.0;
@@ -217,7 +214,7 @@ int tape_step(expint_ctx* c, const void* un, int p, hipStream_t st) {
   return EXPINT_OK;
 }
 
-// The reverse sweeps of step n from tape set p, on the context stream;
+// The reverse sweeps of step n from tape slot p, on the context stream;
 // lambda (c->adj.lam) is updated in place.
 int reverse_step(expint_ctx* c, const void* un, int p) {
   auto& a = c->adj;
@@ -282,8 +279,97 @@ int reverse_step(expint_ctx* c, const void* un, int p) {
   return EXPINT_OK;
 }
 
+// The launches of one gradient, from zeroing the accumulators to the
+// class sums, on the context stream and the two helper streams (joined back
+// into the context stream before the end); the result is left in lam.
+int enqueue_gradient(expint_ctx* c, const void* u0, int32_t nsteps, const void* cot, bool cot_is_target,
+                     int32_t ckpt_every) {
+  int rc;
+  const int nck = nsteps > 0 ? (nsteps + ckpt_every - 1) / ckpt_every : 0;
+  auto& a = c->adj;
+  const int64_t n = c->g.n;
+  const int64_t slots = faceprod_slots(c->g, c->tiling);
+  HIP_TRY(c, launch_fill(EXPINT_F64, 16, 0.0, a.dev, c->stream));
+  HIP_TRY(c, launch_fill(EXPINT_F64, slots * kMaxClasses, 0.0, a.fpart, c->stream));
+  for (int t = 0; t < 2 * a.seg; ++t) HIP_TRY(c, launch_fill(c->dtype, n, 0.0, xs_at(c, t, 0), c->stream));
+  // both segment sets start free
+  for (int q = 0; q < 2; ++q) HIP_TRY(c, hipEventRecord(a.ev_segfree[q], c->stream));
+
+  // Segment sgi uses set sgi & 1: its states and one tape slot per step.
+  auto seg_states = [&](int sgi) -> std::vector<void*>& { return (sgi & 1) ? a.segs2 : a.segs; };
+  auto slot = [&](int sgi, int k) { return (sgi & 1) * a.seg + (k - sgi * ckpt_every); };
+  // The tapes of segment sgi from its first state, already in its states[0],
+  // on stream st: per step the tape (b, sub-step states, Taylor terms) and
+  // the next state u_{k+1} = u_k + x_s.  last_out: where the state after the
+  // segment goes (NULL: nowhere).
+  auto build = [&](int sgi, hipStream_t st, void* last_out) -> int {
+    const int start = sgi * ckpt_every;
+    const int stop = std::min(start + ckpt_every, nsteps);
+    std::vector<void*>& sv = seg_states(sgi);
+    for (int k = start; k < stop; ++k) {
+      const int t = slot(sgi, k);
+      const int r = tape_step(c, sv[k - start], t, st);
+      if (r) return r;
+      void* next = k + 1 < stop ? sv[k - start + 1] : last_out;
+      if (next) HIP_TRY(c, launch_axpby(c->dtype, n, 1.0, sv[k - start], 1.0, xs_at(c, t, c->s), next, st));
+    }
+    return EXPINT_OK;
+  };
+
+  // forward with checkpoints; the last segment's tapes are built as it passes
+  PhaseRange fwd_range("gradient: forward with checkpoints");
+  HIP_TRY(c, launch_copy(c->dtype, n, u0, a.work, c->stream));
+  const int last_start = (nck - 1) * ckpt_every;
+  for (int k = 0; k < last_start; ++k) {
+    if (k % ckpt_every == 0) HIP_TRY(c, launch_copy(c->dtype, n, a.work, a.ckpt[k / ckpt_every], c->stream));
+    // the tapes of the segments before the last may be built from here on
+    if (k == last_start - ckpt_every) HIP_TRY(c, hipEventRecord(a.ev_fwd, c->stream));
+    if ((rc = enqueue_step(c, a.work))) return rc;
+  }
+  if (nck > 0) {
+    HIP_TRY(c, launch_copy(c->dtype, n, a.work, seg_states(nck - 1)[0], c->stream));
+    if ((rc = build(nck - 1, c->stream, a.work))) return rc;
+    HIP_TRY(c, hipEventRecord(a.ev_seg[(nck - 1) & 1], c->stream));
+  }
+  if (cot_is_target) {
+    HIP_TRY(c, launch_reduce(c->dtype, 5, a.work, cot, n, c->partial, a.dev + 9, c->stream));
+    HIP_TRY(c, launch_axpby(c->dtype, n, 1.0, a.work, -1.0, cot, a.lam, c->stream));
+  } else {
+    HIP_TRY(c, launch_copy(c->dtype, n, cot, a.lam, c->stream));
+  }
+
+  fwd_range.end();
+  PhaseRange rev_range("gradient: reverse segments (tapes built one segment ahead on a second stream)");
+  // Two streams from here on: the tapes of segment sgi - 1 are built on
+  // `rec` from its checkpoint while segment sgi reverses on the context
+  // stream.
+  if (nck >= 2) HIP_TRY(c, hipStreamWaitEvent(a.rec, a.ev_fwd, 0));
+  for (int sgi = nck - 1; sgi >= 0; --sgi) {
+    const int start = sgi * ckpt_every;
+    const int stop = std::min(start + ckpt_every, nsteps);
+    const int q = sgi & 1;
+    if (sgi >= 1) {
+      const int qp = (sgi - 1) & 1;
+      HIP_TRY(c, hipStreamWaitEvent(a.rec, a.ev_segfree[qp], 0));
+      HIP_TRY(c, launch_copy(c->dtype, n, a.ckpt[sgi - 1], seg_states(sgi - 1)[0], a.rec));
+      if ((rc = build(sgi - 1, a.rec, nullptr))) return rc;
+      HIP_TRY(c, hipEventRecord(a.ev_seg[qp], a.rec));
+    }
+    HIP_TRY(c, hipStreamWaitEvent(c->stream, a.ev_seg[q], 0));
+    std::vector<void*>& sv = seg_states(sgi);
+    for (int k = stop - 1; k >= start; --k)
+      if ((rc = reverse_step(c, sv[k - start], slot(sgi, k)))) return rc;
+    // every read of this set (states and tapes) is behind this event
+    HIP_TRY(c, hipEventRecord(a.ev_segfree[q], c->stream));
+  }
+  rev_range.end();
+  HIP_TRY(c, launch_faceprod_final(a.fpart, slots, a.dev, c->stream));
+  return EXPINT_OK;
+}
+
 int vjp_core(expint_ctx* c, const void* u0, int32_t nsteps, const void* cot, bool cot_is_target, int32_t ckpt_every,
              double* loss, void* grad_u0, double* grad_rho, double* grad_D) {
+  PhaseRange range("gradient");
   CHECK_CTX(c);
   if (!u0 || !cot || !grad_u0) return set_error(EXPINT_EINVAL, "NULL field");
   if (nsteps < 0) return set_error(EXPINT_EINVAL, "nsteps must be >= 0");
@@ -300,86 +386,9 @@ int vjp_core(expint_ctx* c, const void* u0, int32_t nsteps, const void* cot, boo
   if ((rc = ensure_adj(c, nck, seg))) return rc;
   if ((rc = upload_weights(c))) return rc;
   auto& a = c->adj;
-  const int64_t n = c->g.n;
-  const int64_t slots = faceprod_slots(c->g, c->tiling);
-  HIP_TRY(c, launch_fill(EXPINT_F64, 16, 0.0, a.dev, c->stream));
-  HIP_TRY(c, launch_fill(EXPINT_F64, slots * kMaxClasses, 0.0, a.fpart, c->stream));
-  for (int p = 0; p < 2; ++p) HIP_TRY(c, launch_fill(c->dtype, n, 0.0, xs_at(c, p, 0), c->stream));
-  // both tape sets and both segment-state sets start free
-  for (int p = 0; p < 2; ++p) HIP_TRY(c, hipEventRecord(a.ev_rev[p], c->stream));
-  for (int q = 0; q < 2; ++q) HIP_TRY(c, hipEventRecord(a.ev_segfree[q], c->stream));
-
-  // Segment sgi keeps its states in set sgi & 1.
-  auto seg_states = [&](int sgi) -> std::vector<void*>& { return (sgi & 1) ? a.segs2 : a.segs; };
-  // forward with checkpoints; the last segment's states are kept as they pass
-  HIP_TRY(c, launch_copy(c->dtype, n, u0, a.work, c->stream));
-  const int last_start = (nck - 1) * ckpt_every;
-  for (int k = 0; k < nsteps; ++k) {
-    if (k % ckpt_every == 0) HIP_TRY(c, launch_copy(c->dtype, n, a.work, a.ckpt[k / ckpt_every], c->stream));
-    // the recompute of the segments before the last may start from here on
-    if (k == last_start - ckpt_every) HIP_TRY(c, hipEventRecord(a.ev_fwd, c->stream));
-    if (k >= last_start) HIP_TRY(c, launch_copy(c->dtype, n, a.work, seg_states(nck - 1)[k - last_start], c->stream));
-    if ((rc = enqueue_step(c, a.work))) return rc;
-  }
-  if (cot_is_target) {
-    HIP_TRY(c, launch_reduce(c->dtype, 5, a.work, cot, n, c->partial, a.dev + 9, c->stream));
-    HIP_TRY(c, launch_axpby(c->dtype, n, 1.0, a.work, -1.0, cot, a.lam, c->stream));
-  } else {
-    HIP_TRY(c, launch_copy(c->dtype, n, cot, a.lam, c->stream));
-  }
-
-  // Three streams from here on: the states of segment sgi - 1 are recomputed
-  // on `rec` while segment sgi reverses on the context stream, and within a
-  // segment the tape of step k - 1 is recomputed on `side` while step k
-  // reverses.  Segment sgi uses state set sgi & 1, step k tape set k & 1.
-  if (nck >= 2) HIP_TRY(c, hipStreamWaitEvent(a.rec, a.ev_fwd, 0));
-  const StepBuffers rsb{a.rb[0], {a.rb[1], a.rb[2]}, {a.rb[3], a.rb[4]}};
-  auto recompute = [&](int sgi) -> int {
-    const int q = sgi & 1;
-    const int start = sgi * ckpt_every;
-    const int stop = std::min(start + ckpt_every, nsteps);
-    std::vector<void*>& sv = seg_states(sgi);
-    HIP_TRY(c, hipStreamWaitEvent(a.rec, a.ev_segfree[q], 0));
-    HIP_TRY(c, launch_copy(c->dtype, n, a.ckpt[sgi], sv[0], a.rec));
-    for (int k = start; k < stop - 1; ++k) {
-      HIP_TRY(c, launch_copy(c->dtype, n, sv[k - start], sv[k - start + 1], a.rec));
-      const int r = enqueue_step_on(c, sv[k - start + 1], a.rec, &rsb);
-      if (r) return r;
-    }
-    HIP_TRY(c, hipEventRecord(a.ev_seg[q], a.rec));
-    return EXPINT_OK;
-  };
-  // the last segment's states came from the forward pass
-  if (nck > 0) HIP_TRY(c, hipEventRecord(a.ev_seg[(nck - 1) & 1], c->stream));
-  for (int sgi = nck - 1; sgi >= 0; --sgi) {
-    const int start = sgi * ckpt_every;
-    const int stop = std::min(start + ckpt_every, nsteps);
-    const int q = sgi & 1;
-    std::vector<void*>& sv = seg_states(sgi);
-    if (sgi >= 1 && (rc = recompute(sgi - 1))) return rc;
-    HIP_TRY(c, hipStreamWaitEvent(a.side, a.ev_seg[q], 0));
-    HIP_TRY(c, hipStreamWaitEvent(c->stream, a.ev_seg[q], 0));
-    auto issue_tape = [&](int k) -> int {
-      const int p = k & 1;
-      HIP_TRY(c, hipStreamWaitEvent(a.side, a.ev_rev[p], 0));
-      const int r = tape_step(c, sv[k - start], p, a.side);
-      if (r) return r;
-      HIP_TRY(c, hipEventRecord(a.ev_tape[p], a.side));
-      return EXPINT_OK;
-    };
-    if ((rc = issue_tape(stop - 1))) return rc;
-    for (int k = stop - 1; k >= start; --k) {
-      if (k - 1 >= start && (rc = issue_tape(k - 1))) return rc;
-      const int p = k & 1;
-      HIP_TRY(c, hipStreamWaitEvent(c->stream, a.ev_tape[p], 0));
-      if ((rc = reverse_step(c, sv[k - start], p))) return rc;
-      HIP_TRY(c, hipEventRecord(a.ev_rev[p], c->stream));
-    }
-    // every read of this state set (tapes included) is behind this event
-    HIP_TRY(c, hipEventRecord(a.ev_segfree[q], c->stream));
-  }
-  HIP_TRY(c, launch_copy(c->dtype, n, a.lam, grad_u0, c->stream));
-  HIP_TRY(c, launch_faceprod_final(a.fpart, slots, a.dev, c->stream));
+  if ((rc = enqueue_gradient(c, u0, nsteps, cot, cot_is_target, ckpt_every))) return rc;
+  HIP_TRY(c, launch_copy(c->dtype, c->g.n, a.lam, grad_u0, c->stream));
+  PhaseRange sync_range("gradient: wait for the device");
   double host[16];
   HIP_TRY(c, hipMemcpyAsync(host, a.dev, sizeof(host), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));

@@ -19,6 +19,7 @@
 #include "autotune.hpp"
 #include "modal.hpp"
 #include "schedule.hpp"
+#include "trace.hpp"
 
 using namespace expint;
 
@@ -268,6 +269,7 @@ const char* expint_last_error(void) { return expint::last_error(); }
 
 int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, expint_bc bc,
                   const expint_opts* opts, expint_ctx** out) {
+  PhaseRange range("expint_create");
   if (out) *out = nullptr;
   if (!grid || !df || !opts || !out) return set_error(EXPINT_EINVAL, "NULL argument");
   if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1)
@@ -379,6 +381,7 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
   if ((rc = c->arena.alloc(reinterpret_cast<void**>(&c->red), 2 * sizeof(double)))) return bail(rc);
 
   double bad = 0.0;
+  PhaseRange scan_range("expint_create: coefficients, norm scan, plan");
   if (c->labels_form) {
     c->nclass = df->n_classes;
     for (int a = 0; a < c->nclass; ++a) c->class_D[a] = df->class_D[a];
@@ -425,6 +428,8 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
     if ((rc = c->arena.alloc(&c->y[i], fb))) return bail(rc);
     if ((rc = c->arena.alloc(&c->acc[i], fb))) return bail(rc);
   }
+  scan_range.end();
+  PhaseRange tune_range("expint_create: sweep autotuning");
   {
     const bool lin = c->scheme == EXPINT_SCHEME_LINEARISED;
     const hipError_t e = autotune_sweep(c->dtype, c->bc, c->g, c->coef(), c->y[0], c->acc[0], c->y[1], c->stream,
@@ -447,7 +452,11 @@ int expint_create(const expint_grid* grid, const expint_dfield* df, double rho, 
       return bail(set_error(EXPINT_EHIP, "pair-sweep autotune failed: %s", hipGetErrorString(e)));
     }
   }
-  if (c->algo == EXPINT_ALGO_MODAL && (rc = modal_setup(c))) return bail(rc);
+  tune_range.end();
+  if (c->algo == EXPINT_ALGO_MODAL) {
+    PhaseRange modal_range("expint_create: modal set-up");
+    if ((rc = modal_setup(c))) return bail(rc);
+  }
   if (std::getenv("EXPINT_LOG"))
     std::fprintf(stderr,
                  "[expint] grid %dx%dx%d h=%g dtype=%s scheme=%s ||A||_1=%.17g nu=%.6g plan s=%d m=%d workspace %zu B\n",
@@ -470,13 +479,11 @@ void expint_destroy(expint_ctx* c) {
   if (c->stream && !c->poisoned) (void)hipStreamSynchronize(c->stream);
   destroy_graphs(c->graphs);
   auto& a = c->adj;
-  for (hipStream_t st : {a.side, a.rec}) {
-    if (!st) continue;
-    if (!c->poisoned) (void)hipStreamSynchronize(st);
-    (void)hipStreamDestroy(st);
+  if (a.rec) {
+    if (!c->poisoned) (void)hipStreamSynchronize(a.rec);
+    (void)hipStreamDestroy(a.rec);
   }
-  for (hipEvent_t e : {a.ev_tape[0], a.ev_tape[1], a.ev_rev[0], a.ev_rev[1], a.ev_fwd, a.ev_seg[0], a.ev_seg[1],
-                       a.ev_segfree[0], a.ev_segfree[1]})
+  for (hipEvent_t e : {a.ev_fwd, a.ev_seg[0], a.ev_seg[1], a.ev_segfree[0], a.ev_segfree[1]})
     if (e) (void)hipEventDestroy(e);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   const int dev = c->device;
@@ -601,6 +608,7 @@ int expint_step(expint_ctx* c, void* u) {
 }
 
 int expint_advance(expint_ctx* c, void* u, int32_t nsteps) {
+  PhaseRange range("expint_advance");
   CHECK_CTX(c);
   if (!u) return set_error(EXPINT_EINVAL, "u is NULL");
   if (nsteps < 0) return set_error(EXPINT_EINVAL, "nsteps must be >= 0");
@@ -666,6 +674,7 @@ int run_steps(expint_ctx* c, void* u, int32_t nsteps) {
     GraphEntry e;
     e.key0 = u;
     e.nsteps = 1;
+    PhaseRange range("record step graph");
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     rc = enqueue_step(c, u);
     hipGraph_t gr = nullptr;

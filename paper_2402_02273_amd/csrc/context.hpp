@@ -124,25 +124,23 @@ struct expint_ctx {
   // adjoint workspace: allocated on the first gradient call, regrown on demand
   struct Adj {
     std::vector<void*> ckpt;  // u every ckpt_every steps
-    std::vector<void*> segs;  // states of one checkpoint segment
-    // Two tape sets: the tape of step n - 1 is recomputed on `side` while
-    // step n reverses on the context stream.  Set p holds b_n (bt[p]), the
-    // sub-step states x_0 .. x_s (xs[p (s + 1) ..]) and the Taylor terms
-    // y_1 .. y_m of every sub-step (tape[p s m ..]).
+    // Two segment sets, used by alternate checkpoint segments: the states
+    // u_k of every step of the segment (segs, segs2) and its tape, one slot
+    // per step.  Slot t holds b_k (bts[t]), the sub-step states x_0 .. x_s
+    // (xs[t (s + 1) ..]) and the Taylor terms y_1 .. y_m of every sub-step
+    // (tape[t s m ..]); segment sgi's step k uses slot (sgi & 1) seg + k - start.
+    std::vector<void*> segs;
+    std::vector<void*> segs2;
     std::vector<void*> xs;
     std::vector<void*> tape;
-    void* bt[2] = {nullptr, nullptr};
-    hipStream_t side = nullptr;
-    hipEvent_t ev_tape[2] = {nullptr, nullptr};  // tape set p written
-    hipEvent_t ev_rev[2] = {nullptr, nullptr};   // tape set p no longer read
-    // Two segment-state sets: the states of segment k - 1 are recomputed on
-    // `rec`, with step buffers of its own, while segment k reverses (the
-    // first of them while the forward pass still runs).
-    std::vector<void*> segs2;                    // second set, like segs
-    void* rb[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // rec's step buffers: b, y0, y1, acc0, acc1
+    std::vector<void*> bts;
+    int seg = 0;  // steps per segment set
+    // the tapes of segment k - 1 are built on `rec` while segment k reverses
+    // on the context stream (the first of them while the forward pass still
+    // runs); the last segment's are built by the forward pass itself
     hipStream_t rec = nullptr;
-    hipEvent_t ev_fwd = nullptr;                 // forward pass with checkpoints done
-    hipEvent_t ev_seg[2] = {nullptr, nullptr};   // segment-state set q recomputed
+    hipEvent_t ev_fwd = nullptr;                    // checkpoint of the second-to-last segment written
+    hipEvent_t ev_seg[2] = {nullptr, nullptr};      // segment set q built
     hipEvent_t ev_segfree[2] = {nullptr, nullptr};  // set q no longer read
     void* lam = nullptr;      // adjoint state
     void* gb = nullptr;       // adjoint of b (= P(A) lambda)
