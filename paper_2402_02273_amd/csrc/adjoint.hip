@@ -29,44 +29,69 @@ namespace {
 
 constexpr int kFaceLP = 4;  // x-planes per lane of the vectorised face products
 
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// x plus its value at the lane the DPP pattern CTRL names (a permutation
+// within each row of 16 lanes), moved as two 32-bit halves.
+template <int CTRL>
+__device__ __forceinline__ double dpp_add(double x) {
+  const unsigned long long bits = static_cast<unsigned long long>(__double_as_longlong(x));
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(bits & 0xffffffffull), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(bits >> 32), CTRL, 0xf, 0xf, false);
+  const unsigned long long p = (static_cast<unsigned long long>(static_cast<unsigned int>(hi)) << 32) |
+                               static_cast<unsigned int>(lo);
+  return x + __longlong_as_double(static_cast<long long>(p));
 }
 
-// Sums acc over the workgroup (fixed order) and adds weight * sum into
+// The sum over each row of 16 lanes, in every lane of the row: pairs
+// (quad_perm 1,0,3,2), quads (quad_perm 2,3,0,1), half rows (half mirror),
+// rows (mirror); register moves only, no LDS.
+__device__ __forceinline__ double row_sum(double v) {
+  v = dpp_add<0xb1>(v);
+  v = dpp_add<0x4e>(v);
+  v = dpp_add<0x141>(v);
+  return dpp_add<0x140>(v);
+}
+
+// Sums acc over the workgroup (fixed order: rows of 16 lanes, then the
+// workgroup's rows in order) and adds weight * sum into
 // partial[blockIdx.x * 8 + c] for the NC classes of the grid (the slots of
 // the other classes stay as filled, zero).  Every thread of the workgroup
-// must call it.
+// must call it, in converged control flow.
 template <int NC>
 __device__ __forceinline__ void block_accumulate(double (&acc)[kMaxClasses], double weight, double* partial) {
-  __shared__ double red[kBlock / 64][kMaxClasses];
+  __shared__ double red[kBlock / 16][kMaxClasses];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const double v = wave_sum(acc[c]);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][c] = v;
+    const double v = row_sum(acc[c]);
+    if ((threadIdx.x & 15) == 0) red[threadIdx.x >> 4][c] = v;
   }
   __syncthreads();
   if (threadIdx.x < NC) {
     double v = 0.0;
-    for (int w = 0; w < kBlock / 64; ++w) v += red[w][threadIdx.x];
+    for (int r = 0; r < kBlock / 16; ++r) v += red[r][threadIdx.x];
     double* slot = partial + static_cast<size_t>(blockIdx.x) * kMaxClasses + threadIdx.x;
     *slot = *slot + weight * v;
   }
 }
 
+// Class weights of the faces in LDS with the class index fastest, so that
+// one face's NC weights are adjacent: tab[(a * 8 + b) * face_stride<NC>() + c].
+template <int NC>
+constexpr int face_stride() {
+  return NC <= 2 ? 2 : (NC <= 4 ? 4 : 8);
+}
+
 struct FaceTables {
-  double tab[kMaxClasses * kTab];          // [c][a][b]
-  double wall[kMaxClasses * kMaxClasses];  // [c][a]
+  alignas(16) double tab[kMaxClasses * kTab];  // [a][b][c], see face_stride
+  double wall[kMaxClasses * kMaxClasses];      // [c][a]
 };
 
 // Stages the entries a grid of NC classes can reach (class c, labels a, b
-// below NC), in the tables' own layout.
+// below NC) from the device tables ([c][a][b] and [c][a]).
 template <int NC>
 __device__ __forceinline__ void load_face_tables(FaceTables& ft, const double* dtab, const double* dwall) {
   for (int t = threadIdx.x; t < NC * NC * NC; t += kBlock) {
-    const int o = (t / (NC * NC)) * kTab + ((t / NC) % NC) * kMaxClasses + t % NC;
-    ft.tab[o] = dtab[o];
+    const int c = t / (NC * NC), a = (t / NC) % NC, b = t % NC;
+    ft.tab[(a * kMaxClasses + b) * face_stride<NC>() + c] = dtab[c * kTab + a * kMaxClasses + b];
   }
   if (threadIdx.x < NC * NC) {
     const int o = (threadIdx.x / NC) * kMaxClasses + threadIdx.x % NC;
@@ -77,9 +102,17 @@ __device__ __forceinline__ void load_face_tables(FaceTables& ft, const double* d
 template <int NC>
 __device__ __forceinline__ void add_face(double (&acc)[kMaxClasses], const FaceTables& ft, int la, int lb,
                                          double prod) {
-  const double* w = ft.tab + la * kMaxClasses + lb;
+  const double* w = ft.tab + (la * kMaxClasses + lb) * face_stride<NC>();
 #pragma unroll
-  for (int c = 0; c < NC; ++c) acc[c] += w[c * kTab] * prod;
+  for (int c = 0; c < NC; ++c) acc[c] += w[c] * prod;
+}
+
+// (xp - xq)(yp - yq) with the differences taken in the field's own type (an
+// FP32 difference is exact when the two are within a factor of two, else
+// off by at most one rounding) and the product in FP64.
+template <typename T>
+__device__ __forceinline__ double face_prod(T xp, T xq, T yp, T yq) {
+  return static_cast<double>(xp - xq) * static_cast<double>(yp - yq);
 }
 
 // Scalar form: any grid; grid-stride over voxels.  NC = number of classes.
@@ -104,7 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_faceprod(Geom g, const uint8_t* __re
     const int lp = lab[p];
     const double ybp = static_cast<double>(yb[p]), yp = static_cast<double>(y[p]);
     auto face = [&](int q) {
-      add_face<NC>(acc, ft, lp, lab[q], (ybp - static_cast<double>(yb[q])) * (yp - static_cast<double>(y[q])));
+      add_face<NC>(acc, ft, lp, lab[q], face_prod<T>(yb[p], yb[q], y[p], y[q]));
     };
     if (i < g.nx - 1) face(p + sx);
     if (j < g.ny - 1) face(p + sy);
@@ -181,14 +214,12 @@ __global__ __launch_bounds__(kBlock) void k_faceprod4(Geom g, int gzs, int gy, i
         const int le = label_byte(lc, e);
         const double bp = static_cast<double>(bc.v[e]), vp = static_cast<double>(vc.v[e]);
         // +x and +y faces (the voxel itself at the far walls: product 0)
-        add_face<NC>(acc, ft, le, label_byte(ln, e),
-                     (bp - static_cast<double>(bn.v[e])) * (vp - static_cast<double>(vn.v[e])));
-        add_face<NC>(acc, ft, le, label_byte(ly, e),
-                     (bp - static_cast<double>(by.v[e])) * (vp - static_cast<double>(vy.v[e])));
+        add_face<NC>(acc, ft, le, label_byte(ln, e), face_prod<T>(bc.v[e], bn.v[e], vc.v[e], vn.v[e]));
+        add_face<NC>(acc, ft, le, label_byte(ly, e), face_prod<T>(bc.v[e], by.v[e], vc.v[e], vy.v[e]));
         // +z face
-        const double bq = static_cast<double>(e < 3 ? bc.v[e + 1] : bz);
-        const double vq = static_cast<double>(e < 3 ? vc.v[e + 1] : vz);
-        add_face<NC>(acc, ft, le, e < 3 ? label_byte(lc, e + 1) : lz, (bp - bq) * (vp - vq));
+        const T bq = e < 3 ? bc.v[e + 1] : bz;
+        const T vq = e < 3 ? vc.v[e + 1] : vz;
+        add_face<NC>(acc, ft, le, e < 3 ? label_byte(lc, e + 1) : lz, face_prod<T>(bc.v[e], bq, vc.v[e], vq));
         if (BC) {
           const int nw = (i == 0) + (i == g.nx - 1) + (j == 0) + (j == g.ny - 1) + (e == 0 && k4 == 0) +
                          (e == 3 && wall_hi);
@@ -296,13 +327,11 @@ struct FaceAcc {
     for (int e = 0; e < 4; ++e) {
       const int le = label_byte(lc, e);
       const double bp = static_cast<double>(bc.v[e]), vp = static_cast<double>(vc.v[e]);
-      add_face<NC>(acc, ft, le, label_byte(ln, e),
-                   (bp - static_cast<double>(bn.v[e])) * (vp - static_cast<double>(vn.v[e])));
-      add_face<NC>(acc, ft, le, label_byte(ly, e),
-                   (bp - static_cast<double>(by.v[e])) * (vp - static_cast<double>(vy.v[e])));
-      const double bq = static_cast<double>(e < 3 ? bc.v[e + 1] : bz);
-      const double vq = static_cast<double>(e < 3 ? vc.v[e + 1] : vz);
-      add_face<NC>(acc, ft, le, e < 3 ? label_byte(lc, e + 1) : lz, (bp - bq) * (vp - vq));
+      add_face<NC>(acc, ft, le, label_byte(ln, e), face_prod<T>(bc.v[e], bn.v[e], vc.v[e], vn.v[e]));
+      add_face<NC>(acc, ft, le, label_byte(ly, e), face_prod<T>(bc.v[e], by.v[e], vc.v[e], vy.v[e]));
+      const T bq = e < 3 ? bc.v[e + 1] : bz;
+      const T vq = e < 3 ? vc.v[e + 1] : vz;
+      add_face<NC>(acc, ft, le, e < 3 ? label_byte(lc, e + 1) : lz, face_prod<T>(bc.v[e], bq, vc.v[e], vq));
       if (BC) {
         const int nw = (i == 0) + (i == g.nx - 1) + (j == 0) + (j == g.ny - 1) + (e == 0 && k4 == 0) +
                        (e == 3 && wall_hi);
