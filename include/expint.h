@@ -247,9 +247,10 @@ int expint_step(expint_ctx* ctx, void* u);
 int expint_advance(expint_ctx* ctx, void* u, int32_t nsteps);
 
 /* Deterministic FP64 reductions over a device field of the context dtype:
- * op 0 = sum x, 1 = sum x*y, 2 = max |x|.  y is used by op 1 only.
- * Writes the host scalar *out (synchronises the stream).  The tumour volume
- * diagnostic of the paper's convergence study (section 3.5) is op 0 / n. */
+ * op 0 = sum x, 1 = sum x*y, 2 = max |x|, 3 = sum x / (nx ny nz), the tumour
+ * volume diagnostic of the paper's convergence study (section 3.5).  y is
+ * used by op 1 only.  Writes the host scalar *out (synchronises the
+ * stream). */
 int expint_reduce(expint_ctx* ctx, int32_t op, const void* x, const void* y, double* out);
 
 /* Gradient of loss = 0.5 ||u_T - u_target||^2, u_T = nsteps steps from u0,

@@ -707,13 +707,15 @@ extern "C" {
 
 int expint_reduce(expint_ctx* c, int32_t op, const void* x, const void* y, double* out) {
   CHECK_CTX(c);
-  if (op < 0 || op > 2) return set_error(EXPINT_EINVAL, "reduce op must be 0, 1 or 2");
+  if (op < 0 || op > 3) return set_error(EXPINT_EINVAL, "reduce op must be 0, 1, 2 or 3");
   if (!x || !out || (op == 1 && !y)) return set_error(EXPINT_EINVAL, "NULL argument");
   int rc = ensure_device(c);
   if (rc) return rc;
-  HIP_TRY(c, launch_reduce(c->dtype, op, x, y, c->g.n, c->partial, c->red, c->stream));
+  // op 3, the mean, is the sum (op 0) over the voxel count
+  HIP_TRY(c, launch_reduce(c->dtype, op == 3 ? 0 : op, x, y, c->g.n, c->partial, c->red, c->stream));
   HIP_TRY(c, hipMemcpyAsync(out, c->red, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (op == 3) *out /= static_cast<double>(c->g.n);
   return EXPINT_OK;
 }
 

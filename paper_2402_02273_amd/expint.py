@@ -270,7 +270,7 @@ class ExpInt:
         return u
 
     def reduce(self, op: str, x, y=None) -> float:
-        code = {"sum": 0, "dot": 1, "maxabs": 2}[op]
+        code = {"sum": 0, "dot": 1, "maxabs": 2, "mean": 3}[op]
         out = ctypes.c_double()
         yp = self._field(y, "y") if y is not None else None
         N.check(self.lib.expint_reduce(self._ctx, code, self._field(x, "x"), yp, ctypes.byref(out)))
@@ -278,7 +278,7 @@ class ExpInt:
 
     def tumour_volume(self, u) -> float:
         """Sum of the density over the grid divided by the voxel count."""
-        return self.reduce("sum", u) / self.n
+        return self.reduce("mean", u)
 
     # ---- gradients ----
     def grad(self, u0, nsteps, u_target, ckpt_every=10):

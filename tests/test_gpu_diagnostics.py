@@ -146,6 +146,8 @@ def test_volumes_per_step_vs_oracle(native, scheme, dtype, tol):
     u = dev(w.u0, dtype)
     vols = ctx.advance_volumes(u, w.nsteps)
     np.testing.assert_allclose(vols, ref, rtol=tol)
+    # the single-field volume (reduce op 3) agrees with the last per-step one
+    assert ctx.tumour_volume(u) == pytest.approx(ref[-1], rel=tol)
     # the state is the same as after a plain advance
     u2 = dev(w.u0, dtype)
     ctx.advance(u2, w.nsteps)
