@@ -569,16 +569,11 @@ struct EV {
   uint4 v[NE / 8];
 };
 
-// v if ok, else zeros; per component (a select of whole uint4 aggregates is
-// lowered to a select of their addresses, which forces them into scratch).
+// The 16 bytes of a buffer load as a uint4.
 typedef int i32x4_buf __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ uint4 as_uint4(i32x4_buf v) {
   return make_uint4(static_cast<unsigned>(v.x), static_cast<unsigned>(v.y), static_cast<unsigned>(v.z),
                     static_cast<unsigned>(v.w));
-}
-
-__device__ __forceinline__ uint4 keep_if(bool ok, const uint4& v) {
-  return make_uint4(ok ? v.x : 0u, ok ? v.y : 0u, ok ? v.z : 0u, ok ? v.w : 0u);
 }
 
 template <int PREC, int NE>
@@ -589,6 +584,133 @@ __device__ __forceinline__ void split_n(const float (&v)[NE], EV<NE>& hi, EV<NE>
   for (int e = 0; e < NE; ++e) split<PREC>(v[e], h[e], l[e]);
   __builtin_memcpy(&hi, h, sizeof(h));
   __builtin_memcpy(&lo, l, sizeof(l));
+}
+
+// Output tile of one GEMM workgroup.  Left: (p, mode tile, column tile);
+// right: (row tile, mode tile).  mrows / ncols bound the whole problem.
+struct GemmTile {
+  long m0, c0, mrows, ncols;
+  int p;
+};
+
+template <int SIDE, int GM, int GN>
+__device__ __forceinline__ GemmTile gemm_tile(const ModalArgs& a) {
+  GemmTile t;
+  t.p = 0;
+  if (SIDE == 0) {
+    const long ct = (a.post + GN - 1) / GN, mt = (a.n + GM - 1) / GM;
+    long b = blockIdx.x;
+    const long cti = b % ct;
+    b /= ct;
+    t.m0 = (b % mt) * GM;
+    t.p = static_cast<int>(b / mt);
+    t.c0 = cti * GN;
+    t.mrows = a.n;
+    t.ncols = a.post;
+  } else {
+    const long ct = (a.n + GN - 1) / GN;
+    t.m0 = (blockIdx.x / ct) * GM;
+    t.c0 = (blockIdx.x % ct) * GN;
+    t.mrows = a.pre;
+    t.ncols = a.n;
+  }
+  return t;
+}
+
+// Row table of the phi1 multiplier (left product, kEpiMul): exp(z) is
+// separable, exp(z_row + z_col) = exp(z_row) exp(z_col), so each row's
+// tauD lambda_x and its exponential are formed once per tile (FP64, LDS:
+// rowv[0, GM) and rowv[GM, 2 GM)) and each column's once per lane; per element
+// the multiplier is then tau (e_row e_col - 1) / z.  z <= 0, and z == 0 only
+// for the constant mode, where e_row e_col - 1 is exactly 0 too.  The caller
+// publishes the table with a barrier.
+template <int GM>
+__device__ __forceinline__ void phi1_rows(const ModalArgs& a, const GemmTile& tl, double* rowv) {
+  const int tid = threadIdx.x;
+  if (tid < GM) {
+    const long row = tl.m0 + tid;
+    const double zr = row < tl.mrows ? a.tauD * a.lam_x[row] : 0.0;
+    rowv[tid] = zr;
+    rowv[GM + tid] = exp(zr);
+  }
+}
+
+// Stores a wave's 64 x 64 block, 2 x 2 accumulator tiles of 32 x 32 with
+// D[row][col] at col = lane % 32, row = 8 (r / 4) + 4 (lane / 32) + r % 4:
+// plain, times tau phi1 (kEpiMul, rows from rowv) or added into the output
+// (kEpiAddU).
+template <int SIDE, int EPI, int GM, int GN>
+__device__ __forceinline__ void gemm_epilogue(const ModalArgs& a, const GemmTile& tl, const f32x16 (&acc)[2][2],
+                                              const double* rowv, int wm, int wn, int lane) {
+  float* __restrict__ out = static_cast<float*>(a.out);
+  const int n = a.n;
+  const long m0 = tl.m0, c0 = tl.c0, mrows = tl.mrows, ncols = tl.ncols;
+  const int p = tl.p;
+  const int fr = lane & 31;
+  const long rs = SIDE == 0 ? a.post : n;  // row stride of the output
+  float* const obase = out + (SIDE == 0 ? static_cast<long>(p) * n * a.post : 0);
+  if (m0 + GM <= mrows && c0 + GN <= ncols && rs * GM < (1L << 31)) {
+    // interior tile: no per-element bounds, a uniform base per 32 x 32 block
+    // and a 32-bit offset per element
+    const int irs = static_cast<int>(rs);
+    const int lane_off = 4 * (lane >> 5) * irs + fr;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        float* const tb = obase + (m0 + wm + 32 * t) * rs + c0 + wn + 32 * u;
+        double zc = 0.0, ec = 1.0;  // kEpiMul: tauD (lambda_y + lambda_z) of this lane's column, its exp
+        if (SIDE == 0 && EPI == kEpiMul) {
+          const long col = c0 + wn + 32 * u + fr;
+          zc = a.tauD * (a.lam_y[col / a.nz] + a.lam_z[col % a.nz]);
+          ec = exp(zc);
+        }
+        // add into u: all 16 loads of the block before its stores (a load
+        // after a store to the same buffer would wait for the store's address)
+        float old[16];
+        if (SIDE == 1 && EPI == kEpiAddU) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) old[r] = tb[(8 * (r >> 2) + (r & 3)) * irs + lane_off];
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int off = (8 * (r >> 2) + (r & 3)) * irs + lane_off;
+          float v = acc[t][u][r];
+          if (SIDE == 0 && EPI == kEpiMul) {
+            const int rl = wm + 32 * t + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            v *= phi1_sep(rowv[rl], rowv[GM + rl], zc, ec, static_cast<float>(a.tau));
+          }
+          if (SIDE == 1 && EPI == kEpiAddU) tb[off] = old[r] + v;
+          else tb[off] = v;
+        }
+      }
+    return;
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const long col = c0 + wn + 32 * u + fr;
+      if (col >= ncols) continue;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const long row = m0 + wm + 32 * t + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (row >= mrows) continue;
+        float v = acc[t][u][r];
+        if (SIDE == 0) {
+          if (EPI == kEpiMul) {
+            const int rl = static_cast<int>(row - m0);
+            const double zc = a.tauD * (a.lam_y[col / a.nz] + a.lam_z[col % a.nz]);
+            v *= phi1_sep(rowv[rl], rowv[GM + rl], zc, exp(zc), static_cast<float>(a.tau));
+          }
+          out[static_cast<long>(p) * n * a.post + row * a.post + col] = v;
+        } else {
+          const long idx = row * n + col;
+          if (EPI == kEpiAddU) out[idx] = out[idx] + v;
+          else out[idx] = v;
+        }
+      }
+    }
 }
 
 template <int PREC, int SIDE, int EPI, int TMW, int TNW>
@@ -604,33 +726,13 @@ __global__ __launch_bounds__(64 * TMW * TNW) void k_mode_gemm(ModalArgs a) {
   static_assert(EO % 8 == 0 && EF % 4 == 0, "16-byte staging pieces");
   __shared__ GemmLds<PREC, TMW, TNW> s;
   const float* __restrict__ in = static_cast<const float*>(a.in);
-  float* __restrict__ out = static_cast<float*>(a.out);
   const E* __restrict__ qhi = static_cast<const E*>(a.q);
   const int n = a.n;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / TNW) * 64, wn = (wave % TNW) * 64;  // the wave's block
-
-  // tile coordinates: left: (p, m-tile, column tile); right: (row tile, mode tile)
-  long m0, c0;
-  int p = 0;
-  long mrows, ncols;  // valid rows / columns of the whole problem
-  if (SIDE == 0) {
-    const long ct = (a.post + GN - 1) / GN, mt = (n + GM - 1) / GM;
-    long b = blockIdx.x;
-    const long cti = b % ct;
-    b /= ct;
-    m0 = (b % mt) * GM;
-    p = static_cast<int>(b / mt);
-    c0 = cti * GN;
-    mrows = n;
-    ncols = a.post;
-  } else {
-    const long ct = (n + GN - 1) / GN;
-    m0 = (blockIdx.x / ct) * GM;
-    c0 = (blockIdx.x % ct) * GN;
-    mrows = a.pre;
-    ncols = n;
-  }
+  const GemmTile tl = gemm_tile<SIDE, GM, GN>(a);
+  const long m0 = tl.m0, c0 = tl.c0, mrows = tl.mrows, ncols = tl.ncols;
+  const int p = tl.p;
   const float* __restrict__ inp = in + (SIDE == 0 ? static_cast<long>(p) * n * a.post : 0);
 
   // Staging pieces.  Operator rows (and right-side field rows): thread t ->
@@ -762,92 +864,24 @@ __global__ __launch_bounds__(64 * TMW * TNW) void k_mode_gemm(ModalArgs a) {
   };
   load_chunk(0, pend0);
   load_chunk(min(1, nchunks - 1) * GK, pend1);
-  // phi1 multiplier: exp(z) is separable, exp(z_row + z_col) =
-  // exp(z_row) exp(z_col), so each row's tauD lambda_x and its exponential are
-  // formed once per tile (FP64, LDS) and each column's once per lane; per
-  // element the multiplier is then tau (e_row e_col - 1) / z.  z <= 0, and
-  // z == 0 only for the constant mode, where e_row e_col - 1 is exactly 0 too.
   __shared__ double rowv[SIDE == 0 && EPI == kEpiMul ? 2 * GM : 1];
-  if (SIDE == 0 && EPI == kEpiMul && tid < GM) {
-    const long row = m0 + tid;
-    const double zr = row < mrows ? a.tauD * a.lam_x[row] : 0.0;
-    rowv[tid] = zr;
-    rowv[GM + tid] = exp(zr);
-  }
+  if (SIDE == 0 && EPI == kEpiMul) phi1_rows<GM>(a, tl, rowv);
   store_chunk(pend0, 0);
   __syncthreads();  // also publishes rowv
   for (int c = 0; c < nchunks; c += 2) {
     iteration(c, std::integral_constant<int, 0>{});
     if (c + 1 < nchunks) iteration(c + 1, std::integral_constant<int, 1>{});
   }
-
-  // epilogue: D[row][col], col = lane % 32, row = 8 (r / 4) + 4 (lane / 32) + r % 4
-  const long rs = SIDE == 0 ? a.post : n;  // row stride of the output
-  float* const obase = out + (SIDE == 0 ? static_cast<long>(p) * n * a.post : 0);
-  if (m0 + GM <= mrows && c0 + GN <= ncols && rs * GM < (1L << 31)) {
-    // interior tile: no per-element bounds, a uniform base per 32 x 32 block
-    // and a 32-bit offset per element
-    const int irs = static_cast<int>(rs);
-    const int lane_off = 4 * (lane >> 5) * irs + fr;
+  if (two_acc) {
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        float* const tb = obase + (m0 + wm + 32 * t) * rs + c0 + wn + 32 * u;
-        double zc = 0.0, ec = 1.0;  // kEpiMul: tauD (lambda_y + lambda_z) of this lane's column, its exp
-        if (SIDE == 0 && EPI == kEpiMul) {
-          const long col = c0 + wn + 32 * u + fr;
-          zc = a.tauD * (a.lam_y[col / a.nz] + a.lam_z[col % a.nz]);
-          ec = exp(zc);
-        }
-        // add into u: all 16 loads of the block before its stores (a load
-        // after a store to the same buffer would wait for the store's address)
-        float old[16];
-        if (SIDE == 1 && EPI == kEpiAddU) {
+      for (int u = 0; u < 2; ++u)
 #pragma unroll
-          for (int r = 0; r < 16; ++r) old[r] = tb[(8 * (r >> 2) + (r & 3)) * irs + lane_off];
-        }
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int off = (8 * (r >> 2) + (r & 3)) * irs + lane_off;
-          float v = acc[t][u][r];
-          if (two_acc) v += accx[two_acc ? t : 0][two_acc ? u : 0][r] * (1.0f / kF16LoScale);
-          if (SIDE == 0 && EPI == kEpiMul) {
-            const int rl = wm + 32 * t + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            v *= phi1_sep(rowv[rl], rowv[GM + rl], zc, ec, static_cast<float>(a.tau));
-          }
-          if (SIDE == 1 && EPI == kEpiAddU) tb[off] = old[r] + v;
-          else tb[off] = v;
-        }
-      }
-    return;
+        for (int r = 0; r < 16; ++r)
+          acc[t][u][r] += accx[two_acc ? t : 0][two_acc ? u : 0][r] * (1.0f / kF16LoScale);
   }
-#pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const long col = c0 + wn + 32 * u + fr;
-      if (col >= ncols) continue;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const long row = m0 + wm + 32 * t + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (row >= mrows) continue;
-        float v = acc[t][u][r];
-        if (two_acc) v += accx[two_acc ? t : 0][two_acc ? u : 0][r] * (1.0f / kF16LoScale);
-        if (SIDE == 0) {
-          if (EPI == kEpiMul) {
-            const int rl = static_cast<int>(row - m0);
-            const double zc = a.tauD * (a.lam_y[col / a.nz] + a.lam_z[col % a.nz]);
-            v *= phi1_sep(rowv[rl], rowv[GM + rl], zc, exp(zc), static_cast<float>(a.tau));
-          }
-          out[static_cast<long>(p) * n * a.post + row * a.post + col] = v;
-        } else {
-          const long idx = row * n + col;
-          if (EPI == kEpiAddU) out[idx] = out[idx] + v;
-          else out[idx] = v;
-        }
-      }
-    }
+  gemm_epilogue<SIDE, EPI, GM, GN>(a, tl, acc, rowv, wm, wn, lane);
 }
 
 template <int PREC, int SIDE, int EPI, int TMW, int TNW>
@@ -868,6 +902,163 @@ void launch_mode_gemm(const ModalArgs& a, hipStream_t st) {
   if (!big) launch_mode_gemm_t<PREC, SIDE, EPI, 2, 2>(a, st);
   else if (SIDE == 0) launch_mode_gemm_t<PREC, SIDE, EPI, 4, 2>(a, st);
   else launch_mode_gemm_t<PREC, SIDE, EPI, 2, 4>(a, st);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 mode products on the FP32 matrix cores, in the same LDS-staged GEMM
+// structure: buffer loads of two K chunks held in registers, double-buffered
+// LDS tiles with k contiguous per row (A by m, B by c), 64 x 64 per wave as
+// 2 x 2 tiles of v_mfma_f32_32x32x2_f32, the shared epilogue.
+// A fragment of that instruction is one element per lane: A[row = l % 32]
+// [slot l / 32], B[slot l / 32][col = l % 32].  Which k sits in a slot is
+// free as long as A and B agree, so each lane reads four consecutive k with
+// one 16-byte LDS read (k = kb + 4 (l / 32) + j for the j-th of four
+// instructions): one read per operand and tile feeds four instructions.  The
+// 144-byte row pitch keeps those reads free of bank conflicts.  Products and
+// sums are FP32 throughout.
+// ---------------------------------------------------------------------------
+constexpr int GKP32 = GK + 4;  // padded LDS row of floats
+
+template <int TMW, int TNW>
+struct GemmLds32 {
+  alignas(16) float a[2][64 * TMW][GKP32];
+  alignas(16) float b[2][64 * TNW][GKP32];
+};
+
+template <int SIDE, int EPI, int TMW, int TNW>
+__global__ __launch_bounds__(64 * TMW * TNW) void k_mode_gemm_f32(ModalArgs a) {
+  constexpr int NT = 64 * TMW * TNW;  // threads
+  constexpr int GM = 64 * TMW, GN = 64 * TNW;
+  constexpr int EA = GM * GK / NT, EB = GN * GK / NT;  // staged elements per thread of A and B
+  constexpr int EO = SIDE == 0 ? EA : EB, EF = SIDE == 0 ? EB : EA;
+  static_assert(EO % 4 == 0 && EF % 4 == 0, "16-byte staging pieces");
+  __shared__ GemmLds32<TMW, TNW> s;
+  const int n = a.n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave / TNW) * 64, wn = (wave % TNW) * 64;  // the wave's block
+  const GemmTile tl = gemm_tile<SIDE, GM, GN>(a);
+  const float* __restrict__ inp = static_cast<const float*>(a.in) + (SIDE == 0 ? static_cast<long>(tl.p) * n * a.post : 0);
+
+  // Staging pieces, as in the split kernel: operator rows (and right-side
+  // field rows) thread t -> row t / (32 / E), k offset (t % (32 / E)) * E;
+  // left-side field thread t -> column t % GN, k offset (t / GN) * EF.
+  const int orow_l = tid / (GK / EO), ok_ = (tid % (GK / EO)) * EO;
+  const int frow_l = SIDE == 0 ? tid % GN : tid / (GK / EF);
+  const int fk_ = SIDE == 0 ? (tid / GN) * EF : (tid % (GK / EF)) * EF;
+  const long orow = (SIDE == 0 ? tl.m0 : tl.c0) + orow_l;
+  const bool op_ok = orow < (SIDE == 0 ? tl.mrows : tl.ncols);
+  const long fidx = (SIDE == 0 ? tl.c0 : tl.m0) + frow_l;
+  const bool fld_ok = fidx < (SIDE == 0 ? tl.ncols : tl.mrows);
+
+  // buffer resources; lanes outside the problem point past the end and read 0
+  constexpr uint32_t kPast = 0x80000000u;
+  constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit buffer, gfx9 family
+  const uint32_t fslab = static_cast<uint32_t>(SIDE == 0 ? static_cast<long>(n) * a.post : static_cast<long>(a.pre) * n);
+  const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<void*>(a.q), 0, static_cast<int>(static_cast<uint32_t>(n) * n * 4u), kRsrcWord3);
+  const __amdgpu_buffer_rsrc_t rf =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(inp), 0, static_cast<int>(fslab * 4u), kRsrcWord3);
+  const uint32_t vo_op = op_ok ? static_cast<uint32_t>((orow * n + ok_) * 4) : kPast;
+  const uint32_t vo_f = fld_ok ? static_cast<uint32_t>(SIDE == 0 ? (static_cast<long>(fk_) * a.post + fidx) * 4
+                                                                  : (fidx * n + fk_) * 4)
+                               : kPast;
+
+  struct Pending {
+    uint4 op[EO / 4];
+    float fld[EF];
+  } pend0, pend1;  // named, not an array: a runtime index would put them in scratch
+  auto load_chunk = [&](int k0, Pending& pd) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < EO / 4; ++i) pd.op[i] = as_uint4(__builtin_amdgcn_raw_buffer_load_b128(rq, vo_op + 16 * i, k0 * 4, 0));
+    if (SIDE == 0) {
+#pragma unroll
+      for (int e = 0; e < EF; ++e)
+        pd.fld[e] = __builtin_bit_cast(
+            float, __builtin_amdgcn_raw_buffer_load_b32(rf, vo_f, static_cast<int>((k0 + e) * a.post * 4), 0));
+    } else {
+#pragma unroll
+      for (int i = 0; i < EF / 4; ++i) {
+        const uint4 f = as_uint4(__builtin_amdgcn_raw_buffer_load_b128(rf, vo_f + 16 * i, k0 * 4, 0));
+        pd.fld[4 * i] = __builtin_bit_cast(float, f.x);
+        pd.fld[4 * i + 1] = __builtin_bit_cast(float, f.y);
+        pd.fld[4 * i + 2] = __builtin_bit_cast(float, f.z);
+        pd.fld[4 * i + 3] = __builtin_bit_cast(float, f.w);
+      }
+    }
+  };
+  auto store_chunk = [&](const Pending& pd, int buf) __attribute__((always_inline)) {
+    float(*o)[GKP32] = SIDE == 0 ? s.a[buf] : s.b[buf];
+#pragma unroll
+    for (int i = 0; i < EO / 4; ++i) *reinterpret_cast<uint4*>(&o[orow_l][ok_ + 4 * i]) = pd.op[i];
+    float(*f)[GKP32] = SIDE == 0 ? s.b[buf] : s.a[buf];
+#pragma unroll
+    for (int i = 0; i < EF / 4; ++i)
+      *reinterpret_cast<float4*>(&f[frow_l][fk_ + 4 * i]) =
+          make_float4(pd.fld[4 * i], pd.fld[4 * i + 1], pd.fld[4 * i + 2], pd.fld[4 * i + 3]);
+  };
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) acc[t][u] = f32x16{};
+  const int fr = lane & 31, fk = (lane >> 5) * 4;  // fragment row / column and k offset
+  const int nchunks = n / GK;
+  auto iteration = [&](int c, auto which) __attribute__((always_inline)) {
+    Pending& ld = decltype(which)::value == 0 ? pend0 : pend1;
+    const Pending& nx = decltype(which)::value == 0 ? pend1 : pend0;
+    const int buf = c & 1;
+    load_chunk(min(c + 2, nchunks - 1) * GK, ld);  // past the end: a harmless reload
+#pragma unroll
+    for (int kb = 0; kb < GK; kb += 8) {
+      float4 av[2], bv[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        av[t] = *reinterpret_cast<const float4*>(&s.a[buf][wm + 32 * t + fr][kb + fk]);
+        bv[t] = *reinterpret_cast<const float4*>(&s.b[buf][wn + 32 * t + fr][kb + fk]);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int u = 0; u < 2; ++u)
+            acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[t][j], bv[u][j], acc[t][u], 0, 0, 0);
+    }
+    if (c + 1 < nchunks) store_chunk(nx, buf ^ 1);
+    __syncthreads();
+  };
+  load_chunk(0, pend0);
+  load_chunk(min(1, nchunks - 1) * GK, pend1);
+  __shared__ double rowv[SIDE == 0 && EPI == kEpiMul ? 2 * GM : 1];
+  if (SIDE == 0 && EPI == kEpiMul) phi1_rows<GM>(a, tl, rowv);
+  store_chunk(pend0, 0);
+  __syncthreads();  // also publishes rowv
+  for (int c = 0; c < nchunks; c += 2) {
+    iteration(c, std::integral_constant<int, 0>{});
+    if (c + 1 < nchunks) iteration(c + 1, std::integral_constant<int, 1>{});
+  }
+  gemm_epilogue<SIDE, EPI, GM, GN>(a, tl, acc, rowv, wm, wn, lane);
+}
+
+template <int SIDE, int EPI, int TMW, int TNW>
+void launch_mode_gemm_f32_t(const ModalArgs& a, hipStream_t st) {
+  constexpr int GM = 64 * TMW, GN = 64 * TNW;
+  long blocks;
+  if (SIDE == 0) blocks = static_cast<long>(a.pre) * ((a.n + GM - 1) / GM) * ((a.post + GN - 1) / GN);
+  else blocks = ((static_cast<long>(a.pre) + GM - 1) / GM) * ((a.n + GN - 1) / GN);
+  k_mode_gemm_f32<SIDE, EPI, TMW, TNW><<<dim3(static_cast<unsigned>(blocks)), dim3(64 * TMW * TNW), 0, st>>>(a);
+}
+
+// Tile shape as for the split products: all 256 modes in one tile when
+// n >= 256, else 128 x 128.
+template <int SIDE, int EPI>
+void launch_mode_gemm_f32(const ModalArgs& a, hipStream_t st) {
+  const char* e = std::getenv("EXPINT_MODAL_GEMM_TILE");
+  const bool big = e ? e[0] == 'b' : a.n >= 256;
+  if (!big) launch_mode_gemm_f32_t<SIDE, EPI, 2, 2>(a, st);
+  else if (SIDE == 0) launch_mode_gemm_f32_t<SIDE, EPI, 4, 2>(a, st);
+  else launch_mode_gemm_f32_t<SIDE, EPI, 2, 4>(a, st);
 }
 
 // Which matrix-core kernel runs the split products: the LDS-staged GEMM
@@ -942,6 +1133,10 @@ template <int PREC, int SIDE, int EPI>
 void launch_mode_t(const ModalArgs& a, hipStream_t st) {
   if constexpr (is_split<PREC>()) {
     launch_mode_mfma<PREC, SIDE, EPI>(a, st);
+    return;
+  }
+  if (PREC == kPrecF32 && modal_use_gemm() && gemm_offsets_fit(a)) {
+    launch_mode_gemm_f32<SIDE, EPI>(a, st);
     return;
   }
   long tiles;
