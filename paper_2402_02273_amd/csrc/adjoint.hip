@@ -30,12 +30,13 @@ namespace {
 constexpr int kFaceLP = 4;  // x-planes per lane of the vectorised face products
 
 // x plus its value at the lane the DPP pattern CTRL names (a permutation
-// within each row of 16 lanes), moved as two 32-bit halves.
+// within each row of 16 lanes), moved as two 32-bit halves.  Every lane has
+// a source, so bound control is set and the moves need no old value.
 template <int CTRL>
 __device__ __forceinline__ double dpp_add(double x) {
   const unsigned long long bits = static_cast<unsigned long long>(__double_as_longlong(x));
-  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(bits & 0xffffffffull), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(bits >> 32), CTRL, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(bits & 0xffffffffull), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(bits >> 32), CTRL, 0xf, 0xf, true);
   const unsigned long long p = (static_cast<unsigned long long>(static_cast<unsigned int>(hi)) << 32) |
                                static_cast<unsigned int>(lo);
   return x + __longlong_as_double(static_cast<long long>(p));
@@ -51,25 +52,38 @@ __device__ __forceinline__ double row_sum(double v) {
   return dpp_add<0x140>(v);
 }
 
-// Sums acc over the workgroup (fixed order: rows of 16 lanes, then the
-// workgroup's rows in order) and adds weight * sum into
-// partial[blockIdx.x * 8 + c] for the NC classes of the grid (the slots of
-// the other classes stay as filled, zero).  Every thread of the workgroup
-// must call it, in converged control flow.
+// The value of the workgroup's partial slot for class c, read at the start
+// of a kernel by lane 16 c so that its latency overlaps the sweep (each slot
+// is written by one workgroup per launch, and launches are stream-ordered).
 template <int NC>
-__device__ __forceinline__ void block_accumulate(double (&acc)[kMaxClasses], double weight, double* partial) {
+__device__ __forceinline__ double slot_prefetch(const double* partial) {
+  const int tid = static_cast<int>(threadIdx.x);
+  return (tid & 15) == 0 && (tid >> 4) < NC ? partial[static_cast<size_t>(blockIdx.x) * kMaxClasses + (tid >> 4)]
+                                            : 0.0;
+}
+
+// Sums acc over the workgroup in a fixed order (rows of 16 lanes; then the
+// workgroup's 16 row sums of class c, as row c of 16 lanes) and writes
+// prev + weight * sum into partial[blockIdx.x * 8 + c] for the NC classes of
+// the grid (the slots of the other classes stay as filled, zero); prev is
+// what slot_prefetch read.  Every thread of the workgroup must call it, in
+// converged control flow.
+template <int NC>
+__device__ __forceinline__ void block_accumulate(double (&acc)[kMaxClasses], double weight, double* partial,
+                                                 double prev) {
+  static_assert(kBlock == 256 && 16 * NC <= kBlock, "16 rows of 16 lanes; one row per class for the second level");
   __shared__ double red[kBlock / 16][kMaxClasses];
+  const int tid = static_cast<int>(threadIdx.x);
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const double v = row_sum(acc[c]);
-    if ((threadIdx.x & 15) == 0) red[threadIdx.x >> 4][c] = v;
+    if ((tid & 15) == 0) red[tid >> 4][c] = v;
   }
   __syncthreads();
-  if (threadIdx.x < NC) {
-    double v = 0.0;
-    for (int r = 0; r < kBlock / 16; ++r) v += red[r][threadIdx.x];
-    double* slot = partial + static_cast<size_t>(blockIdx.x) * kMaxClasses + threadIdx.x;
-    *slot = *slot + weight * v;
+  if (tid < 16 * NC) {  // whole rows, so every lane a DPP move reads is active
+    const int c = tid >> 4;
+    const double v = row_sum(red[tid & 15][c]);
+    if ((tid & 15) == 0) partial[static_cast<size_t>(blockIdx.x) * kMaxClasses + c] = prev + weight * v;
   }
 }
 
@@ -100,11 +114,17 @@ __device__ __forceinline__ void load_face_tables(FaceTables& ft, const double* d
 }
 
 template <int NC>
-__device__ __forceinline__ void add_face(double (&acc)[kMaxClasses], const FaceTables& ft, int la, int lb,
-                                         double prod) {
-  const double* w = ft.tab + (la * kMaxClasses + lb) * face_stride<NC>();
+__device__ __forceinline__ void add_face_pair(double (&acc)[kMaxClasses], const FaceTables& ft, int pair,
+                                              double prod) {
+  const double* w = ft.tab + pair * face_stride<NC>();
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] += w[c] * prod;
+}
+
+template <int NC>
+__device__ __forceinline__ void add_face(double (&acc)[kMaxClasses], const FaceTables& ft, int la, int lb,
+                                         double prod) {
+  add_face_pair<NC>(acc, ft, la * kMaxClasses + lb, prod);
 }
 
 // (xp - xq)(yp - yq) with the differences taken in the field's own type (an
@@ -122,6 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_faceprod(Geom g, const uint8_t* __re
                                                      const T* __restrict__ yb, const T* __restrict__ y, double weight,
                                                      double* __restrict__ partial) {
   __shared__ FaceTables ft;
+  const double prev = slot_prefetch<NC>(partial);
   load_face_tables<NC>(ft, dtab, dwall);
   __syncthreads();
   double acc[kMaxClasses];
@@ -151,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_faceprod(Geom g, const uint8_t* __re
       }
     }
   }
-  block_accumulate<NC>(acc, weight, partial);
+  block_accumulate<NC>(acc, weight, partial, prev);
 }
 
 // z-vectorised form (nz % 4 == 0, 4-value aligned fields): the z-segments of
@@ -165,6 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_faceprod4(Geom g, int gzs, int gy, i
                                                       const T* __restrict__ y, double weight,
                                                       double* __restrict__ partial) {
   __shared__ FaceTables ft;
+  const double prev = slot_prefetch<NC>(partial);
   load_face_tables<NC>(ft, dtab, dwall);
   __syncthreads();
   double acc[kMaxClasses];
@@ -236,7 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_faceprod4(Geom g, int gzs, int gy, i
       q += sx4;
     }
   }
-  block_accumulate<NC>(acc, weight, partial);
+  block_accumulate<NC>(acc, weight, partial, prev);
 }
 
 // acc[c] += sum over slots b of partial[b][c]: thread t sums the slots
@@ -323,15 +345,19 @@ struct FaceAcc {
     T vz = __shfl_down(vc.v[0], 1, rw);
     if (wall_hi) vz = vc.v[3];
     else if (edge_hi) vz = vz_edge;
+    // face class pairs a * 8 + b of the four voxels, one per byte (labels are
+    // below 8, so the bytes do not carry)
+    const uint32_t pa = lc << 3;
+    const uint32_t px = pa + ln, py = pa + ly, pz = pa + ((lc >> 8) | (static_cast<uint32_t>(lz) << 24));
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int le = label_byte(lc, e);
       const double bp = static_cast<double>(bc.v[e]), vp = static_cast<double>(vc.v[e]);
-      add_face<NC>(acc, ft, le, label_byte(ln, e), face_prod<T>(bc.v[e], bn.v[e], vc.v[e], vn.v[e]));
-      add_face<NC>(acc, ft, le, label_byte(ly, e), face_prod<T>(bc.v[e], by.v[e], vc.v[e], vy.v[e]));
+      add_face_pair<NC>(acc, ft, label_byte(px, e), face_prod<T>(bc.v[e], bn.v[e], vc.v[e], vn.v[e]));
+      add_face_pair<NC>(acc, ft, label_byte(py, e), face_prod<T>(bc.v[e], by.v[e], vc.v[e], vy.v[e]));
       const T bq = e < 3 ? bc.v[e + 1] : bz;
       const T vq = e < 3 ? vc.v[e + 1] : vz;
-      add_face<NC>(acc, ft, le, e < 3 ? label_byte(lc, e + 1) : lz, face_prod<T>(bc.v[e], bq, vc.v[e], vq));
+      add_face_pair<NC>(acc, ft, label_byte(pz, e), face_prod<T>(bc.v[e], bq, vc.v[e], vq));
       if (BC) {
         const int nw = (i == 0) + (i == g.nx - 1) + (j == 0) + (j == g.ny - 1) + (e == 0 && k4 == 0) +
                        (e == 3 && wall_hi);
@@ -367,6 +393,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_face4(Geom g, int gzs, int gy,
                                                         double* __restrict__ partial, T* __restrict__ dbar) {
   __shared__ LdsCoef<T> s;
   __shared__ FaceTables ft;
+  const double prev = slot_prefetch<NC>(partial);
   const int L = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
   const int zs = L % gzs;
   const int t = L / gzs;
@@ -387,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_face4(Geom g, int gzs, int gy,
   const bool live = j < g.ny && k4 < (g.nz >> 2);
   if (live) face.load(y, i0);
   sweep_column4<T, BC, LP, KIND, kGeneric, false>(g, cf.labels, s, a, i0, j, k4, kq, rw, live, ready, face);
-  block_accumulate<NC>(face.acc, weight, partial);
+  block_accumulate<NC>(face.acc, weight, partial, prev);
 }
 
 // Launch shape of k_sweep_face4: the sweeps' z-segments, Tiling::flp planes
