@@ -374,19 +374,23 @@ __device__ __forceinline__ void sweep_column4(const Geom& g, const uint8_t* lab,
       lzr = lab[4 * q + 4];
     }
     const int wall_x = BC ? wall_y + (i == 0) + (i == g.nx - 1) : 0;
+    // class pairs le * 8 + l of the four voxels with each neighbour, one per
+    // byte (labels are below 8, so the bytes do not carry): one table index
+    // per face from a byte extract
+    const uint32_t pc = lc << 3;
+    const uint32_t pm = pc + lm, pn = pc + ln, pa = pc + la, pb = pc + lb;
+    const uint32_t pzm = pc + ((lc << 8) | static_cast<uint32_t>(lzl));
+    const uint32_t pzp = pc + ((lc >> 8) | (static_cast<uint32_t>(lzr) << 24));
     T ax[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const T v = xc.v[e];
       const int le = label_byte(lc, e);
-      const T* row = s.tab + le * kMaxClasses;
       const T vzm = e > 0 ? xc.v[e - 1] : zl;
-      const int lzm = e > 0 ? label_byte(lc, e - 1) : lzl;
       const T vzp = e < 3 ? xc.v[e + 1] : zr;
-      const int lzp = e < 3 ? label_byte(lc, e + 1) : lzr;
-      ax[e] = row[label_byte(lm, e)] * (xm.v[e] - v) + row[label_byte(ln, e)] * (xn.v[e] - v) +
-              row[label_byte(la, e)] * (ya.v[e] - v) + row[label_byte(lb, e)] * (yb.v[e] - v) +
-              row[lzm] * (vzm - v) + row[lzp] * (vzp - v);
+      ax[e] = s.tab[label_byte(pm, e)] * (xm.v[e] - v) + s.tab[label_byte(pn, e)] * (xn.v[e] - v) +
+              s.tab[label_byte(pa, e)] * (ya.v[e] - v) + s.tab[label_byte(pb, e)] * (yb.v[e] - v) +
+              s.tab[label_byte(pzm, e)] * (vzm - v) + s.tab[label_byte(pzp, e)] * (vzp - v);
       if (BC) {
         const int nw = wall_x + (e == 0 && wall_lo) + (e == 3 && wall_hi);
         ax[e] -= s.wall[le] * v * T(nw);
