@@ -180,7 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_faceprod(Geom g, const uint8_t* __re
 // kFaceLP planes; the +z face of its last voxel pairs with the next lane's first
 // (shuffle), the next segment's first (load) or nothing at the wall.
 template <typename T, int BC, int NC>
-__global__ __launch_bounds__(kBlock) void k_faceprod4(Geom g, int gzs, int gy, int rw, const uint8_t* __restrict__ lab,
+__global__ __launch_bounds__(kBlock) void k_faceprod4(Geom g, ColumnGrid cg, const uint8_t* __restrict__ lab,
                                                       const double* __restrict__ dtab,
                                                       const double* __restrict__ dwall, const T* __restrict__ yb,
                                                       const T* __restrict__ y, double weight,
@@ -193,15 +193,9 @@ __global__ __launch_bounds__(kBlock) void k_faceprod4(Geom g, int gzs, int gy, i
 #pragma unroll
   for (int c = 0; c < kMaxClasses; ++c) acc[c] = 0.0;
   const int L = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
-  const int zs = L % gzs;
-  const int t = L / gzs;
-  const int ybk = t % gy;
-  const int i0 = (t / gy) * kFaceLP;
-  const int tid = static_cast<int>(threadIdx.x);
-  const int kq = tid & (rw - 1);
-  const int j = ybk * (kBlock / rw) + tid / rw;
+  const ColumnTile c = column_tile(cg, L, kFaceLP, static_cast<int>(threadIdx.x));
+  const int i0 = c.i0, kq = c.kq, j = c.j, k4 = c.k4, rw = cg.rw;
   const int nz4 = g.nz >> 2;
-  const int k4 = zs * rw + kq;
   const bool live = j < g.ny && k4 < nz4;
   if (live) {
     const int sx4 = g.ny * nz4;
@@ -387,7 +381,7 @@ struct FaceAcc {
 // weight * (its sums) into slot b.  kTermJ also adds weight * ybar * y into
 // dbar.
 template <typename T, int BC, int KIND, int NC, int LP>
-__global__ __launch_bounds__(kBlock) void k_sweep_face4(Geom g, int gzs, int gy, int rw, Coef cf, SweepArgs a,
+__global__ __launch_bounds__(kBlock) void k_sweep_face4(Geom g, ColumnGrid cg, Coef cf, SweepArgs a,
                                                         const T* __restrict__ y, const double* __restrict__ dtab,
                                                         const double* __restrict__ dwall, double weight,
                                                         double* __restrict__ partial, T* __restrict__ dbar) {
@@ -395,14 +389,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep_face4(Geom g, int gzs, int gy,
   __shared__ FaceTables ft;
   const double prev = slot_prefetch<NC>(partial);
   const int L = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
-  const int zs = L % gzs;
-  const int t = L / gzs;
-  const int ybk = t % gy;
-  const int i0 = (t / gy) * LP;
   const int tid = static_cast<int>(threadIdx.x);
-  const int kq = tid & (rw - 1);
-  const int j = ybk * (kBlock / rw) + tid / rw;
-  const int k4 = zs * rw + kq;
+  const ColumnTile c = column_tile(cg, L, LP, tid);
+  const int i0 = c.i0, kq = c.kq, j = c.j, k4 = c.k4, rw = cg.rw;
   // both tables are staged after the first field loads are in flight; every
   // thread passes this barrier once
   auto ready = [&]() {
@@ -432,12 +421,12 @@ hipError_t sweep_face_typed(const Geom& g, const Tiling& tl, const Coef& cf, con
                             void* dbar, hipStream_t st) {
   const Tiling ft = sweep_face_tiling(tl);
   const int rows = kBlock / ft.rw;
-  const int gzs = ((g.nz >> 2) + ft.rw - 1) / ft.rw, gy = (g.ny + rows - 1) / rows;
+  const ColumnGrid cg(((g.nz >> 2) + ft.rw - 1) / ft.rw, (g.ny + rows - 1) / rows, ft.rw);
   const dim3 grid(static_cast<unsigned>(sweep_blocks(g, ft))), block(kBlock);
   const T* yy = static_cast<const T*>(y);
   T* db = static_cast<T*>(dbar);
 #define EXPINT_SWEEP_FACE(NC_, LP_)                                                                     \
-  k_sweep_face4<T, BC, KIND, NC_, LP_><<<grid, block, 0, st>>>(g, gzs, gy, ft.rw, cf, a, yy, dtab, dwall, weight, \
+  k_sweep_face4<T, BC, KIND, NC_, LP_><<<grid, block, 0, st>>>(g, cg, cf, a, yy, dtab, dwall, weight,      \
                                                               partial, db)
 #define EXPINT_SWEEP_FACE_LP(NC_)                     \
   switch (ft.lp) {                                    \
@@ -486,9 +475,9 @@ void faceprod_nc(const Geom& g, const Tiling& tl, bool vec, const uint8_t* label
   if (vec) {
     const Tiling ft = face_tiling(tl);
     const int rows = kBlock / ft.rw;
-    const int gzs = ((g.nz >> 2) + ft.rw - 1) / ft.rw, gy = (g.ny + rows - 1) / rows;
+    const ColumnGrid cg(((g.nz >> 2) + ft.rw - 1) / ft.rw, (g.ny + rows - 1) / rows, ft.rw);
     const dim3 grid(static_cast<unsigned>(sweep_blocks(g, ft)));
-    k_faceprod4<T, BC, NC><<<grid, block, 0, st>>>(g, gzs, gy, ft.rw, labels, dtab, dwall, yb, y, weight, partial);
+    k_faceprod4<T, BC, NC><<<grid, block, 0, st>>>(g, cg, labels, dtab, dwall, yb, y, weight, partial);
   } else {
     k_faceprod<T, BC, NC><<<dim3(kReduceBlocks), block, 0, st>>>(g, labels, dtab, dwall, yb, y, weight, partial);
   }

@@ -39,6 +39,40 @@ inline int enum_value(const E& e) {
 
 inline constexpr int dtype_bytes(expint_dtype dt) { return dt == EXPINT_F64 ? 8 : 4; }
 
+// Unsigned division by a divisor d (1 <= d < 2^31) fixed at launch, for
+// dividends below 2^31, as a multiply and a shift: with s = 31 + ceil(log2 d)
+// and m = ceil(2^s / d) (below 2^32), floor(x * m / 2^s) = floor(x / d).
+// (m d - 2^s < d and x < 2^31 <= 2^s / d keep x (m d - 2^s) / (d 2^s) below
+// 1/d, less than the gap between x / d and the next integer.)  With a dividend
+// that is uniform over the wavefront the kernels compute it on the scalar
+// unit, where a runtime division would take a float reciprocal on the vector
+// unit.
+struct FastDiv {
+  uint32_t d = 1, m = 1u << 31, s = 31;
+  FastDiv() = default;
+  explicit FastDiv(uint32_t divisor) : d(divisor) {
+    uint32_t l = 0;
+    while ((1ull << l) < divisor) ++l;
+    s = 31 + l;
+    m = static_cast<uint32_t>(((1ull << s) + divisor - 1) / divisor);
+  }
+  __host__ __device__ uint32_t div(uint32_t x) const {
+    return static_cast<uint32_t>((static_cast<uint64_t>(x) * m) >> s);
+  }
+};
+
+// Tile decomposition of the z-vectorised sweeps: workgroup L covers
+// z-segment L % gzs (rw lanes of 4 voxels), row block (L / gzs) % gy of
+// kBlock / rw rows and the plane group L / (gzs gy); rw is a power of two.
+struct ColumnGrid {
+  FastDiv zs, y;  // gzs, gy
+  int rw, rw_log2;
+  ColumnGrid() = default;
+  ColumnGrid(int gzs, int gy, int rw_) : zs(static_cast<uint32_t>(gzs)), y(static_cast<uint32_t>(gy)), rw(rw_), rw_log2(0) {
+    while ((1 << rw_log2) < rw) ++rw_log2;
+  }
+};
+
 struct Geom {
   int nx, ny, nz;
   int64_t n;

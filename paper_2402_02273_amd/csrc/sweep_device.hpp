@@ -43,6 +43,27 @@ __device__ __forceinline__ int xcd_remap(int L, int nb) {
   return L;
 }
 
+// The tile of workgroup L (after xcd_remap) in the z-vectorised sweeps'
+// decomposition (ColumnGrid), with lp planes per lane, and thread tid's place
+// in it: z-segment zs, row block yb, first plane i0, lane index kq in the
+// segment, row j and 4-voxel vector k4.  The divisions by the tile counts
+// are multiplies by host-computed constants, on the scalar unit.
+struct ColumnTile {
+  int zs, yb, i0, kq, j, k4;
+};
+__device__ __forceinline__ ColumnTile column_tile(const ColumnGrid& cg, int L, int lp, int tid) {
+  ColumnTile c;
+  const int t = static_cast<int>(cg.zs.div(static_cast<uint32_t>(L)));
+  c.zs = L - t * static_cast<int>(cg.zs.d);
+  const int xg = static_cast<int>(cg.y.div(static_cast<uint32_t>(t)));
+  c.yb = t - xg * static_cast<int>(cg.y.d);
+  c.i0 = xg * lp;
+  c.kq = tid & (cg.rw - 1);
+  c.j = c.yb * (kBlock >> cg.rw_log2) + (tid >> cg.rw_log2);
+  c.k4 = c.zs * cg.rw + c.kq;
+  return c;
+}
+
 // kTermJ is a Taylor-term sweep of the linearised operator
 // J = A + rho diag(1 - 2 u_n) (TermOp::ju, TermOp::jrho): the diagonal term is
 // added to the stencil result before the term's outputs are formed.

@@ -13,15 +13,16 @@ namespace expint {
 // One sweep over a bx x by patch of lp consecutive x-planes (see
 // sweep_column for the per-thread work).
 template <typename T, int BC, int LP, int KIND, int FL>
-__global__ __launch_bounds__(kBlock) void k_sweep(Geom g, int gx, int gy, Coef cf, SweepArgs a) {
+__global__ __launch_bounds__(kBlock) void k_sweep(Geom g, FastDiv gx, FastDiv gy, Coef cf, SweepArgs a) {
   __shared__ LdsCoef<T> s;
   load_tables(s, cf, threadIdx.y * blockDim.x + threadIdx.x, kBlock);
   __syncthreads();
   const int L = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
-  const int bxi = L % gx;
-  const int t = L / gx;
-  const int byi = t % gy;
-  const int i0 = (t / gy) * LP;
+  const int t = static_cast<int>(gx.div(static_cast<uint32_t>(L)));
+  const int bxi = L - t * static_cast<int>(gx.d);
+  const int xg = static_cast<int>(gy.div(static_cast<uint32_t>(t)));
+  const int byi = t - xg * static_cast<int>(gy.d);
+  const int i0 = xg * LP;
   const int j = byi * static_cast<int>(blockDim.y) + static_cast<int>(threadIdx.y);
   const int k = bxi * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x);
   if (j >= g.ny || k >= g.nz) return;
@@ -32,17 +33,12 @@ __global__ __launch_bounds__(kBlock) void k_sweep(Geom g, int gx, int gy, Coef c
 // z-segment of rw lanes, lp planes; NT: Taylor-term outputs by non-temporal
 // stores.
 template <typename T, int BC, int LP, int KIND, int FL, bool NT>
-__global__ __launch_bounds__(kBlock) void k_sweep4(Geom g, int gzs, int gy, int rw, Coef cf, SweepArgs a) {
+__global__ __launch_bounds__(kBlock) void k_sweep4(Geom g, ColumnGrid cg, Coef cf, SweepArgs a) {
   __shared__ LdsCoef<T> s;
   const int L = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
-  const int zs = L % gzs;
-  const int t = L / gzs;
-  const int yb = t % gy;
-  const int i0 = (t / gy) * LP;
   const int tid = static_cast<int>(threadIdx.x);
-  const int kq = tid & (rw - 1);
-  const int j = yb * (kBlock / rw) + tid / rw;
-  const int k4 = zs * rw + kq;
+  const ColumnTile c = column_tile(cg, L, LP, tid);
+  const int i0 = c.i0, kq = c.kq, j = c.j, k4 = c.k4, rw = cg.rw;
   // the class table is staged after the first field loads are in flight
   auto ready = [&]() {
     load_tables(s, cf, tid, kBlock);
@@ -56,28 +52,28 @@ template <typename T, int BC, int KIND, int FL>
 static void sweep_lp(const Geom& g, const Tiling& tl, const Coef& cf, const SweepArgs& a, hipStream_t st) {
   if (tl.vec) {
     const int rows = kBlock / tl.rw;
-    const int gzs = ((g.nz >> 2) + tl.rw - 1) / tl.rw, gy = (g.ny + rows - 1) / rows;
+    const ColumnGrid cg(((g.nz >> 2) + tl.rw - 1) / tl.rw, (g.ny + rows - 1) / rows, tl.rw);
     const dim3 grid(static_cast<unsigned>(sweep_blocks(g, tl))), block(kBlock);
     // the store policy applies to the Taylor terms of A; those of the
     // linearised operator were measured slower with non-temporal stores
     if constexpr (KIND == kTerm) {
       if (tl.nt) {
         switch (tl.lp) {
-          case 1: k_sweep4<T, BC, 1, KIND, FL, true><<<grid, block, 0, st>>>(g, gzs, gy, tl.rw, cf, a); break;
-          case 2: k_sweep4<T, BC, 2, KIND, FL, true><<<grid, block, 0, st>>>(g, gzs, gy, tl.rw, cf, a); break;
-          default: k_sweep4<T, BC, 4, KIND, FL, true><<<grid, block, 0, st>>>(g, gzs, gy, tl.rw, cf, a); break;
+          case 1: k_sweep4<T, BC, 1, KIND, FL, true><<<grid, block, 0, st>>>(g, cg, cf, a); break;
+          case 2: k_sweep4<T, BC, 2, KIND, FL, true><<<grid, block, 0, st>>>(g, cg, cf, a); break;
+          default: k_sweep4<T, BC, 4, KIND, FL, true><<<grid, block, 0, st>>>(g, cg, cf, a); break;
         }
         return;
       }
     }
     switch (tl.lp) {
-      case 1: k_sweep4<T, BC, 1, KIND, FL, false><<<grid, block, 0, st>>>(g, gzs, gy, tl.rw, cf, a); break;
-      case 2: k_sweep4<T, BC, 2, KIND, FL, false><<<grid, block, 0, st>>>(g, gzs, gy, tl.rw, cf, a); break;
-      default: k_sweep4<T, BC, 4, KIND, FL, false><<<grid, block, 0, st>>>(g, gzs, gy, tl.rw, cf, a); break;
+      case 1: k_sweep4<T, BC, 1, KIND, FL, false><<<grid, block, 0, st>>>(g, cg, cf, a); break;
+      case 2: k_sweep4<T, BC, 2, KIND, FL, false><<<grid, block, 0, st>>>(g, cg, cf, a); break;
+      default: k_sweep4<T, BC, 4, KIND, FL, false><<<grid, block, 0, st>>>(g, cg, cf, a); break;
     }
     return;
   }
-  const int gx = (g.nz + tl.bx - 1) / tl.bx, gy = (g.ny + tl.by - 1) / tl.by;
+  const FastDiv gx(static_cast<uint32_t>((g.nz + tl.bx - 1) / tl.bx)), gy(static_cast<uint32_t>((g.ny + tl.by - 1) / tl.by));
   const dim3 grid(static_cast<unsigned>(sweep_blocks(g, tl))), block(tl.bx, tl.by);
   switch (tl.lp) {
     case 1: k_sweep<T, BC, 1, KIND, FL><<<grid, block, 0, st>>>(g, gx, gy, cf, a); break;

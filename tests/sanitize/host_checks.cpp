@@ -309,7 +309,32 @@ void diagnostics_paths() {
 
 }  // namespace
 
+// FastDiv (the kernels' tile decomposition) against the division operator:
+// every divisor the launches can see up to 4096 on dividends at the edges of
+// each quotient, and large divisors and dividends up to 2^31 - 1.
+void fastdiv_paths() {
+  unsigned long long bad = 0;
+  auto one = [&](uint32_t d, uint32_t x) {
+    if (expint::FastDiv(d).div(x) != x / d) ++bad;
+  };
+  for (uint32_t d = 1; d <= 4096; ++d) {
+    for (uint32_t x = 0; x < 3 * d + 3; ++x) one(d, x);
+    for (uint32_t q : {1000u, 65535u, 1000000u, (0x7fffffffu / d) - 1, 0x7fffffffu / d}) {
+      for (uint32_t r : {0u, 1u, d - 1}) {
+        const unsigned long long x = static_cast<unsigned long long>(q) * d + r;
+        if (x <= 0x7fffffffull) one(d, static_cast<uint32_t>(x));
+      }
+    }
+    one(d, 0x7fffffffu);
+  }
+  for (uint32_t d : {65535u, 65536u, 65537u, 1000003u, 0x3fffffffu, 0x40000000u, 0x40000001u, 0x7fffffffu})
+    for (uint32_t x : {0u, 1u, d - 1, d, d + 1, 2 * (d - 1) + 1, 0x7ffffffeu, 0x7fffffffu})
+      if (x <= 0x7fffffffu) one(d, x);
+  check(bad == 0, "FastDiv equals integer division");
+}
+
 int main() {
+  fastdiv_paths();
   create_paths();
   batch_paths();
   plan_paths();
