@@ -198,13 +198,13 @@ hipError_t autotune_pairs(expint_dtype dt, expint_bc bc, const Geom& g, const Co
 }
 
 hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Coef& cf, void* f0, void* f1, void* f2,
-                          hipStream_t st, bool allow_vec, Tiling* out, void* ju, double jrho) {
+                          hipStream_t st, bool allow_vec, Tiling* out, void* ju, double jrho, bool vec_only) {
   *out = default_tiling(g);
   // EXPINT_TILE=scalar / vec restricts the candidates to one sweep shape
   const char* shape = std::getenv("EXPINT_TILE");
   const int only = shape ? (shape[0] == 'v' ? 2 : (shape[0] == 's' ? 1 : 0)) : 0;
   const bool vec_ok = allow_vec && vec_sweep_ok(g, cf.labels_form) && only != 1;
-  const bool scalar_ok = !(only == 2 && vec_ok);
+  const bool scalar_ok = !((only == 2 || vec_only) && vec_ok);
   const char* env = std::getenv("EXPINT_AUTOTUNE");
   if (env && env[0] == '0') {
     if (!scalar_ok) {

@@ -26,8 +26,12 @@ namespace expint {
 // linearised operator J = A + jrho diag(1 - 2 ju) instead, which a linearised
 // step runs: those read u_n as well and keep plain stores, so they are tuned
 // apart (their own cache and tuning-file key: flags bit 8).
+// vec_only: where the grid allows the z-vectorised shape, time only those
+// shapes (the batch: its batched scalar sweeps lose more against the vector
+// ones than single-grid timings show).
 hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Coef& cf, void* f0, void* f1, void* f2,
-                          hipStream_t st, bool allow_vec, Tiling* out, void* ju = nullptr, double jrho = 0.0);
+                          hipStream_t st, bool allow_vec, Tiling* out, void* ju = nullptr, double jrho = 0.0,
+                          bool vec_only = false);
 
 // Decides whether the step takes its Taylor terms two at a time (pair
 // sweeps, label form only) and with which tiling.  mode SINGLE: never (ty = 0

@@ -151,7 +151,7 @@ int setup_instance(expint_batch* b, Inst& in, const uint8_t* labels_src) {
   in.norm1 = out[0];
   const bool lin = b->scheme == EXPINT_SCHEME_LINEARISED;
   BHIP(autotune_sweep(b->dtype, b->bc, in.g, in.coef(), in.ws.y[0], in.ws.acc[0], in.ws.y[1], b->stream, true,
-                      &in.tiling, lin ? in.ws.acc[1] : nullptr, in.rho));
+                      &in.tiling, lin ? in.ws.acc[1] : nullptr, in.rho, /*vec_only=*/true));
   return EXPINT_OK;
 }
 
@@ -238,14 +238,14 @@ int build_schedule(expint_batch* b, void* const* u) {
             it.vec = 1;
             it.bx = ti.rw;
             it.by = kBlock / ti.rw;
-            it.gx = ((in.g.nz >> 2) + ti.rw - 1) / ti.rw;
+            it.gx = FastDiv(static_cast<uint32_t>(((in.g.nz >> 2) + ti.rw - 1) / ti.rw));
           } else {
             it.bx = ti.bx;
             it.by = ti.by;
-            it.gx = (in.g.nz + it.bx - 1) / it.bx;
+            it.gx = FastDiv(static_cast<uint32_t>((in.g.nz + it.bx - 1) / it.bx));
           }
           it.bx_log2 = it.bx == 64 ? 6 : (it.bx == 32 ? 5 : 4);
-          it.gy = (in.g.ny + it.by - 1) / it.by;
+          it.gy = FastDiv(static_cast<uint32_t>((in.g.ny + it.by - 1) / it.by));
           it.labels = in.labels;
           it.rho = in.rho;
           if (t == 0) {

@@ -58,10 +58,11 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchItem* __restrict__ 
     }
     const BatchItem& it = si[lo];
     const int L = w - it.block_start;
-    const int bxi = L % it.gx;
-    const int t = L / it.gx;
-    const int byi = t % it.gy;
-    const int i0 = (t / it.gy) * LP;
+    const int t = static_cast<int>(it.gx.div(static_cast<uint32_t>(L)));
+    const int bxi = L - t * static_cast<int>(it.gx.d);
+    const int xg = static_cast<int>(it.gy.div(static_cast<uint32_t>(t)));
+    const int byi = t - xg * static_cast<int>(it.gy.d);
+    const int i0 = xg * LP;
     const int j = byi * it.by + (static_cast<int>(threadIdx.x) >> it.bx_log2);
     const int kq = static_cast<int>(threadIdx.x) & (it.bx - 1);
     const int k = bxi * it.bx + kq;  // vec: the lane's 4-voxel vector index

@@ -13,9 +13,10 @@ constexpr int kBatchMaxOps = 64;  // ops per batched launch (the host splits lar
 struct BatchItem {
   int block_start;      // offset of this instance's tiles in the launch's work list
   int nx, ny, nz;
-  int gx, gy, by;       // tiles along z and y; rows (y) per tile
+  FastDiv gx, gy;       // tiles along z and y (divisors of the tile index)
+  int by;               // rows (y) per tile
   int bx, bx_log2;      // threads along z (16, 32 or 64); vec: lanes per z-segment
-  int vec, pad;         // vec: z-vectorised sweep (gx = z-segments)
+  int vec;              // vec: z-vectorised sweep (gx = z-segments)
   const uint8_t* labels;
   double rho;
   TermOp op;
