@@ -1061,6 +1061,208 @@ void launch_mode_gemm_f32(const ModalArgs& a, hipStream_t st) {
   else launch_mode_gemm_f32_t<SIDE, EPI, 2, 4>(a, st);
 }
 
+// ---------------------------------------------------------------------------
+// FP64 mode products on the FP64 matrix cores (v_mfma_f64_16x16x4_f64), in
+// the same LDS-staged structure with K chunks of 16.  A wave's 64 x 64 block
+// is 4 x 4 tiles of 16 x 16.  Fragment layout (checked on the device): lane l
+// holds A[l % 16][slot l / 16] and B[slot l / 16][l % 16]; output element r of
+// lane l is D[l / 16 + 4 r][l % 16].  As in the FP32 kernel each lane reads
+// four consecutive k (two 16-byte LDS reads) and feeds them to four
+// instructions (k = kb + 4 (l / 16) + j for the j-th), so A and B agree on
+// every slot.  Products and sums are FP64; the phi1 multiplier uses
+// e^(zr + zc) - 1 = em_r em_c + em_r + em_c with em = expm1 of the row and
+// column parts (FP64, a few ulps: both are <= 0, so the sum never cancels
+// below half of em_r + em_c).
+// ---------------------------------------------------------------------------
+constexpr int GK64 = 16;          // K chunk
+constexpr int GKP64 = GK64 + 2;   // padded LDS row of doubles (144 bytes)
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <int TMW, int TNW>
+struct GemmLds64 {
+  alignas(16) double a[2][64 * TMW][GKP64];
+  alignas(16) double b[2][64 * TNW][GKP64];
+};
+
+template <int SIDE, int EPI, int GM, int GN>
+__device__ __forceinline__ void gemm_epilogue_f64(const ModalArgs& a, const GemmTile& tl, const f64x4 (&acc)[4][4],
+                                                  const double* rowv, int wm, int wn, int lane) {
+  double* __restrict__ out = static_cast<double*>(a.out);
+  const int n = a.n;
+  const long m0 = tl.m0, c0 = tl.c0, mrows = tl.mrows, ncols = tl.ncols;
+  const long rs = SIDE == 0 ? a.post : n;  // row stride of the output
+  double* const obase = out + (SIDE == 0 ? static_cast<long>(tl.p) * n * a.post : 0);
+  const int fc = lane & 15, fr = lane >> 4;
+  const double tau = a.tau;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const long col = c0 + wn + 16 * u + fc;
+    if (col >= ncols) continue;
+    double zc = 0.0, emc = 0.0;  // kEpiMul: tauD (lambda_y + lambda_z) of this column, its expm1
+    if (SIDE == 0 && EPI == kEpiMul) {
+      zc = a.tauD * (a.lam_y[col / a.nz] + a.lam_z[col % a.nz]);
+      emc = expm1(zc);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rl = wm + 16 * t + fr + 4 * r;  // row in the tile
+        const long row = m0 + rl;
+        if (row >= mrows) continue;
+        double v = acc[t][u][r];
+        if (SIDE == 0 && EPI == kEpiMul) {
+          const double z = rowv[rl] + zc, emr = rowv[GM + rl];
+          v *= z == 0.0 ? tau : tau * (fma(emr, emc, emr + emc) / z);
+        }
+        double* const o = obase + row * rs + col;
+        if (SIDE == 1 && EPI == kEpiAddU) *o = *o + v;
+        else *o = v;
+      }
+  }
+}
+
+template <int SIDE, int EPI, int TMW, int TNW>
+__global__ __launch_bounds__(64 * TMW * TNW) void k_mode_gemm_f64(ModalArgs a) {
+  constexpr int NT = 64 * TMW * TNW;  // threads
+  constexpr int GM = 64 * TMW, GN = 64 * TNW;
+  constexpr int EA = GM * GK64 / NT, EB = GN * GK64 / NT;  // staged elements per thread of A and B
+  constexpr int EO = SIDE == 0 ? EA : EB, EF = SIDE == 0 ? EB : EA;
+  static_assert(EO % 2 == 0 && EF % 2 == 0, "16-byte staging pieces");
+  __shared__ GemmLds64<TMW, TNW> s;
+  const int n = a.n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave / TNW) * 64, wn = (wave % TNW) * 64;  // the wave's block
+  const GemmTile tl = gemm_tile<SIDE, GM, GN>(a);
+  const double* __restrict__ inp =
+      static_cast<const double*>(a.in) + (SIDE == 0 ? static_cast<long>(tl.p) * n * a.post : 0);
+
+  // staging pieces as in the other kernels (E = 2 doubles per 16 bytes)
+  const int orow_l = tid / (GK64 / EO), ok_ = (tid % (GK64 / EO)) * EO;
+  const int frow_l = SIDE == 0 ? tid % GN : tid / (GK64 / EF);
+  const int fk_ = SIDE == 0 ? (tid / GN) * EF : (tid % (GK64 / EF)) * EF;
+  const long orow = (SIDE == 0 ? tl.m0 : tl.c0) + orow_l;
+  const bool op_ok = orow < (SIDE == 0 ? tl.mrows : tl.ncols);
+  const long fidx = (SIDE == 0 ? tl.c0 : tl.m0) + frow_l;
+  const bool fld_ok = fidx < (SIDE == 0 ? tl.ncols : tl.mrows);
+
+  // buffer resources; lanes outside the problem point past the end and read 0
+  constexpr uint32_t kPast = 0x80000000u;
+  constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit buffer, gfx9 family
+  const uint32_t fslab = static_cast<uint32_t>(SIDE == 0 ? static_cast<long>(n) * a.post : static_cast<long>(a.pre) * n);
+  const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<void*>(a.q), 0, static_cast<int>(static_cast<uint32_t>(n) * n * 8u), kRsrcWord3);
+  const __amdgpu_buffer_rsrc_t rf =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(inp), 0, static_cast<int>(fslab * 8u), kRsrcWord3);
+  const uint32_t vo_op = op_ok ? static_cast<uint32_t>((orow * n + ok_) * 8) : kPast;
+  const uint32_t vo_f = fld_ok ? static_cast<uint32_t>(SIDE == 0 ? (static_cast<long>(fk_) * a.post + fidx) * 8
+                                                                  : (fidx * n + fk_) * 8)
+                               : kPast;
+
+  struct Pending {
+    uint4 op[EO / 2];
+    uint2 fld[EF];
+  } pend0, pend1;  // named, not an array: a runtime index would put them in scratch
+  auto load_chunk = [&](int k0, Pending& pd) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < EO / 2; ++i) pd.op[i] = as_uint4(__builtin_amdgcn_raw_buffer_load_b128(rq, vo_op + 16 * i, k0 * 8, 0));
+    if (SIDE == 0) {
+#pragma unroll
+      for (int e = 0; e < EF; ++e) {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b64(rf, vo_f, static_cast<int>((k0 + e) * a.post * 8), 0);
+        pd.fld[e] = make_uint2(static_cast<unsigned>(w[0]), static_cast<unsigned>(w[1]));
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < EF / 2; ++i) {
+        const uint4 f = as_uint4(__builtin_amdgcn_raw_buffer_load_b128(rf, vo_f + 16 * i, k0 * 8, 0));
+        pd.fld[2 * i] = make_uint2(f.x, f.y);
+        pd.fld[2 * i + 1] = make_uint2(f.z, f.w);
+      }
+    }
+  };
+  auto store_chunk = [&](const Pending& pd, int buf) __attribute__((always_inline)) {
+    double(*o)[GKP64] = SIDE == 0 ? s.a[buf] : s.b[buf];
+#pragma unroll
+    for (int i = 0; i < EO / 2; ++i) *reinterpret_cast<uint4*>(&o[orow_l][ok_ + 2 * i]) = pd.op[i];
+    double(*f)[GKP64] = SIDE == 0 ? s.b[buf] : s.a[buf];
+#pragma unroll
+    for (int i = 0; i < EF / 2; ++i)
+      *reinterpret_cast<uint4*>(&f[frow_l][fk_ + 2 * i]) =
+          make_uint4(pd.fld[2 * i].x, pd.fld[2 * i].y, pd.fld[2 * i + 1].x, pd.fld[2 * i + 1].y);
+  };
+
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[t][u] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int fr = lane & 15, fk = (lane >> 4) * 4;  // fragment row / column and k offset
+  const int nchunks = n / GK64;
+  auto iteration = [&](int c, auto which) __attribute__((always_inline)) {
+    Pending& ld = decltype(which)::value == 0 ? pend0 : pend1;
+    const Pending& nx = decltype(which)::value == 0 ? pend1 : pend0;
+    const int buf = c & 1;
+    load_chunk(min(c + 2, nchunks - 1) * GK64, ld);  // past the end: a harmless reload
+    f64x4 bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double* pb = &s.b[buf][wn + 16 * u + fr][fk];
+      const double2 b01 = *reinterpret_cast<const double2*>(pb);
+      const double2 b23 = *reinterpret_cast<const double2*>(pb + 2);
+      bv[u] = f64x4{b01.x, b01.y, b23.x, b23.y};
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double* pa = &s.a[buf][wm + 16 * t + fr][fk];
+      const double2 a01 = *reinterpret_cast<const double2*>(pa);
+      const double2 a23 = *reinterpret_cast<const double2*>(pa + 2);
+      const f64x4 av = {a01.x, a01.y, a23.x, a23.y};
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], bv[u][j], acc[t][u], 0, 0, 0);
+    }
+    if (c + 1 < nchunks) store_chunk(nx, buf ^ 1);
+    __syncthreads();
+  };
+  load_chunk(0, pend0);
+  load_chunk(min(1, nchunks - 1) * GK64, pend1);
+  // row table of the multiplier: z_row and expm1(z_row), FP64
+  __shared__ double rowv[SIDE == 0 && EPI == kEpiMul ? 2 * GM : 1];
+  if (SIDE == 0 && EPI == kEpiMul && tid < GM) {
+    const long row = tl.m0 + tid;
+    const double zr = row < tl.mrows ? a.tauD * a.lam_x[row] : 0.0;
+    rowv[tid] = zr;
+    rowv[GM + tid] = expm1(zr);
+  }
+  store_chunk(pend0, 0);
+  __syncthreads();  // also publishes rowv
+  for (int c = 0; c < nchunks; c += 2) {
+    iteration(c, std::integral_constant<int, 0>{});
+    if (c + 1 < nchunks) iteration(c + 1, std::integral_constant<int, 1>{});
+  }
+  gemm_epilogue_f64<SIDE, EPI, GM, GN>(a, tl, acc, rowv, wm, wn, lane);
+}
+
+template <int SIDE, int EPI, int TMW, int TNW>
+void launch_mode_gemm_f64_t(const ModalArgs& a, hipStream_t st) {
+  constexpr int GM = 64 * TMW, GN = 64 * TNW;
+  long blocks;
+  if (SIDE == 0) blocks = static_cast<long>(a.pre) * ((a.n + GM - 1) / GM) * ((a.post + GN - 1) / GN);
+  else blocks = ((static_cast<long>(a.pre) + GM - 1) / GM) * ((a.n + GN - 1) / GN);
+  k_mode_gemm_f64<SIDE, EPI, TMW, TNW><<<dim3(static_cast<unsigned>(blocks)), dim3(64 * TMW * TNW), 0, st>>>(a);
+}
+
+template <int SIDE, int EPI>
+void launch_mode_gemm_f64(const ModalArgs& a, hipStream_t st) {
+  const char* e = std::getenv("EXPINT_MODAL_GEMM_TILE");
+  const bool big = e ? e[0] == 'b' : a.n >= 256;
+  if (!big) launch_mode_gemm_f64_t<SIDE, EPI, 2, 2>(a, st);
+  else if (SIDE == 0) launch_mode_gemm_f64_t<SIDE, EPI, 4, 2>(a, st);
+  else launch_mode_gemm_f64_t<SIDE, EPI, 2, 4>(a, st);
+}
+
 // Which matrix-core kernel runs the split products: the LDS-staged GEMM
 // (default) or the strip kernels (EXPINT_MODAL_KERNEL=strip).
 bool modal_use_gemm() {
@@ -1113,10 +1315,11 @@ void launch_mode_mfma_nb(const ModalArgs& a, hipStream_t st) {
 }
 
 // Whether the GEMM's 32-bit buffer offsets reach every byte of the operator
-// (hi and lo) and of one field slab (left: n x post, right: pre x n floats).
-bool gemm_offsets_fit(const ModalArgs& a) {
+// (split precisions: hi and lo) and of one field slab (left: n x post,
+// right: pre x n elements of elem bytes).
+bool gemm_offsets_fit(const ModalArgs& a, long elem = 4) {
   const long slab = a.post == 1 ? static_cast<long>(a.pre) * a.n : static_cast<long>(a.n) * a.post;
-  return slab * 4 < (1L << 31) && 4L * a.n * a.n < (1L << 31);
+  return slab * elem < (1L << 31) && elem * a.n * a.n < (1L << 31);
 }
 
 template <int PREC, int SIDE, int EPI>
@@ -1137,6 +1340,10 @@ void launch_mode_t(const ModalArgs& a, hipStream_t st) {
   }
   if (PREC == kPrecF32 && modal_use_gemm() && gemm_offsets_fit(a)) {
     launch_mode_gemm_f32<SIDE, EPI>(a, st);
+    return;
+  }
+  if (PREC == kPrecF64 && modal_use_gemm() && gemm_offsets_fit(a, 8)) {
+    launch_mode_gemm_f64<SIDE, EPI>(a, st);
     return;
   }
   long tiles;
