@@ -631,12 +631,25 @@ def run_c5(args):
     # (with reaction), else the fp16 split form
     ok = [k for k, r in rows.items() if r.get("meets_bar")]
     head = min(ok, key=lambda k: rows[k]["ms_per_step"]) if ok else "modal_fp16_split"
-    gemm = rows["modal_fp16_split"]["mode_product_x"]
-    # a mode product executes 3 * 2n flops per 8 bytes moved (fp32 in and out):
-    # 192 flop/B at n = 256, below the 16-bit ridge of 2500 / 8 = 312 flop/B,
-    # so HBM is the binding roofline; the matrix-core fraction is reported too
-    intensity = 3 * 2.0 * n / 8.0
-    ridge = peaks["modal_fp16_split"] * 1e12 / (HBM_PEAK_GBS * 1e9)
+    # roofline of the headline form's mode product (x axis); a stencil
+    # headline has none, so the fp16 split product stands in
+    rform = head if head in peaks else "modal_fp16_split"
+    kernels = {"modal_f64": ("k_mode_gemm_f64, x axis (FP64 matrix cores, 256 x 128 tiles)", 8, 1, "gemm_f64_x", "k_mode_gemm_f64"),
+               "modal_f32": ("k_mode_gemm_f32, x axis (FP32 matrix cores, 256 x 128 tiles)", 4, 1, "gemm_f32_x", "k_mode_gemm_f32"),
+               "modal_bf16_split": ("k_mode_gemm bf16 split, x axis (LDS-staged MFMA GEMM, 256 x 128 tiles)", 4, 3,
+                                    "gemm_bf16_x", "k_mode_gemm"),
+               "modal_fp16_split": ("k_mode_gemm fp16 split, x axis (LDS-staged MFMA GEMM, 256 x 128 tiles)", 4, 3,
+                                    "gemm_fp16_x", "k_mode_gemm")}
+    kname, elem, execd, tkey, tkern = kernels[rform]
+    gemm = rows[rform]["mode_product_x"]
+    # a mode product executes execd * 2n flops per 2 elem bytes moved (the
+    # field in and out); below the form's ridge HBM binds, above it the
+    # matrix cores do
+    intensity = execd * 2.0 * n / (2.0 * elem)
+    ridge = peaks[rform] * 1e12 / (HBM_PEAK_GBS * 1e9)
+    hbm = intensity < ridge
+    mpeak = {"modal_f64": None, "modal_f32": None, "modal_bf16_split": measured["mfma_bf16_TFLOPs"],
+             "modal_fp16_split": measured["mfma_fp16_TFLOPs"]}[rform]
     diff = runs["rho_0"]
 
     def speedup(a, b, table):
@@ -660,19 +673,22 @@ def run_c5(args):
         "config": {"workload": "256^3 uniform D=0.1, no-flux, rho 0.025, tau 7.3 d, Gaussian blob at the centre",
                    "headline_form": head},
         "roofline": {
-            "kernel": "k_mode_gemm fp16 split, x axis (LDS-staged MFMA GEMM, 256 x 128 tiles)",
-            "bound": "hbm" if intensity < ridge else "mfma",
-            "achieved": gemm["GBs"] if intensity < ridge else gemm["executed_TFLOPs"],
-            "peak": HBM_PEAK_GBS if intensity < ridge else peaks["modal_fp16_split"],
-            "unit": "GB/s" if intensity < ridge else "TFLOP/s",
-            "frac": gemm["GBs"] / HBM_PEAK_GBS if intensity < ridge else gemm["executed_TFLOPs"] / 2500.0,
-            "traffic": load_traffic(f"gemm_fp16_x_{n}", "k_mode_gemm"),
+            "kernel": kname,
+            "form": rform,
+            "bound": "hbm" if hbm else "mfma",
+            "achieved": gemm["GBs"] if hbm else gemm["executed_TFLOPs"],
+            "peak": HBM_PEAK_GBS if hbm else peaks[rform],
+            "unit": "GB/s" if hbm else "TFLOP/s",
+            "frac": gemm["GBs"] / HBM_PEAK_GBS if hbm else gemm["executed_TFLOPs"] / peaks[rform],
+            "traffic": load_traffic(f"{tkey}_{n}", tkern),
             "intensity_flop_per_byte": intensity,
             "ridge_flop_per_byte": ridge,
             "mfma_TFLOPs_executed": gemm["executed_TFLOPs"],
-            "mfma_frac": gemm["executed_TFLOPs"] / peaks["modal_fp16_split"],
+            "mfma_frac": gemm["executed_TFLOPs"] / peaks[rform],
+            "hbm_GBs": gemm["GBs"],
+            "hbm_frac": gemm["GBs"] / HBM_PEAK_GBS,
             "frac_of_measured_hbm": gemm["GBs"] / measured["copy_hbm_GBs"],
-            "frac_of_measured_mfma": gemm["executed_TFLOPs"] / measured["mfma_fp16_TFLOPs"],
+            "frac_of_measured_mfma": gemm["executed_TFLOPs"] / mpeak if mpeak else None,
         },
         "measured_peaks": measured,
         "variants": rows,

@@ -1103,6 +1103,18 @@ __device__ __forceinline__ void gemm_epilogue_f64(const ModalArgs& a, const Gemm
       zc = a.tauD * (a.lam_y[col / a.nz] + a.lam_z[col % a.nz]);
       emc = expm1(zc);
     }
+    // add into u: the column's 16 loads before its stores (a load after a
+    // store to the same buffer would wait for the store)
+    double old[4][4];
+    if (SIDE == 1 && EPI == kEpiAddU) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const long row = m0 + wm + 16 * t + fr + 4 * r;
+          old[t][r] = row < mrows ? obase[row * rs + col] : 0.0;
+        }
+    }
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -1116,7 +1128,7 @@ __device__ __forceinline__ void gemm_epilogue_f64(const ModalArgs& a, const Gemm
           v *= z == 0.0 ? tau : tau * (fma(emr, emc, emr + emc) / z);
         }
         double* const o = obase + row * rs + col;
-        if (SIDE == 1 && EPI == kEpiAddU) *o = *o + v;
+        if (SIDE == 1 && EPI == kEpiAddU) *o = old[t][r] + v;
         else *o = v;
       }
   }
