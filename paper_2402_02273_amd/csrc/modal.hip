@@ -12,15 +12,20 @@
 // out[p][i'][q] = sum_i Qop[i'][i] in[p][i][q].  Two GEMM shapes:
 //   left  (x and y axes): C_p (n x post) = Qop (n x n) * B_p (n x post)
 //   right (z axis, post = 1): C (pre x n) = B (pre x n) * Qop^T
-// A workgroup of 4 waves computes a 64 x 64 output tile; the K dimension is
-// staged through LDS in chunks of 32.  Arithmetic:
-//   kPrecF64 / kPrecF32  plain vector FMA (4 x 4 outputs per thread);
-//   kPrecBF16 / kPrecF16 matrix cores (v_mfma_f32_32x32x16, FP32 accumulate)
-//                        on hi + lo split operands: x = hi + lo with hi = rnd(x),
+// Every precision runs on the matrix cores in a pipelined LDS-staged GEMM
+// (k_mode_gemm, k_mode_gemm_f32, k_mode_gemm_f64: all n modes per tile at
+// n >= 256, so the field is read once).  Arithmetic:
+//   kPrecF64             v_mfma_f64_16x16x4_f64, FP64 products and sums;
+//   kPrecF32             v_mfma_f32_32x32x2_f32, FP32 products and sums;
+//   kPrecBF16 / kPrecF16 v_mfma_f32_32x32x16 with FP32 accumulation on hi + lo
+//                        split operands: x = hi + lo with hi = rnd(x),
 //                        lo = rnd(x - hi); the product uses hi*hi + hi*lo + lo*hi.
 //                        For FP16 the lo parts are scaled by 2^11 (kept out of
 //                        the subnormal range) and the cross terms accumulate
 //                        separately, rescaled at the end.
+// The earlier kernels (k_mode: 64 x 64 tiles, 4 waves, K staged in chunks of
+// 32; strip kernels for the split precisions) remain behind
+// EXPINT_MODAL_KERNEL=strip.
 // Every dimension of the grid must be a multiple of 32 (checked on the host).
 
 #include "modal.hpp"
@@ -1275,8 +1280,9 @@ void launch_mode_gemm_f64(const ModalArgs& a, hipStream_t st) {
   else launch_mode_gemm_f64_t<SIDE, EPI, 2, 4>(a, st);
 }
 
-// Which matrix-core kernel runs the split products: the LDS-staged GEMM
-// (default) or the strip kernels (EXPINT_MODAL_KERNEL=strip).
+// Which kernels run the mode products: the LDS-staged GEMMs (default) or the
+// earlier ones (EXPINT_MODAL_KERNEL=strip: strip kernels for the split
+// precisions, k_mode for FP32 and FP64).
 bool modal_use_gemm() {
   const char* e = std::getenv("EXPINT_MODAL_KERNEL");
   return !(e && e[0] == 's');
