@@ -197,14 +197,41 @@ hipError_t autotune_pairs(expint_dtype dt, expint_bc bc, const Geom& g, const Co
   return hipSuccess;
 }
 
-hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Coef& cf, void* f0, void* f1, void* f2,
-                          hipStream_t st, bool allow_vec, Tiling* out, void* ju, double jrho, bool vec_only) {
-  *out = default_tiling(g);
+int autotune_key_flags(const Geom& g, const Coef& cf, bool allow_vec, bool ju, bool vec_only) {
   // EXPINT_TILE=scalar / vec restricts the candidates to one sweep shape
   const char* shape = std::getenv("EXPINT_TILE");
   const int only = shape ? (shape[0] == 'v' ? 2 : (shape[0] == 's' ? 1 : 0)) : 0;
   const bool vec_ok = allow_vec && vec_sweep_ok(g, cf.labels_form) && only != 1;
   const bool scalar_ok = !((only == 2 || vec_only) && vec_ok);
+  return (cf.labels_form ? 1 : 0) | (vec_ok ? 2 : 0) | (scalar_ok ? 4 : 0) | (ju ? 8 : 0);
+}
+
+bool autotune_find(expint_dtype dt, expint_bc bc, const Geom& g, int flags, Tiling* out) {
+  const Key key{g.nx, g.ny, g.nz, static_cast<int>(dt), static_cast<int>(bc), flags};
+  std::lock_guard<std::mutex> lk(g_mu);
+  load_tune_file();
+  auto it = g_cache.find(key);
+  if (it == g_cache.end()) return false;
+  *out = it->second;
+  return true;
+}
+
+void autotune_keep(expint_dtype dt, expint_bc bc, const Geom& g, int flags, const Tiling& t) {
+  const Key key{g.nx, g.ny, g.nz, static_cast<int>(dt), static_cast<int>(bc), flags};
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_cache[key] = t;
+  char line[160];
+  std::snprintf(line, sizeof(line), "sweep %s %d %d %d %d %d %d\n", key_text(key).c_str(), t.bx, t.by, t.lp, t.vec,
+                t.rw, t.nt);
+  append_tune_file(line);
+}
+
+hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Coef& cf, void* f0, void* f1, void* f2,
+                          hipStream_t st, bool allow_vec, Tiling* out, void* ju, double jrho, bool vec_only) {
+  *out = default_tiling(g);
+  const int flags = autotune_key_flags(g, cf, allow_vec, ju != nullptr, vec_only);
+  const bool vec_ok = (flags & 2) != 0;
+  const bool scalar_ok = (flags & 4) != 0;
   const char* env = std::getenv("EXPINT_AUTOTUNE");
   if (env && env[0] == '0') {
     if (!scalar_ok) {
@@ -215,8 +242,7 @@ hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Co
     }
     return hipSuccess;
   }
-  const Key key{g.nx, g.ny, g.nz, static_cast<int>(dt), static_cast<int>(bc),
-                (cf.labels_form ? 1 : 0) | (vec_ok ? 2 : 0) | (scalar_ok ? 4 : 0) | (ju ? 8 : 0)};
+  const Key key{g.nx, g.ny, g.nz, static_cast<int>(dt), static_cast<int>(bc), flags};
   {
     std::lock_guard<std::mutex> lk(g_mu);
     load_tune_file();

@@ -33,6 +33,20 @@ hipError_t autotune_sweep(expint_dtype dt, expint_bc bc, const Geom& g, const Co
                           hipStream_t st, bool allow_vec, Tiling* out, void* ju = nullptr, double jrho = 0.0,
                           bool vec_only = false);
 
+// The flags of the key autotune_sweep files its choice for this grid under
+// (bit 1 label form, 2 z-vectorised shapes timed, 4 scalar shapes timed,
+// 8 linearised operator); they follow EXPINT_TILE as the search does.
+int autotune_key_flags(const Geom& g, const Coef& cf, bool allow_vec, bool ju, bool vec_only);
+
+// A tiling chosen in a wider context than one grid's sweeps (a batch times
+// whole steps of all its grids), kept in the same process cache and tuning
+// file under (grid, dtype, bc, flags); the caller sets a flags bit of its own
+// (16 for the batch) on top of autotune_key_flags.  autotune_find reads the
+// tuning file first, as autotune_sweep does, and returns false if there is
+// no entry; autotune_keep stores and appends one.
+bool autotune_find(expint_dtype dt, expint_bc bc, const Geom& g, int flags, Tiling* out);
+void autotune_keep(expint_dtype dt, expint_bc bc, const Geom& g, int flags, const Tiling& t);
+
 // Decides whether the step takes its Taylor terms two at a time (pair
 // sweeps, label form only) and with which tiling.  mode SINGLE: never (ty = 0
 // in *out).  PAIRS: always, in the fastest pair tiling.  AUTO: times every

@@ -29,6 +29,9 @@ using namespace expint;
 namespace {
 
 constexpr int kMaxGrid = 4096;  // workgroups of one batched launch (grid stride beyond)
+// flags bit of the tuning entries a batch files its final tilings under, on
+// top of the key flags of the grid's own sweep search
+constexpr int kBatchTuneFlag = 16;
 
 struct Inst {
   Geom g{};
@@ -44,6 +47,8 @@ struct Inst {
   void* tab = nullptr;
   void* wallc = nullptr;
   Tiling tiling;
+  int ctx_flags = 0;     // tuning key flags of this instance's batch-context entry
+  bool ctx_set = false;  // tiling read from such an entry: the plane pass leaves it
   StepBuffers ws;
   std::vector<double> tab_host;  // class table (64) + wall table (8), FP64
   Coef coef() const {
@@ -150,8 +155,11 @@ int setup_instance(expint_batch* b, Inst& in, const uint8_t* labels_src) {
   if (out[1] != 0.0) return set_error(EXPINT_EINVAL, "a label is >= n_classes (%d)", in.nclass);
   in.norm1 = out[0];
   const bool lin = b->scheme == EXPINT_SCHEME_LINEARISED;
-  BHIP(autotune_sweep(b->dtype, b->bc, in.g, in.coef(), in.ws.y[0], in.ws.acc[0], in.ws.y[1], b->stream, true,
-                      &in.tiling, lin ? in.ws.acc[1] : nullptr, in.rho, /*vec_only=*/true));
+  in.ctx_flags = autotune_key_flags(in.g, in.coef(), true, lin, /*vec_only=*/true) | kBatchTuneFlag;
+  in.ctx_set = autotune_find(b->dtype, b->bc, in.g, in.ctx_flags, &in.tiling);
+  if (!in.ctx_set)
+    BHIP(autotune_sweep(b->dtype, b->bc, in.g, in.coef(), in.ws.y[0], in.ws.acc[0], in.ws.y[1], b->stream, true,
+                        &in.tiling, lin ? in.ws.acc[1] : nullptr, in.rho, /*vec_only=*/true));
   return EXPINT_OK;
 }
 
@@ -317,6 +325,80 @@ int build_schedule(expint_batch* b, void* const* u) {
   return EXPINT_OK;
 }
 
+// Planes per lane of the instances, chosen on whole recorded steps.  Each
+// grid's own search times one sweep launched alone, where one plane per lane
+// (the most waves) tends to win; a batched step runs many instances per
+// launch and several groups at once, so the waves are there anyway, and more
+// planes per lane, which re-read fewer neighbour planes, can be faster.  Every
+// candidate plane count (1, 2, 4, for every instance the pass may change) is
+// recorded as the step it would run and timed over a few replays; the
+// fastest is kept.  The timed steps read and write workspace fields only:
+// each instance's state is stood in for by one of its two term or two sum
+// fields that the step's last sweep does not read (it adds into the state
+// element by element, so the stand-in must not be its stencil source or its
+// running sum).  Their values are meaningless; the caller's fields are not
+// touched.
+int tune_batch_planes(expint_batch* b) {
+  const int count = static_cast<int>(b->inst.size());
+  std::vector<void*> su(count, nullptr);
+  for (int i = 0; i < count; ++i) {
+    Inst& in = b->inst[i];
+    // the last sweep reads at most two fields: one of the four is free
+    const std::vector<TermOp> ops = phi1_schedule(in.ws, in.s, in.m, b->tau, in.ws.b, nullptr, in.ws.b);
+    for (void* f : {in.ws.y[0], in.ws.y[1], in.ws.acc[0], in.ws.acc[1]}) {
+      if (f != ops.back().src && f != ops.back().acc_in) {
+        su[i] = f;
+        break;
+      }
+    }
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t ev = hipEventCreate(&e0);
+  if (ev == hipSuccess) ev = hipEventCreate(&e1);
+  if (ev != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail_hip(b, ev, "hipEventCreate");
+  }
+  int rc = EXPINT_OK;
+  int best_lp = 0;
+  float best = -1.f;
+  for (int lp : {1, 2, 4}) {
+    for (Inst& in : b->inst)
+      if (!in.ctx_set) in.tiling.lp = lp;
+    if ((rc = build_schedule(b, su.data()))) break;
+    // one replay to warm up and size the timed run (at least ~4 ms, 2..20 replays)
+    hipError_t e = hipEventRecord(e0, b->stream);
+    if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    const int reps = std::max(2, std::min(20, static_cast<int>(4.0f / std::max(ms, 1e-3f)) + 1));
+    if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(b->exec, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      rc = fail_hip(b, e, "timing a batched step");
+      break;
+    }
+    ms /= reps;
+    if (std::getenv("EXPINT_LOG")) std::fprintf(stderr, "[expint] batch planes per lane %d: %.3f ms per step\n", lp, ms);
+    if (best < 0.f || ms < best) {
+      best = ms;
+      best_lp = lp;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  destroy_graph(b);
+  if (rc) return rc;
+  for (Inst& in : b->inst)
+    if (!in.ctx_set) in.tiling.lp = best_lp;
+  return EXPINT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -425,6 +507,23 @@ int expint_batch_create(int32_t count, const expint_grid* grids, const expint_df
     } else if (!choose_plan(b->tau * (in.norm1 + (b->scheme == EXPINT_SCHEME_LINEARISED ? in.rho : 0.0)), tol,
                             theta_max, &in.s, &in.m)) {
       return bail(set_error(EXPINT_EINVAL, "instance %d: no admissible plan", i));
+    }
+  }
+  {
+    // instances without a batch-context tuning entry: planes per lane chosen
+    // on whole steps, then filed for later batches and processes
+    bool any = false;
+    for (const Inst& in : b->inst) any = any || !in.ctx_set;
+    const char* env = std::getenv("EXPINT_AUTOTUNE");
+    if (any && !(env && env[0] == '0')) {
+      PhaseRange tr("batch plane tuning");
+      if ((rc = tune_batch_planes(b))) return bail(rc);
+      for (Inst& in : b->inst) {
+        if (in.ctx_set) continue;
+        Tiling t;
+        if (!autotune_find(b->dtype, b->bc, in.g, in.ctx_flags, &t))
+          autotune_keep(b->dtype, b->bc, in.g, in.ctx_flags, in.tiling);
+      }
     }
   }
   if (std::getenv("EXPINT_LOG")) {

@@ -227,7 +227,9 @@ def test_small_batch_linearised_vs_oracle(native, dtype, tol):
 def test_batch_mixed_pinned_shapes_vs_oracle(native, monkeypatch, tmp_path):
     # each instance pinned to a different sweep shape and plane count through
     # a tuning file: the batch splits its launches by plane count and mixes
-    # the scalar and z-vectorised shapes inside a launch
+    # the scalar and z-vectorised shapes inside a launch.  A batch reads its
+    # final tilings under the key flags of the grid's own search (3: label
+    # form, z-vectorised shapes only) plus 16, the batch-context bit
     from paper_2402_02273_amd.expint import ExpIntBatch
 
     shapes = [(9, 10, 12), (6, 33, 68), (17, 5, 264), (12, 12, 20)]
@@ -242,7 +244,7 @@ def test_batch_mixed_pinned_shapes_vs_oracle(native, monkeypatch, tmp_path):
     for dtype, tol in ((torch.float64, 1e-10), (torch.float32, 1e-5)):
         dt = 1 if dtype == torch.float32 else 0
         path = tmp_path / f"tune{dt}.txt"
-        lines = [f"sweep {nx} {ny} {nz} {dt} 0 7 " + " ".join(map(str, t)) for (nx, ny, nz), t in zip(shapes, tiles)]
+        lines = [f"sweep {nx} {ny} {nz} {dt} 0 19 " + " ".join(map(str, t)) for (nx, ny, nz), t in zip(shapes, tiles)]
         path.write_text("\n".join(lines) + "\n")
         monkeypatch.setenv("EXPINT_TUNE_FILE", str(path))
         print(f"[case] batch pinned shapes {dtype}", flush=True)
@@ -256,3 +258,42 @@ def test_batch_mixed_pinned_shapes_vs_oracle(native, monkeypatch, tmp_path):
             ref, _ = oracle_run(inst, tau, 3)
             assert rel(us[i].cpu().numpy(), ref) < tol, (dtype, i)
         del b
+
+
+def test_batch_plane_pass_files_one_plane_count(native, monkeypatch, tmp_path):
+    # grids no other test uses, so nothing is cached for them: creating the
+    # batch times whole steps for 1, 2 and 4 planes per lane on stand-in
+    # workspace fields and files the winner for every grid under the
+    # batch-context key (flags 3 + 16); a second batch reads those lines back
+    # and times nothing.  The run matches the oracle either way.
+    from paper_2402_02273_amd.expint import ExpIntBatch
+
+    shapes = [(10, 14, 24), (13, 9, 40), (11, 6, 16)]
+    insts = []
+    for i, shape in enumerate(shapes):
+        labels = random_labels(shape, 3, seed=270 + i)
+        insts.append({"labels": labels, "class_D": (0.0, 0.12 + 0.01 * i, 0.012), "rho": 0.03,
+                      "u0": random_field(shape, seed=280 + i) * (labels != 0)})
+    path = tmp_path / "tune.txt"
+    path.write_text("")
+    monkeypatch.setenv("EXPINT_TUNE_FILE", str(path))
+    print("[case] batch plane pass", flush=True)
+    b = ExpIntBatch(insts, tau=7.3, dtype=torch.float32, device=DEV)
+    lines = path.read_text().splitlines()
+    ctx = [ln.split() for ln in lines if ln.startswith("sweep ") and ln.split()[6] == "19"]
+    assert sorted(tuple(map(int, c[1:4])) for c in ctx) == sorted(shapes)
+    assert len({c[9] for c in ctx}) == 1 and ctx[0][9] in ("1", "2", "4")  # one plane count
+    assert all(c[10] == "1" for c in ctx)  # z-vectorised shapes
+    us = [dev(i["u0"], torch.float32) for i in insts]
+    b.advance(us, 3)
+    for i, inst in enumerate(insts):
+        ref, _ = oracle_run(inst, 7.3, 3, key="f32")
+        assert rel(us[i].cpu().numpy(), ref) < 1e-5, i
+    del b
+    b2 = ExpIntBatch(insts, tau=7.3, dtype=torch.float32, device=DEV)
+    assert path.read_text().splitlines() == lines
+    us2 = [dev(i["u0"], torch.float32) for i in insts]
+    b2.advance(us2, 3)
+    for a, c in zip(us, us2):
+        assert torch.equal(a, c)
+    del b2
