@@ -281,8 +281,15 @@ typedef struct expint_batch expint_batch;
 /* count instances, each with its own grid, label field, class table and rho
  * (arrays of length count; dfield entries must use the label form).  Shared
  * bc and opts (dtype, tau, tol, theta_max).  Every instance gets its own
- * plan (LINEARISED: for tau (||A||_1 + rho_i)).  Errors as expint_create;
- * EXPRK2 gives EXPINT_EUNSUPPORTED. */
+ * plan (LINEARISED: for tau (||A||_1 + rho_i)).  Creation also picks each
+ * instance's sweep shape: the grid's own search chooses among the
+ * z-vectorised shapes where the grid allows them.  Then, unless every
+ * instance already has a batch entry in the tuning cache or file, whole
+ * steps of the batch are timed with 1, 2 and 4 x-planes per lane.  They run
+ * on workspace stand-ins for the states (a few to twenty replays of each, a
+ * few tens of ms for 64 heads), and the fastest count is kept and filed.
+ * EXPINT_AUTOTUNE=0 skips all timing.  Errors as expint_create; EXPRK2 gives
+ * EXPINT_EUNSUPPORTED. */
 int expint_batch_create(int32_t count, const expint_grid* grids, const expint_dfield* dfields,
                         const double* rho, expint_bc bc, const expint_opts* opts,
                         expint_batch** out);

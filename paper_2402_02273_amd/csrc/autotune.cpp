@@ -24,6 +24,8 @@ std::map<Key, PairTiling> g_pair_cache;
 // same shapes without timing anything.  Lines:
 //   sweep nx ny nz dtype bc flags  bx by lp vec rw nt
 //   pair  nx ny nz dtype bc forced ty lp
+// flags: 1 label form, 2 z-vectorised shapes timed, 4 scalar shapes timed,
+// 8 linearised operator, 16 a batch's final choice (autotune_keep).
 std::string g_loaded_file;  // the tuning file last read into the caches
 
 const char* tune_file() {
