@@ -284,7 +284,8 @@ def run_c2(args):
         model_pv = RHS_BYTES(w_bytes) + 2 * (plan.s * plan.m - 1) * sweep_model + 3 * w_bytes \
             + (2 * plan.s - 1) * w_bytes
     out = {
-        "metric": METRIC,
+        # the stored oracle states (the accuracy gate) exist for 128^3 only
+        "metric": METRIC if args.n == 128 else METRIC.replace("128^3 (rel-L2<=1e-5 vs FP64 oracle)", f"{args.n}^3"),
         "value": value,
         "unit": "voxel-updates/s",
         "n_gpus": 1,
