@@ -605,13 +605,20 @@ def run_c5(args):
                 row["meets_bar"] = row["rel_l2_vs_oracle"] <= bar[dt]
                 row["bar"] = bar[dt]
                 del d
+            if algo == "modal":
+                row["modal_dct"] = ctx.launch_info()["modal_dct"]
             if algo == "modal" and rho > 0:
-                flop = 2.0 * n * w.nvox  # one mode product, algorithmic
+                flop = 2.0 * n * w.nvox  # one dense mode product, algorithmic
                 ms_x = ctx.profile("mode_x", reps=20)
                 ms_z = ctx.profile("mode_z", reps=20)
-                byts = 2.0 * w.nvox * (8 if dt == torch.float64 else 4)
+                byts = 2.0 * w.nvox * (8 if dt == torch.float64 else 4)  # the field in and out
                 execd = {"none": 1, "bf16_split": 3, "fp16_split": 3}[mp]
-                for key, msk in (("mode_product_x", ms_x), ("mode_product_z", ms_z)):
+                for key, msk, bit in (("mode_product_x", ms_x, 1), ("mode_product_z", ms_z, 4)):
+                    if row["modal_dct"] & bit:  # a fast-transform pass: bytes only
+                        row[key] = {"ms": msk, "GBs": byts / (msk * 1e-3) / 1e9,
+                                    "pass": "fast cosine transforms" + (
+                                        " (forward, phi1 multiplier, inverse)" if bit == 1 else " (forward)")}
+                        continue
                     row[key] = {"ms": msk, "alg_TFLOPs": flop / (msk * 1e-3) / 1e12,
                                 "executed_TFLOPs": execd * flop / (msk * 1e-3) / 1e12,
                                 "GBs": byts / (msk * 1e-3) / 1e9}
@@ -643,12 +650,21 @@ def run_c5(args):
                                     "gemm_fp16_x", "k_mode_gemm")}
     kname, elem, execd, tkey, tkern = kernels[rform]
     gemm = rows[rform]["mode_product_x"]
-    # a mode product executes execd * 2n flops per 2 elem bytes moved (the
-    # field in and out); below the form's ridge HBM binds, above it the
+    dct_x = bool(rows[rform].get("modal_dct", 0) & 1)
+    if dct_x:
+        # the x axis runs as fast transforms: one pass reads and writes the
+        # field once (forward DCT-II, multiplier, inverse DCT-III), a few tens
+        # of flops per element, so HBM binds
+        kname = ("k_mode_dct, x pass: forward DCT-II, phi1 multiplier and inverse DCT-III in one pass ("
+                 + ("FP64" if elem == 8 else "FP32") + ")")
+        tkey, tkern = ("dct_f64_x" if elem == 8 else "dct_f32_x"), "k_mode_dct"
+        gemm = dict(gemm, executed_TFLOPs=None)
+    # a dense mode product executes execd * 2n flops per 2 elem bytes moved
+    # (the field in and out); below the form's ridge HBM binds, above it the
     # matrix cores do
     intensity = execd * 2.0 * n / (2.0 * elem)
     ridge = peaks[rform] * 1e12 / (HBM_PEAK_GBS * 1e9)
-    hbm = intensity < ridge
+    hbm = dct_x or intensity < ridge
     mpeak = {"modal_f64": None, "modal_f32": None, "modal_bf16_split": measured["mfma_bf16_TFLOPs"],
              "modal_fp16_split": measured["mfma_fp16_TFLOPs"]}[rform]
     diff = runs["rho_0"]
@@ -682,14 +698,14 @@ def run_c5(args):
             "unit": "GB/s" if hbm else "TFLOP/s",
             "frac": gemm["GBs"] / HBM_PEAK_GBS if hbm else gemm["executed_TFLOPs"] / peaks[rform],
             "traffic": load_traffic(f"{tkey}_{n}", tkern),
-            "intensity_flop_per_byte": intensity,
+            "intensity_flop_per_byte": None if dct_x else intensity,
             "ridge_flop_per_byte": ridge,
             "mfma_TFLOPs_executed": gemm["executed_TFLOPs"],
-            "mfma_frac": gemm["executed_TFLOPs"] / peaks[rform],
+            "mfma_frac": gemm["executed_TFLOPs"] / peaks[rform] if gemm["executed_TFLOPs"] else None,
             "hbm_GBs": gemm["GBs"],
             "hbm_frac": gemm["GBs"] / HBM_PEAK_GBS,
             "frac_of_measured_hbm": gemm["GBs"] / measured["copy_hbm_GBs"],
-            "frac_of_measured_mfma": gemm["executed_TFLOPs"] / mpeak if mpeak else None,
+            "frac_of_measured_mfma": gemm["executed_TFLOPs"] / mpeak if mpeak and gemm["executed_TFLOPs"] else None,
         },
         "measured_peaks": measured,
         "variants": rows,

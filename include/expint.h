@@ -199,6 +199,10 @@ typedef struct {
   int32_t lp;           /* single-term sweeps: x-planes per thread */
   int32_t nt;           /* vectorised sweep: 1 = the Taylor terms of A store their outputs
                          * non-temporally (autotuned; LINEARISED contexts: always 0) */
+  int32_t modal_dct;    /* modal contexts: bit a set if the mode products along axis a
+                         * (0 = x, 1 = y, 2 = z) run as fast cosine transforms (zero flux,
+                         * FP64 or FP32, that axis 32, 64, 128 or 256 long;
+                         * EXPINT_MODAL_DCT=0 in the environment at creation: none); 0 otherwise */
 } expint_launch_info;
 
 /* The context's launch configuration.  EXPINT_EINVAL for NULL arguments. */
@@ -322,8 +326,11 @@ int expint_get_stream(const expint_ctx* ctx, void** stream);
  * launch: kernel 0 = Taylor term that adds a pair of terms to the running sum
  * (reads the source, the sum; writes the term, the sum), 1 = Taylor term that
  * only writes its term, 2 = right-hand side A u + rho u (1 - u); modal
- * contexts also 3 = mode product along x (left GEMM shape), 4 = mode product
- * along z (right GEMM shape); contexts that take their Taylor terms two at a
+ * contexts also 3 = the pass along x as the step runs it (the dense mode
+ * product in the left GEMM shape, or, where x runs as fast transforms, the
+ * forward transform, the phi1 multiplier and the inverse transform in one
+ * pass), 4 = the forward pass along z (dense product in the right GEMM shape,
+ * or the forward transform); contexts that take their Taylor terms two at a
  * time (pair sweeps, label form) also 5 = pair sweep inside a sub-step (reads
  * the source, the sum; writes the second term, the sum), else
  * EXPINT_EUNSUPPORTED.  Uses only the context workspace; synchronises. */

@@ -72,6 +72,7 @@ class LaunchInfo(ctypes.Structure):
         ("rw", ctypes.c_int32),
         ("lp", ctypes.c_int32),
         ("nt", ctypes.c_int32),
+        ("modal_dct", ctypes.c_int32),
     ]
 
 

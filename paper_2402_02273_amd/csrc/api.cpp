@@ -511,6 +511,10 @@ int expint_get_launch(const expint_ctx* c, expint_launch_info* info) {
   info->rw = c->tiling.vec ? c->tiling.rw : 0;
   info->lp = c->tiling.lp;
   info->nt = c->tiling.vec && c->scheme != EXPINT_SCHEME_LINEARISED ? c->tiling.nt : 0;
+  info->modal_dct = 0;
+  if (c->algo == EXPINT_ALGO_MODAL)
+    for (int ax = 0; ax < 3; ++ax)
+      if (c->modal.dct_tw[ax]) info->modal_dct |= 1 << ax;
   return EXPINT_OK;
 }
 
@@ -772,7 +776,31 @@ int expint_profile(expint_ctx* c, int32_t kernel, int32_t reps, double* ms) {
       ma.post = 1;
     }
   }
+  // an axis whose products run as fast transforms: the pass the step runs
+  // (x: forward transform, multiplier and inverse transform; z: the forward
+  // transform)
+  const int max = kernel == 3 ? 0 : 2;
+  const bool dct = mode && c->modal.dct_tw[max] != nullptr;
+  DctArgs da;
+  if (dct) {
+    da.in = ma.in;
+    da.out = ma.out;
+    da.pre = ma.pre;
+    da.n = ma.n;
+    da.post = ma.post;
+    da.tw = c->modal.dct_tw[max];
+    da.mk = c->modal.dct_mk[max];
+    da.lam_x = c->modal.lam[0];
+    da.lam_y = c->modal.lam[1];
+    da.lam_z = c->modal.lam[2];
+    da.tauD = c->tau * c->modal.Dc;
+    da.tau = c->tau;
+    da.nz = c->g.nz;
+  }
   auto launch = [&]() -> hipError_t {
+    if (dct)
+      return launch_mode_dct(c->modal.prec, kernel == 3 ? 0 : 1, kernel == 3 ? kDctFwdMulInv : kDctFwd, kEpiStore,
+                             da, c->stream);
     if (mode) return launch_mode_product(c->modal.prec, kernel == 3 ? 0 : 1, kEpiStore, ma, c->stream);
     if (kernel == 2) return launch_rhs(c->dtype, c->bc, c->g, c->tiling, cf, c->acc[1], c->b, c->rho, c->stream);
     if (kernel == 5) return launch_pair(c->dtype, c->bc, c->g, c->ptiling, cf, op, c->stream);

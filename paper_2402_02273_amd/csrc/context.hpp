@@ -119,6 +119,10 @@ struct expint_ctx {
     void* q[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};  // [axis][fwd, inv]
     double* lam[3] = {nullptr, nullptr, nullptr};
     void* t[2] = {nullptr, nullptr};
+    // fast-transform tables of the axes whose products run as DCTs (zero
+    // flux, FP64 or FP32, a power-of-two length dct_axis_ok), else NULL
+    double* dct_tw[3] = {nullptr, nullptr, nullptr};
+    double* dct_mk[3] = {nullptr, nullptr, nullptr};
   } modal;
 
   // adjoint workspace: allocated on the first gradient call, regrown on demand

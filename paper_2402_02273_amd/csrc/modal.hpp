@@ -1,6 +1,8 @@
 // Modal (per-axis mode product) form of tau phi1(tau A) for uniform D.
 #pragma once
 
+#include <vector>
+
 #include "internal.hpp"
 
 namespace expint {
@@ -29,6 +31,35 @@ struct ModalArgs {
 };
 
 hipError_t launch_mode_product(int prec, int side, int epi, const ModalArgs& a, hipStream_t st);
+
+// Mode products in the zero-flux (cosine) basis by fast transforms: the
+// orthonormal DCT-II (forward, Q^T) or DCT-III (inverse, Q) of every pencil
+// along the middle axis of (pre, n, post) (side 0) or along the contiguous
+// axis (side 1, post == 1), n a power of two from 32 to 256 (dct_axis_ok).
+enum DctMode { kDctFwd = 0, kDctInv = 1, kDctFwdMulInv = 2 };
+struct DctArgs {
+  const void* in = nullptr;
+  void* out = nullptr;
+  int pre = 1, n = 1;
+  long post = 1;
+  const double* tw = nullptr;  // 2n: cos, -sin of 2 pi e / n for e < n (16-byte aligned)
+  const double* mk = nullptr;  // 2n: cos, sin of pi k / (2n) for k < n (16-byte aligned)
+  double c0 = 0.0, c1 = 0.0;   // set by launch_mode_dct: sqrt(1/n), sqrt(2/n)
+  // kDctFwdMulInv (side 0, x axis, pre == 1): between the two transforms
+  // element (i, j, k) is multiplied by tau phi1(tauD (lam_x[i] + lam_y[j] +
+  // lam_z[k])), as kEpiMul does
+  const double* lam_x = nullptr;
+  const double* lam_y = nullptr;
+  const double* lam_z = nullptr;
+  double tauD = 0.0, tau = 0.0;
+  int nz = 1;
+};
+bool dct_axis_ok(int n);
+// prec kPrecF64 or kPrecF32; mode DctMode; epi kEpiStore or (kDctInv, side 1)
+// kEpiAddU.  hipErrorInvalidValue for anything else.
+hipError_t launch_mode_dct(int prec, int side, int mode, int epi, const DctArgs& a, hipStream_t st);
+// The tables of DctArgs for an axis of n points (host arrays).
+void dct_tables(int n, std::vector<double>& tw, std::vector<double>& mk);
 hipError_t launch_label_mask(const uint8_t* labels, int64_t n, unsigned* mask, hipStream_t st);
 
 }  // namespace expint

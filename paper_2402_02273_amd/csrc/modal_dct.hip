@@ -1,0 +1,383 @@
+// Mode products in the zero-flux basis by fast transforms (section 2.2's
+// separable phi1 for uniform D).
+//
+// With zero flux the 1D eigenbasis is the orthonormal cosine basis
+// Q[i][k] = c_k cos(pi k (i + 1/2) / n), so the forward mode product along an
+// axis (Q^T) is the orthonormal DCT-II of every pencil along it and the
+// inverse (Q) the orthonormal DCT-III.  A dense product costs 2n flops per
+// element; these transforms cost O(log n), so a pass is bound by moving the
+// field once through HBM instead of by the matrix cores.
+//
+// DCT-II through a complex DFT of the same length (Makhoul, "A fast cosine
+// transform in one and multiple dimensions", IEEE TASSP 1980): reorder the
+// pencil as v[m] = x[2m], v[n-1-m] = x[2m+1] (m < n/2), take V = DFT(v), and
+// X[k] = c_k Re(e^{-i pi k/(2n)} V[k]).  The DCT-III runs it backwards:
+// V[k] = e^{i pi k/(2n)} (X[k]/c_k - i X[n-k]/c_{n-k}) (the second term 0 at
+// k = 0), v = the inverse DFT of V (1/n included), x[2m] = Re v[m],
+// x[2m+1] = Re v[n-1-m].
+//
+// The DFT of length n = N1 N2 is taken in two passes (Cooley-Tukey): with
+// b = b1 + N1 b2 and a = a1 + N2 a2,
+//   out[a] = sum_{b1} w_{N1}^{b1 a2} w^{b1 a1} sum_{b2} in[b] w_{N2}^{b2 a1},
+// w = e^{-2 pi i / n} (conjugate for the inverse).  Thread b1 of a pencil
+// does the inner DFT over b2 in registers and multiplies by w^{b1 a1}; after
+// an exchange through LDS, thread a1 does the outer DFT over b1.  The pass-1
+// inputs are gathered from the real pencil in LDS (the reordering or the
+// inverse's pre-twiddle applied on the way); pass 1 stores T[b1][a1] at slot
+// b1 + (N1 + 1) a1 of a complex view of the same memory, so the lanes of one
+// store are adjacent slots and the lanes of one pass-2 read are N1 + 1 slots
+// apart: neither conflicts on LDS banks.
+//
+// A workgroup is NTH threads (dct_threads: 128 for FP64, whose complex tile
+// then takes 35 KB of LDS and four workgroups share a CU, else 256): W
+// pencils of TPP = max(N1, N2) threads each.  The
+// field tile (W pencils of n values) is read from and written to global
+// memory in the order that keeps accesses contiguous: W adjacent columns per
+// row for side 0, whole pencils for side 1.  The fused x pass (kDctFwdMulInv)
+// transforms forward, multiplies by the phi1 factor of each mode and
+// transforms back, so the field crosses HBM once for all three.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "modal.hpp"
+
+namespace expint {
+
+namespace {
+
+template <typename T>
+struct CxT;
+template <>
+struct CxT<double> {
+  using type = double2;
+};
+template <>
+struct CxT<float> {
+  using type = float2;
+};
+
+// Threads per workgroup of the transform kernels.
+template <typename T>
+constexpr int dct_threads() {
+  return sizeof(T) == 8 ? 128 : 256;
+}
+
+template <typename C>
+__device__ __forceinline__ C cmul(const C& a, const C& b) {
+  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+template <int R>
+constexpr int bitrev(int i) {
+  int r = 0;
+  for (int b = 1; b < R; b <<= 1) {
+    r = (r << 1) | (i & 1);
+    i >>= 1;
+  }
+  return r;
+}
+
+// cos and sin of 2 pi e / 16 for e < 4, correctly rounded to double
+constexpr double kC16[4] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173};
+constexpr double kS16[4] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+
+// v * w^e with w = e^{-2 pi i / 16} (conjugated for the inverse), e < 8 a
+// compile-time constant: e = 0 and e = 4 (a quarter turn) cost no multiply.
+template <int E, bool INV, typename C>
+__device__ __forceinline__ C twiddle16(const C& v) {
+  using T = decltype(v.x);
+  if constexpr (E == 0) {
+    return v;
+  } else if constexpr (E == 4) {
+    return INV ? C{-v.y, v.x} : C{v.y, -v.x};  // times +i or -i
+  } else {
+    const T c = static_cast<T>(E < 4 ? kC16[E] : -kS16[E - 4]);
+    const T s = static_cast<T>(E < 4 ? kS16[E] : kC16[E - 4]);
+    // w^E = c - i s (forward), c + i s (inverse)
+    return INV ? C{c * v.x - s * v.y, c * v.y + s * v.x} : C{c * v.x + s * v.y, c * v.y - s * v.x};
+  }
+}
+
+// One butterfly stage of the R-point DIT DFT (blocks of LEN), unrolled at
+// compile time.
+template <int R, int LEN, int JJ, bool INV, typename C>
+__device__ __forceinline__ void dit_stage(C (&y)[R]) {
+  if constexpr (JJ < LEN / 2) {
+#pragma unroll
+    for (int s = 0; s < R; s += LEN) {
+      const C u = y[s + JJ];
+      const C v = twiddle16<JJ * (16 / LEN), INV>(y[s + JJ + LEN / 2]);
+      y[s + JJ] = C{u.x + v.x, u.y + v.y};
+      y[s + JJ + LEN / 2] = C{u.x - v.x, u.y - v.y};
+    }
+    dit_stage<R, LEN, JJ + 1, INV>(y);
+  }
+}
+template <int R, int LEN, bool INV, typename C>
+__device__ __forceinline__ void dit_stages(C (&y)[R]) {
+  if constexpr (LEN <= R) {
+    dit_stage<R, LEN, 0, INV>(y);
+    dit_stages<R, LEN * 2, INV>(y);
+  }
+}
+
+// In-place DFT of R <= 16 points in registers (radix 2, decimation in time,
+// output in natural order), forward sign e^{-2 pi i / R} or its conjugate;
+// the twiddles are the compile-time constants above.  No scaling.
+template <int R, bool INV, typename C>
+__device__ __forceinline__ void dft_reg(C (&x)[R]) {
+  static_assert(R >= 2 && R <= 16 && (R & (R - 1)) == 0, "register DFTs of 2 to 16 points");
+  C y[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) y[bitrev<R>(i)] = x[i];
+  dit_stages<R, 2, INV>(y);
+#pragma unroll
+  for (int i = 0; i < R; ++i) x[i] = y[i];
+}
+
+// Two-pass DFT of the pencil w whose pass-1 inputs thread j (< N1) holds in
+// x1 (index j + N1 b2 at x1[b2]).  On return thread j (< N2) holds output
+// j + N2 a2 at y2[a2].  Ends with a barrier: the tile may be overwritten.
+template <typename C, int N1, int N2, bool INV>
+__device__ __forceinline__ void pencil_dft(C* lds, int w, int j, C (&x1)[N2], C (&y2)[N1],
+                                           const double* __restrict__ tw) {
+  constexpr int CS = (N1 + 1) * N2;
+  C* const pc = lds + w * CS;
+  if (j < N1) {
+    dft_reg<N2, INV>(x1);
+#pragma unroll
+    for (int a1 = 0; a1 < N2; ++a1) {
+      C v = x1[a1];
+      if (a1 != 0 && j != 0) {
+        const double2 te = reinterpret_cast<const double2*>(tw)[j * a1];  // j a1 < N1 N2
+        const C t{static_cast<decltype(v.x)>(te.x), static_cast<decltype(v.x)>(INV ? -te.y : te.y)};
+        v = cmul(t, v);
+      }
+      pc[j + (N1 + 1) * a1] = v;
+    }
+  }
+  __syncthreads();
+  if (j < N2) {
+#pragma unroll
+    for (int b1 = 0; b1 < N1; ++b1) y2[b1] = pc[b1 + (N1 + 1) * j];
+    dft_reg<N1, INV>(y2);
+  }
+  __syncthreads();
+}
+
+template <typename T, int N1, int N2, int SIDE, int MODE, int EPI>
+__global__ __launch_bounds__(dct_threads<T>()) void k_mode_dct(DctArgs a) {
+  using C = typename CxT<T>::type;
+  constexpr int N = N1 * N2;
+  constexpr int TPP = N1 > N2 ? N1 : N2;  // threads per pencil
+  constexpr int NTH = dct_threads<T>();   // threads per workgroup
+  constexpr int W = NTH / TPP;            // pencils per workgroup
+  constexpr int CS = (N1 + 1) * N2;       // complex slots per pencil
+  constexpr int RS = N + 1;               // real slots per pencil (the same memory)
+  constexpr int PER = W * N / NTH;        // tile elements per thread
+  static_assert(RS * sizeof(T) <= CS * sizeof(C), "the real view fits in the complex tile");
+  __shared__ C lds[W * CS];
+  __shared__ double rowt[MODE == kDctFwdMulInv ? 2 * N : 1];
+  T* const lr = reinterpret_cast<T*>(lds);
+  const int t = threadIdx.x, w = t / TPP, j = t % TPP;
+
+  const T* __restrict__ in = static_cast<const T*>(a.in);
+  T* __restrict__ out = static_cast<T*>(a.out);
+  // tile element e: pencil e % W, index e / W (side 0: W adjacent columns of
+  // one row are contiguous) or pencil e / N, index e % N (side 1)
+  auto pencil_of = [](int e) { return SIDE == 0 ? e % W : e / N; };
+  auto index_of = [](int e) { return SIDE == 0 ? e / W : e % N; };
+  const long tiles_per_p = SIDE == 0 ? a.post / W : 1;
+  auto tile_base = [&](long tile, long& col0) {
+    if (SIDE == 0) {
+      const long p = tile / tiles_per_p;
+      col0 = (tile - p * tiles_per_p) * W;
+      return p * N * a.post + col0;
+    }
+    col0 = 0;
+    return tile * W * N;
+  };
+  auto goff = [&](long gbase, int e) {
+    return SIDE == 0 ? gbase + static_cast<long>(index_of(e)) * a.post + pencil_of(e) : gbase + static_cast<long>(e);
+  };
+
+  if (MODE == kDctFwdMulInv) {
+    // x-mode part of the multiplier: zr = tauD lam_x[k] and expm1(zr)
+    for (int k = t; k < N; k += NTH) {
+      const double zr = a.tauD * a.lam_x[k];
+      rowt[k] = zr;
+      rowt[N + k] = expm1(zr);
+    }
+  }
+  // one tile per workgroup: all its loads in flight at once
+  long col0 = 0;
+  const long gbase = tile_base(blockIdx.x, col0);
+  {
+    T v[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) v[r] = in[goff(gbase, t + NTH * r)];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = t + NTH * r;
+      lr[pencil_of(e) * RS + index_of(e)] = v[r];
+    }
+  }
+  __syncthreads();
+  {
+
+    T* const pr = lr + w * RS;  // this thread's pencil, real view
+    C x1[N2], y2[N1];
+    if (MODE != kDctInv) {
+      // forward: pass-1 inputs from the reordered pencil
+      if (j < N1) {
+#pragma unroll
+        for (int b2 = 0; b2 < N2; ++b2) {
+          const int m = j + N1 * b2;
+          const int i = m < N / 2 ? 2 * m : 2 * (N - 1 - m) + 1;
+          x1[b2] = C{pr[i], T(0)};
+        }
+      }
+      __syncthreads();  // the real tile becomes the complex one
+      pencil_dft<C, N1, N2, false>(lds, w, j, x1, y2, a.tw);
+      if (j < N2) {
+        double zc = 0.0, emc = 0.0;
+        if (MODE == kDctFwdMulInv) {
+          const long q = col0 + w;  // column (y mode, z mode) of this x pencil
+          zc = a.tauD * (a.lam_y[q / a.nz] + a.lam_z[q % a.nz]);
+          emc = expm1(zc);
+        }
+#pragma unroll
+        for (int a2 = 0; a2 < N1; ++a2) {
+          const int k = j + N2 * a2;
+          const double2 cs = reinterpret_cast<const double2*>(a.mk)[k];
+          const T ck = static_cast<T>(k == 0 ? a.c0 : a.c1);
+          T y = ck * (static_cast<T>(cs.x) * y2[a2].x + static_cast<T>(cs.y) * y2[a2].y);
+          if (MODE == kDctFwdMulInv) {
+            const double z = rowt[k] + zc, emr = rowt[N + k];
+            y = static_cast<T>(static_cast<double>(y) * (z == 0.0 ? a.tau : a.tau * (fma(emr, emc, emr + emc) / z)));
+          }
+          pr[k] = y;
+        }
+      }
+      __syncthreads();
+    }
+    if (MODE != kDctFwd) {
+      // inverse: pass-1 inputs V[k] = e^{i pi k/(2n)} (X[k]/c_k - i X[n-k]/c_{n-k})
+      if (j < N1) {
+#pragma unroll
+        for (int b2 = 0; b2 < N2; ++b2) {
+          const int k = j + N1 * b2;
+          const T yk = pr[k] * static_cast<T>(k == 0 ? 1.0 / a.c0 : 1.0 / a.c1);
+          const T ynk = k == 0 ? T(0) : pr[N - k] * static_cast<T>(1.0 / a.c1);
+          const double2 cs = reinterpret_cast<const double2*>(a.mk)[k];
+          const T c = static_cast<T>(cs.x), sn = static_cast<T>(cs.y);
+          x1[b2] = C{c * yk + sn * ynk, sn * yk - c * ynk};
+        }
+      }
+      __syncthreads();
+      pencil_dft<C, N1, N2, true>(lds, w, j, x1, y2, a.tw);
+      if (j < N2) {
+        const T inv_n = T(1) / T(N);
+#pragma unroll
+        for (int a2 = 0; a2 < N1; ++a2) {
+          const int m = j + N2 * a2;
+          const int i = m < N / 2 ? 2 * m : 2 * (N - 1 - m) + 1;
+          pr[i] = y2[a2].x * inv_n;
+        }
+      }
+      __syncthreads();
+    }
+
+    if (EPI == kEpiAddU) {
+      T old[PER];
+#pragma unroll
+      for (int r = 0; r < PER; ++r) old[r] = out[goff(gbase, t + NTH * r)];
+#pragma unroll
+      for (int r = 0; r < PER; ++r) {
+        const int e = t + NTH * r;
+        out[goff(gbase, e)] = old[r] + lr[pencil_of(e) * RS + index_of(e)];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < PER; ++r) {
+        const int e = t + NTH * r;
+        out[goff(gbase, e)] = lr[pencil_of(e) * RS + index_of(e)];
+      }
+    }
+  }
+}
+
+template <typename T, int N1, int N2, int SIDE, int MODE, int EPI>
+void launch_dct_k(const DctArgs& a, long ntiles, hipStream_t st) {
+  k_mode_dct<T, N1, N2, SIDE, MODE, EPI><<<dim3(static_cast<unsigned>(ntiles)), dct_threads<T>(), 0, st>>>(a);
+}
+
+template <typename T, int N1, int N2>
+hipError_t launch_dct_n(int side, int mode, int epi, const DctArgs& a, hipStream_t st) {
+  constexpr int TPP = N1 > N2 ? N1 : N2, W = dct_threads<T>() / TPP;
+  if (side == 0) {
+    if (a.post % W != 0) return hipErrorInvalidValue;
+    const long ntiles = a.pre * (a.post / W);
+    if (mode == kDctFwd) launch_dct_k<T, N1, N2, 0, kDctFwd, kEpiStore>(a, ntiles, st);
+    else if (mode == kDctInv) launch_dct_k<T, N1, N2, 0, kDctInv, kEpiStore>(a, ntiles, st);
+    else launch_dct_k<T, N1, N2, 0, kDctFwdMulInv, kEpiStore>(a, ntiles, st);
+  } else {
+    if (a.pre % W != 0) return hipErrorInvalidValue;
+    const long ntiles = a.pre / W;
+    if (mode == kDctFwd) launch_dct_k<T, N1, N2, 1, kDctFwd, kEpiStore>(a, ntiles, st);
+    else if (epi == kEpiAddU) launch_dct_k<T, N1, N2, 1, kDctInv, kEpiAddU>(a, ntiles, st);
+    else launch_dct_k<T, N1, N2, 1, kDctInv, kEpiStore>(a, ntiles, st);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dct_t(int side, int mode, int epi, const DctArgs& a, hipStream_t st) {
+  switch (a.n) {
+    case 32: return launch_dct_n<T, 4, 8>(side, mode, epi, a, st);
+    case 64: return launch_dct_n<T, 8, 8>(side, mode, epi, a, st);
+    case 128: return launch_dct_n<T, 8, 16>(side, mode, epi, a, st);
+    case 256: return launch_dct_n<T, 16, 16>(side, mode, epi, a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+bool dct_axis_ok(int n) { return n == 32 || n == 64 || n == 128 || n == 256; }
+
+void dct_tables(int n, std::vector<double>& tw, std::vector<double>& mk) {
+  const double pi = 3.14159265358979323846;
+  tw.assign(2 * static_cast<size_t>(n), 0.0);
+  mk.assign(2 * static_cast<size_t>(n), 0.0);
+  for (int e = 0; e < n; ++e) {
+    const double th = 2.0 * pi * e / n;  // below 2 pi: the argument carries one rounding
+    tw[2 * e] = std::cos(th);
+    tw[2 * e + 1] = -std::sin(th);
+  }
+  for (int k = 0; k < n; ++k) {
+    const double th = pi * k / (2.0 * n);
+    mk[2 * k] = std::cos(th);
+    mk[2 * k + 1] = std::sin(th);
+  }
+}
+
+hipError_t launch_mode_dct(int prec, int side, int mode, int epi, const DctArgs& a, hipStream_t st) {
+  if (!a.in || !a.out || !a.tw || !a.mk || a.pre < 1 || a.post < 1 || !dct_axis_ok(a.n)) return hipErrorInvalidValue;
+  if (side == 1 && a.post != 1) return hipErrorInvalidValue;
+  if (mode == kDctFwdMulInv && (side != 0 || a.pre != 1 || !a.lam_x || !a.lam_y || !a.lam_z))
+    return hipErrorInvalidValue;
+  if (epi == kEpiAddU && (side != 1 || mode != kDctInv)) return hipErrorInvalidValue;
+  if (epi != kEpiStore && epi != kEpiAddU) return hipErrorInvalidValue;
+  DctArgs b = a;  // with the basis scale factors c_0 = sqrt(1/n), c_k = sqrt(2/n)
+  b.c0 = std::sqrt(1.0 / a.n);
+  b.c1 = std::sqrt(2.0 / a.n);
+  if (prec == kPrecF64) return launch_dct_t<double>(side, mode, epi, b, st);
+  if (prec == kPrecF32) return launch_dct_t<float>(side, mode, epi, b, st);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace expint

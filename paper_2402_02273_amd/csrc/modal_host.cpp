@@ -13,6 +13,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -139,6 +140,18 @@ int modal_setup(expint_ctx* c) {
     if ((rc = upload_op(c, inv, n, &c->modal.q[ax][1]))) return rc;
     if ((rc = c->arena.alloc(reinterpret_cast<void**>(&c->modal.lam[ax]), n * sizeof(double)))) return rc;
     HIP_TRY(c, hipMemcpy(c->modal.lam[ax], lam.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    // zero flux, FP64 or FP32, a power-of-two length: the products along this
+    // axis run as fast cosine transforms (EXPINT_MODAL_DCT=0: dense products)
+    const char* de = std::getenv("EXPINT_MODAL_DCT");
+    if (c->bc == EXPINT_NOFLUX && (c->modal.prec == kPrecF64 || c->modal.prec == kPrecF32) && dct_axis_ok(n) &&
+        !(de && de[0] == '0')) {
+      std::vector<double> tw, mk;
+      dct_tables(n, tw, mk);
+      if ((rc = c->arena.alloc(reinterpret_cast<void**>(&c->modal.dct_tw[ax]), tw.size() * sizeof(double)))) return rc;
+      if ((rc = c->arena.alloc(reinterpret_cast<void**>(&c->modal.dct_mk[ax]), mk.size() * sizeof(double)))) return rc;
+      HIP_TRY(c, hipMemcpy(c->modal.dct_tw[ax], tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice));
+      HIP_TRY(c, hipMemcpy(c->modal.dct_mk[ax], mk.data(), mk.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
   }
   const size_t fb = c->field_bytes();
   if ((rc = c->arena.alloc(&c->modal.t[0], fb))) return rc;
@@ -167,16 +180,55 @@ int modal_phi1(expint_ctx* c, const void* b, void* out, bool add_into_out) {
     HIP_TRY(c, launch_mode_product(md.prec, side, epi, a, c->stream));
     return EXPINT_OK;
   };
+  // an axis with fast-transform tables runs its products as DCTs (mode
+  // kDctFwd / kDctInv; along x the forward transform, the multiplier and the
+  // inverse transform in one pass), the others as dense products
+  DctArgs d;
+  d.lam_x = a.lam_x;
+  d.lam_y = a.lam_y;
+  d.lam_z = a.lam_z;
+  d.tauD = a.tauD;
+  d.tau = a.tau;
+  d.nz = nz;
+  auto run_dct = [&](int side, int mode, int epi, int axis, const void* in, void* o, int pre, int n, long post) -> int {
+    d.in = in;
+    d.out = o;
+    d.tw = md.dct_tw[axis];
+    d.mk = md.dct_mk[axis];
+    d.pre = pre;
+    d.n = n;
+    d.post = post;
+    HIP_TRY(c, launch_mode_dct(md.prec, side, mode, epi, d, c->stream));
+    return EXPINT_OK;
+  };
+  const long nyz = static_cast<long>(ny) * nz;
   int rc;
   // forward: z (right), y (left), x (left, with the multiplier)
-  if ((rc = run(1, kEpiStore, 2, 0, b, md.t[0], nx * ny, nz, 1))) return rc;
-  if ((rc = run(0, kEpiStore, 1, 0, md.t[0], md.t[1], nx, ny, nz))) return rc;
-  if ((rc = run(0, kEpiMul, 0, 0, md.t[1], md.t[0], 1, nx, static_cast<long>(ny) * nz))) return rc;
-  // inverse: x, y (left), z (right, into out)
-  if ((rc = run(0, kEpiStore, 0, 1, md.t[0], md.t[1], 1, nx, static_cast<long>(ny) * nz))) return rc;
-  if ((rc = run(0, kEpiStore, 1, 1, md.t[1], md.t[0], nx, ny, nz))) return rc;
-  if ((rc = run(1, add_into_out ? kEpiAddU : kEpiStore, 2, 1, md.t[0], out, nx * ny, nz, 1))) return rc;
-  return EXPINT_OK;
+  if (md.dct_tw[2]) rc = run_dct(1, kDctFwd, kEpiStore, 2, b, md.t[0], nx * ny, nz, 1);
+  else rc = run(1, kEpiStore, 2, 0, b, md.t[0], nx * ny, nz, 1);
+  if (rc) return rc;
+  if (md.dct_tw[1]) rc = run_dct(0, kDctFwd, kEpiStore, 1, md.t[0], md.t[1], nx, ny, nz);
+  else rc = run(0, kEpiStore, 1, 0, md.t[0], md.t[1], nx, ny, nz);
+  if (rc) return rc;
+  // x: the field ends in `cur`, `spare` is free
+  void* cur = md.t[0];
+  void* spare = md.t[1];
+  if (md.dct_tw[0]) {
+    if ((rc = run_dct(0, kDctFwdMulInv, kEpiStore, 0, md.t[1], md.t[0], 1, nx, nyz))) return rc;
+  } else {
+    if ((rc = run(0, kEpiMul, 0, 0, md.t[1], md.t[0], 1, nx, nyz))) return rc;
+    if ((rc = run(0, kEpiStore, 0, 1, md.t[0], md.t[1], 1, nx, nyz))) return rc;
+    cur = md.t[1];
+    spare = md.t[0];
+  }
+  // inverse: y (left), z (right, into out)
+  if (md.dct_tw[1]) rc = run_dct(0, kDctInv, kEpiStore, 1, cur, spare, nx, ny, nz);
+  else rc = run(0, kEpiStore, 1, 1, cur, spare, nx, ny, nz);
+  if (rc) return rc;
+  const int zepi = add_into_out ? kEpiAddU : kEpiStore;
+  if (md.dct_tw[2]) rc = run_dct(1, kDctInv, zepi, 2, spare, out, nx * ny, nz, 1);
+  else rc = run(1, zepi, 2, 1, spare, out, nx * ny, nz, 1);
+  return rc;
 }
 
 }  // namespace expint

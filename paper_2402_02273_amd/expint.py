@@ -324,7 +324,8 @@ class ExpInt:
 
         kernel: "flush" (Taylor term adding a pair of terms to the running sum),
         "skip" (Taylor term writing only its term), "rhs", for modal
-        contexts "mode_x" / "mode_z" (one mode product along x / z), for
+        contexts "mode_x" / "mode_z" (the pass along x as the step runs it /
+        the forward pass along z: a dense mode product, or fast transforms), for
         contexts with pair sweeps "pair" (two terms in one sweep)."""
         ms = ctypes.c_double()
         kid = {"flush": 0, "skip": 1, "rhs": 2, "mode_x": 3, "mode_z": 4, "pair": 5}[kernel]

@@ -42,11 +42,50 @@ def modal_ctx(shape, dtype, mp="none", bc="noflux", D=0.1, rho=0.025, tau=7.3):
 @pytest.mark.parametrize("shape", [(32, 32, 32), (32, 64, 96), (96, 32, 64)])
 @pytest.mark.parametrize("bc", ["noflux", "dirichlet0"])
 def test_modal_phi1_f64(native, shape, bc):
+    # zero flux: the power-of-two axes run as fast cosine transforms; the
+    # sine basis of zero ghost values keeps the dense products
     b = random_field(shape, seed=3, lo=-1, hi=1)
     ctx = modal_ctx(shape, torch.float64, bc=bc)
+    want = sum(1 << ax for ax, n in enumerate(shape) if n in (32, 64, 128, 256)) if bc == "noflux" else 0
+    assert ctx.launch_info()["modal_dct"] == want
     got = ctx.phi1(dev(b, torch.float64)).cpu().numpy()
     ref = oref.modal_phi1(b, 0.1, 1.0, 7.3, bc)
     assert rel(got, ref) < 1e-13
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-13), (torch.float32, 1e-6)])
+# every transform length (32, 64, 128, 256) on each axis, and axes of other
+# lengths (96, 160) that keep the dense products in the same chain
+@pytest.mark.parametrize("shape", [(32, 64, 128), (256, 32, 64), (64, 256, 32), (128, 96, 256), (160, 128, 32)])
+def test_modal_fast_transforms_vs_oracle(native, monkeypatch, dtype, tol, shape):
+    # zero-flux products along power-of-two axes run as fast cosine
+    # transforms (the x pass fused with the multiplier); the same phi1 and
+    # the same step through the dense products (EXPINT_MODAL_DCT=0) and the
+    # FP64 oracle agree
+    b = random_field(shape, seed=13, lo=-1, hi=1)
+    u0 = random_field(shape, seed=14)
+    ref = oref.modal_phi1(b, 0.1, 1.0, 7.3, "noflux")
+    out = {}
+    for mode in ("fast", "dense"):
+        if mode == "dense":
+            monkeypatch.setenv("EXPINT_MODAL_DCT", "0")
+        else:
+            monkeypatch.delenv("EXPINT_MODAL_DCT", raising=False)
+        ctx = modal_ctx(shape, dtype)
+        want = sum(1 << ax for ax, n in enumerate(shape) if n in (32, 64, 128, 256)) if mode == "fast" else 0
+        assert ctx.launch_info()["modal_dct"] == want
+        assert ctx.profile("mode_x", reps=2) > 0 and ctx.profile("mode_z", reps=2) > 0
+        got = ctx.phi1(dev(b, dtype)).cpu().numpy()
+        u = dev(u0, dtype)
+        ctx.advance(u, 2)
+        out[mode] = (got, u.cpu().numpy())
+        err = rel(got, ref)
+        print(f"[result] modal phi1 {shape} {dtype} {mode}: rel-L2 vs FP64 oracle {err:.2e}", flush=True)
+        assert err < tol, mode
+        del ctx
+    assert rel(out["fast"][1], out["dense"][1]) < tol
+    uref = oref.modal_advance(u0, 0.1, 1.0, 0.025, 7.3, 2)
+    assert rel(out["fast"][1], uref) < tol
 
 
 @pytest.mark.parametrize("mp", MPS)
