@@ -38,8 +38,10 @@ FORMS = [
     ("stencil_taylor_f32", torch.float32, "stencil_taylor", "none", 1e-5, 1e-5),
     ("stencil_taylor_f64", torch.float64, "stencil_taylor", "none", 1e-10, 1e-10),
     ("modal_f64", torch.float64, "modal", "none", 1e-10, 2e-10),
-    # measured on MI355X: 7.3e-4 / 1.3e-3, 2.9e-3 / 4.5e-3, 8.9e-2 / 2.7e-1
-    ("modal_f32", torch.float32, "modal", "none", 1.5e-3, 2.5e-3),
+    # measured on MI355X: 1.43-1.50e-3 / 3.3e-3 (FP32 fast cosine transforms;
+    # 7.3e-4 / 1.3e-3 with the FP32 dense products), 2.9e-3 / 4.5e-3,
+    # 8.9e-2 / 2.7e-1
+    ("modal_f32", torch.float32, "modal", "none", 3e-3, 7e-3),
     ("modal_fp16_split", torch.float32, "modal", "fp16_split", 6e-3, 9e-3),
     ("modal_bf16_split", torch.float32, "modal", "bf16_split", 0.2, 0.6),
 ]
