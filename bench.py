@@ -705,6 +705,9 @@ def run_c5(args):
             "hbm_GBs": gemm["GBs"],
             "hbm_frac": gemm["GBs"] / HBM_PEAK_GBS,
             "frac_of_measured_hbm": gemm["GBs"] / measured["copy_hbm_GBs"],
+            # the same bytes over the committed kernel-trace average (fast transforms)
+            "frac_rocprof": (rocprof_frac(f"{tkey}_{n}", tkern, 2.0 * w.nvox * elem, HBM_PEAK_GBS)
+                             if dct_x else None),
             "frac_of_measured_mfma": gemm["executed_TFLOPs"] / mpeak if mpeak and gemm["executed_TFLOPs"] else None,
         },
         "measured_peaks": measured,

@@ -59,6 +59,15 @@ struct CxT<float> {
   using type = float2;
 };
 
+// The tile of workgroup L of nb.  The dispatcher deals workgroups to the 8
+// XCDs round-robin, each with its own L2; adjacent side-0 tiles read the two
+// halves of the same 128-byte lines, so XCD x takes the contiguous run of
+// tiles [x nb/8, (x+1) nb/8) and every line is fetched into one L2 only.
+__device__ __forceinline__ long dct_tile(long L, long nb) {
+  if ((nb & 7) == 0) return (L & 7) * (nb >> 3) + (L >> 3);
+  return L;
+}
+
 // Threads per workgroup of the transform kernels.
 template <typename T>
 constexpr int dct_threads() {
@@ -214,7 +223,7 @@ __global__ __launch_bounds__(dct_threads<T>()) void k_mode_dct(DctArgs a) {
   }
   // one tile per workgroup: all its loads in flight at once
   long col0 = 0;
-  const long gbase = tile_base(blockIdx.x, col0);
+  const long gbase = tile_base(dct_tile(blockIdx.x, gridDim.x), col0);
   {
     T v[PER];
 #pragma unroll
