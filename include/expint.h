@@ -211,7 +211,9 @@ int expint_get_launch(const expint_ctx* ctx, expint_launch_info* info);
 /* Replace rho and (label form) the class diffusivities.  replan != 0
  * recomputes ||A||_1 and (s, m) unless the plan was fixed in the options;
  * replan == 0 keeps the current (s, m) (finite-difference checks need the
- * computed map to stay smooth).  class_D may be NULL to keep it. */
+ * computed map to stay smooth).  class_D may be NULL to keep it.  Modal
+ * contexts need class_D uniform over the classes present in the grid, else
+ * EXPINT_EUNSUPPORTED and nothing changes. */
 int expint_set_params(expint_ctx* ctx, double rho, const double* class_D, int32_t replan);
 
 /* y = A x (device fields).  x and y must not overlap. */

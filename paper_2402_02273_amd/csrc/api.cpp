@@ -200,6 +200,8 @@ int enqueue_step_on(expint_ctx* c, void* u, hipStream_t st, const StepBuffers* s
   if ((st != c->stream || sb) && (c->algo == EXPINT_ALGO_MODAL || c->scheme == EXPINT_SCHEME_EXPRK2))
     return set_error(EXPINT_EUNSUPPORTED, "this step runs on the context stream only");
   void* const bv = sb ? sb->b : c->b;
+  // the modal form with z transforms forms b inside its first pass
+  if (c->algo == EXPINT_ALGO_MODAL && modal_fuses_rhs(c)) return modal_phi1(c, nullptr, u, true, u);
   HIP_TRY(c, launch_rhs(c->dtype, c->bc, c->g, c->tiling, c->coef(), u, bv, c->rho, st));
   if (c->algo == EXPINT_ALGO_MODAL) return modal_phi1(c, c->b, u, true);
   if (c->scheme == EXPINT_SCHEME_EXPRK2) {
@@ -527,8 +529,11 @@ int expint_set_params(expint_ctx* c, double rho, const double* class_D, int32_t 
     if (!c->labels_form) return set_error(EXPINT_EINVAL, "class_D given for a dense-D context");
     for (int a = 0; a < c->nclass; ++a)
       if (!finite_nonneg(class_D[a])) return set_error(EXPINT_EINVAL, "class_D[%d] must be finite and >= 0", a);
+    // the modal form keeps a uniform D: checked before anything changes
+    if (c->algo == EXPINT_ALGO_MODAL && (rc = modal_diffusivity(c, class_D, false))) return rc;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     for (int a = 0; a < c->nclass; ++a) c->class_D[a] = class_D[a];
+    if (c->algo == EXPINT_ALGO_MODAL) (void)modal_diffusivity(c, class_D, true);
     if ((rc = upload_tables(c))) return rc;
   }
   c->rho = rho;

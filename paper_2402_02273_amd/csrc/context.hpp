@@ -116,6 +116,7 @@ struct expint_ctx {
   struct Modal {
     int prec = 0;                       // ModalPrec
     double Dc = 0.0;                    // the uniform diffusivity
+    unsigned present = 0;               // bit a: some voxel has class a
     void* q[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};  // [axis][fwd, inv]
     double* lam[3] = {nullptr, nullptr, nullptr};
     void* t[2] = {nullptr, nullptr};
@@ -212,6 +213,13 @@ double plan_norm(const expint_ctx* c);
 int check_finite_field(expint_ctx* c, const void* u);
 // modal path (modal_host.cpp)
 int modal_setup(expint_ctx* c);
-int modal_phi1(expint_ctx* c, const void* b, void* out, bool add_into_out);
+// u_rhs non-NULL: b is the right-hand side A u_rhs + rho u_rhs (1 - u_rhs),
+// computed inside the first pass where z runs as fast transforms (returns
+// false if it does not: the caller forms b itself)
+bool modal_fuses_rhs(const expint_ctx* c);
+// The uniform diffusivity of class_D over the classes present in the grid
+// (EXPINT_EUNSUPPORTED if they differ); with set, stored as the modal D.
+int modal_diffusivity(expint_ctx* c, const double* class_D, bool set);
+int modal_phi1(expint_ctx* c, const void* b, void* out, bool add_into_out, const void* u_rhs = nullptr);
 
 }  // namespace expint

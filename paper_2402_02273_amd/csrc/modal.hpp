@@ -36,7 +36,7 @@ hipError_t launch_mode_product(int prec, int side, int epi, const ModalArgs& a, 
 // orthonormal DCT-II (forward, Q^T) or DCT-III (inverse, Q) of every pencil
 // along the middle axis of (pre, n, post) (side 0) or along the contiguous
 // axis (side 1, post == 1), n a power of two from 32 to 256 (dct_axis_ok).
-enum DctMode { kDctFwd = 0, kDctInv = 1, kDctFwdMulInv = 2 };
+enum DctMode { kDctFwd = 0, kDctInv = 1, kDctFwdMulInv = 2, kDctRhsFwd = 3 };
 struct DctArgs {
   const void* in = nullptr;
   void* out = nullptr;
@@ -53,10 +53,16 @@ struct DctArgs {
   const double* lam_z = nullptr;
   double tauD = 0.0, tau = 0.0;
   int nz = 1;
+  // kDctRhsFwd (side 1, z axis, pre == nx ny): `in` is the state u and the
+  // pass transforms b = dh2 L u + rho u (1 - u) instead, L the zero-flux
+  // 7-point Laplacian of the nx x ny x n grid (faces at the walls left out)
+  double dh2 = 0.0, rho = 0.0;
+  int nx = 1, ny = 1;
 };
 bool dct_axis_ok(int n);
 // prec kPrecF64 or kPrecF32; mode DctMode; epi kEpiStore or (kDctInv, side 1)
-// kEpiAddU.  hipErrorInvalidValue for anything else.
+// kEpiAddU; kDctRhsFwd needs side 1 and ny a multiple of the workgroup's
+// pencil count (32 suffices).  hipErrorInvalidValue for anything else.
 hipError_t launch_mode_dct(int prec, int side, int mode, int epi, const DctArgs& a, hipStream_t st);
 // The tables of DctArgs for an axis of n points (host arrays).
 void dct_tables(int n, std::vector<double>& tw, std::vector<double>& mk);

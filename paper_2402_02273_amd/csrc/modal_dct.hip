@@ -224,7 +224,58 @@ __global__ __launch_bounds__(dct_threads<T>()) void k_mode_dct(DctArgs a) {
   // one tile per workgroup: all its loads in flight at once
   long col0 = 0;
   const long gbase = tile_base(dct_tile(blockIdx.x, gridDim.x), col0);
-  {
+  if constexpr (MODE == kDctRhsFwd) {
+    // The tile is W rows (x, y0 .. y0 + W - 1) of one x plane.  LDS rows
+    // 0 .. W + 1 take u at y0 - 1 .. y0 + W; the x +- 1 rows come straight
+    // into registers.  A neighbour across a wall is the voxel itself, so its
+    // difference is exactly 0, as for a face left out.
+    static_assert(SIDE == 1, "the right-hand side pass runs along z");
+    static_assert((W + 2) * RS * sizeof(T) <= W * CS * sizeof(C), "halo rows fit in the tile");
+    constexpr int PH = ((W + 2) * N + NTH - 1) / NTH;
+    const long r0 = gbase / N;
+    const int x = static_cast<int>(r0 / a.ny), y0 = static_cast<int>(r0 - static_cast<long>(x) * a.ny);
+    const long plane = static_cast<long>(a.ny) * N;
+    const T* __restrict__ ux = in + static_cast<long>(x) * plane;
+    {
+      T h[PH];
+#pragma unroll
+      for (int r = 0; r < PH; ++r) {
+        const int e = t + NTH * r;
+        const int y = min(max(y0 - 1 + e / N, 0), a.ny - 1);
+        h[r] = e < (W + 2) * N ? ux[static_cast<long>(y) * N + e % N] : T(0);
+      }
+#pragma unroll
+      for (int r = 0; r < PH; ++r) {
+        const int e = t + NTH * r;
+        if (e < (W + 2) * N) lr[(e / N) * RS + e % N] = h[r];
+      }
+    }
+    T xm[PER], xp[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const long o = gbase + t + NTH * r - static_cast<long>(x) * plane;  // offset in the plane
+      xm[r] = ux[(x > 0 ? -plane : 0) + o];
+      xp[r] = ux[(x < a.nx - 1 ? plane : 0) + o];
+    }
+    __syncthreads();
+    T bv[PER];
+    const T dh2 = static_cast<T>(a.dh2), rho = static_cast<T>(a.rho);
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = t + NTH * r, wr = e / N, z = e % N;
+      const T* const row = lr + (wr + 1) * RS;
+      const T c = row[z];
+      const T lap = (xm[r] - c) + (xp[r] - c) + (lr[wr * RS + z] - c) + (lr[(wr + 2) * RS + z] - c) +
+                    (row[z > 0 ? z - 1 : z] - c) + (row[z < N - 1 ? z + 1 : z] - c);
+      bv[r] = dh2 * lap + rho * c * (T(1) - c);
+    }
+    __syncthreads();  // every halo read is done before the tile is overwritten
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = t + NTH * r;
+      lr[pencil_of(e) * RS + index_of(e)] = bv[r];
+    }
+  } else {
     T v[PER];
 #pragma unroll
     for (int r = 0; r < PER; ++r) v[r] = in[goff(gbase, t + NTH * r)];
@@ -273,7 +324,7 @@ __global__ __launch_bounds__(dct_threads<T>()) void k_mode_dct(DctArgs a) {
       }
       __syncthreads();
     }
-    if (MODE != kDctFwd) {
+    if (MODE == kDctInv || MODE == kDctFwdMulInv) {
       // inverse: pass-1 inputs V[k] = e^{i pi k/(2n)} (X[k]/c_k - i X[n-k]/c_{n-k})
       if (j < N1) {
 #pragma unroll
@@ -337,6 +388,7 @@ hipError_t launch_dct_n(int side, int mode, int epi, const DctArgs& a, hipStream
     if (a.pre % W != 0) return hipErrorInvalidValue;
     const long ntiles = a.pre / W;
     if (mode == kDctFwd) launch_dct_k<T, N1, N2, 1, kDctFwd, kEpiStore>(a, ntiles, st);
+    else if (mode == kDctRhsFwd) launch_dct_k<T, N1, N2, 1, kDctRhsFwd, kEpiStore>(a, ntiles, st);
     else if (epi == kEpiAddU) launch_dct_k<T, N1, N2, 1, kDctInv, kEpiAddU>(a, ntiles, st);
     else launch_dct_k<T, N1, N2, 1, kDctInv, kEpiStore>(a, ntiles, st);
   }
@@ -380,6 +432,11 @@ hipError_t launch_mode_dct(int prec, int side, int mode, int epi, const DctArgs&
   if (mode == kDctFwdMulInv && (side != 0 || a.pre != 1 || !a.lam_x || !a.lam_y || !a.lam_z))
     return hipErrorInvalidValue;
   if (epi == kEpiAddU && (side != 1 || mode != kDctInv)) return hipErrorInvalidValue;
+  if (mode == kDctRhsFwd) {
+    const int w = (prec == kPrecF64 ? 128 : 256) / (a.n >= 128 ? 16 : 8);  // pencils per workgroup
+    if (side != 1 || a.nx < 1 || a.ny < 1 || a.ny % w != 0 || static_cast<long>(a.nx) * a.ny != a.pre)
+      return hipErrorInvalidValue;
+  }
   if (epi != kEpiStore && epi != kEpiAddU) return hipErrorInvalidValue;
   DctArgs b = a;  // with the basis scale factors c_0 = sqrt(1/n), c_k = sqrt(2/n)
   b.c0 = std::sqrt(1.0 / a.n);

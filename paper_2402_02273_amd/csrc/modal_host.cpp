@@ -111,16 +111,8 @@ int modal_setup(expint_ctx* c) {
   HIP_TRY(c, hipMemcpyAsync(&hmask, mask, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->arena.release(mask);
-  bool first = true;
-  for (int a = 0; a < c->nclass; ++a) {
-    if (!(hmask & (1u << a))) continue;
-    if (first) {
-      c->modal.Dc = c->class_D[a];
-      first = false;
-    } else if (c->class_D[a] != c->modal.Dc) {
-      return set_error(EXPINT_EUNSUPPORTED, "the modal path needs a uniform diffusivity (classes %d differ)", a);
-    }
-  }
+  c->modal.present = hmask;
+  if ((rc = modal_diffusivity(c, c->class_D, true))) return rc;
   c->modal.prec = c->dtype == EXPINT_F64 ? kPrecF64
                   : c->mp == EXPINT_MP_BF16_SPLIT ? kPrecBF16
                   : c->mp == EXPINT_MP_FP16_SPLIT ? kPrecF16
@@ -159,8 +151,27 @@ int modal_setup(expint_ctx* c) {
   return EXPINT_OK;
 }
 
-// out = tau phi1(tau A) b (add_into_out: out += ...), by six mode products.
-int modal_phi1(expint_ctx* c, const void* b, void* out, bool add_into_out) {
+bool modal_fuses_rhs(const expint_ctx* c) { return c->modal.dct_tw[2] != nullptr; }
+
+int modal_diffusivity(expint_ctx* c, const double* class_D, bool set) {
+  bool first = true;
+  double Dc = 0.0;
+  for (int a = 0; a < c->nclass; ++a) {
+    if (!(c->modal.present & (1u << a))) continue;
+    if (first) {
+      Dc = class_D[a];
+      first = false;
+    } else if (class_D[a] != Dc) {
+      return set_error(EXPINT_EUNSUPPORTED, "the modal path needs a uniform diffusivity (classes %d differ)", a);
+    }
+  }
+  if (set) c->modal.Dc = Dc;
+  return EXPINT_OK;
+}
+
+// out = tau phi1(tau A) b (add_into_out: out += ...), by six mode products;
+// with u_rhs the first pass forms b = A u_rhs + f(u_rhs) itself.
+int modal_phi1(expint_ctx* c, const void* b, void* out, bool add_into_out, const void* u_rhs) {
   const auto& md = c->modal;
   const int nx = c->g.nx, ny = c->g.ny, nz = c->g.nz;
   ModalArgs a;
@@ -204,8 +215,18 @@ int modal_phi1(expint_ctx* c, const void* b, void* out, bool add_into_out) {
   const long nyz = static_cast<long>(ny) * nz;
   int rc;
   // forward: z (right), y (left), x (left, with the multiplier)
-  if (md.dct_tw[2]) rc = run_dct(1, kDctFwd, kEpiStore, 2, b, md.t[0], nx * ny, nz, 1);
-  else rc = run(1, kEpiStore, 2, 0, b, md.t[0], nx * ny, nz, 1);
+  if (u_rhs && !md.dct_tw[2]) return set_error(EXPINT_EINVAL, "the right-hand side is fused only where z runs as fast transforms");
+  if (md.dct_tw[2] && u_rhs) {
+    d.dh2 = md.Dc / (c->h * c->h);
+    d.rho = c->rho;
+    d.nx = nx;
+    d.ny = ny;
+    rc = run_dct(1, kDctRhsFwd, kEpiStore, 2, u_rhs, md.t[0], nx * ny, nz, 1);
+  } else if (md.dct_tw[2]) {
+    rc = run_dct(1, kDctFwd, kEpiStore, 2, b, md.t[0], nx * ny, nz, 1);
+  } else {
+    rc = run(1, kEpiStore, 2, 0, b, md.t[0], nx * ny, nz, 1);
+  }
   if (rc) return rc;
   if (md.dct_tw[1]) rc = run_dct(0, kDctFwd, kEpiStore, 1, md.t[0], md.t[1], nx, ny, nz);
   else rc = run(0, kEpiStore, 1, 0, md.t[0], md.t[1], nx, ny, nz);

@@ -190,3 +190,32 @@ def test_modal_gradient_rejected(native):
         ctx.grad(u0, 2, u0, ckpt_every=1)
     with pytest.raises(ExpIntError, match="EUNSUPPORTED"):
         ctx.vjp(u0, 2, u0, ckpt_every=1)
+
+
+@pytest.mark.parametrize("dense", [False, True])
+def test_modal_set_params_keeps_one_diffusivity(native, monkeypatch, dense):
+    # two classes present with one D: set_params may change it (and rho) if
+    # the classes stay equal, and the step (its right-hand side formed inside
+    # the first transform pass, or by the stencil sweep with dense products)
+    # then follows the new values; unequal values are refused and change
+    # nothing
+    from paper_2402_02273_amd import _native as N
+    from paper_2402_02273_amd.expint import ExpInt
+
+    if dense:
+        monkeypatch.setenv("EXPINT_MODAL_DCT", "0")
+    shape = (32, 64, 32)
+    labels = np.ones(shape, dtype=np.uint8)
+    labels[:16] = 2
+    u0 = random_field(shape, seed=21)
+    ctx = ExpInt(shape, labels=labels, class_D=(0.0, 0.1, 0.1), rho=0.025, tau=7.3, dtype=torch.float64,
+                 algo="modal", device=DEV)
+    assert ctx.launch_info()["modal_dct"] == (0 if dense else 7)
+    ctx.set_params(rho=0.02, class_D=(0.5, 0.2, 0.2))  # class 0 is absent: its D does not count
+    with pytest.raises(N.ExpIntError) as err:
+        ctx.set_params(rho=0.03, class_D=(0.0, 0.2, 0.3))
+    assert err.value.code == N.EUNSUPPORTED
+    u = dev(u0, torch.float64)
+    ctx.advance(u, 3)
+    ref = oref.modal_advance(u0, 0.2, 1.0, 0.02, 7.3, 3)
+    assert rel(u.cpu().numpy(), ref) < 1e-13
