@@ -35,7 +35,10 @@
 // memory in the order that keeps accesses contiguous: W adjacent columns per
 // row for side 0, whole pencils for side 1.  The fused x pass (kDctFwdMulInv)
 // transforms forward, multiplies by the phi1 factor of each mode and
-// transforms back, so the field crosses HBM once for all three.
+// transforms back, so the field crosses HBM once for all three.  The first
+// pass of a step (kDctRhsFwd) reads the state u and forms the right-hand side
+// A u + rho u (1 - u) on the way in (uniform D, zero flux), so the step needs
+// no stencil sweep of its own.
 
 #include <hip/hip_runtime.h>
 
