@@ -68,7 +68,10 @@ typedef enum { EXPINT_NOFLUX = 0, EXPINT_DIRICHLET0 = 1 } expint_bc;
 /* EXPINT_ALGO_STENCIL_TAYLOR: matrix-free stencil inside the scaled Taylor
  * series (any D).  EXPINT_ALGO_MODAL: uniform D only, A diagonalised by
  * per-axis cosine (no-flux) or sine (Dirichlet) modes; phi1 applied exactly
- * in that basis with dense per-axis mode products.  AUTO picks STENCIL_TAYLOR. */
+ * in that basis by per-axis mode products: fast cosine transforms along
+ * no-flux axes of 32, 64, 128 or 256 points (FP64 and FP32 arithmetic, the
+ * step's right-hand side formed inside the first pass when z is one), dense
+ * products otherwise.  AUTO picks STENCIL_TAYLOR. */
 typedef enum {
   EXPINT_ALGO_AUTO = 0,
   EXPINT_ALGO_STENCIL_TAYLOR = 1,
@@ -76,8 +79,9 @@ typedef enum {
 } expint_algo;
 
 /* Arithmetic of the modal path's mode products (EXPINT_F32 contexts only):
- * NONE = fp32 vector FMA; BF16_SPLIT / FP16_SPLIT = matrix-core products of
- * hi + lo split operands with fp32 accumulation. */
+ * NONE = FP32 (fast transforms where they apply, else FP32 matrix-core
+ * products); BF16_SPLIT / FP16_SPLIT = dense matrix-core products of hi + lo
+ * split operands with fp32 accumulation, on every axis. */
 typedef enum {
   EXPINT_MP_NONE = 0,
   EXPINT_MP_BF16_SPLIT = 1,
