@@ -5,8 +5,8 @@
 // Q[i][k] = c_k cos(pi k (i + 1/2) / n), so the forward mode product along an
 // axis (Q^T) is the orthonormal DCT-II of every pencil along it and the
 // inverse (Q) the orthonormal DCT-III.  A dense product costs 2n flops per
-// element; these transforms cost O(log n), so a pass is bound by moving the
-// field once through HBM instead of by the matrix cores.
+// element; these transforms cost O(log n), a few tens of flops per element,
+// so a pass reads and writes the field once and needs no matrix cores.
 //
 // DCT-II through a complex DFT of the same length (Makhoul, "A fast cosine
 // transform in one and multiple dimensions", IEEE TASSP 1980): reorder the
@@ -30,10 +30,10 @@
 //
 // A workgroup is NTH threads (dct_threads: 128 for FP64, whose complex tile
 // then takes 35 KB of LDS and four workgroups share a CU, else 256): W
-// pencils of TPP = max(N1, N2) threads each.  The
-// field tile (W pencils of n values) is read from and written to global
-// memory in the order that keeps accesses contiguous: W adjacent columns per
-// row for side 0, whole pencils for side 1.  The fused x pass (kDctFwdMulInv)
+// pencils of TPP = max(N1, N2) threads each.  The field tile (W pencils of n
+// values) is read from and written to global memory in the order that keeps
+// accesses contiguous: W adjacent columns per row for side 0, whole pencils
+// for side 1.  The fused x pass (kDctFwdMulInv)
 // transforms forward, multiplies by the phi1 factor of each mode and
 // transforms back, so the field crosses HBM once for all three.  The first
 // pass of a step (kDctRhsFwd) reads the state u and forms the right-hand side
