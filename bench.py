@@ -508,7 +508,24 @@ def run_c4(args):
 
     # the first call also allocates the gradient workspace
     ms_first = _timed(go, None)
+    # roofline of the gradient's dominant kernel, the fused reverse sweep: a
+    # Taylor term that reads its source, a second field, the labels and the
+    # tape field of the face products, and writes the term (4w + 1 bytes per
+    # voxel), timed alone on the gradient's workspace (the z-vectorised shape
+    # only), best of three runs of 500 launches
+    ms_face = min(ctx.profile("face", reps=500) for _ in range(3)) if ctx.launch_info()["vec"] else None
     ms = min(_timed(go, None) for _ in range(3))
+    roof = None
+    if ms_face:
+        wb = 8 if args.dtype == "f64" else 4
+        byts = w.nvox * (4 * wb + 1)
+        gbs = byts / (ms_face * 1e-3) / 1e9
+        key = f"face_{args.dtype}_{w.shape[0]}" if args.scheme == "exp_euler" else None
+        roof = {"kernel": "k_sweep_face4 (the gradient's fused reverse sweep: Taylor term and class face products)",
+                "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                "traffic": load_traffic(key, "k_sweep_face4") if key else None,
+                "bytes_per_launch": byts, "ms_per_launch": ms_face,
+                "frac_rocprof": rocprof_frac(key, "k_sweep_face4", byts, HBM_PEAK_GBS) if key else None}
     errs = None
     if os.path.exists(gpath) and args.scheme == "exp_euler":
         g = np.load(gpath)
@@ -539,6 +556,7 @@ def run_c4(args):
                       else "model-free blob + noise")
                    + (", linearised step" if args.scheme == "linearised" else ""),
                    "scheme": args.scheme, "plan": [ctx.plan.s, ctx.plan.m]},
+        "roofline": roof,
         "errors_vs_oracle": errs,
     }
     print(json.dumps(out), flush=True)

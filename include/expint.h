@@ -339,7 +339,11 @@ int expint_get_stream(const expint_ctx* ctx, void** stream);
  * or the forward transform); contexts that take their Taylor terms two at a
  * time (pair sweeps, label form) also 5 = pair sweep inside a sub-step (reads
  * the source, the sum; writes the second term, the sum), else
- * EXPINT_EUNSUPPORTED.  Uses only the context workspace; synchronises. */
+ * EXPINT_EUNSUPPORTED; 6 = the gradient's fused reverse sweep (a Taylor term
+ * reading the source and a second field and writing the term, with the class
+ * face products against a tape field), after a first gradient call on the
+ * context and where it takes the fused form (z-vectorised shape, label form),
+ * else EXPINT_EUNSUPPORTED.  Uses only the context workspace; synchronises. */
 int expint_profile(expint_ctx* ctx, int32_t kernel, int32_t reps, double* ms);
 
 /* ---- Peak probes (measurement of the device; not part of the method). ---- */

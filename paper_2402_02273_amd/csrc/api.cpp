@@ -731,7 +731,9 @@ int expint_reduce(expint_ctx* c, int32_t op, const void* x, const void* y, doubl
 int expint_profile(expint_ctx* c, int32_t kernel, int32_t reps, double* ms) {
   CHECK_CTX(c);
   if (reps < 1 || !ms) return set_error(EXPINT_EINVAL, "reps must be >= 1 and ms non-NULL");
-  if (kernel < 0 || kernel > 5) return set_error(EXPINT_EINVAL, "kernel id must be in 0..5");
+  if (kernel < 0 || kernel > 6) return set_error(EXPINT_EINVAL, "kernel id must be in 0..6");
+  if (kernel == 6 && !c->adj.fpart)
+    return set_error(EXPINT_EUNSUPPORTED, "kernel id 6 times the gradient's reverse sweep: run a gradient first");
   if ((kernel == 3 || kernel == 4) && c->algo != EXPINT_ALGO_MODAL)
     return set_error(EXPINT_EINVAL, "kernel ids 3 and 4 time the modal path's mode products");
   if (kernel == 5 && c->ptiling.ty == 0)
@@ -802,7 +804,30 @@ int expint_profile(expint_ctx* c, int32_t kernel, int32_t reps, double* ms) {
     da.tau = c->tau;
     da.nz = c->g.nz;
   }
+  // 6: the gradient's fused reverse sweep, a Taylor term (source y0, second
+  // source acc0, term written to y1) with the class face products against the
+  // tape field acc1 into the gradient's slots (zeroed again afterwards)
+  TermOp rop;
+  const bool lin = c->scheme == EXPINT_SCHEME_LINEARISED;
+  if (kernel == 6) {
+    rop.src = c->y[0];
+    rop.bsrc = c->acc[0];
+    rop.cb = 1.0;
+    rop.c = c->tau / c->s / 2.0;
+    rop.y_out = c->y[1];
+    classify_term(rop);
+    if (lin) {
+      rop.ju = c->b;  // u_n
+      rop.jrho = c->rho;
+    }
+    if (rop.flavor != kGeneric ||
+        !sweep_face_ok(c->dtype, c->g, c->tiling, c->coef(), {rop.src, rop.bsrc, rop.y_out, c->acc[1], c->b}))
+      return set_error(EXPINT_EUNSUPPORTED, "this context's reverse sweeps do not take the fused form");
+  }
   auto launch = [&]() -> hipError_t {
+    if (kernel == 6)
+      return launch_term_face(c->dtype, c->bc, c->g, c->tiling, c->coef(), rop, c->nclass, c->acc[1], c->adj.dtab,
+                              c->adj.dwall, 1.0, c->adj.fpart, lin ? c->adj.dbar : nullptr, c->stream);
     if (dct)
       return launch_mode_dct(c->modal.prec, kernel == 3 ? 0 : 1, kernel == 3 ? kDctFwdMulInv : kDctFwd, kEpiStore,
                              da, c->stream);
@@ -828,6 +853,11 @@ int expint_profile(expint_ctx* c, int32_t kernel, int32_t reps, double* ms) {
   *ms = static_cast<double>(t) / reps;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (kernel == 6) {
+    HIP_TRY(c, launch_fill(EXPINT_F64, faceprod_slots(c->g, c->tiling) * kMaxClasses, 0.0, c->adj.fpart, c->stream));
+    if (lin) HIP_TRY(c, launch_fill(c->dtype, c->g.n, 0.0, c->adj.dbar, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
   return EXPINT_OK;
 }
 

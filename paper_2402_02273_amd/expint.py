@@ -326,9 +326,10 @@ class ExpInt:
         "skip" (Taylor term writing only its term), "rhs", for modal
         contexts "mode_x" / "mode_z" (the pass along x as the step runs it /
         the forward pass along z: a dense mode product, or fast transforms), for
-        contexts with pair sweeps "pair" (two terms in one sweep)."""
+        contexts with pair sweeps "pair" (two terms in one sweep), after a
+        gradient call "face" (the gradient's fused reverse sweep)."""
         ms = ctypes.c_double()
-        kid = {"flush": 0, "skip": 1, "rhs": 2, "mode_x": 3, "mode_z": 4, "pair": 5}[kernel]
+        kid = {"flush": 0, "skip": 1, "rhs": 2, "mode_x": 3, "mode_z": 4, "pair": 5, "face": 6}[kernel]
         N.check(self.lib.expint_profile(self._ctx, kid, int(reps), ctypes.byref(ms)))
         return ms.value
 

@@ -251,3 +251,27 @@ def test_repeated_gradients(native, dtype, tol):
         assert loss4 == pytest.approx(L4, rel=tol)
         assert rel(g4.cpu().numpy(), gu4) < tol
         check_scalars(r4, d4, grho4, gD4, tol)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_profile_of_the_reverse_sweep_leaves_the_gradient_alone(native, dtype):
+    # expint_profile id 6 times the gradient's fused reverse sweep on the
+    # gradient's own workspace: refused before a gradient has set that up;
+    # afterwards it times, and the next gradient has the same bits
+    from paper_2402_02273_amd import _native as N
+
+    shape = (12, 10, 32)
+    labels = random_labels(shape, 3, seed=61)
+    u0 = random_field(shape, seed=62) * (labels != 0)
+    target = random_field(shape, seed=63)
+    cd, rho, tau, K = (0.0, 0.10, 0.010), 0.02, 7.3, 3
+    ctx = make_ctx(labels, cd, dtype, rho=rho, tau=tau)
+    with pytest.raises(N.ExpIntError) as err:
+        ctx.profile("face", reps=2)
+    assert err.value.code == N.EUNSUPPORTED
+    first = ctx.grad(dev(u0, dtype), K, dev(target, dtype), ckpt_every=2)
+    if ctx.launch_info()["vec"]:
+        assert ctx.profile("face", reps=5) > 0
+    second = ctx.grad(dev(u0, dtype), K, dev(target, dtype), ckpt_every=2)
+    assert first[0] == second[0] and first[2] == second[2] and list(first[3]) == list(second[3])
+    assert torch.equal(first[1], second[1])
