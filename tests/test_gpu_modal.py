@@ -219,3 +219,23 @@ def test_modal_set_params_keeps_one_diffusivity(native, monkeypatch, dense):
     ctx.advance(u, 3)
     ref = oref.modal_advance(u0, 0.2, 1.0, 0.02, 7.3, 3)
     assert rel(u.cpu().numpy(), ref) < 1e-13
+
+
+@pytest.mark.parametrize("dense", [False, True])
+def test_modal_step_with_grid_spacing(native, monkeypatch, dense):
+    # h = 0.5: the eigenvalues scale by 1/h^2, and so does the Laplacian of
+    # the right-hand side formed inside the first transform pass
+    from paper_2402_02273_amd.expint import ExpInt
+
+    if dense:
+        monkeypatch.setenv("EXPINT_MODAL_DCT", "0")
+    shape, h, D, rho, tau, K = (32, 64, 32), 0.5, 0.05, 0.025, 3.0, 3
+    labels = np.ones(shape, dtype=np.uint8)
+    u0 = random_field(shape, seed=31)
+    ctx = ExpInt(shape, h, labels=labels, class_D=(0.0, D), rho=rho, tau=tau, dtype=torch.float64, algo="modal",
+                 device=DEV)
+    assert ctx.launch_info()["modal_dct"] == (0 if dense else 7)
+    u = dev(u0, torch.float64)
+    ctx.advance(u, K)
+    ref = oref.modal_advance(u0, D, h, rho, tau, K)
+    assert rel(u.cpu().numpy(), ref) < 1e-13
