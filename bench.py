@@ -596,6 +596,9 @@ def run_c5(args):
     forms = (
         ("modal_f64", torch.float64, "modal", "none"),
         ("modal_f32", torch.float32, "modal", "none"),
+        # FP32 with dense products on the FP32 matrix cores (fast transforms
+        # off), the plain FP32 counterpart of the split forms' dense products
+        ("modal_f32_dense", torch.float32, "modal", "none"),
         ("modal_bf16_split", torch.float32, "modal", "bf16_split"),
         ("modal_fp16_split", torch.float32, "modal", "fp16_split"),
         ("stencil_taylor_f32", torch.float32, "stencil_taylor", "none"),
@@ -609,8 +612,13 @@ def run_c5(args):
         del ref
         rows = {}
         for name, dt, algo, mp in forms:
-            ctx = ExpInt(w.shape, labels=w.labels, class_D=w.class_D, rho=rho, tau=w.tau, dtype=dt, algo=algo,
-                         mp=mp, device="cuda:0")
+            if name.endswith("_dense"):
+                os.environ["EXPINT_MODAL_DCT"] = "0"
+            try:
+                ctx = ExpInt(w.shape, labels=w.labels, class_D=w.class_D, rho=rho, tau=w.tau, dtype=dt, algo=algo,
+                             mp=mp, device="cuda:0")
+            finally:
+                os.environ.pop("EXPINT_MODAL_DCT", None)
             u = u0d.to(dt).clone()
             ctx.advance(u, 2)
             u.copy_(u0d.to(dt))
@@ -702,7 +710,7 @@ def run_c5(args):
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"modal_fp16_split": "fp16 split (fp32 accumulate)", "modal_bf16_split": "bf16 split (fp32 accumulate)",
-                  "modal_f32": "f32", "modal_f64": "f64", "stencil_taylor_f32": "f32",
+                  "modal_f32": "f32", "modal_f32_dense": "f32", "modal_f64": "f64", "stencil_taylor_f32": "f32",
                   "stencil_taylor_f64": "f64"}[head],
         "data": "synthetic",
         "config": {"workload": "256^3 uniform D=0.1, no-flux, rho 0.025, tau 7.3 d, Gaussian blob at the centre",
@@ -736,6 +744,9 @@ def run_c5(args):
         "speedup_rho0_fp16_split_over_f32_modal": speedup("modal_fp16_split", "modal_f32", diff),
         "speedup_rho0_fp16_split_over_f32_stencil": speedup("modal_fp16_split", "stencil_taylor_f32", diff),
         "speedup_rho0_bf16_split_over_f32_modal": speedup("modal_bf16_split", "modal_f32", diff),
+        # the split forms against FP32 on the same dense products, at matched
+        # accuracy (~1e-7 for both without reaction)
+        "speedup_rho0_fp16_split_over_f32_modal_dense": speedup("modal_fp16_split", "modal_f32_dense", diff),
     }
     print(json.dumps(out), flush=True)
 
