@@ -28,9 +28,21 @@
 // store are adjacent slots and the lanes of one pass-2 read are N1 + 1 slots
 // apart: neither conflicts on LDS banks.
 //
-// A workgroup is NTH threads (dct_threads: 128 for FP64, whose complex tile
-// then takes 35 KB of LDS and four workgroups share a CU, else 256): W
-// pencils of TPP = max(N1, N2) threads each.  The field tile (W pencils of n
+// Two real pencils share one complex DFT: the pencil a goes in as the real
+// part and b as the imaginary part.  Forward, with Z = DFT(v_a + i v_b),
+// V_a[k] = (Z[k] + conj Z[n-k]) / 2 and V_b[k] = (Z[k] - conj Z[n-k]) / (2i);
+// Z[n-k] sits in lane (N2 - j) mod N2 of the same pencil team (register
+// N1 - 1 - a2, or lane 0's own register (N1 - a2) mod N1) and is fetched by a
+// lane shuffle.  Inverse, the DFT of the real v_a + i v_b is V_a + i V_b, so
+// the inverse DFT of that sum gives v_a as its real part and v_b as its
+// imaginary part.  This halves the DFT work of a pencil.
+//
+// A workgroup is NTH threads (dct_threads): TEAMS teams of TPP = max(N1, N2)
+// threads, each team one complex DFT, so W = 2 TEAMS pencils (TEAMS where the
+// pass forms the right-hand side, whose halo rows take the LDS).  FP64 runs
+// 128 threads, whose complex tiles take 35 KB of LDS so that four
+// workgroups share a CU; FP32 256 (128 for the short axes, so that a tile
+// holds at most 32 pencils: every grid dimension is a multiple of 32).  The field tile (W pencils of n
 // values) is read from and written to global memory in the order that keeps
 // accesses contiguous: W adjacent columns per row for side 0, whole pencils
 // for side 1.  The fused x pass (kDctFwdMulInv)
@@ -71,10 +83,14 @@ __device__ __forceinline__ long dct_tile(long L, long nb) {
   return L;
 }
 
-// Threads per workgroup of the transform kernels.
-template <typename T>
+// Threads per workgroup of the transform kernels, and pencils per tile.
+template <typename T, int TPP, int MODE>
 constexpr int dct_threads() {
-  return sizeof(T) == 8 ? 128 : 256;
+  return sizeof(T) == 8 || (TPP < 16 && MODE != kDctRhsFwd) ? 128 : 256;
+}
+template <typename T, int TPP, int MODE>
+constexpr int dct_pencils() {
+  return (MODE == kDctRhsFwd ? 1 : 2) * dct_threads<T, TPP, MODE>() / TPP;
 }
 
 template <typename C>
@@ -181,27 +197,26 @@ __device__ __forceinline__ void pencil_dft(C* lds, int w, int j, C (&x1)[N2], C 
 }
 
 template <typename T, int N1, int N2, int SIDE, int MODE, int EPI>
-__global__ __launch_bounds__(dct_threads<T>()) void k_mode_dct(DctArgs a) {
+__global__ __launch_bounds__((dct_threads<T, (N1 > N2 ? N1 : N2), MODE>()), 2) void k_mode_dct(DctArgs a) {
   using C = typename CxT<T>::type;
   constexpr int N = N1 * N2;
-  constexpr int TPP = N1 > N2 ? N1 : N2;  // threads per pencil
-  constexpr int NTH = dct_threads<T>();   // threads per workgroup
-  constexpr int W = NTH / TPP;            // pencils per workgroup
-  constexpr int CS = (N1 + 1) * N2;       // complex slots per pencil
-  constexpr int RS = N + 1;               // real slots per pencil (the same memory)
-  constexpr int PER = W * N / NTH;        // tile elements per thread
-  static_assert(RS * sizeof(T) <= CS * sizeof(C), "the real view fits in the complex tile");
-  __shared__ C lds[W * CS];
+  constexpr int TPP = N1 > N2 ? N1 : N2;             // threads per DFT
+  constexpr bool PAIR = MODE != kDctRhsFwd;          // two pencils per DFT
+  constexpr int NTH = dct_threads<T, TPP, MODE>();  // threads per workgroup
+  constexpr int TEAMS = NTH / TPP;                   // DFTs per workgroup
+  constexpr int W = dct_pencils<T, TPP, MODE>();     // pencils per workgroup
+  constexpr int CS = (N1 + 1) * N2;                  // complex slots per DFT
+  constexpr int RS = N + 1;                          // real slots per pencil (the same memory)
+  constexpr int PER = W * N / NTH;                   // tile elements per thread
+  static_assert(W * RS * sizeof(T) <= TEAMS * CS * sizeof(C), "the real view fits in the complex tiles");
+  static_assert(!PAIR || N2 == TPP, "the pass-2 outputs of a DFT span its team");
+  __shared__ C lds[TEAMS * CS];
   __shared__ double rowt[MODE == kDctFwdMulInv ? 2 * N : 1];
   T* const lr = reinterpret_cast<T*>(lds);
-  const int t = threadIdx.x, w = t / TPP, j = t % TPP;
+  const int t = threadIdx.x, w = t / TPP, j = t % TPP;  // team, thread in the team
 
   const T* __restrict__ in = static_cast<const T*>(a.in);
   T* __restrict__ out = static_cast<T*>(a.out);
-  // tile element e: pencil e % W, index e / W (side 0: W adjacent columns of
-  // one row are contiguous) or pencil e / N, index e % N (side 1)
-  auto pencil_of = [](int e) { return SIDE == 0 ? e % W : e / N; };
-  auto index_of = [](int e) { return SIDE == 0 ? e / W : e % N; };
   const long tiles_per_p = SIDE == 0 ? a.post / W : 1;
   auto tile_base = [&](long tile, long& col0) {
     if (SIDE == 0) {
@@ -212,9 +227,21 @@ __global__ __launch_bounds__(dct_threads<T>()) void k_mode_dct(DctArgs a) {
     col0 = 0;
     return tile * W * N;
   };
-  auto goff = [&](long gbase, int e) {
-    return SIDE == 0 ? gbase + static_cast<long>(index_of(e)) * a.post + pencil_of(e) : gbase + static_cast<long>(e);
+  // Element r of this thread is tile element e = t + NTH r: pencil e % W and
+  // index e / W on side 0 (W adjacent columns of one row are contiguous),
+  // pencil e / N and index e % N on side 1.  NTH is a multiple of W, and N
+  // and NTH divide one another, so each address is a per-thread part plus a
+  // step in r that is uniform (global) or a compile-time constant (LDS): the
+  // addresses cost no registers across the transforms.
+  static_assert(NTH % W == 0 && (N % NTH == 0 || NTH % N == 0), "tile elements step evenly");
+  auto lds_of = [&](int r) {  // real-view slot of element r
+    if (SIDE == 0) return (t % W) * RS + t / W + r * (NTH / W);
+    if (NTH <= N) return ((r * NTH) / N) * RS + t + (r * NTH) % N;
+    return (t / N + r * (NTH / N)) * RS + t % N;
   };
+  const long rstep = SIDE == 0 ? static_cast<long>(NTH / W) * a.post : NTH;  // elements from r to r + 1
+  const unsigned lane_b =                                                    // this thread's bytes from the row
+      static_cast<unsigned>(SIDE == 0 ? (t / W) * a.post + t % W : t) * static_cast<unsigned>(sizeof(T));
 
   if (MODE == kDctFwdMulInv) {
     // x-mode part of the multiplier: zr = tauD lam_x[k] and expm1(zr)
@@ -227,13 +254,17 @@ __global__ __launch_bounds__(dct_threads<T>()) void k_mode_dct(DctArgs a) {
   // one tile per workgroup: all its loads in flight at once
   long col0 = 0;
   const long gbase = tile_base(dct_tile(blockIdx.x, gridDim.x), col0);
+  auto gin = [&](int r) {
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(in + gbase + r * rstep) + lane_b);
+  };
+  auto gout = [&](int r) { return reinterpret_cast<T*>(reinterpret_cast<char*>(out + gbase + r * rstep) + lane_b); };
   if constexpr (MODE == kDctRhsFwd) {
     // The tile is W rows (x, y0 .. y0 + W - 1) of one x plane.  LDS rows
     // 0 .. W + 1 take u at y0 - 1 .. y0 + W; the x +- 1 rows come straight
     // into registers.  A neighbour across a wall is the voxel itself, so its
     // difference is exactly 0, as for a face left out.
     static_assert(SIDE == 1, "the right-hand side pass runs along z");
-    static_assert((W + 2) * RS * sizeof(T) <= W * CS * sizeof(C), "halo rows fit in the tile");
+    static_assert(!PAIR && (W + 2) * RS * sizeof(T) <= TEAMS * CS * sizeof(C), "halo rows fit in the tile");
     constexpr int PH = ((W + 2) * N + NTH - 1) / NTH;
     const long r0 = gbase / N;
     const int x = static_cast<int>(r0 / a.ny), y0 = static_cast<int>(r0 - static_cast<long>(x) * a.ny);
@@ -274,70 +305,93 @@ __global__ __launch_bounds__(dct_threads<T>()) void k_mode_dct(DctArgs a) {
     }
     __syncthreads();  // every halo read is done before the tile is overwritten
 #pragma unroll
-    for (int r = 0; r < PER; ++r) {
-      const int e = t + NTH * r;
-      lr[pencil_of(e) * RS + index_of(e)] = bv[r];
-    }
+    for (int r = 0; r < PER; ++r) lr[lds_of(r)] = bv[r];
   } else {
     T v[PER];
 #pragma unroll
-    for (int r = 0; r < PER; ++r) v[r] = in[goff(gbase, t + NTH * r)];
+    for (int r = 0; r < PER; ++r) v[r] = *gin(r);
 #pragma unroll
-    for (int r = 0; r < PER; ++r) {
-      const int e = t + NTH * r;
-      lr[pencil_of(e) * RS + index_of(e)] = v[r];
-    }
+    for (int r = 0; r < PER; ++r) lr[lds_of(r)] = v[r];
   }
   __syncthreads();
   {
 
-    T* const pr = lr + w * RS;  // this thread's pencil, real view
+    // the team's pencils, real view: a (and b when paired)
+    T* const pa = lr + (PAIR ? 2 * w : w) * RS;
+    T* const pb = pa + RS;
     C x1[N2], y2[N1];
     if (MODE != kDctInv) {
-      // forward: pass-1 inputs from the reordered pencil
+      // forward: pass-1 inputs from the reordered pencils
       if (j < N1) {
 #pragma unroll
         for (int b2 = 0; b2 < N2; ++b2) {
           const int m = j + N1 * b2;
           const int i = m < N / 2 ? 2 * m : 2 * (N - 1 - m) + 1;
-          x1[b2] = C{pr[i], T(0)};
+          x1[b2] = C{pa[i], PAIR ? pb[i] : T(0)};
         }
       }
       __syncthreads();  // the real tile becomes the complex one
       pencil_dft<C, N1, N2, false>(lds, w, j, x1, y2, a.tw);
-      if (j < N2) {
-        double zc = 0.0, emc = 0.0;
+      if constexpr (PAIR) {
+        double zca = 0.0, emca = 0.0, zcb = 0.0, emcb = 0.0;
         if (MODE == kDctFwdMulInv) {
-          const long q = col0 + w;  // column (y mode, z mode) of this x pencil
-          zc = a.tauD * (a.lam_y[q / a.nz] + a.lam_z[q % a.nz]);
-          emc = expm1(zc);
+          const long qa = col0 + 2 * w, qb = qa + 1;  // columns (y mode, z mode) of the two x pencils
+          zca = a.tauD * (a.lam_y[qa / a.nz] + a.lam_z[qa % a.nz]);
+          zcb = a.tauD * (a.lam_y[qb / a.nz] + a.lam_z[qb % a.nz]);
+          emca = expm1(zca);
+          emcb = expm1(zcb);
         }
+        const int jp = (TPP - j) & (TPP - 1);  // lane of Z[n - k] in the team
+#pragma unroll
+        for (int a2 = 0; a2 < N1; ++a2) {
+          const int k = j + N2 * a2;
+          const C zo = y2[(N1 - a2) & (N1 - 1)];
+          const T sx = __shfl(y2[N1 - 1 - a2].x, jp, TPP);
+          const T sy = __shfl(y2[N1 - 1 - a2].y, jp, TPP);
+          const T nr = j == 0 ? zo.x : sx, ni = j == 0 ? zo.y : sy;
+          const T zr = y2[a2].x, zi = y2[a2].y;
+          const double2 cs = reinterpret_cast<const double2*>(a.mk)[k];
+          const T c = static_cast<T>(cs.x), sn = static_cast<T>(cs.y);
+          const T ck = static_cast<T>(0.5 * (k == 0 ? a.c0 : a.c1));
+          T ya = ck * (c * (zr + nr) + sn * (zi - ni));
+          T yb = ck * (c * (zi + ni) + sn * (nr - zr));
+          if (MODE == kDctFwdMulInv) {
+            const double zr0 = rowt[k], emr = rowt[N + k];
+            const double za = zr0 + zca, zb = zr0 + zcb;
+            ya = static_cast<T>(static_cast<double>(ya) *
+                                (za == 0.0 ? a.tau : a.tau * (fma(emr, emca, emr + emca) / za)));
+            yb = static_cast<T>(static_cast<double>(yb) *
+                                (zb == 0.0 ? a.tau : a.tau * (fma(emr, emcb, emr + emcb) / zb)));
+          }
+          pa[k] = ya;
+          pb[k] = yb;
+        }
+      } else if (j < N2) {
 #pragma unroll
         for (int a2 = 0; a2 < N1; ++a2) {
           const int k = j + N2 * a2;
           const double2 cs = reinterpret_cast<const double2*>(a.mk)[k];
           const T ck = static_cast<T>(k == 0 ? a.c0 : a.c1);
-          T y = ck * (static_cast<T>(cs.x) * y2[a2].x + static_cast<T>(cs.y) * y2[a2].y);
-          if (MODE == kDctFwdMulInv) {
-            const double z = rowt[k] + zc, emr = rowt[N + k];
-            y = static_cast<T>(static_cast<double>(y) * (z == 0.0 ? a.tau : a.tau * (fma(emr, emc, emr + emc) / z)));
-          }
-          pr[k] = y;
+          pa[k] = ck * (static_cast<T>(cs.x) * y2[a2].x + static_cast<T>(cs.y) * y2[a2].y);
         }
       }
       __syncthreads();
     }
     if (MODE == kDctInv || MODE == kDctFwdMulInv) {
       // inverse: pass-1 inputs V[k] = e^{i pi k/(2n)} (X[k]/c_k - i X[n-k]/c_{n-k})
+      // of both pencils, packed as V_a + i V_b
       if (j < N1) {
+        const T r0 = static_cast<T>(1.0 / a.c0), r1 = static_cast<T>(1.0 / a.c1);
 #pragma unroll
         for (int b2 = 0; b2 < N2; ++b2) {
           const int k = j + N1 * b2;
-          const T yk = pr[k] * static_cast<T>(k == 0 ? 1.0 / a.c0 : 1.0 / a.c1);
-          const T ynk = k == 0 ? T(0) : pr[N - k] * static_cast<T>(1.0 / a.c1);
           const double2 cs = reinterpret_cast<const double2*>(a.mk)[k];
           const T c = static_cast<T>(cs.x), sn = static_cast<T>(cs.y);
-          x1[b2] = C{c * yk + sn * ynk, sn * yk - c * ynk};
+          const T yka = pa[k] * (k == 0 ? r0 : r1), ykb = pb[k] * (k == 0 ? r0 : r1);
+          const T ynka = k == 0 ? T(0) : pa[N - k] * r1, ynkb = k == 0 ? T(0) : pb[N - k] * r1;
+          const T ar = c * yka + sn * ynka, ai = sn * yka - c * ynka;
+          const T br = c * ykb + sn * ynkb, bi = sn * ykb - c * ynkb;
+          x1[b2] = C{ar - bi, ai + br};
         }
       }
       __syncthreads();
@@ -348,7 +402,8 @@ __global__ __launch_bounds__(dct_threads<T>()) void k_mode_dct(DctArgs a) {
         for (int a2 = 0; a2 < N1; ++a2) {
           const int m = j + N2 * a2;
           const int i = m < N / 2 ? 2 * m : 2 * (N - 1 - m) + 1;
-          pr[i] = y2[a2].x * inv_n;
+          pa[i] = y2[a2].x * inv_n;
+          pb[i] = y2[a2].y * inv_n;
         }
       }
       __syncthreads();
@@ -357,45 +412,40 @@ __global__ __launch_bounds__(dct_threads<T>()) void k_mode_dct(DctArgs a) {
     if (EPI == kEpiAddU) {
       T old[PER];
 #pragma unroll
-      for (int r = 0; r < PER; ++r) old[r] = out[goff(gbase, t + NTH * r)];
+      for (int r = 0; r < PER; ++r) old[r] = *gout(r);
 #pragma unroll
-      for (int r = 0; r < PER; ++r) {
-        const int e = t + NTH * r;
-        out[goff(gbase, e)] = old[r] + lr[pencil_of(e) * RS + index_of(e)];
-      }
+      for (int r = 0; r < PER; ++r) *gout(r) = old[r] + lr[lds_of(r)];
     } else {
 #pragma unroll
-      for (int r = 0; r < PER; ++r) {
-        const int e = t + NTH * r;
-        out[goff(gbase, e)] = lr[pencil_of(e) * RS + index_of(e)];
-      }
+      for (int r = 0; r < PER; ++r) *gout(r) = lr[lds_of(r)];
     }
   }
 }
 
 template <typename T, int N1, int N2, int SIDE, int MODE, int EPI>
-void launch_dct_k(const DctArgs& a, long ntiles, hipStream_t st) {
-  k_mode_dct<T, N1, N2, SIDE, MODE, EPI><<<dim3(static_cast<unsigned>(ntiles)), dct_threads<T>(), 0, st>>>(a);
+hipError_t launch_dct_k(const DctArgs& a, hipStream_t st) {
+  constexpr int TPP = N1 > N2 ? N1 : N2, W = dct_pencils<T, TPP, MODE>();
+  if (SIDE == 0 ? a.post % W != 0 : a.pre % W != 0) return hipErrorInvalidValue;
+  // a thread's offset within a tile row is 32-bit
+  if (SIDE == 0 && static_cast<double>(dct_threads<T, TPP, MODE>() / W) * a.post * sizeof(T) >= 4294967296.0)
+    return hipErrorInvalidValue;
+  const long ntiles = SIDE == 0 ? a.pre * (a.post / W) : a.pre / W;
+  k_mode_dct<T, N1, N2, SIDE, MODE, EPI>
+      <<<dim3(static_cast<unsigned>(ntiles)), dct_threads<T, TPP, MODE>(), 0, st>>>(a);
+  return hipGetLastError();
 }
 
 template <typename T, int N1, int N2>
 hipError_t launch_dct_n(int side, int mode, int epi, const DctArgs& a, hipStream_t st) {
-  constexpr int TPP = N1 > N2 ? N1 : N2, W = dct_threads<T>() / TPP;
   if (side == 0) {
-    if (a.post % W != 0) return hipErrorInvalidValue;
-    const long ntiles = a.pre * (a.post / W);
-    if (mode == kDctFwd) launch_dct_k<T, N1, N2, 0, kDctFwd, kEpiStore>(a, ntiles, st);
-    else if (mode == kDctInv) launch_dct_k<T, N1, N2, 0, kDctInv, kEpiStore>(a, ntiles, st);
-    else launch_dct_k<T, N1, N2, 0, kDctFwdMulInv, kEpiStore>(a, ntiles, st);
-  } else {
-    if (a.pre % W != 0) return hipErrorInvalidValue;
-    const long ntiles = a.pre / W;
-    if (mode == kDctFwd) launch_dct_k<T, N1, N2, 1, kDctFwd, kEpiStore>(a, ntiles, st);
-    else if (mode == kDctRhsFwd) launch_dct_k<T, N1, N2, 1, kDctRhsFwd, kEpiStore>(a, ntiles, st);
-    else if (epi == kEpiAddU) launch_dct_k<T, N1, N2, 1, kDctInv, kEpiAddU>(a, ntiles, st);
-    else launch_dct_k<T, N1, N2, 1, kDctInv, kEpiStore>(a, ntiles, st);
+    if (mode == kDctFwd) return launch_dct_k<T, N1, N2, 0, kDctFwd, kEpiStore>(a, st);
+    if (mode == kDctInv) return launch_dct_k<T, N1, N2, 0, kDctInv, kEpiStore>(a, st);
+    return launch_dct_k<T, N1, N2, 0, kDctFwdMulInv, kEpiStore>(a, st);
   }
-  return hipGetLastError();
+  if (mode == kDctFwd) return launch_dct_k<T, N1, N2, 1, kDctFwd, kEpiStore>(a, st);
+  if (mode == kDctRhsFwd) return launch_dct_k<T, N1, N2, 1, kDctRhsFwd, kEpiStore>(a, st);
+  if (epi == kEpiAddU) return launch_dct_k<T, N1, N2, 1, kDctInv, kEpiAddU>(a, st);
+  return launch_dct_k<T, N1, N2, 1, kDctInv, kEpiStore>(a, st);
 }
 
 template <typename T>
