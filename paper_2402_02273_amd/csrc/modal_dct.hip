@@ -38,11 +38,11 @@
 // imaginary part.  This halves the DFT work of a pencil.
 //
 // A workgroup is NTH threads (dct_threads): TEAMS teams of TPP = max(N1, N2)
-// threads, each team one complex DFT, so W = 2 TEAMS pencils (TEAMS where the
-// pass forms the right-hand side, whose halo rows take the LDS).  FP64 runs
-// 128 threads, whose complex tiles take 35 KB of LDS so that four
-// workgroups share a CU; FP32 256 (128 for the short axes, so that a tile
-// holds at most 32 pencils: every grid dimension is a multiple of 32).  The field tile (W pencils of n
+// threads, each team one complex DFT, so W = 2 TEAMS pencils.  FP64 runs 128
+// threads, whose complex tiles take 35 KB of LDS (37 KB with the halo rows of
+// the right-hand side pass) so that four workgroups share a CU; FP32 256
+// (128 for the short axes, so that a tile holds at most 32 pencils: every
+// grid dimension is a multiple of 32).  The field tile (W pencils of n
 // values) is read from and written to global memory in the order that keeps
 // accesses contiguous: W adjacent columns per row for side 0, whole pencils
 // for side 1.  The fused x pass (kDctFwdMulInv)
@@ -84,13 +84,13 @@ __device__ __forceinline__ long dct_tile(long L, long nb) {
 }
 
 // Threads per workgroup of the transform kernels, and pencils per tile.
-template <typename T, int TPP, int MODE>
+template <typename T, int TPP>
 constexpr int dct_threads() {
-  return sizeof(T) == 8 || (TPP < 16 && MODE != kDctRhsFwd) ? 128 : 256;
+  return sizeof(T) == 8 || TPP < 16 ? 128 : 256;
 }
-template <typename T, int TPP, int MODE>
+template <typename T, int TPP>
 constexpr int dct_pencils() {
-  return (MODE == kDctRhsFwd ? 1 : 2) * dct_threads<T, TPP, MODE>() / TPP;
+  return 2 * dct_threads<T, TPP>() / TPP;
 }
 
 template <typename C>
@@ -197,20 +197,23 @@ __device__ __forceinline__ void pencil_dft(C* lds, int w, int j, C (&x1)[N2], C 
 }
 
 template <typename T, int N1, int N2, int SIDE, int MODE, int EPI>
-__global__ __launch_bounds__((dct_threads<T, (N1 > N2 ? N1 : N2), MODE>()), 2) void k_mode_dct(DctArgs a) {
+__global__ __launch_bounds__((dct_threads<T, (N1 > N2 ? N1 : N2)>()), 2) void k_mode_dct(DctArgs a) {
   using C = typename CxT<T>::type;
   constexpr int N = N1 * N2;
-  constexpr int TPP = N1 > N2 ? N1 : N2;             // threads per DFT
-  constexpr bool PAIR = MODE != kDctRhsFwd;          // two pencils per DFT
-  constexpr int NTH = dct_threads<T, TPP, MODE>();  // threads per workgroup
-  constexpr int TEAMS = NTH / TPP;                   // DFTs per workgroup
-  constexpr int W = dct_pencils<T, TPP, MODE>();     // pencils per workgroup
-  constexpr int CS = (N1 + 1) * N2;                  // complex slots per DFT
-  constexpr int RS = N + 1;                          // real slots per pencil (the same memory)
-  constexpr int PER = W * N / NTH;                   // tile elements per thread
+  constexpr int TPP = N1 > N2 ? N1 : N2;       // threads per DFT
+  constexpr int NTH = dct_threads<T, TPP>();   // threads per workgroup
+  constexpr int TEAMS = NTH / TPP;             // DFTs per workgroup
+  constexpr int W = dct_pencils<T, TPP>();     // pencils per workgroup, two per DFT
+  constexpr int CS = (N1 + 1) * N2;            // complex slots per DFT
+  constexpr int RS = N + 1;                    // real slots per pencil (the same memory)
+  constexpr int PER = W * N / NTH;             // tile elements per thread
+  // complex slots of the tile: the complex view, or the W + 2 halo rows of
+  // the right-hand side pass if those take more
+  constexpr int HALO_C = static_cast<int>(((W + 2) * RS * sizeof(T) + sizeof(C) - 1) / sizeof(C));
+  constexpr int LDS_C = MODE == kDctRhsFwd && HALO_C > TEAMS * CS ? HALO_C : TEAMS * CS;
   static_assert(W * RS * sizeof(T) <= TEAMS * CS * sizeof(C), "the real view fits in the complex tiles");
-  static_assert(!PAIR || N2 == TPP, "the pass-2 outputs of a DFT span its team");
-  __shared__ C lds[TEAMS * CS];
+  static_assert(N2 == TPP, "the pass-2 outputs of a DFT span its team");
+  __shared__ C lds[LDS_C];
   __shared__ double rowt[MODE == kDctFwdMulInv ? 2 * N : 1];
   T* const lr = reinterpret_cast<T*>(lds);
   const int t = threadIdx.x, w = t / TPP, j = t % TPP;  // team, thread in the team
@@ -264,7 +267,7 @@ __global__ __launch_bounds__((dct_threads<T, (N1 > N2 ? N1 : N2), MODE>()), 2) v
     // into registers.  A neighbour across a wall is the voxel itself, so its
     // difference is exactly 0, as for a face left out.
     static_assert(SIDE == 1, "the right-hand side pass runs along z");
-    static_assert(!PAIR && (W + 2) * RS * sizeof(T) <= TEAMS * CS * sizeof(C), "halo rows fit in the tile");
+    static_assert((W + 2) * RS * sizeof(T) <= LDS_C * sizeof(C), "halo rows fit in the tile");
     constexpr int PH = ((W + 2) * N + NTH - 1) / NTH;
     const long r0 = gbase / N;
     const int x = static_cast<int>(r0 / a.ny), y0 = static_cast<int>(r0 - static_cast<long>(x) * a.ny);
@@ -316,8 +319,8 @@ __global__ __launch_bounds__((dct_threads<T, (N1 > N2 ? N1 : N2), MODE>()), 2) v
   __syncthreads();
   {
 
-    // the team's pencils, real view: a (and b when paired)
-    T* const pa = lr + (PAIR ? 2 * w : w) * RS;
+    // the team's two pencils, real view
+    T* const pa = lr + 2 * w * RS;
     T* const pb = pa + RS;
     C x1[N2], y2[N1];
     if (MODE != kDctInv) {
@@ -327,12 +330,12 @@ __global__ __launch_bounds__((dct_threads<T, (N1 > N2 ? N1 : N2), MODE>()), 2) v
         for (int b2 = 0; b2 < N2; ++b2) {
           const int m = j + N1 * b2;
           const int i = m < N / 2 ? 2 * m : 2 * (N - 1 - m) + 1;
-          x1[b2] = C{pa[i], PAIR ? pb[i] : T(0)};
+          x1[b2] = C{pa[i], pb[i]};
         }
       }
       __syncthreads();  // the real tile becomes the complex one
       pencil_dft<C, N1, N2, false>(lds, w, j, x1, y2, a.tw);
-      if constexpr (PAIR) {
+      {
         double zca = 0.0, emca = 0.0, zcb = 0.0, emcb = 0.0;
         if (MODE == kDctFwdMulInv) {
           const long qa = col0 + 2 * w, qb = qa + 1;  // columns (y mode, z mode) of the two x pencils
@@ -365,14 +368,6 @@ __global__ __launch_bounds__((dct_threads<T, (N1 > N2 ? N1 : N2), MODE>()), 2) v
           }
           pa[k] = ya;
           pb[k] = yb;
-        }
-      } else if (j < N2) {
-#pragma unroll
-        for (int a2 = 0; a2 < N1; ++a2) {
-          const int k = j + N2 * a2;
-          const double2 cs = reinterpret_cast<const double2*>(a.mk)[k];
-          const T ck = static_cast<T>(k == 0 ? a.c0 : a.c1);
-          pa[k] = ck * (static_cast<T>(cs.x) * y2[a2].x + static_cast<T>(cs.y) * y2[a2].y);
         }
       }
       __syncthreads();
@@ -424,14 +419,17 @@ __global__ __launch_bounds__((dct_threads<T, (N1 > N2 ? N1 : N2), MODE>()), 2) v
 
 template <typename T, int N1, int N2, int SIDE, int MODE, int EPI>
 hipError_t launch_dct_k(const DctArgs& a, hipStream_t st) {
-  constexpr int TPP = N1 > N2 ? N1 : N2, W = dct_pencils<T, TPP, MODE>();
+  constexpr int TPP = N1 > N2 ? N1 : N2, W = dct_pencils<T, TPP>();
   if (SIDE == 0 ? a.post % W != 0 : a.pre % W != 0) return hipErrorInvalidValue;
+  // the right-hand side pass: a tile is W rows of one x plane
+  if (MODE == kDctRhsFwd && (a.nx < 1 || a.ny < 1 || a.ny % W != 0 || static_cast<long>(a.nx) * a.ny != a.pre))
+    return hipErrorInvalidValue;
   // a thread's offset within a tile row is 32-bit
-  if (SIDE == 0 && static_cast<double>(dct_threads<T, TPP, MODE>() / W) * a.post * sizeof(T) >= 4294967296.0)
+  if (SIDE == 0 && static_cast<double>(dct_threads<T, TPP>() / W) * a.post * sizeof(T) >= 4294967296.0)
     return hipErrorInvalidValue;
   const long ntiles = SIDE == 0 ? a.pre * (a.post / W) : a.pre / W;
   k_mode_dct<T, N1, N2, SIDE, MODE, EPI>
-      <<<dim3(static_cast<unsigned>(ntiles)), dct_threads<T, TPP, MODE>(), 0, st>>>(a);
+      <<<dim3(static_cast<unsigned>(ntiles)), dct_threads<T, TPP>(), 0, st>>>(a);
   return hipGetLastError();
 }
 
@@ -485,11 +483,7 @@ hipError_t launch_mode_dct(int prec, int side, int mode, int epi, const DctArgs&
   if (mode == kDctFwdMulInv && (side != 0 || a.pre != 1 || !a.lam_x || !a.lam_y || !a.lam_z))
     return hipErrorInvalidValue;
   if (epi == kEpiAddU && (side != 1 || mode != kDctInv)) return hipErrorInvalidValue;
-  if (mode == kDctRhsFwd) {
-    const int w = (prec == kPrecF64 ? 128 : 256) / (a.n >= 128 ? 16 : 8);  // pencils per workgroup
-    if (side != 1 || a.nx < 1 || a.ny < 1 || a.ny % w != 0 || static_cast<long>(a.nx) * a.ny != a.pre)
-      return hipErrorInvalidValue;
-  }
+  if (mode == kDctRhsFwd && side != 1) return hipErrorInvalidValue;
   if (epi != kEpiStore && epi != kEpiAddU) return hipErrorInvalidValue;
   DctArgs b = a;  // with the basis scale factors c_0 = sqrt(1/n), c_k = sqrt(2/n)
   b.c0 = std::sqrt(1.0 / a.n);
