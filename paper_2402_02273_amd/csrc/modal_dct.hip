@@ -196,6 +196,8 @@ __device__ __forceinline__ void pencil_dft(C* lds, int w, int j, C (&x1)[N2], C 
   __syncthreads();
 }
 
+// At least two waves per SIMD: the passes are latency-bound, and a register
+// budget above 256 would halve the waves in flight (every pass fits now).
 template <typename T, int N1, int N2, int SIDE, int MODE, int EPI>
 __global__ __launch_bounds__((dct_threads<T, (N1 > N2 ? N1 : N2)>()), 2) void k_mode_dct(DctArgs a) {
   using C = typename CxT<T>::type;
