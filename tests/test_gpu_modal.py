@@ -125,7 +125,12 @@ def test_modal_equals_stencil_taylor(native):
     um, us = dev(w.u0, torch.float64), dev(w.u0, torch.float64)
     cm.advance(um, w.nsteps)
     cs.advance(us, w.nsteps)
-    assert rel(um.cpu().numpy(), us.cpu().numpy()) < 1e-12
+    a, b = um.cpu().numpy(), us.cpu().numpy()
+    vox = np.abs(a - b).max() / np.abs(b).max()
+    print(f"[result] modal vs stencil-Taylor FP64 64^3 x5: rel-L2 {rel(a, b):.2e}, max voxel {vox:.2e}", flush=True)
+    assert rel(a, b) < 1e-12
+    # every voxel, not only the norm: a wrong face at a tile edge would show here
+    assert vox < 1e-12
 
 
 def test_modal_rejections(native):
