@@ -60,6 +60,11 @@ struct DctArgs {
   int nx = 1, ny = 1;
 };
 bool dct_axis_ok(int n);
+// A side-0 pass addresses a thread's elements from a 32-bit offset within a
+// tile row: false where a pass along an axis of n points with `post` columns
+// would need more (FP64 x axis: ny nz of 2^26 or more), so that axis keeps
+// the dense products.
+bool dct_rows_ok(int prec, int n, int side, long post);
 // prec kPrecF64 or kPrecF32; mode DctMode; epi kEpiStore or (kDctInv, side 1)
 // kEpiAddU; kDctRhsFwd needs side 1 and ny a multiple of the workgroup's
 // pencil count (32 suffices).  hipErrorInvalidValue for anything else.

@@ -463,6 +463,20 @@ hipError_t launch_dct_t(int side, int mode, int epi, const DctArgs& a, hipStream
 
 bool dct_axis_ok(int n) { return n == 32 || n == 64 || n == 128 || n == 256; }
 
+namespace {
+template <typename T, int TPP>
+bool dct_rows_fit(long post) {
+  return static_cast<double>(dct_threads<T, TPP>() / dct_pencils<T, TPP>()) * post * sizeof(T) < 4294967296.0;
+}
+}  // namespace
+
+bool dct_rows_ok(int prec, int n, int side, long post) {
+  if (side != 0) return true;
+  const bool f64 = prec == kPrecF64, wide = n >= 128;
+  return f64 ? (wide ? dct_rows_fit<double, 16>(post) : dct_rows_fit<double, 8>(post))
+             : (wide ? dct_rows_fit<float, 16>(post) : dct_rows_fit<float, 8>(post));
+}
+
 void dct_tables(int n, std::vector<double>& tw, std::vector<double>& mk) {
   const double pi = 3.14159265358979323846;
   tw.assign(2 * static_cast<size_t>(n), 0.0);

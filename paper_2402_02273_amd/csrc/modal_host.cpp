@@ -132,11 +132,13 @@ int modal_setup(expint_ctx* c) {
     if ((rc = upload_op(c, inv, n, &c->modal.q[ax][1]))) return rc;
     if ((rc = c->arena.alloc(reinterpret_cast<void**>(&c->modal.lam[ax]), n * sizeof(double)))) return rc;
     HIP_TRY(c, hipMemcpy(c->modal.lam[ax], lam.data(), n * sizeof(double), hipMemcpyHostToDevice));
-    // zero flux, FP64 or FP32, a power-of-two length: the products along this
-    // axis run as fast cosine transforms (EXPINT_MODAL_DCT=0: dense products)
+    // zero flux, FP64 or FP32, a power-of-two length, tile rows within a
+    // 32-bit offset: the products along this axis run as fast cosine
+    // transforms (EXPINT_MODAL_DCT=0: dense products)
     const char* de = std::getenv("EXPINT_MODAL_DCT");
+    const long post = ax == 0 ? static_cast<long>(c->g.ny) * c->g.nz : ax == 1 ? c->g.nz : 1;
     if (c->bc == EXPINT_NOFLUX && (c->modal.prec == kPrecF64 || c->modal.prec == kPrecF32) && dct_axis_ok(n) &&
-        !(de && de[0] == '0')) {
+        dct_rows_ok(c->modal.prec, n, ax == 2 ? 1 : 0, post) && !(de && de[0] == '0')) {
       std::vector<double> tw, mk;
       dct_tables(n, tw, mk);
       if ((rc = c->arena.alloc(reinterpret_cast<void**>(&c->modal.dct_tw[ax]), tw.size() * sizeof(double)))) return rc;
